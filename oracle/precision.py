@@ -1,0 +1,76 @@
+"""Oracle: emulation of the reduced-precision smoother.  TEST INFRASTRUCTURE
+ONLY.
+
+The paper runs everything in (presumably) FP64.  The reduced-precision
+variant keeps the coarse space in FP64 and stores the smoother operators at
+lower precision.  This module rounds values at the same storage points, with
+round-to-nearest-even, and performs the arithmetic in between in FP64 (grain
+blocks) or FP32 (contact blocks), as the variant prescribes:
+
+* grain blocks: the FP64 Cholesky factor L_i of A_gi is inverted in FP64,
+  W_i = L_i^-1, and W_i is rounded to the storage precision; the smoother is
+  z = W_i^T (W_i r) evaluated in FP64 on the rounded W_i;
+* contact blocks: A_zeta is rounded to FP32, factored and inverted in FP32,
+  and the FP32 inverse factor is rounded to the storage precision.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def round_f32(x):
+    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def round_bf16(x):
+    """Round FP64 values to bfloat16 (via FP32), round-to-nearest-even."""
+    f = np.asarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    bias = 0x7FFF + ((u >> 16) & 1)
+    u = ((u + bias) & 0xFFFF0000).astype(np.uint32)
+    return u.view(np.float32).astype(np.float64)
+
+
+def round_to(x, precision):
+    if precision == "f64":
+        return np.asarray(x, dtype=np.float64)
+    if precision == "f32":
+        return round_f32(x)
+    if precision == "bf16":
+        return round_bf16(x)
+    raise ValueError(precision)
+
+
+class LowPrecisionSmoother:
+    def __init__(self, H, precision, tile=64):
+        self.H = H
+        self.precision = precision
+        self.grain_W = []
+        for ch in H.grain_chol:
+            if ch is None:
+                self.grain_W.append(None)
+                continue
+            L = np.tril(ch[0])
+            Wi = sla.solve_triangular(L, np.eye(L.shape[0]), lower=True)
+            self.grain_W.append(round_to(Wi, precision))
+        self.contact_W = []
+        for d in H.contact_dofs:
+            Az = H.A[d][:, d].toarray().astype(np.float32)
+            L32 = np.linalg.cholesky(Az).astype(np.float32)
+            W32 = sla.solve_triangular(L32, np.eye(L32.shape[0], dtype=np.float32), lower=True)
+            self.contact_W.append(round_to(W32.astype(np.float64), precision))
+
+    def apply_grains(self, r):
+        z = np.zeros_like(r)
+        for dofs, Wi in zip(self.H.grain_dofs, self.grain_W):
+            if Wi is None:
+                continue
+            z[dofs] = Wi.T @ (Wi @ r[dofs])
+        return z
+
+    def apply_contacts(self, r):
+        z = np.zeros_like(r)
+        for dofs, Wz in zip(self.H.contact_dofs, self.contact_W):
+            z[dofs] += Wz.T @ (Wz @ r[dofs])
+        return z
