@@ -1,0 +1,222 @@
+/*
+ * hplmm.h -- C ABI of the MI355X hPLMM library (libhplmm.so).
+ *
+ * The library solves the displacement-form linear-elastic system
+ *     A x = b                                               (paper Eq. 4)
+ * assembled with trilinear (Q1) hexahedra on a voxel grid (Sec. 2), with
+ * right-preconditioned flexible GMRES and the algebraic hPLMM preconditioner
+ *     M^-1 = M_G^-1 + M_L^-1 (I - A M_G^-1)                  (Eq. 16)
+ * whose coarse part M_G^-1 = P^ (P^T A P^)^-1 P^T, P^ = W Q P (Eqs. 18-24)
+ * is built from per-grain shape and correction vectors and Gaussian mortars
+ * (Eqs. 7-8), and whose smoother M_L = M_CG is the contact-grain additive
+ * Schwarz smoother (Eqs. 25-26).
+ *
+ * Conventions shared by every entry point:
+ *  - Nodes are the free FEM nodes (nodes touched by a solid voxel that are
+ *    not on the clamped plane z = 0), numbered 0..n_nodes-1.  Degrees of
+ *    freedom are node-major: dof 3*v + c, c = x, y, z.  Vectors have 3*n_nodes
+ *    float64 entries.
+ *  - "host" arrays are ordinary CPU memory owned by the caller unless stated;
+ *    the library copies what it keeps.  "device" arrays are HIP device memory
+ *    (e.g. PyTorch CUDA tensors on ROCm) owned by the caller.
+ *  - `stream` is a hipStream_t passed as void* (NULL = default stream).
+ *    Device work is enqueued on that stream.
+ *  - Every function returns an hplmm_status; errors never unwind across the
+ *    ABI.  hplmm_last_error() gives a text message for the calling thread.
+ *  - A handle is not thread safe; distinct handles are independent.
+ */
+#ifndef HPLMM_H
+#define HPLMM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t hplmm_status;
+#define HPLMM_OK                 0
+#define HPLMM_NOT_CONVERGED      1   /* solve hit maxit; x holds the last iterate   */
+#define HPLMM_E_ARG             -1   /* invalid argument, size or layout            */
+#define HPLMM_E_PARTITION       -2   /* partition does not cover the nodes, or two
+                                        grains' interiors are coupled by A          */
+#define HPLMM_E_NOT_SPD         -3   /* a local or coarse Cholesky pivot was <= 0    */
+#define HPLMM_E_SINGULAR_COARSE -4   /* coarse correction pivot b_i^T c_i <= 0       */
+#define HPLMM_E_HIP             -5   /* a HIP runtime call failed                    */
+#define HPLMM_E_OOM             -6   /* device allocation failed                     */
+#define HPLMM_E_NONFINITE       -7   /* NaN/Inf in a Krylov quantity                 */
+#define HPLMM_E_STATE           -8   /* call out of order (e.g. apply before setup)  */
+
+typedef struct hplmm_handle hplmm_handle;
+
+/* ---------------------------------------------------------------------------
+ * Problem description (host side, no GPU needed).
+ * ------------------------------------------------------------------------- */
+
+/* Assembled fine system, block-sparse with 3x3 blocks (paper Eq. 4).
+ * row_ptr[n_nodes+1] (int64), col_idx[nnzb] (int32, ascending within each
+ * row, pattern symmetric), val[9*nnzb] row-major 3x3 blocks (float64).
+ * rhs[3*n_nodes]: load vector b.  node_xyz[3*n_nodes]: integer lattice
+ * coordinates (i, j, k) of every node.  When returned by
+ * hplmm_assemble_voxels the arrays are owned by the library and released with
+ * hplmm_system_free; when passed in, they are the caller's. */
+typedef struct hplmm_system {
+    int64_t n_nodes;
+    int64_t nnzb;
+    int64_t *row_ptr;
+    int32_t *col_idx;
+    double  *val;
+    double  *rhs;
+    int32_t *node_xyz;
+} hplmm_system;
+
+/* Decomposition into grain grids, contact interfaces and contact grids
+ * (Sec. 3.1-3.2).  n_nodes must equal the system's.  node_grain[n_nodes]: grain id of a grain-interior node, or
+ * -1 for an interface node.  Interfaces as CSR: iface_ptr[n_ifaces+1],
+ * iface_nodes[...] (ascending node ids).  Contact grids as CSR:
+ * contact_ptr[n_contacts+1], contact_nodes[...] (ascending).  Every node is
+ * in exactly one grain interior or one interface.  Library-owned when
+ * returned by hplmm_partition_from_voxels (free with hplmm_partition_free). */
+typedef struct hplmm_partition {
+    int64_t  n_nodes;
+    int32_t  n_grains;
+    int32_t *node_grain;
+    int32_t  n_ifaces;
+    int64_t *iface_ptr;
+    int32_t *iface_nodes;
+    int32_t  n_contacts;
+    int64_t *contact_ptr;
+    int32_t *contact_nodes;
+} hplmm_partition;
+
+/* Assemble the Q1 stiffness matrix and load of a voxel solid (Sec. 2,
+ * Eqs. 1-4).  solid[nx*ny*nz] (uint8, x fastest), E[nx*ny*nz] Young's modulus
+ * per voxel (ignored on void), nu Poisson ratio, traction[3] the uniform
+ * traction on the top face z = nz of the top solid layer (consistent load,
+ * a quarter per face node).  Voxel edge length 1; the plane z = 0 is clamped.
+ * Host only.  On error *out is zeroed. */
+hplmm_status hplmm_assemble_voxels(int32_t nx, int32_t ny, int32_t nz,
+                                   const uint8_t *solid, const double *E, double nu,
+                                   const double *traction, hplmm_system *out);
+void hplmm_system_free(hplmm_system *sys);
+
+/* Classify nodes and build interfaces and contact grids from a voxel
+ * labelling (Sec. 3.1).  voxel_label[nx*ny*nz]: grain id in [0, n_labels)
+ * for solid voxels (ignored on void).  A node whose touching solid voxels
+ * carry one label is interior to that grain; otherwise it is an interface
+ * node, and an interface is a connected set (two nodes connect when both are
+ * corners of one solid voxel) of interface nodes with the same set of touching
+ * labels.  Interfaces are numbered by smallest node id.  Contact grid c holds
+ * every node within Chebyshev lattice distance w_zeta of interface c (the
+ * dilation of Sec. 3.1).  Host only. */
+hplmm_status hplmm_partition_from_voxels(int32_t nx, int32_t ny, int32_t nz,
+                                         const uint8_t *solid, const int32_t *voxel_label,
+                                         int32_t n_labels, int32_t w_zeta,
+                                         hplmm_partition *out);
+void hplmm_partition_free(hplmm_partition *part);
+
+/* Mortar space (Sec. 3.3): n = mortar nodes per interface (n = 1 is PLMM),
+ * beta = Gaussian spread (Eq. 8; the paper uses 4). */
+typedef struct hplmm_mortar {
+    int32_t n;
+    double  beta;
+} hplmm_mortar;
+
+/* Smoother precision: 64 = float64; 32 = float32 contact factorisation and
+ * float32 smoother operators; 16 = float32 contact factorisation and
+ * bfloat16 smoother operators.  The coarse space (basis, coarse operator,
+ * coarse solve) and the Krylov solver are float64 in every mode. */
+typedef struct hplmm_options {
+    int32_t smoother_precision;
+} hplmm_options;
+
+/* Place the mortar nodes of one interface (Sec. 3.3, Eq. 7): xyz[3*N] lattice
+ * coordinates of its nodes in interface order; writes nu = min(n, N) node
+ * indices (into 0..N-1) to idx_out.  Host only; exposed for testing. */
+hplmm_status hplmm_place_mortars(const int32_t *xyz, int32_t N, int32_t n, int32_t *idx_out);
+
+/* ---------------------------------------------------------------------------
+ * Preconditioner and solver (device).
+ * ------------------------------------------------------------------------- */
+
+/* Symbolic phase: validate the system and partition, place mortars and
+ * compute Gaussian weights (Eqs. 7-8), decide the correction columns from
+ * the load (a grain whose load is identically zero gets none), build the
+ * device data layout and the launch plans, and upload A, b and all index
+ * maps to the current device.  Host arrays are copied and may be released
+ * afterwards.  b may be NULL (no correction columns).  The returned handle
+ * owns all device memory until hplmm_destroy. */
+hplmm_status hplmm_plan(const hplmm_system *sys, const hplmm_partition *part,
+                        const hplmm_mortar *mortar, const hplmm_options *opt,
+                        void *stream, hplmm_handle **out);
+
+/* Host-only dry run of hplmm_plan: the same validation and planning, then a
+ * bounds check of every launch task list and index map against the buffers
+ * they address, without touching a device.  sizes (may be NULL) receives
+ * int64[16] = {n_nodes, nnzb, n_grains, n_ifaces, n_contacts, n_mortar_dofs,
+ * n_corr, n_coarse, grain_mats, f64 arena elements, f32 arena elements, bf16
+ * arena elements, f64 tile tasks, f64 tile pairs, gemv tasks, gemv pairs}. */
+hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_partition *part,
+                              const hplmm_mortar *mortar, const hplmm_options *opt, int64_t *sizes);
+
+/* Numeric set-up on the device (the paper's T_MG + T_ML): gather grain,
+ * contact and coupling blocks; batched Cholesky and triangular inversion of
+ * grain blocks A_gi and contact blocks; basis X_i = A_gi^-1 [-Abar_gi | b_gi]
+ * (Eqs. 23-24); Galerkin coarse operator P^T A P^ (Eq. 18) and its
+ * factorisation.  Asynchronous on `stream` except for one final check of the
+ * pivot flags (reported as HPLMM_E_NOT_SPD / HPLMM_E_SINGULAR_COARSE). */
+hplmm_status hplmm_setup(hplmm_handle *h, void *stream);
+
+/* z = Op r for r, z device vectors of 3*n_nodes float64 (must not alias).
+ * which: 0 = M^-1 (Eq. 16), 1 = M_G^-1 (Eq. 18), 2 = M_CG^-1 (Eq. 25),
+ *        3 = M_zeta^-1, 4 = M_g^-1 (Eq. 26).  Asynchronous on `stream`. */
+hplmm_status hplmm_apply(hplmm_handle *h, int32_t which, const double *r_dev,
+                         double *z_dev, void *stream);
+
+/* y = A x (device vectors, must not alias).  Asynchronous. */
+hplmm_status hplmm_spmv(hplmm_handle *h, const double *x_dev, double *y_dev, void *stream);
+
+/* Solve A x = b with right-preconditioned flexible GMRES(restart) and M.
+ * b_dev: right-hand side (device); x_dev: initial guess on entry (device),
+ * solution on exit.  Stops when the true residual |b - A x| / |b| < rtol
+ * (checked whenever the Arnoldi estimate drops below rtol and at every
+ * restart) or after maxit Arnoldi steps.  fixed_iters > 0 runs exactly that
+ * many steps and forms x.  Synchronises with the host once per step.
+ * info (may be NULL) receives the counts, times and the residual history
+ * (res_hist: caller buffer of res_hist_cap doubles, may be NULL). */
+typedef struct hplmm_solve_info {
+    int32_t iters;
+    double  rel_res_true;
+    double  t_solve_ms;
+    double *res_hist;
+    int32_t res_hist_cap;
+    int32_t res_hist_len;
+} hplmm_solve_info;
+
+hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, double rtol,
+                         int32_t restart, int32_t maxit, int32_t fixed_iters,
+                         hplmm_solve_info *info, void *stream);
+
+/* Introspection for tests and benchmarks.  what:
+ *   0 sizes: int64[16] = {n_nodes, nnzb, n_grains, n_ifaces, n_contacts,
+ *            n_mortar_dofs, n_corr, n_coarse, grain_mats, max_grain_dofs,
+ *            max_contact_dofs, sell_slices, sell_padded_blocks, 0, 0, 0}
+ *   1 mortar node ids: int32 per interface, concatenated in interface order
+ *            (nu_c entries each, local indices into the interface's nodes)
+ *   2 Gaussian weights: float64, per interface row-major N_c x nu_c
+ *   3 correction grains: int32[n_corr] grain ids, ascending
+ *   4 coarse matrix: float64 n_coarse x n_coarse row-major (after setup):
+ *            mortar block then the correction diagonal
+ *   5 setup phase times in ms: double[4] = {grains, contacts, coarse, total}
+ *   6 device bytes held: int64[1]
+ * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
+hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
+                         int64_t *needed_bytes);
+
+void        hplmm_destroy(hplmm_handle *h);
+const char *hplmm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPLMM_H */

@@ -1,0 +1,52 @@
+/*
+ * hplmm_debug.h -- test hooks of libhplmm.
+ *
+ * These entry points exist so that tests can check single kernels of the
+ * library (one 64x64 tile contraction, one diagonal-tile factorisation) and
+ * the intermediate state of the set-up against an independent reference.
+ * They are not needed to use the solver.  Same conventions as hplmm.h.
+ */
+#ifndef HPLMM_DEBUG_H
+#define HPLMM_DEBUG_H
+
+#include "hplmm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* One tile task of the set-up contraction kernel on caller device buffers:
+ * C (op)= alpha [P] sum_p op(A_p) op(B_p) with 64x64 column-major tiles.
+ * A_dev, B_dev: npairs tiles each, consecutive; C_dev: one tile; P_dev: one
+ * tile or NULL; flags: bit0 transpose A, bit1 transpose B, bit2 accumulate
+ * into C, bit3 alpha = -1, bit4 left-multiply by P.  precision 64 or 32 selects
+ * float64 or float32 tiles (all buffers of that type). */
+hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A_dev, const void *B_dev, int32_t npairs,
+                                   const void *P_dev, void *C_dev, int32_t flags, void *stream);
+
+/* One diagonal-tile factorisation: A_dev (64x64 column-major, SPD; lower part
+ * read) is overwritten by its Cholesky factor L (zeros above), W_dev gets
+ * L^-1 and Wt_dev gets L^-T.  Returns HPLMM_E_NOT_SPD on a bad pivot. */
+hplmm_status hplmm_debug_diag(int32_t precision, void *A_dev, void *W_dev, void *Wt_dev, void *stream);
+
+/* Run the numeric set-up of a planned handle up to a stage and stop:
+ *   stage 0: zero and gather grain blocks, coupling blocks and loads
+ *   stage 1: + grain factorisation (Cholesky and inverse)
+ *   stage 2: + basis products
+ *   stage 3: full set-up (same as hplmm_setup).
+ * Synchronises before returning. */
+hplmm_status hplmm_debug_setup_stage(hplmm_handle *h, int32_t stage, void *stream);
+
+/* Copy count elements starting at element offset off of an internal arena
+ * (0 = float64, 1 = float32, 2 = bfloat16 bits) to host memory. */
+hplmm_status hplmm_debug_read_arena(hplmm_handle *h, int32_t arena, int64_t off, int64_t count, void *host_out);
+
+/* Layout of a planned handle for tests: int64 per grain matrix m (grain id,
+ * dofs, tiles nt, columns ncol, column tiles ntc, A offset, W offset, Wt
+ * offset, R offset, Y offset, K offset) -- 11 values per matrix. */
+hplmm_status hplmm_debug_grain_layout(hplmm_handle *h, int64_t *out, int64_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPLMM_DEBUG_H */

@@ -1,0 +1,609 @@
+// C ABI of libhplmm: plan, numeric set-up, preconditioner application,
+// flexible GMRES and introspection.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "../../include/hplmm_debug.h"
+#include "handle.h"
+
+struct hplmm_handle {
+    hplmm::Handle h;
+};
+
+namespace hplmm {
+
+static void hip_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(HPLMM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+static void run_program(const TaskLists &tl, T *arena, const std::vector<Launch> &prog, int32_t *flag, hipStream_t s) {
+    for (const Launch &L : prog) {
+        switch (L.kind) {
+            case LK_DIAG: launch_diag<T>(arena, arena, arena, tl.d_diag + L.start, L.count, flag, s); break;
+            case LK_GEMM: launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s); break;
+            case LK_TRANSPOSE: launch_tile_transpose<T>(arena, arena, tl.d_copy + L.start, L.count, s); break;
+        }
+    }
+}
+
+static void zero(void *p, int64_t bytes, hipStream_t s) {
+    if (bytes > 0) hip_check(hipMemsetAsync(p, 0, (size_t)bytes, s), "hipMemsetAsync");
+}
+
+static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
+    hipEvent_t ev[4];
+    for (auto &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    const int32_t init_flag[2] = {0, 0x7fffffff};
+    hip_check(hipMemcpyAsync(h.d_flag, init_flag, sizeof(init_flag), hipMemcpyHostToDevice, s), "flag init");
+    hip_check(hipEventRecord(ev[0], s), "event");
+    // ---- grains: blocks, factor, inverse, basis (Eqs. 23-24) ----
+    zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
+    if (!h.gm_roff.empty()) {
+        const int64_t r0 = h.gm_roff[0];
+        int64_t rlen = 0;
+        for (size_t m = 0; m < h.gm_roff.size(); ++m) rlen += h.gset.nt[m] * h.gm_ntc[m] * TE;
+        zero(h.ar64 + r0, sizeof(double) * rlen, s);
+    }
+    launch_gather_grain_blocks(h.csr, h.gg, h.d_b, h.ar64, s);
+    launch_set_ones(h.d_pad_g, (int64_t)h.pad_ones_g.size(), h.ar64, s);
+    launch_gather_abar(h.csr, h.d_abar, h.n_abar, h.cm, h.gg, h.ar64, s);
+    if (stage < 1) {
+        hip_check(hipStreamSynchronize(s), "stage");
+        return;
+    }
+    run_program<double>(h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
+    if (stage < 2) {
+        hip_check(hipStreamSynchronize(s), "stage");
+        return;
+    }
+    run_program<double>(h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
+    if (stage < 3) {
+        hip_check(hipStreamSynchronize(s), "stage");
+        return;
+    }
+    launch_gather_scalar(h.d_corr_koff, h.n_corr, h.ar64, h.corr_d, s);
+    if (h.smoother_precision == 32) {
+        launch_convert_f64_f32(h.ar64 + h.gset.w_base, h.ar32 + h.gset.low_w_base, h.gset.region, s);
+        launch_convert_f64_f32(h.ar64 + h.gset.wt_base, h.ar32 + h.gset.low_wt_base, h.gset.region, s);
+    } else if (h.smoother_precision == 16) {
+        launch_convert_f64_bf16(h.ar64 + h.gset.w_base, h.arbf + h.gset.low_w_base, h.gset.region, s);
+        launch_convert_f64_bf16(h.ar64 + h.gset.wt_base, h.arbf + h.gset.low_wt_base, h.gset.region, s);
+    }
+    hip_check(hipEventRecord(ev[1], s), "event");
+    // ---- contact grids (Eq. 26) ----
+    if (h.smoother_precision == 64) {
+        zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
+        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
+        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
+        run_program<double>(h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s);
+    } else {
+        zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
+        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
+        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
+        launch_convert_f64_f32(h.ar64 + h.c_stage_base, h.ar32 + h.cset.a_base, h.cset.region, s);
+        run_program<float>(h.tl32, h.ar32, h.cset.factor_prog, h.d_flag, s);
+        if (h.smoother_precision == 16) {
+            launch_convert_f32_bf16(h.ar32 + h.cset.w_base, h.arbf + h.cset.low_w_base, h.cset.region, s);
+            launch_convert_f32_bf16(h.ar32 + h.cset.wt_base, h.arbf + h.cset.low_wt_base, h.cset.region, s);
+        }
+    }
+    hip_check(hipEventRecord(ev[2], s), "event");
+    // ---- coarse operator P^T A P (Eq. 18) and its factorisation ----
+    if (h.n_mortar > 0) {
+        zero(h.ar64 + h.sset.a_base, sizeof(double) * h.sset.region, s);
+        launch_coarse_assemble(h.d_pairs, h.n_pairs, h.d_edges, h.d_krefs, h.cm, h.csr.val, h.ar64, h.ar64,
+                               h.sset.a_base, s);
+        launch_set_ones(h.d_pad_s, (int64_t)h.pad_ones_s.size(), h.ar64, s);
+        run_program<double>(h.tl64, h.ar64, h.sset.factor_prog, h.d_flag, s);
+    }
+    hip_check(hipEventRecord(ev[3], s), "event");
+    hip_check(hipGetLastError(), "kernel launch");
+    int32_t flag[2];
+    hip_check(hipMemcpyAsync(flag, h.d_flag, sizeof(flag), hipMemcpyDeviceToHost, s), "flag copy");
+    std::vector<double> cd((size_t)h.n_corr);
+    if (h.n_corr)
+        hip_check(hipMemcpyAsync(cd.data(), h.corr_d, sizeof(double) * cd.size(), hipMemcpyDeviceToHost, s), "corr copy");
+    hip_check(hipStreamSynchronize(s), "set-up");
+    float ms[3];
+    for (int i = 0; i < 3; ++i) hip_check(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]), "elapsed");
+    h.t_setup_ms[0] = ms[0];
+    h.t_setup_ms[1] = ms[1];
+    h.t_setup_ms[2] = ms[2];
+    h.t_setup_ms[3] = (double)ms[0] + ms[1] + ms[2];
+    for (auto &e : ev) (void)hipEventDestroy(e);
+    if (flag[0]) {
+        const int set = flag[1] >> 26, m = flag[1] & ((1 << 26) - 1);
+        const char *names[3] = {"grain", "contact-grid", "coarse"};
+        fail(HPLMM_E_NOT_SPD, std::string("non-positive Cholesky pivot in ") + names[set < 3 ? set : 0] +
+                                  " block " + std::to_string(m));
+    }
+    for (size_t j = 0; j < cd.size(); ++j)
+        if (!(cd[j] > 0.0)) fail(HPLMM_E_SINGULAR_COARSE, "coarse correction pivot <= 0 for correction " + std::to_string(j));
+    h.ready = true;
+}
+
+static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, double *y, hipStream_t s) {
+    if (r.count == 0) return;
+    const GemvTask *t = h.d_vtasks + r.start;
+    if (!smoother_low || h.smoother_precision == 64)
+        launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s);
+    else if (h.smoother_precision == 32)
+        launch_gemv<float>(h.ar32, x, y, t, h.d_vpairs, r.count, s);
+    else
+        launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s);
+}
+
+// Contact-grid smoother (reduced precision applies to the stored operators).
+static void contact_solve(Handle &h, const double *rr, hipStream_t s) {
+    launch_gather(h.d_c_slot_dof, rr, h.cx, h.cset.vec_len, s);
+    const bool low = h.smoother_precision != 64;
+    if (h.smoother_precision == 32) {
+        launch_gemv<float>(h.ar32, h.cx, h.ct, h.d_vtasks + h.cset.gemv_W.start, h.d_vpairs, h.cset.gemv_W.count, s);
+        launch_gemv<float>(h.ar32, h.ct, h.cy, h.d_vtasks + h.cset.gemv_Wt.start, h.d_vpairs, h.cset.gemv_Wt.count, s);
+    } else {
+        gemv_set(h, h.cset.gemv_W, low, h.cx, h.ct, s);
+        gemv_set(h, h.cset.gemv_Wt, low, h.ct, h.cy, s);
+    }
+}
+
+static void grain_solve(Handle &h, const double *rr, hipStream_t s) {
+    launch_gather(h.d_g_slot_dof, rr, h.gx, h.gset.vec_len, s);
+    const bool low = h.smoother_precision != 64;
+    gemv_set(h, h.gset.gemv_W, low, h.gx, h.gt, s);
+    gemv_set(h, h.gset.gemv_Wt, low, h.gt, h.gy, s);
+}
+
+// z1 = M_G^-1 r = P^ (P^T A P^)^-1 P^T r   (Eq. 18)
+static void coarse_apply(Handle &h, const double *r, double *z, hipStream_t s) {
+    launch_gather(h.d_g_slot_dof, r, h.gx, h.gset.vec_len, s);
+    gemv_set(h, h.gemv_XT, false, h.gx, h.gc_t, s);
+    launch_coarse_rhs(h.cm, r, h.gc_t, h.sf, s);
+    gemv_set(h, h.sset.gemv_W, false, h.sf, h.st, s);
+    gemv_set(h, h.sset.gemv_Wt, false, h.st, h.su, s);
+    launch_corr_solve(h.cm, h.sf, h.su, s);
+    launch_gather(h.d_gcol_upos, h.su, h.gc_u, h.gcol_len, s);
+    gemv_set(h, h.gemv_X, false, h.gc_u, h.gy, s);
+    launch_prolong_nodes(h.cm, h.n_nodes, h.d_g_dof_slot, h.gy, h.su, z, s);
+}
+
+static void apply_op(Handle &h, int32_t which, const double *r, double *z, hipStream_t s) {
+    const int64_t N = h.N;
+    switch (which) {
+        case 1:
+            coarse_apply(h, r, z, s);
+            return;
+        case 3:
+            contact_solve(h, r, s);
+            launch_combine(N, nullptr, nullptr, nullptr, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, z, s);
+            return;
+        case 4:
+            grain_solve(h, r, s);
+            launch_combine(N, nullptr, h.d_g_dof_slot, h.gy, nullptr, nullptr, nullptr, z, s);
+            return;
+        case 2: {
+            // M_CG^-1 r = M_zeta^-1 r + M_g^-1 (r - A M_zeta^-1 r)   (Eq. 25)
+            contact_solve(h, r, s);
+            launch_combine(N, nullptr, nullptr, nullptr, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, h.z2, s);
+            launch_spmv(h.sell, h.z2, r, h.r2, s);
+            grain_solve(h, h.r2, s);
+            launch_combine(N, h.z2, h.d_g_dof_slot, h.gy, nullptr, nullptr, nullptr, z, s);
+            return;
+        }
+        case 0: {
+            // M^-1 r = M_G^-1 r + M_CG^-1 (r - A M_G^-1 r)   (Eq. 16)
+            coarse_apply(h, r, h.z1, s);
+            launch_spmv(h.sell, h.z1, r, h.r1, s);
+            contact_solve(h, h.r1, s);
+            launch_combine(N, nullptr, nullptr, nullptr, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, h.z2, s);
+            launch_spmv(h.sell, h.z2, h.r1, h.r2, s);
+            grain_solve(h, h.r2, s);
+            launch_combine(N, h.z1, h.d_g_dof_slot, h.gy, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, z, s);
+            return;
+        }
+        default:
+            fail(HPLMM_E_ARG, "which must be 0..4");
+    }
+}
+
+// ---- flexible GMRES (right preconditioning) --------------------------------------
+static void ensure_krylov(Handle &h, int32_t restart) {
+    if (h.kr_restart >= restart) return;
+    h.kr_restart = restart;
+    h.V = h.dalloc<double>((int64_t)(restart + 1) * h.N);
+    h.Z = h.dalloc<double>((int64_t)restart * h.N);
+    h.w = h.dalloc<double>(h.N);
+    h.kr_blocks = multidot_blocks(h.N);
+    h.part = h.dalloc<double>((int64_t)h.kr_blocks * (restart + 2));
+    h.hbuf = h.dalloc<double>(restart + 4);
+    h.h2 = h.dalloc<double>(restart + 4);
+    h.ydev = h.dalloc<double>(restart + 4);
+}
+
+static double device_dot(Handle &h, const double *a, const double *b, double *dst, hipStream_t s) {
+    launch_multidot(a, 0, 1, b, h.N, h.part, h.kr_blocks, s);
+    launch_reduce_parts(h.part, h.kr_blocks, 1, dst, 0, s);
+    double v;
+    hip_check(hipMemcpyAsync(&v, dst, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
+    hip_check(hipStreamSynchronize(s), "sync");
+    return v;
+}
+
+static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, int32_t m, int32_t maxit,
+                          int32_t fixed, hplmm_solve_info *info, hipStream_t s) {
+    ensure_krylov(h, m);
+    const int64_t N = h.N;
+    const double bnorm = std::sqrt(device_dot(h, b, b, h.hbuf, s));
+    std::vector<double> hist;
+    int32_t it = 0;
+    double rel = 0.0;
+    bool conv = false;
+    const int32_t limit = fixed > 0 ? fixed : maxit;
+    if (bnorm == 0.0) {
+        hip_check(hipMemsetAsync(x, 0, sizeof(double) * (size_t)N, s), "memset");
+        conv = true;
+    }
+    std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 2);
+    while (!conv && it < limit) {
+        launch_spmv(h.sell, x, b, h.V, s);       // r0 = b - A x
+        const double beta = std::sqrt(device_dot(h, h.V, h.V, h.hbuf, s));
+        rel = beta / bnorm;
+        if (!std::isfinite(beta)) fail(HPLMM_E_NONFINITE, "non-finite residual");
+        if (fixed <= 0 && rel < rtol) {
+            conv = true;
+            break;
+        }
+        launch_normalize(h.V, h.hbuf, h.V, N, s);
+        std::fill(H.begin(), H.end(), 0.0);
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int32_t j = 0;
+        for (; j < m && it < limit; ++j) {
+            double *vj = h.V + (int64_t)j * N, *zj = h.Z + (int64_t)j * N;
+            apply_op(h, 0, vj, zj, s);
+            launch_spmv(h.sell, zj, nullptr, h.w, s);
+            // classical Gram-Schmidt, twice
+            launch_multidot(h.V, N, j + 1, h.w, N, h.part, h.kr_blocks, s);
+            launch_reduce_parts(h.part, h.kr_blocks, j + 1, h.hbuf, 0, s);
+            launch_subtract_combination(h.V, N, j + 1, h.hbuf, h.w, N, s);
+            launch_multidot(h.V, N, j + 1, h.w, N, h.part, h.kr_blocks, s);
+            launch_reduce_parts(h.part, h.kr_blocks, j + 1, h.h2, 0, s);
+            launch_subtract_combination(h.V, N, j + 1, h.h2, h.w, N, s);
+            launch_axpby(1.0, h.hbuf, 1.0, h.h2, h.hbuf, j + 1, s);
+            launch_multidot(h.w, 0, 1, h.w, N, h.part, h.kr_blocks, s);
+            launch_reduce_parts(h.part, h.kr_blocks, 1, h.hbuf + j + 1, 0, s);
+            launch_normalize(h.w, h.hbuf + j + 1, h.V + (int64_t)(j + 1) * N, N, s);
+            hip_check(hipMemcpyAsync(hv.data(), h.hbuf, sizeof(double) * (size_t)(j + 2), hipMemcpyDeviceToHost, s), "copy h");
+            hip_check(hipStreamSynchronize(s), "step");
+            hv[(size_t)j + 1] = std::sqrt(hv[(size_t)j + 1]);
+            for (int32_t i = 0; i <= j + 1; ++i)
+                if (!std::isfinite(hv[(size_t)i])) fail(HPLMM_E_NONFINITE, "non-finite Arnoldi coefficient");
+            double *col = &H[(size_t)j * (m + 1)];
+            for (int32_t i = 0; i <= j + 1; ++i) col[i] = hv[(size_t)i];
+            for (int32_t i = 0; i < j; ++i) {
+                const double t = cs[i] * col[i] + sn[i] * col[i + 1];
+                col[i + 1] = -sn[i] * col[i] + cs[i] * col[i + 1];
+                col[i] = t;
+            }
+            const double d = std::hypot(col[j], col[j + 1]);
+            cs[j] = col[j] / d;
+            sn[j] = col[j + 1] / d;
+            col[j] = d;
+            col[j + 1] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            ++it;
+            hist.push_back(std::fabs(g[j + 1]) / bnorm);
+            if (fixed <= 0 && std::fabs(g[j + 1]) / bnorm < rtol) {
+                ++j;
+                break;
+            }
+        }
+        const int32_t k = j;
+        std::vector<double> y(k);
+        for (int32_t i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int32_t l = i + 1; l < k; ++l) t -= H[(size_t)l * (m + 1) + i] * y[l];
+            y[i] = t / H[(size_t)i * (m + 1) + i];
+        }
+        hip_check(hipMemcpyAsync(h.ydev, y.data(), sizeof(double) * (size_t)k, hipMemcpyHostToDevice, s), "copy y");
+        launch_add_combination(h.Z, N, k, h.ydev, x, N, s);
+        launch_spmv(h.sell, x, b, h.w, s);
+        rel = std::sqrt(device_dot(h, h.w, h.w, h.hbuf, s)) / bnorm;
+        if (fixed <= 0 && rel < rtol) conv = true;
+    }
+    if (info) {
+        info->iters = it;
+        info->rel_res_true = rel;
+        info->res_hist_len = 0;
+        if (info->res_hist && info->res_hist_cap > 0) {
+            const int32_t n = std::min<int32_t>(info->res_hist_cap, (int32_t)hist.size());
+            std::memcpy(info->res_hist, hist.data(), sizeof(double) * (size_t)n);
+            info->res_hist_len = n;
+        }
+    }
+    if (fixed > 0) return HPLMM_OK;
+    return conv ? HPLMM_OK : HPLMM_NOT_CONVERGED;
+}
+
+}  // namespace hplmm
+
+using namespace hplmm;
+
+static hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+extern "C" hplmm_status hplmm_plan(const hplmm_system *sys, const hplmm_partition *part, const hplmm_mortar *mortar,
+                                   const hplmm_options *opt, void *stream, hplmm_handle **out) {
+    return guarded([&]() -> hplmm_status {
+        if (!out) fail(HPLMM_E_ARG, "out is NULL");
+        *out = nullptr;
+        if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
+        hplmm_options o{64};
+        if (opt) o = *opt;
+        int dev = 0;
+        hip_check(hipGetDevice(&dev), "hipGetDevice");
+        auto *hh = new hplmm_handle();
+        try {
+            hh->h.device = dev;
+            build_plan(hh->h, *sys, *part, *mortar, o, as_stream(stream), false);
+        } catch (...) {
+            delete hh;
+            throw;
+        }
+        *out = hh;
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_partition *part,
+                                         const hplmm_mortar *mortar, const hplmm_options *opt, int64_t *sizes) {
+    return guarded([&]() -> hplmm_status {
+        if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
+        hplmm_options o{64};
+        if (opt) o = *opt;
+        Handle h;
+        build_plan(h, *sys, *part, *mortar, o, nullptr, true);
+        if (sizes) {
+            int64_t v[16] = {h.n_nodes, h.nnzb, h.n_grains, h.n_ifaces, h.n_contacts, h.n_mortar, h.n_corr,
+                             h.n_coarse, (int64_t)h.gset.n.size(), h.ar64_n, h.ar32_n, h.arbf_n,
+                             (int64_t)h.tl64.gemm.size(), (int64_t)h.tl64.pairs.size(), (int64_t)h.vtasks.size(),
+                             (int64_t)h.vpairs.size()};
+            std::memcpy(sizes, v, sizeof(v));
+        }
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_setup(hplmm_handle *hh, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        hh->h.ready = false;
+        numeric_setup(hh->h, as_stream(stream));
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_apply(hplmm_handle *hh, int32_t which, const double *r, double *z, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !r || !z) fail(HPLMM_E_ARG, "NULL argument");
+        if (r == z) fail(HPLMM_E_ARG, "r and z must not alias");
+        if (!hh->h.ready) fail(HPLMM_E_STATE, "hplmm_setup has not completed");
+        apply_op(hh->h, which, r, z, as_stream(stream));
+        hip_check(hipGetLastError(), "kernel launch");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_spmv(hplmm_handle *hh, const double *x, double *y, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !x || !y) fail(HPLMM_E_ARG, "NULL argument");
+        if (x == y) fail(HPLMM_E_ARG, "x and y must not alias");
+        launch_spmv(hh->h.sell, x, nullptr, y, as_stream(stream));
+        hip_check(hipGetLastError(), "kernel launch");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_solve(hplmm_handle *hh, const double *b, double *x, double rtol, int32_t restart,
+                                    int32_t maxit, int32_t fixed_iters, hplmm_solve_info *info, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !b || !x) fail(HPLMM_E_ARG, "NULL argument");
+        if (b == x) fail(HPLMM_E_ARG, "b and x must not alias");
+        if (!hh->h.ready) fail(HPLMM_E_STATE, "hplmm_setup has not completed");
+        if (restart < 1 || restart > 120 || maxit < 0) fail(HPLMM_E_ARG, "restart must be in [1, 120], maxit >= 0");
+        const auto t0 = std::chrono::steady_clock::now();
+        const hplmm_status st = gmres(hh->h, b, x, rtol, restart, maxit, fixed_iters, info, as_stream(stream));
+        const auto t1 = std::chrono::steady_clock::now();
+        if (info) info->t_solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+        return st;
+    });
+}
+
+extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, int64_t cap, int64_t *needed) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        Handle &h = hh->h;
+        std::vector<char> buf;
+        auto put = [&](const void *p, size_t n) { buf.insert(buf.end(), (const char *)p, (const char *)p + n); };
+        switch (what) {
+            case 0: {
+                int64_t mx_g = 0, mx_c = 0;
+                for (auto v : h.gset.n) mx_g = std::max(mx_g, v);
+                for (auto v : h.cset.n) mx_c = std::max(mx_c, v);
+                int64_t v[16] = {h.n_nodes, h.nnzb, h.n_grains, h.n_ifaces, h.n_contacts, h.n_mortar, h.n_corr,
+                                 h.n_coarse, (int64_t)h.gset.n.size(), mx_g, mx_c, h.sell.n_slices,
+                                 h.sell_padded_blocks, 0, 0, 0};
+                put(v, sizeof(v));
+                break;
+            }
+            case 1: put(h.h_mortar_idx.data(), sizeof(int32_t) * h.h_mortar_idx.size()); break;
+            case 2: put(h.h_H.data(), sizeof(double) * h.h_H.size()); break;
+            case 3: put(h.h_corr_grains.data(), sizeof(int32_t) * h.h_corr_grains.size()); break;
+            case 4: {
+                if (!h.ready) fail(HPLMM_E_STATE, "hplmm_setup has not completed");
+                const int64_t nc = h.n_coarse;
+                // The coarse factor overwrote S; rebuild S = L L^T on the host from
+                // the lower tiles of L, and append the correction diagonal.
+                std::vector<double> Ltiles((size_t)h.sset.region);
+                if (h.sset.region)
+                    hip_check(hipMemcpy(Ltiles.data(), h.ar64 + h.sset.a_base, sizeof(double) * Ltiles.size(),
+                                        hipMemcpyDeviceToHost), "copy");
+                std::vector<double> cd((size_t)h.n_corr);
+                if (h.n_corr)
+                    hip_check(hipMemcpy(cd.data(), h.corr_d, sizeof(double) * cd.size(), hipMemcpyDeviceToHost), "copy");
+                const int64_t nm = h.n_mortar;
+                std::vector<double> L((size_t)(nm * nm), 0.0);
+                for (int64_t r = 0; r < nm; ++r)
+                    for (int64_t c = 0; c <= r; ++c)
+                        L[(size_t)(r * nm + c)] =
+                            Ltiles[(size_t)(tri_index(r / TS, c / TS) * TE + (c % TS) * TS + (r % TS))];
+                std::vector<double> S((size_t)(nc * nc), 0.0);
+                for (int64_t r = 0; r < nm; ++r)
+                    for (int64_t c = 0; c <= r; ++c) {
+                        double t = 0.0;
+                        for (int64_t k = 0; k <= c; ++k) t += L[(size_t)(r * nm + k)] * L[(size_t)(c * nm + k)];
+                        S[(size_t)(r * nc + c)] = S[(size_t)(c * nc + r)] = t;
+                    }
+                for (int64_t j = 0; j < h.n_corr; ++j) S[(size_t)((nm + j) * nc + nm + j)] = cd[(size_t)j];
+                put(S.data(), sizeof(double) * S.size());
+                break;
+            }
+            case 5: put(h.t_setup_ms, sizeof(h.t_setup_ms)); break;
+            case 6: put(&h.dev_bytes, sizeof(int64_t)); break;
+            default: fail(HPLMM_E_ARG, "unknown query");
+        }
+        if (needed) *needed = (int64_t)buf.size();
+        if (out && cap > 0) std::memcpy(out, buf.data(), (size_t)std::min<int64_t>(cap, (int64_t)buf.size()));
+        return HPLMM_OK;
+    });
+}
+
+extern "C" void hplmm_destroy(hplmm_handle *hh) {
+    if (!hh) return;
+    (void)hipDeviceSynchronize();
+    delete hh;
+}
+
+// ---- test hooks ---------------------------------------------------------------------
+extern "C" hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A, const void *B, int32_t npairs,
+                                              const void *Pm, void *Cm, int32_t flags, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!A || !B || !Cm || npairs < 1 || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
+        if ((flags & GF_POST) && !Pm) fail(HPLMM_E_ARG, "P needed");
+        hipStream_t s = as_stream(stream);
+        const size_t es = precision == 64 ? 8 : 4;
+        // gather everything into one scratch arena: [A tiles][B tiles][P][C]
+        const int64_t n_el = (int64_t)(2 * npairs + 2) * TE;
+        void *ar = nullptr;
+        hip_check(hipMalloc(&ar, es * (size_t)n_el), "hipMalloc");
+        char *base = (char *)ar;
+        hip_check(hipMemcpyAsync(base, A, es * TE * npairs, hipMemcpyDeviceToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(base + es * TE * npairs, B, es * TE * npairs, hipMemcpyDeviceToDevice, s), "copy");
+        if (Pm) hip_check(hipMemcpyAsync(base + es * TE * 2 * npairs, Pm, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(base + es * TE * (2 * npairs + 1), Cm, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        std::vector<GemmPair> pr;
+        for (int32_t p = 0; p < npairs; ++p) pr.push_back({(int64_t)p * TE, (int64_t)(npairs + p) * TE});
+        GemmTask t{(int64_t)(2 * npairs + 1) * TE, (int64_t)(2 * npairs) * TE, 0, npairs, flags, 0};
+        GemmTask *dt = nullptr;
+        GemmPair *dp = nullptr;
+        hip_check(hipMalloc(&dt, sizeof(t)), "hipMalloc");
+        hip_check(hipMalloc(&dp, sizeof(GemmPair) * pr.size()), "hipMalloc");
+        hip_check(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(dp, pr.data(), sizeof(GemmPair) * pr.size(), hipMemcpyHostToDevice, s), "copy");
+        if (precision == 64)
+            launch_tile_gemm<double>((double *)ar, dt, dp, 1, s);
+        else
+            launch_tile_gemm<float>((float *)ar, dt, dp, 1, s);
+        hip_check(hipMemcpyAsync(Cm, base + es * TE * (2 * npairs + 1), es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        (void)hipFree(ar);
+        (void)hipFree(dt);
+        (void)hipFree(dp);
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_debug_diag(int32_t precision, void *A, void *W, void *Wt, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!A || !W || !Wt || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
+        hipStream_t s = as_stream(stream);
+        const size_t es = precision == 64 ? 8 : 4;
+        void *ar = nullptr;
+        hip_check(hipMalloc(&ar, es * 3 * TE), "hipMalloc");
+        char *base = (char *)ar;
+        hip_check(hipMemcpyAsync(base, A, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        DiagTask t{0, TE, 2 * TE, 7, 0};
+        DiagTask *dt = nullptr;
+        int32_t *flag = nullptr;
+        hip_check(hipMalloc(&dt, sizeof(t)), "hipMalloc");
+        hip_check(hipMalloc(&flag, 8), "hipMalloc");
+        const int32_t f0[2] = {0, 0x7fffffff};
+        hip_check(hipMemcpyAsync(flag, f0, 8, hipMemcpyHostToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s), "copy");
+        if (precision == 64)
+            launch_diag<double>((double *)ar, (double *)ar, (double *)ar, dt, 1, flag, s);
+        else
+            launch_diag<float>((float *)ar, (float *)ar, (float *)ar, dt, 1, flag, s);
+        hip_check(hipMemcpyAsync(A, base, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(W, base + es * TE, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        hip_check(hipMemcpyAsync(Wt, base + 2 * es * TE, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        int32_t fl[2];
+        hip_check(hipMemcpyAsync(fl, flag, 8, hipMemcpyDeviceToHost, s), "copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        (void)hipFree(ar);
+        (void)hipFree(dt);
+        (void)hipFree(flag);
+        if (fl[0]) fail(HPLMM_E_NOT_SPD, "non-positive pivot");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_debug_setup_stage(hplmm_handle *hh, int32_t stage, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        hh->h.ready = false;
+        numeric_setup(hh->h, as_stream(stream), stage);
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_debug_read_arena(hplmm_handle *hh, int32_t arena, int64_t off, int64_t count,
+                                               void *out) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !out || off < 0 || count < 0) fail(HPLMM_E_ARG, "bad arguments");
+        Handle &h = hh->h;
+        const void *base = arena == 0 ? (const void *)h.ar64 : arena == 1 ? (const void *)h.ar32 : (const void *)h.arbf;
+        const int64_t n = arena == 0 ? h.ar64_n : arena == 1 ? h.ar32_n : h.arbf_n;
+        const size_t es = arena == 0 ? 8 : arena == 1 ? 4 : 2;
+        if (off + count > n) fail(HPLMM_E_ARG, "range outside the arena");
+        hip_check(hipDeviceSynchronize(), "sync");
+        hip_check(hipMemcpy(out, (const char *)base + es * off, es * count, hipMemcpyDeviceToHost), "copy");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_debug_grain_layout(hplmm_handle *hh, int64_t *out, int64_t cap) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !out) fail(HPLMM_E_ARG, "bad arguments");
+        Handle &h = hh->h;
+        const int64_t nm = (int64_t)h.gset.n.size();
+        if (cap < 11 * nm) fail(HPLMM_E_ARG, "buffer too small");
+        for (int64_t m = 0; m < nm; ++m) {
+            int64_t *o = out + 11 * m;
+            o[0] = h.gm_grain[(size_t)m];
+            o[1] = h.gset.n[(size_t)m];
+            o[2] = h.gset.nt[(size_t)m];
+            o[3] = h.gm_ncol[(size_t)m];
+            o[4] = h.gm_ntc[(size_t)m];
+            o[5] = h.gset.a_base + h.gset.rel[(size_t)m];
+            o[6] = h.gset.w_base + h.gset.rel[(size_t)m];
+            o[7] = h.gset.wt_base + h.gset.rel[(size_t)m];
+            o[8] = h.gm_roff[(size_t)m];
+            o[9] = h.gm_ytoff[(size_t)m];
+            o[10] = h.gm_koff[(size_t)m];
+        }
+        return HPLMM_OK;
+    });
+}

@@ -1,0 +1,88 @@
+// Batched dense tile kernels of libhplmm (declarations shared by the host
+// planner and the kernel file).
+//
+// Dense matrices are stored as 64x64 tiles, each tile contiguous and
+// column-major (element (r, c) of a tile at c*64 + r).  Symmetric and lower
+// triangular matrices keep only their lower tiles, packed: tile (I, J), I >= J,
+// at index I*(I+1)/2 + J.  Every tile of every batched matrix lives in one
+// "arena" buffer per element type and is addressed by an element offset.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hplmm {
+
+constexpr int TS = 64;          // tile edge
+constexpr int TE = TS * TS;     // elements per tile
+
+__host__ __device__ inline int64_t tri_tiles(int64_t nt) { return nt * (nt + 1) / 2; }
+__host__ __device__ inline int64_t tri_index(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
+
+enum GemmFlags : int32_t {
+    GF_TRANS_A = 1,     // use op(A) = A^T
+    GF_TRANS_B = 2,     // use op(B) = B^T
+    GF_ACCUM = 4,       // C += alpha * sum (else C = alpha * sum)
+    GF_NEGATE = 8,      // alpha = -1 (else +1)
+    GF_POST = 16,       // C = alpha * P * sum, P = tile at post_off (no accumulate)
+};
+
+// One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p).
+struct GemmTask {
+    int64_t c_off;
+    int64_t post_off;
+    int32_t pair_start;
+    int32_t pair_count;
+    int32_t flags;
+    int32_t pad;
+};
+
+struct GemmPair {
+    int64_t a_off;
+    int64_t b_off;
+};
+
+// Diagonal-tile factorisation: A(a_off) = L L^T in place (upper part zeroed),
+// W(w_off) = L^-1, Wt(wt_off) = L^-T.  `id` is reported on a bad pivot.
+struct DiagTask {
+    int64_t a_off;
+    int64_t w_off;
+    int64_t wt_off;
+    int32_t id;
+    int32_t pad;
+};
+
+// Tiled matrix-vector product: y[y_off .. +64) (+)= sum_p T_p x[x_off_p .. +64)
+struct GemvTask {
+    int64_t y_off;
+    int32_t pair_start;
+    int32_t pair_count;
+};
+
+struct GemvPair {
+    int64_t t_off;
+    int64_t x_off;
+};
+
+struct CopyTask {  // dst tile = src tile^T
+    int64_t src_off;
+    int64_t dst_off;
+};
+
+// Launchers (stream-ordered, asynchronous).  `flag` points to a device int32
+// pair {status bits, first bad id}.
+template <class T>
+void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
+                      hipStream_t s);
+template <class T>
+void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int64_t ntasks,
+                 int32_t *flag, hipStream_t s);
+template <class T>
+void launch_tile_transpose(T *arena_src, T *arena_dst, const CopyTask *tasks, int64_t ntasks,
+                           hipStream_t s);
+template <class T>
+void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
+                 const GemvPair *pairs, int64_t ntasks, hipStream_t s);
+
+}  // namespace hplmm

@@ -1,0 +1,343 @@
+// Batched dense tile kernels for gfx950 (CDNA4).
+//
+// All batched dense linear algebra of the set-up (Cholesky, triangular
+// inversion, basis products, Galerkin products) is expressed as lists of
+// 64x64 tile tasks built on the host; one launch processes one list.  The
+// contraction kernel stages operand tiles through LDS and multiplies them on
+// the matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32), four
+// wavefronts per 64x64 output tile, each owning a 32x32 quadrant.
+#include <hip/hip_runtime.h>
+
+#include "dense.h"
+
+namespace hplmm {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+template <class T>
+struct Mfma;
+// Output layout of one 16x16 block: register r of lane l holds row row(l>>4, r),
+// column l & 15.  The FP64 and FP32 instructions interleave rows differently.
+template <>
+struct Mfma<double> {
+    typedef v4d acc_t;
+    static __device__ __forceinline__ acc_t mac(double a, double b, acc_t c) {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lq, int r) { return lq + 4 * r; }
+};
+template <>
+struct Mfma<float> {
+    typedef v4f acc_t;
+    static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
+};
+
+constexpr int LD = TS + 1;  // padded LDS row length (elements)
+
+// Load a column-major 64x64 tile into LDS as S[k][m] = op(tile)[m][k].
+template <class T>
+__device__ __forceinline__ void load_op_tile(T *S, const T *__restrict__ src, bool trans) {
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int q = 0; q < TE / 256; ++q) {
+        const int e = t + 256 * q;
+        const T v = src[e];
+        // element e of the stored tile is (row e%64, col e/64)
+        const int r = e & (TS - 1), c = e >> 6;
+        if (!trans)
+            S[c * LD + r] = v;   // op = identity: m = r, k = c
+        else
+            S[r * LD + c] = v;   // op = transpose: m = c, k = r
+    }
+}
+
+// Load B so that S[k][n] = op(B)[k][n].
+template <class T>
+__device__ __forceinline__ void load_opB_tile(T *S, const T *__restrict__ src, bool trans) {
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int q = 0; q < TE / 256; ++q) {
+        const int e = t + 256 * q;
+        const T v = src[e];
+        const int r = e & (TS - 1), c = e >> 6;
+        if (!trans)
+            S[r * LD + c] = v;   // B[k=r][n=c]
+        else
+            S[c * LD + r] = v;   // op(B)[k][n] = B[n][k]: n = r, k = c
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void mfma_tile(const T *As, const T *Bs, typename Mfma<T>::acc_t acc[2][2],
+                                          int lane, int wm, int wn) {
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+    for (int kk = 0; kk < TS; kk += 4) {
+        const int k = kk + lk;
+        const T a0 = As[k * LD + wm + lr];
+        const T a1 = As[k * LD + wm + 16 + lr];
+        const T b0 = Bs[k * LD + wn + lr];
+        const T b1 = Bs[k * LD + wn + 16 + lr];
+        acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+        acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+        acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+        acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
+                                                        const GemmTask *__restrict__ tasks,
+                                                        const GemmPair *__restrict__ pairs) {
+    __shared__ T As[TS * LD];
+    __shared__ T Bs[TS * LD];
+    const GemmTask tk = tasks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+    typename Mfma<T>::acc_t acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+    const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
+    for (int p = 0; p < tk.pair_count; ++p) {
+        const GemmPair pr = pairs[tk.pair_start + p];
+        __syncthreads();
+        load_op_tile(As, arena + pr.a_off, ta);
+        load_opB_tile(Bs, arena + pr.b_off, tb);
+        __syncthreads();
+        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+    }
+    const int lr = lane & 15, lq = lane >> 4;
+    if (tk.flags & GF_POST) {
+        // C = P * S with S the accumulated sum: S becomes the B operand.
+        __syncthreads();
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 4; ++r) {
+                    const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
+                    Bs[m * LD + n] = acc[i][j][r];
+                    acc[i][j][r] = 0;
+                }
+        load_op_tile(As, arena + tk.post_off, false);
+        __syncthreads();
+        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+    }
+    // stage the result column-major in LDS, then store coalesced
+    __syncthreads();
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int r = 0; r < 4; ++r) {
+                const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
+                As[n * LD + m] = acc[i][j][r];
+            }
+    __syncthreads();
+    T *C = arena + tk.c_off;
+    const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
+    const bool accum = (tk.flags & GF_ACCUM) && !(tk.flags & GF_POST);
+    const int t = threadIdx.x;
+#pragma unroll 4
+    for (int q = 0; q < TE / 256; ++q) {
+        const int e = t + 256 * q;
+        const int m = e & (TS - 1), n = e >> 6;
+        const T v = alpha * As[n * LD + m];
+        C[e] = accum ? C[e] + v : v;
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restrict__ Wa,
+                                                   T *__restrict__ Wta,
+                                                   const DiagTask *__restrict__ tasks,
+                                                   int32_t *__restrict__ flag) {
+    __shared__ T L[TS * LD];   // L[r*LD + c]
+    __shared__ T W[TS * LD];
+    const DiagTask tk = tasks[blockIdx.x];
+    const int t = threadIdx.x;
+    T *a = A + tk.a_off;
+    for (int e = t; e < TE; e += 256) {
+        const int r = e & (TS - 1), c = e >> 6;
+        L[r * LD + c] = (r >= c) ? a[e] : T(0);
+        W[r * LD + c] = T(0);
+    }
+    __syncthreads();
+    __shared__ int bad;
+    if (t == 0) bad = 0;
+    for (int j = 0; j < TS; ++j) {
+        if (t == 0) {
+            T d = L[j * LD + j];
+            if (!(d > T(0)) || !(d < T(INFINITY))) {
+                bad = 1;
+                d = T(1);
+            }
+            L[j * LD + j] = sqrt(d);
+        }
+        __syncthreads();
+        const T piv = L[j * LD + j];
+        if (t > j && t < TS) L[t * LD + j] /= piv;
+        __syncthreads();
+        const int c = j + 1 + (t & 63);
+        if (c < TS) {
+            const T lcj = L[c * LD + j];
+            for (int i = c + (t >> 6); i < TS; i += 4) L[i * LD + c] -= L[i * LD + j] * lcj;
+        }
+        __syncthreads();
+    }
+    // W = L^-1, one column per thread
+    if (t < TS) {
+        const int j = t;
+        W[j * LD + j] = T(1) / L[j * LD + j];
+        for (int i = j + 1; i < TS; ++i) {
+            T s = 0;
+            for (int k = j; k < i; ++k) s += L[i * LD + k] * W[k * LD + j];
+            W[i * LD + j] = -s / L[i * LD + i];
+        }
+    }
+    __syncthreads();
+    T *w = Wa + tk.w_off;
+    T *wt = Wta + tk.wt_off;
+    for (int e = t; e < TE; e += 256) {
+        const int r = e & (TS - 1), c = e >> 6;
+        a[e] = L[r * LD + c];
+        w[e] = W[r * LD + c];
+        wt[e] = W[c * LD + r];
+    }
+    if (t == 0 && bad) {
+        atomicOr(&flag[0], 1);
+        atomicMin(&flag[1], tk.id);
+    }
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) tile_transpose_kernel(const T *__restrict__ src, T *__restrict__ dst,
+                                                             const CopyTask *__restrict__ tasks) {
+    __shared__ T S[TS * LD];
+    const CopyTask tk = tasks[blockIdx.x];
+    const int t = threadIdx.x;
+    const T *s = src + tk.src_off;
+    for (int e = t; e < TE; e += 256) {
+        const int r = e & (TS - 1), c = e >> 6;
+        S[r * LD + c] = s[e];
+    }
+    __syncthreads();
+    T *d = dst + tk.dst_off;
+    for (int e = t; e < TE; e += 256) {
+        const int r = e & (TS - 1), c = e >> 6;   // dst(r, c) = src(c, r)
+        d[e] = S[c * LD + r];
+    }
+}
+
+// ---- tiled GEMV --------------------------------------------------------
+template <class T>
+struct Vec16;  // 16-byte load of consecutive tile elements, widened to double
+template <>
+struct Vec16<double> {
+    static constexpr int R = 2;
+    static __device__ __forceinline__ void load(const double *p, double *o) {
+        const double2 v = *reinterpret_cast<const double2 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+    }
+};
+template <>
+struct Vec16<float> {
+    static constexpr int R = 4;
+    static __device__ __forceinline__ void load(const float *p, double *o) {
+        const float4 v = *reinterpret_cast<const float4 *>(p);
+        o[0] = v.x;
+        o[1] = v.y;
+        o[2] = v.z;
+        o[3] = v.w;
+    }
+};
+template <>
+struct Vec16<uint16_t> {   // bfloat16 storage
+    static constexpr int R = 8;
+    static __device__ __forceinline__ void load(const uint16_t *p, double *o) {
+        const uint4 v = *reinterpret_cast<const uint4 *>(p);
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = (double)__uint_as_float(w[i] << 16);
+            o[2 * i + 1] = (double)__uint_as_float(w[i] & 0xffff0000u);
+        }
+    }
+};
+
+template <class T>
+__global__ void __launch_bounds__(256) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
+                                                   double *__restrict__ y, const GemvTask *__restrict__ tasks,
+                                                   const GemvPair *__restrict__ pairs) {
+    constexpr int R = Vec16<T>::R;          // rows per lane
+    constexpr int LPC = TS / R;             // lanes per column
+    __shared__ double red[4 * R * TS];
+    const GemvTask tk = tasks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int phase = lane / LPC, row0 = (lane % LPC) * R;
+    double acc[R];
+#pragma unroll
+    for (int i = 0; i < R; ++i) acc[i] = 0.0;
+    for (int p = wave; p < tk.pair_count; p += 4) {
+        const GemvPair pr = pairs[tk.pair_start + p];
+        const T *tile = arena + pr.t_off;
+        const double *xs = x + pr.x_off;
+#pragma unroll 8
+        for (int c = phase; c < TS; c += R) {
+            double v[R];
+            Vec16<T>::load(tile + c * TS + row0, v);
+            const double xc = xs[c];
+#pragma unroll
+            for (int i = 0; i < R; ++i) acc[i] += v[i] * xc;
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < R; ++i) red[(wave * R + phase) * TS + row0 + i] = acc[i];
+    __syncthreads();
+    if (threadIdx.x < TS) {
+        double s = 0.0;
+        for (int q = 0; q < 4 * R; ++q) s += red[q * TS + threadIdx.x];
+        y[tk.y_off + threadIdx.x] = s;
+    }
+}
+
+// ---- launchers -----------------------------------------------------------
+static inline unsigned grid_of(int64_t n) { return (unsigned)n; }
+
+template <class T>
+void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(tile_gemm_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, tasks, pairs);
+}
+template <class T>
+void launch_diag(T *a, T *w, T *wt, const DiagTask *tasks, int64_t ntasks, int32_t *flag, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(diag_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, a, w, wt, tasks, flag);
+}
+template <class T>
+void launch_tile_transpose(T *src, T *dst, const CopyTask *tasks, int64_t ntasks, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(tile_transpose_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, src, dst, tasks);
+}
+template <class T>
+void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const GemvPair *pairs,
+                 int64_t ntasks, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(gemv_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs);
+}
+
+template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);
+template void launch_tile_gemm<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);
+template void launch_diag<double>(double *, double *, double *, const DiagTask *, int64_t, int32_t *, hipStream_t);
+template void launch_diag<float>(float *, float *, float *, const DiagTask *, int64_t, int32_t *, hipStream_t);
+template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);
+template void launch_tile_transpose<float>(float *, float *, const CopyTask *, int64_t, hipStream_t);
+template void launch_gemv<double>(const double *, const double *, double *, const GemvTask *, const GemvPair *,
+                                  int64_t, hipStream_t);
+template void launch_gemv<float>(const float *, const double *, double *, const GemvTask *, const GemvPair *,
+                                 int64_t, hipStream_t);
+template void launch_gemv<uint16_t>(const uint16_t *, const double *, double *, const GemvTask *,
+                                    const GemvPair *, int64_t, hipStream_t);
+
+}  // namespace hplmm

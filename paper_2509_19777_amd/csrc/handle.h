@@ -1,0 +1,174 @@
+// Internal state of an hplmm_handle: sizes, device buffers, task lists.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+#include "dense.h"
+#include "sparse.h"
+
+namespace hplmm {
+
+enum LaunchKind : int32_t { LK_DIAG = 0, LK_GEMM = 1, LK_TRANSPOSE = 2 };
+
+struct Launch {
+    int32_t kind;
+    int64_t start;
+    int64_t count;
+};
+
+// Host-side task lists of one element type (uploaded once).
+struct TaskLists {
+    std::vector<GemmTask> gemm;
+    std::vector<GemmPair> pairs;
+    std::vector<DiagTask> diag;
+    std::vector<CopyTask> copy;
+    GemmTask *d_gemm = nullptr;
+    GemmPair *d_pairs = nullptr;
+    DiagTask *d_diag = nullptr;
+    CopyTask *d_copy = nullptr;
+};
+
+struct Range {
+    int64_t start = 0, count = 0;
+};
+
+// A batch of symmetric positive definite matrices stored as packed lower
+// tiles; A (factored in place to L), W = L^-1 and Wt = L^-T share the same
+// relative layout in three regions of one arena.
+struct DenseSet {
+    std::vector<int64_t> n, nt, rel;   // size, tiles per side, relative offset
+    int64_t region = 0;                // elements per region
+    int64_t a_base = 0, w_base = 0, wt_base = 0;   // absolute arena offsets
+    std::vector<Launch> factor_prog;   // potrf + trtri + transposes
+    Range gemv_W, gemv_Wt;             // apply-time task ranges
+    int64_t vec_len = 0;               // local vector length (sum nt*64)
+    std::vector<int64_t> voff;         // local vector offset per matrix
+    int64_t low_w_base = 0, low_wt_base = 0;   // offsets in the reduced-precision arena
+};
+
+struct Handle {
+    int device = 0;
+    std::vector<void *> allocs;
+    int64_t dev_bytes = 0;
+
+    // sizes
+    int64_t n_nodes = 0, N = 0, nnzb = 0;
+    int32_t n_grains = 0, n_ifaces = 0, n_contacts = 0;
+    int64_t n_mortar = 0, n_corr = 0, n_coarse = 0;
+    int32_t smoother_precision = 64;
+    bool ready = false;
+
+    // fine matrix
+    FineCsr csr{};
+    SellMatrix sell{};
+    int64_t sell_padded_blocks = 0;
+    double *d_b = nullptr;
+
+    // interface and coarse maps
+    CoarseMaps cm{};
+    std::vector<int32_t> h_mortar_idx;     // per interface nu_c local ids
+    std::vector<int64_t> h_iface_hoff;
+    std::vector<double> h_H;
+    std::vector<int32_t> h_corr_grains;
+
+    // grains
+    DenseSet gset;
+    std::vector<int32_t> gm_grain, gm_ncol, gm_ntc, gm_k, gm_corr;
+    std::vector<int64_t> gm_roff, gm_ytoff, gm_xtoff, gm_koff, gm_coff;
+    int64_t gcol_len = 0;
+    GrainGather gg{};
+    AbarWork *d_abar = nullptr;
+    int64_t n_abar = 0;
+    int64_t *d_g_slot_dof = nullptr;   // grain vector slot -> dof
+    int64_t *d_g_dof_slot = nullptr;   // dof -> grain vector slot
+    int64_t *d_gcol_upos = nullptr;    // grain column slot -> coarse vector position
+    std::vector<Launch> basis_prog;    // Y = W R, X = Wt Y, K = Y^T Y, XT
+    Range gemv_XT, gemv_X;
+    std::vector<int64_t> pad_ones_g;   // identity on padded diagonals
+    int64_t *d_pad_g = nullptr;
+
+    // contacts
+    DenseSet cset;
+    ContactGather cg{};
+    int64_t n_citems = 0;
+    int64_t *d_c_slot_dof = nullptr;
+    int64_t *d_c_dof_ptr = nullptr;
+    int64_t *d_c_dof_slot = nullptr;
+    std::vector<int64_t> pad_ones_c;
+    int64_t *d_pad_c = nullptr;
+    int64_t c_stage_base = 0;          // fp64 staging region (reduced-precision mode)
+    int64_t *d_c_aoff_stage = nullptr;
+
+    // coarse
+    DenseSet sset;
+    int64_t cvec_len = 0;
+    CoarsePair *d_pairs = nullptr;
+    int64_t n_pairs = 0;
+    CoarseEdge *d_edges = nullptr;
+    CoarseKRef *d_krefs = nullptr;
+    int64_t *d_corr_koff = nullptr;
+    std::vector<int64_t> pad_ones_s;
+    int64_t *d_pad_s = nullptr;
+
+    // arenas
+    double *ar64 = nullptr;
+    int64_t ar64_n = 0;
+    float *ar32 = nullptr;
+    int64_t ar32_n = 0;
+    uint16_t *arbf = nullptr;
+    int64_t arbf_n = 0;
+    TaskLists tl64, tl32;
+    GemvTask *d_vtasks = nullptr;
+    GemvPair *d_vpairs = nullptr;
+    std::vector<GemvTask> vtasks;
+    std::vector<GemvPair> vpairs;
+    int64_t grain_region_zero_n = 0;   // elements zeroed before each set-up
+
+    // vectors
+    double *gx = nullptr, *gt = nullptr, *gy = nullptr;   // grain local
+    double *gc_t = nullptr, *gc_u = nullptr;               // grain columns
+    double *cx = nullptr, *ct = nullptr, *cy = nullptr;   // contact local
+    double *sf = nullptr, *st = nullptr, *su = nullptr;   // coarse
+    double *z1 = nullptr, *z2 = nullptr, *r1 = nullptr, *r2 = nullptr, *tmpN = nullptr;
+    double *corr_d = nullptr;
+    int32_t *d_flag = nullptr;
+
+    // Krylov workspace
+    int32_t kr_restart = 0;
+    double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *hbuf = nullptr, *h2 = nullptr;
+    double *ydev = nullptr;
+    int32_t kr_blocks = 0;
+
+    // timings
+    double t_setup_ms[4] = {0, 0, 0, 0};
+
+    template <class T>
+    T *dalloc(int64_t n) {
+        if (n <= 0) n = 1;
+        void *p = nullptr;
+        if (hipMalloc(&p, sizeof(T) * (size_t)n) != hipSuccess) fail(HPLMM_E_OOM, "hipMalloc failed");
+        allocs.push_back(p);
+        dev_bytes += (int64_t)(sizeof(T) * (size_t)n);
+        return (T *)p;
+    }
+    template <class T>
+    T *upload(const std::vector<T> &v, hipStream_t s) {
+        T *p = dalloc<T>((int64_t)v.size());
+        if (!v.empty() && hipMemcpyAsync(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice, s) != hipSuccess)
+            fail(HPLMM_E_HIP, "hipMemcpyAsync failed");
+        return p;
+    }
+    ~Handle() {
+        for (void *p : allocs) (void)hipFree(p);
+    }
+};
+
+// plan.cpp
+void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
+                const hplmm_options &opt, hipStream_t s, bool dry_run);
+std::vector<int32_t> place_mortars(const int32_t *xyz, int32_t N, int32_t n);
+
+}  // namespace hplmm

@@ -1,0 +1,831 @@
+// Symbolic phase of libhplmm: validation, mortars (Sec. 3.3), the grouping
+// W and reduction Q (Eqs. 20-21), the column layout of P (Eq. 23), contact
+// grids (Eq. 26), device data layout and all launch task lists.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <unordered_map>
+
+#include "handle.h"
+
+namespace hplmm {
+
+namespace {
+
+int64_t ceil_tiles(int64_t n) { return (n + TS - 1) / TS; }
+
+// Gaussian mortar weights (Eq. 8) of one interface: H (N x nu) row-major.
+std::vector<double> gaussian_weights(const std::vector<int32_t> &xyz, int32_t N, const std::vector<int32_t> &idx,
+                                     double beta) {
+    const int32_t nu = (int32_t)idx.size();
+    std::vector<double> H((size_t)N * nu, 0.0);
+    if (nu == 1) {
+        std::fill(H.begin(), H.end(), 1.0);
+        return H;
+    }
+    if (nu == N) {
+        for (int32_t v = 0; v < N; ++v) H[(size_t)v * nu + v] = 1.0;
+        return H;
+    }
+    auto d2 = [&](int32_t a, int32_t b) {
+        const double dx = (double)(xyz[3 * a] - xyz[3 * b]), dy = (double)(xyz[3 * a + 1] - xyz[3 * b + 1]),
+                     dz = (double)(xyz[3 * a + 2] - xyz[3 * b + 2]);
+        return dx * dx + dy * dy + dz * dz;
+    };
+    std::vector<double> dmin((size_t)nu, INFINITY);
+    for (int32_t i = 0; i < nu; ++i)
+        for (int32_t j = 0; j < nu; ++j)
+            if (i != j) dmin[(size_t)i] = std::min(dmin[(size_t)i], d2(idx[(size_t)i], idx[(size_t)j]));
+    for (int32_t v = 0; v < N; ++v) {
+        double s = 0.0;
+        for (int32_t i = 0; i < nu; ++i) {
+            const double a = std::exp(-d2(v, idx[(size_t)i]) / (beta * dmin[(size_t)i]));
+            H[(size_t)v * nu + i] = a;
+            s += a;
+        }
+        for (int32_t i = 0; i < nu; ++i) H[(size_t)v * nu + i] /= s;
+    }
+    return H;
+}
+
+// Append the factorisation program of a dense set: blocked right-looking
+// Cholesky (diagonal tile, panel L_ik = A_ik L_kk^-T, trailing update),
+// then the triangular inverse W = L^-1 by diagonals, then Wt = W^T tiles.
+void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id) {
+    const int64_t nm = (int64_t)ds.n.size();
+    int64_t maxnt = 0;
+    for (auto t : ds.nt) maxnt = std::max(maxnt, t);
+    auto A = [&](int64_t m, int64_t I, int64_t J) { return ds.a_base + ds.rel[m] + tri_index(I, J) * TE; };
+    auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
+    auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
+    for (int64_t k = 0; k < maxnt; ++k) {
+        Launch d{LK_DIAG, (int64_t)tl.diag.size(), 0};
+        for (int64_t m = 0; m < nm; ++m)
+            if (ds.nt[m] > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), (int32_t)(set_id * (1 << 26) + m), 0});
+        d.count = (int64_t)tl.diag.size() - d.start;
+        ds.factor_prog.push_back(d);
+        Launch p{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nm; ++m)
+            for (int64_t i = k + 1; i < ds.nt[m]; ++i) {
+                tl.gemm.push_back({A(m, i, k), -1, (int32_t)tl.pairs.size(), 1, 0, 0});
+                tl.pairs.push_back({A(m, i, k), Wt(m, k, k)});
+            }
+        p.count = (int64_t)tl.gemm.size() - p.start;
+        if (p.count) ds.factor_prog.push_back(p);
+        Launch u{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nm; ++m)
+            for (int64_t i = k + 1; i < ds.nt[m]; ++i)
+                for (int64_t j = k + 1; j <= i; ++j) {
+                    tl.gemm.push_back({A(m, i, j), -1, (int32_t)tl.pairs.size(), 1,
+                                       GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
+                    tl.pairs.push_back({A(m, i, k), A(m, j, k)});
+                }
+        u.count = (int64_t)tl.gemm.size() - u.start;
+        if (u.count) ds.factor_prog.push_back(u);
+    }
+    // W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj, computed for i - j = 1, 2, ...
+    for (int64_t d = 1; d < maxnt; ++d) {
+        Launch t{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nm; ++m)
+            for (int64_t j = 0; j + d < ds.nt[m]; ++j) {
+                const int64_t i = j + d;
+                tl.gemm.push_back({W(m, i, j), W(m, i, i), (int32_t)tl.pairs.size(), (int32_t)d, GF_POST | GF_NEGATE, 0});
+                for (int64_t k = j; k < i; ++k) tl.pairs.push_back({A(m, i, k), W(m, k, j)});
+            }
+        t.count = (int64_t)tl.gemm.size() - t.start;
+        if (t.count) ds.factor_prog.push_back(t);
+    }
+    Launch c{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
+    for (int64_t m = 0; m < nm; ++m)
+        for (int64_t i = 0; i < ds.nt[m]; ++i)
+            for (int64_t j = 0; j < i; ++j) tl.copy.push_back({W(m, i, j), Wt(m, i, j)});
+    c.count = (int64_t)tl.copy.size() - c.start;
+    if (c.count) ds.factor_prog.push_back(c);
+}
+
+// Apply-time GEMV task lists y = W x and y = W^T x of a dense set.
+void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<GemvPair> &vp, int64_t w_abs,
+                         int64_t wt_abs) {
+    const int64_t nm = (int64_t)ds.n.size();
+    ds.gemv_W.start = (int64_t)vt.size();
+    // schedule the longest rows first
+    std::vector<std::pair<int64_t, int64_t>> order;
+    for (int64_t m = 0; m < nm; ++m)
+        for (int64_t I = 0; I < ds.nt[m]; ++I) order.push_back({m, I});
+    std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) { return a.second > b.second; });
+    for (auto [m, I] : order) {
+        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(I + 1)});
+        for (int64_t J = 0; J <= I; ++J) vp.push_back({w_abs + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS});
+    }
+    ds.gemv_W.count = (int64_t)vt.size() - ds.gemv_W.start;
+    std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) {
+        return (ds.nt[a.first] - a.second) > (ds.nt[b.first] - b.second);
+    });
+    ds.gemv_Wt.start = (int64_t)vt.size();
+    for (auto [m, I] : order) {
+        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(ds.nt[m] - I)});
+        for (int64_t J = I; J < ds.nt[m]; ++J)
+            vp.push_back({wt_abs + ds.rel[m] + tri_index(J, I) * TE, ds.voff[m] + J * TS});
+    }
+    ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
+}
+
+void layout_set(DenseSet &ds) {
+    ds.rel.resize(ds.n.size());
+    ds.nt.resize(ds.n.size());
+    ds.voff.resize(ds.n.size());
+    int64_t off = 0, vo = 0;
+    for (size_t m = 0; m < ds.n.size(); ++m) {
+        ds.nt[m] = ceil_tiles(ds.n[m]);
+        ds.rel[m] = off;
+        off += tri_tiles(ds.nt[m]) * TE;
+        ds.voff[m] = vo;
+        vo += ds.nt[m] * TS;
+    }
+    ds.region = off;
+    ds.vec_len = vo;
+}
+
+void pad_ones(const DenseSet &ds, std::vector<int64_t> &out, int64_t a_base) {
+    for (size_t m = 0; m < ds.n.size(); ++m)
+        for (int64_t r = ds.n[m]; r < ds.nt[m] * TS; ++r)
+            out.push_back(a_base + ds.rel[m] + tri_index(r / TS, r / TS) * TE + (r % TS) * TS + (r % TS));
+}
+
+}  // namespace
+
+void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
+                const hplmm_options &opt, hipStream_t s, bool dry_run) {
+    const int64_t n = sys.n_nodes;
+    if (n <= 0 || !sys.row_ptr || !sys.col_idx || !sys.val || !sys.node_xyz)
+        fail(HPLMM_E_ARG, "system arrays missing");
+    if (!part.node_grain || part.n_grains < 0 || part.n_ifaces < 0 || (part.n_ifaces > 0 && (!part.iface_ptr || !part.iface_nodes)))
+        fail(HPLMM_E_ARG, "partition arrays missing");
+    if (part.n_nodes != n) fail(HPLMM_E_ARG, "partition and system disagree on n_nodes");
+    if (part.n_contacts < 0 || (part.n_contacts > 0 && (!part.contact_ptr || !part.contact_nodes)))
+        fail(HPLMM_E_ARG, "contact arrays missing");
+    if (mort.n <= 0 || !(mort.beta > 0)) fail(HPLMM_E_ARG, "mortar n must be > 0 and beta > 0");
+    if (opt.smoother_precision != 64 && opt.smoother_precision != 32 && opt.smoother_precision != 16)
+        fail(HPLMM_E_ARG, "smoother_precision must be 64, 32 or 16");
+    h.smoother_precision = opt.smoother_precision;
+    h.n_nodes = n;
+    h.N = 3 * n;
+    h.nnzb = sys.row_ptr[n];
+    if (sys.row_ptr[0] != 0) fail(HPLMM_E_ARG, "row_ptr[0] must be 0");
+    for (int64_t v = 0; v < n; ++v) {
+        if (sys.row_ptr[v + 1] < sys.row_ptr[v]) fail(HPLMM_E_ARG, "row_ptr not monotone");
+        for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p) {
+            const int32_t w = sys.col_idx[p];
+            if (w < 0 || w >= n) fail(HPLMM_E_ARG, "column index out of range");
+            if (p > sys.row_ptr[v] && sys.col_idx[p - 1] >= w) fail(HPLMM_E_ARG, "columns not strictly ascending");
+            // symmetric pattern
+            const int32_t *b0 = sys.col_idx + sys.row_ptr[w], *b1 = sys.col_idx + sys.row_ptr[w + 1];
+            if (!std::binary_search(b0, b1, (int32_t)v)) fail(HPLMM_E_ARG, "sparsity pattern not symmetric");
+        }
+    }
+    h.n_grains = part.n_grains;
+    h.n_ifaces = part.n_ifaces;
+    h.n_contacts = part.n_contacts;
+    // ---- classification (W, Eq. 20) ---------------------------------------
+    std::vector<int32_t> node_iface((size_t)n, -1), node_irow((size_t)n, -1);
+    for (int32_t c = 0; c < part.n_ifaces; ++c) {
+        if (part.iface_ptr[c + 1] <= part.iface_ptr[c]) fail(HPLMM_E_PARTITION, "empty interface");
+        for (int64_t p = part.iface_ptr[c]; p < part.iface_ptr[c + 1]; ++p) {
+            const int32_t v = part.iface_nodes[p];
+            if (v < 0 || v >= n) fail(HPLMM_E_PARTITION, "interface node out of range");
+            if (node_iface[(size_t)v] >= 0) fail(HPLMM_E_PARTITION, "node in two interfaces");
+            node_iface[(size_t)v] = c;
+            node_irow[(size_t)v] = (int32_t)(p - part.iface_ptr[c]);
+        }
+    }
+    for (int64_t v = 0; v < n; ++v) {
+        const int32_t g = part.node_grain[v];
+        if (g >= part.n_grains || g < -1) fail(HPLMM_E_PARTITION, "grain id out of range");
+        if ((g >= 0) == (node_iface[(size_t)v] >= 0))
+            fail(HPLMM_E_PARTITION, "every node must be interior to one grain or on one interface");
+    }
+    for (int64_t v = 0; v < n; ++v)
+        for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p) {
+            const int32_t gv = part.node_grain[v], gw = part.node_grain[sys.col_idx[p]];
+            if (gv >= 0 && gw >= 0 && gv != gw) fail(HPLMM_E_PARTITION, "A couples the interiors of two grains");
+        }
+    // ---- mortars (Eqs. 7-8) and Q ------------------------------------------
+    std::vector<int32_t> iface_nu((size_t)part.n_ifaces);
+    std::vector<int64_t> iface_moff((size_t)part.n_ifaces), iface_hoff((size_t)part.n_ifaces);
+    h.h_H.clear();
+    h.h_mortar_idx.clear();
+    int64_t moff = 0;
+    for (int32_t c = 0; c < part.n_ifaces; ++c) {
+        const int64_t p0 = part.iface_ptr[c];
+        const int32_t Nc = (int32_t)(part.iface_ptr[c + 1] - p0);
+        std::vector<int32_t> xyz((size_t)Nc * 3);
+        for (int32_t v = 0; v < Nc; ++v)
+            for (int d = 0; d < 3; ++d) xyz[(size_t)3 * v + d] = sys.node_xyz[3 * (int64_t)part.iface_nodes[p0 + v] + d];
+        auto idx = place_mortars(xyz.data(), Nc, mort.n);
+        auto H = gaussian_weights(xyz, Nc, idx, mort.beta);
+        iface_nu[(size_t)c] = (int32_t)idx.size();
+        iface_moff[(size_t)c] = moff;
+        iface_hoff[(size_t)c] = (int64_t)h.h_H.size();
+        moff += 3 * (int64_t)idx.size();
+        h.h_H.insert(h.h_H.end(), H.begin(), H.end());
+        h.h_mortar_idx.insert(h.h_mortar_idx.end(), idx.begin(), idx.end());
+    }
+    h.h_iface_hoff = iface_hoff;
+    h.n_mortar = moff;
+    // ---- grain matrices and the columns of P (Eq. 23) -----------------------
+    std::vector<std::vector<int32_t>> gnodes((size_t)part.n_grains);
+    for (int64_t v = 0; v < n; ++v)
+        if (part.node_grain[v] >= 0) gnodes[(size_t)part.node_grain[v]].push_back((int32_t)v);
+    std::vector<int32_t> grain_mat((size_t)part.n_grains, -1);
+    std::vector<int32_t> node_gmat((size_t)n, -1), node_local((size_t)n, -1);
+    for (int32_t g = 0; g < part.n_grains; ++g) {
+        if (gnodes[(size_t)g].empty()) continue;
+        grain_mat[(size_t)g] = (int32_t)h.gm_grain.size();
+        h.gm_grain.push_back(g);
+    }
+    const int64_t nG = (int64_t)h.gm_grain.size();
+    for (int64_t m = 0; m < nG; ++m) {
+        auto &nodes = gnodes[(size_t)h.gm_grain[(size_t)m]];
+        for (size_t l = 0; l < nodes.size(); ++l) {
+            node_gmat[(size_t)nodes[l]] = (int32_t)m;
+            node_local[(size_t)nodes[l]] = (int32_t)l;
+        }
+        h.gset.n.push_back(3 * (int64_t)nodes.size());
+    }
+    for (int32_t c = 0; c < part.n_ifaces; ++c)
+        for (int64_t p = part.iface_ptr[c]; p < part.iface_ptr[c + 1]; ++p)
+            node_local[(size_t)part.iface_nodes[p]] = (int32_t)(p - part.iface_ptr[c]);
+    // interfaces coupled to each grain's interior (nonzero columns of Abar_gi)
+    std::vector<std::vector<int32_t>> gadj((size_t)nG);
+    std::vector<AbarWork> abar;
+    {
+        std::vector<int32_t> seen;
+        for (int64_t v = 0; v < n; ++v) {
+            const int32_t m = node_gmat[(size_t)v];
+            if (m < 0) continue;
+            seen.clear();
+            for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p) {
+                const int32_t c = node_iface[(size_t)sys.col_idx[p]];
+                if (c >= 0 && std::find(seen.begin(), seen.end(), c) == seen.end()) seen.push_back(c);
+            }
+            std::sort(seen.begin(), seen.end());
+            for (int32_t c : seen) {
+                gadj[(size_t)m].push_back(c);
+                abar.push_back({(int32_t)v, c, (int32_t)m, node_local[(size_t)v], 0, 0});
+            }
+        }
+    }
+    std::vector<std::unordered_map<int32_t, int32_t>> lcol((size_t)nG);
+    h.gm_k.resize(nG);
+    h.gm_corr.assign(nG, -1);
+    h.gm_ncol.resize(nG);
+    h.gm_ntc.resize(nG);
+    h.h_corr_grains.clear();
+    for (int64_t m = 0; m < nG; ++m) {
+        auto &a = gadj[(size_t)m];
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+        int32_t k = 0;
+        for (int32_t c : a) {
+            lcol[(size_t)m][c] = k;
+            k += 3 * iface_nu[(size_t)c];
+        }
+        h.gm_k[(size_t)m] = k;
+        bool loaded = false;
+        if (sys.rhs)
+            for (int32_t v : gnodes[(size_t)h.gm_grain[(size_t)m]])
+                for (int d = 0; d < 3; ++d) loaded |= sys.rhs[3 * (int64_t)v + d] != 0.0;
+        if (loaded) {
+            h.gm_corr[(size_t)m] = (int32_t)h.h_corr_grains.size();
+            h.h_corr_grains.push_back(h.gm_grain[(size_t)m]);
+        }
+        h.gm_ncol[(size_t)m] = k + (loaded ? 1 : 0);
+        h.gm_ntc[(size_t)m] = (int32_t)ceil_tiles(h.gm_ncol[(size_t)m]);
+    }
+    for (auto &w : abar) w.lcol0 = lcol[(size_t)w.m][w.c];
+    h.n_corr = (int64_t)h.h_corr_grains.size();
+    h.n_coarse = h.n_mortar + h.n_corr;
+    // ---- contact grids (Eq. 26) -----------------------------------------------
+    std::vector<int64_t> cn_cnt((size_t)n + 1, 0);
+    for (int32_t c = 0; c < part.n_contacts; ++c) {
+        if (part.contact_ptr[c + 1] <= part.contact_ptr[c]) fail(HPLMM_E_PARTITION, "empty contact grid");
+        for (int64_t p = part.contact_ptr[c]; p < part.contact_ptr[c + 1]; ++p) {
+            const int32_t v = part.contact_nodes[p];
+            if (v < 0 || v >= n) fail(HPLMM_E_PARTITION, "contact node out of range");
+            if (p > part.contact_ptr[c] && part.contact_nodes[p - 1] >= v)
+                fail(HPLMM_E_PARTITION, "contact nodes must be strictly ascending");
+            cn_cnt[(size_t)v + 1]++;
+        }
+        h.cset.n.push_back(3 * (part.contact_ptr[c + 1] - part.contact_ptr[c]));
+    }
+    // ---- layout ------------------------------------------------------------------
+    layout_set(h.gset);
+    layout_set(h.cset);
+    if (h.n_mortar > 0) h.sset.n.push_back(h.n_mortar);
+    layout_set(h.sset);
+    int64_t off64 = 0, off32 = 0, offbf = 0;
+    auto take64 = [&](int64_t k) { const int64_t o = off64; off64 += k; return o; };
+    h.gset.a_base = take64(h.gset.region);
+    h.gset.w_base = take64(h.gset.region);
+    h.gset.wt_base = take64(h.gset.region);
+    h.gm_roff.resize(nG);
+    h.gm_ytoff.resize(nG);
+    h.gm_xtoff.resize(nG);
+    h.gm_koff.resize(nG);
+    h.gm_coff.resize(nG);
+    int64_t r_region = 0, k_region = 0;
+    for (int64_t m = 0; m < nG; ++m) {
+        r_region += h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE;
+        k_region += tri_tiles(h.gm_ntc[(size_t)m]) * TE;
+    }
+    const int64_t r_base = take64(r_region), y_base = take64(r_region), xt_base = take64(r_region),
+                  k_base = take64(k_region);
+    {
+        int64_t ro = 0, ko = 0, co = 0;
+        for (int64_t m = 0; m < nG; ++m) {
+            h.gm_roff[(size_t)m] = r_base + ro;
+            h.gm_ytoff[(size_t)m] = y_base + ro;
+            h.gm_xtoff[(size_t)m] = xt_base + ro;
+            ro += h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE;
+            h.gm_koff[(size_t)m] = k_base + ko;
+            ko += tri_tiles(h.gm_ntc[(size_t)m]) * TE;
+            h.gm_coff[(size_t)m] = co;
+            co += h.gm_ntc[(size_t)m] * TS;
+        }
+        h.gcol_len = co;
+    }
+    const bool lowp = h.smoother_precision != 64;
+    if (!lowp) {
+        h.cset.a_base = take64(h.cset.region);
+        h.cset.w_base = take64(h.cset.region);
+        h.cset.wt_base = take64(h.cset.region);
+    } else {
+        h.c_stage_base = take64(h.cset.region);
+        h.cset.a_base = off32;
+        off32 += h.cset.region;
+        h.cset.w_base = off32;
+        off32 += h.cset.region;
+        h.cset.wt_base = off32;
+        off32 += h.cset.region;
+    }
+    h.sset.a_base = take64(h.sset.region);
+    h.sset.w_base = take64(h.sset.region);
+    h.sset.wt_base = take64(h.sset.region);
+    // reduced-precision smoother copies
+    if (h.smoother_precision == 32) {
+        h.gset.low_w_base = off32;
+        off32 += h.gset.region;
+        h.gset.low_wt_base = off32;
+        off32 += h.gset.region;
+        h.cset.low_w_base = h.cset.w_base;
+        h.cset.low_wt_base = h.cset.wt_base;
+    } else if (h.smoother_precision == 16) {
+        h.gset.low_w_base = offbf;
+        offbf += h.gset.region;
+        h.gset.low_wt_base = offbf;
+        offbf += h.gset.region;
+        h.cset.low_w_base = offbf;
+        offbf += h.cset.region;
+        h.cset.low_wt_base = offbf;
+        offbf += h.cset.region;
+    }
+    h.ar64_n = off64;
+    h.ar32_n = off32;
+    h.arbf_n = offbf;
+    h.grain_region_zero_n = h.gset.region;
+    // ---- task lists ---------------------------------------------------------------
+    build_factor_program(h.gset, h.tl64, 0);
+    if (!lowp)
+        build_factor_program(h.cset, h.tl64, 1);
+    else
+        build_factor_program(h.cset, h.tl32, 1);
+    build_factor_program(h.sset, h.tl64, 2);
+    // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
+    {
+        auto &tl = h.tl64;
+        auto Wg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.w_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+        auto Wtg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.wt_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+        auto Rt = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
+        Launch L1{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(), (int32_t)(I + 1), 0, 0});
+                    for (int64_t J = 0; J <= I; ++J) tl.pairs.push_back({Wg(m, I, J), Rt(h.gm_roff[(size_t)m], m, J, C)});
+                }
+        L1.count = (int64_t)tl.gemm.size() - L1.start;
+        if (L1.count) h.basis_prog.push_back(L1);
+        Launch L2{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(h.gm_roff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(),
+                                       (int32_t)(h.gset.nt[m] - I), 0, 0});
+                    for (int64_t J = I; J < h.gset.nt[m]; ++J)
+                        tl.pairs.push_back({Wtg(m, J, I), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
+                }
+        L2.count = (int64_t)tl.gemm.size() - L2.start;
+        if (L2.count) h.basis_prog.push_back(L2);
+        Launch L3{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C1 = 0; C1 < h.gm_ntc[(size_t)m]; ++C1)
+                for (int64_t C2 = 0; C2 <= C1; ++C2) {
+                    tl.gemm.push_back({h.gm_koff[(size_t)m] + tri_index(C1, C2) * TE, -1, (int32_t)tl.pairs.size(),
+                                       (int32_t)h.gset.nt[m], GF_TRANS_A, 0});
+                    for (int64_t I = 0; I < h.gset.nt[m]; ++I)
+                        tl.pairs.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C1), Rt(h.gm_ytoff[(size_t)m], m, I, C2)});
+                }
+        L3.count = (int64_t)tl.gemm.size() - L3.start;
+        if (L3.count) h.basis_prog.push_back(L3);
+        Launch L4{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I)
+                    tl.copy.push_back({Rt(h.gm_roff[(size_t)m], m, I, C),
+                                       h.gm_xtoff[(size_t)m] + (I * h.gm_ntc[(size_t)m] + C) * TE});
+        L4.count = (int64_t)tl.copy.size() - L4.start;
+        if (L4.count) h.basis_prog.push_back(L4);
+    }
+    // apply-time GEMV lists
+    {
+        const int64_t gw = lowp ? h.gset.low_w_base : h.gset.w_base;
+        const int64_t gwt = lowp ? h.gset.low_wt_base : h.gset.wt_base;
+        build_smoother_gemv(h.gset, h.vtasks, h.vpairs, gw, gwt);
+        const int64_t cw = h.smoother_precision == 16 ? h.cset.low_w_base : h.cset.w_base;
+        const int64_t cwt = h.smoother_precision == 16 ? h.cset.low_wt_base : h.cset.wt_base;
+        build_smoother_gemv(h.cset, h.vtasks, h.vpairs, cw, cwt);
+        build_smoother_gemv(h.sset, h.vtasks, h.vpairs, h.sset.w_base, h.sset.wt_base);
+        // restriction t = X^T x, prolongation z = X u
+        h.gemv_XT.start = (int64_t)h.vtasks.size();
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C) {
+                h.vtasks.push_back({h.gm_coff[(size_t)m] + C * TS, (int32_t)h.vpairs.size(), (int32_t)h.gset.nt[m]});
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I)
+                    h.vpairs.push_back({h.gm_xtoff[(size_t)m] + (I * h.gm_ntc[(size_t)m] + C) * TE, h.gset.voff[m] + I * TS});
+            }
+        h.gemv_XT.count = (int64_t)h.vtasks.size() - h.gemv_XT.start;
+        h.gemv_X.start = (int64_t)h.vtasks.size();
+        for (int64_t m = 0; m < nG; ++m) {
+            if (h.gm_ntc[(size_t)m] == 0) continue;
+            for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                h.vtasks.push_back({h.gset.voff[m] + I * TS, (int32_t)h.vpairs.size(), (int32_t)h.gm_ntc[(size_t)m]});
+                for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                    h.vpairs.push_back({h.gm_roff[(size_t)m] + (C * h.gset.nt[m] + I) * TE, h.gm_coff[(size_t)m] + C * TS});
+            }
+        }
+        h.gemv_X.count = (int64_t)h.vtasks.size() - h.gemv_X.start;
+    }
+    pad_ones(h.gset, h.pad_ones_g, h.gset.a_base);
+    pad_ones(h.cset, h.pad_ones_c, lowp ? h.c_stage_base : h.cset.a_base);
+    pad_ones(h.sset, h.pad_ones_s, h.sset.a_base);
+    // ---- index maps ------------------------------------------------------------------
+    const int64_t s_pad = h.sset.vec_len;   // corrections follow the padded mortar block
+    h.cvec_len = s_pad + h.n_corr;
+    std::vector<int64_t> fpos((size_t)h.n_coarse);
+    for (int64_t q = 0; q < h.n_mortar; ++q) fpos[(size_t)q] = q;
+    for (int64_t j = 0; j < h.n_corr; ++j) fpos[(size_t)(h.n_mortar + j)] = s_pad + j;
+    std::vector<int32_t> q_iface((size_t)h.n_mortar), q_local((size_t)h.n_mortar);
+    for (int32_t c = 0; c < part.n_ifaces; ++c)
+        for (int32_t j = 0; j < 3 * iface_nu[(size_t)c]; ++j) {
+            q_iface[(size_t)(iface_moff[(size_t)c] + j)] = c;
+            q_local[(size_t)(iface_moff[(size_t)c] + j)] = j;
+        }
+    // t-slot lists: grains adjacent to the interface of each mortar dof, ascending
+    std::vector<std::vector<int32_t>> iface_gm((size_t)part.n_ifaces);
+    for (int64_t m = 0; m < nG; ++m)
+        for (int32_t c : gadj[(size_t)m]) iface_gm[(size_t)c].push_back((int32_t)m);
+    std::vector<int64_t> tptr(1, 0), tslot;
+    for (int64_t q = 0; q < h.n_mortar; ++q) {
+        const int32_t c = q_iface[(size_t)q];
+        for (int32_t m : iface_gm[(size_t)c]) tslot.push_back(h.gm_coff[(size_t)m] + lcol[(size_t)m][c] + q_local[(size_t)q]);
+        tptr.push_back((int64_t)tslot.size());
+    }
+    std::vector<int64_t> corr_koff;
+    for (int64_t m = 0; m < nG; ++m) {
+        const int32_t j = h.gm_corr[(size_t)m];
+        if (j < 0) continue;
+        (void)j;
+    }
+    for (int64_t j = 0; j < h.n_corr; ++j) {
+        const int32_t m = grain_mat[(size_t)h.h_corr_grains[(size_t)j]];
+        const int64_t kc = h.gm_k[(size_t)m];
+        tslot.push_back(h.gm_coff[(size_t)m] + kc);
+        tptr.push_back((int64_t)tslot.size());
+        corr_koff.push_back(h.gm_koff[(size_t)m] + tri_index(kc / TS, kc / TS) * TE + (kc % TS) * TS + (kc % TS));
+    }
+    std::vector<int64_t> gcol_upos((size_t)std::max<int64_t>(h.gcol_len, 1), -1);
+    for (int64_t m = 0; m < nG; ++m) {
+        for (int32_t c : gadj[(size_t)m])
+            for (int32_t j = 0; j < 3 * iface_nu[(size_t)c]; ++j)
+                gcol_upos[(size_t)(h.gm_coff[(size_t)m] + lcol[(size_t)m][c] + j)] = iface_moff[(size_t)c] + j;
+        if (h.gm_corr[(size_t)m] >= 0)
+            gcol_upos[(size_t)(h.gm_coff[(size_t)m] + h.gm_k[(size_t)m])] = s_pad + h.gm_corr[(size_t)m];
+    }
+    std::vector<int64_t> g_slot_dof((size_t)std::max<int64_t>(h.gset.vec_len, 1), -1), g_dof_slot((size_t)h.N, -1);
+    for (int64_t m = 0; m < nG; ++m) {
+        auto &nodes = gnodes[(size_t)h.gm_grain[(size_t)m]];
+        for (size_t l = 0; l < nodes.size(); ++l)
+            for (int d = 0; d < 3; ++d) {
+                const int64_t slot = h.gset.voff[m] + 3 * (int64_t)l + d, dof = 3 * (int64_t)nodes[l] + d;
+                g_slot_dof[(size_t)slot] = dof;
+                g_dof_slot[(size_t)dof] = slot;
+            }
+    }
+    // contacts: per-node membership (ascending contact id) and slot maps
+    for (int64_t v = 0; v < n; ++v) cn_cnt[(size_t)v + 1] += cn_cnt[(size_t)v];
+    std::vector<int32_t> node_cmat((size_t)std::max<int64_t>(cn_cnt[(size_t)n], 1)), node_cloc(node_cmat.size());
+    std::vector<int32_t> item_node, item_mat, item_local;
+    {
+        std::vector<int64_t> fill(cn_cnt.begin(), cn_cnt.end() - 1);
+        for (int32_t c = 0; c < part.n_contacts; ++c)
+            for (int64_t p = part.contact_ptr[c]; p < part.contact_ptr[c + 1]; ++p) {
+                const int32_t v = part.contact_nodes[p];
+                const int32_t l = (int32_t)(p - part.contact_ptr[c]);
+                node_cmat[(size_t)fill[(size_t)v]] = c;
+                node_cloc[(size_t)fill[(size_t)v]++] = l;
+                item_node.push_back(v);
+                item_mat.push_back(c);
+                item_local.push_back(l);
+            }
+    }
+    std::vector<int64_t> c_slot_dof((size_t)std::max<int64_t>(h.cset.vec_len, 1), -1);
+    std::vector<int64_t> c_dof_ptr((size_t)h.N + 1, 0), c_dof_slot;
+    for (int32_t c = 0; c < part.n_contacts; ++c)
+        for (int64_t p = part.contact_ptr[c]; p < part.contact_ptr[c + 1]; ++p)
+            for (int d = 0; d < 3; ++d)
+                c_slot_dof[(size_t)(h.cset.voff[c] + 3 * (p - part.contact_ptr[c]) + d)] = 3 * (int64_t)part.contact_nodes[p] + d;
+    for (int64_t v = 0; v < n; ++v)
+        for (int d = 0; d < 3; ++d) {
+            for (int64_t q = cn_cnt[(size_t)v]; q < cn_cnt[(size_t)v + 1]; ++q)
+                c_dof_slot.push_back(h.cset.voff[node_cmat[(size_t)q]] + 3 * (int64_t)node_cloc[(size_t)q] + d);
+            c_dof_ptr[(size_t)(3 * v + d + 1)] = (int64_t)c_dof_slot.size();
+        }
+    // coarse Galerkin pairs: interface-interface edges of A and shared grains
+    std::vector<CoarseEdge> edges;
+    std::vector<CoarseKRef> krefs;
+    std::vector<CoarsePair> pairs;
+    {
+        struct EdgeKey {
+            int64_t key;
+            CoarseEdge e;
+        };
+        std::vector<EdgeKey> ek;
+        const int64_t NI = std::max<int32_t>(part.n_ifaces, 1);
+        for (int64_t v = 0; v < n; ++v) {
+            const int32_t c = node_iface[(size_t)v];
+            if (c < 0) continue;
+            for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p) {
+                const int32_t w = sys.col_idx[p];
+                const int32_t c2 = node_iface[(size_t)w];
+                if (c2 < 0 || c2 > c) continue;
+                ek.push_back({(int64_t)c * NI + c2, {p, node_irow[(size_t)v], node_irow[(size_t)w]}});
+            }
+        }
+        std::stable_sort(ek.begin(), ek.end(), [](const EdgeKey &a, const EdgeKey &b) { return a.key < b.key; });
+        struct KKey {
+            int64_t key;
+            CoarseKRef r;
+        };
+        std::vector<KKey> kk;
+        for (int64_t m = 0; m < nG; ++m) {
+            auto &a = gadj[(size_t)m];
+            for (size_t i = 0; i < a.size(); ++i)
+                for (size_t j = 0; j <= i; ++j)
+                    kk.push_back({(int64_t)a[i] * NI + a[j],
+                                  {h.gm_koff[(size_t)m], lcol[(size_t)m][a[i]], lcol[(size_t)m][a[j]]}});
+        }
+        std::stable_sort(kk.begin(), kk.end(), [](const KKey &a, const KKey &b) { return a.key < b.key; });
+        size_t ie = 0, ik = 0;
+        while (ie < ek.size() || ik < kk.size()) {
+            int64_t key = INT64_MAX;
+            if (ie < ek.size()) key = std::min(key, ek[ie].key);
+            if (ik < kk.size()) key = std::min(key, kk[ik].key);
+            CoarsePair pr{};
+            pr.c = (int32_t)(key / NI);
+            pr.c2 = (int32_t)(key % NI);
+            pr.e_start = (int64_t)edges.size();
+            while (ie < ek.size() && ek[ie].key == key) edges.push_back(ek[ie++].e);
+            pr.e_count = (int32_t)((int64_t)edges.size() - pr.e_start);
+            pr.k_start = (int64_t)krefs.size();
+            while (ik < kk.size() && kk[ik].key == key) krefs.push_back(kk[ik++].r);
+            pr.k_count = (int32_t)((int64_t)krefs.size() - pr.k_start);
+            pairs.push_back(pr);
+        }
+    }
+    // ---- SELL-64 fine matrix ---------------------------------------------------------
+    std::vector<int64_t> slice_step;
+    std::vector<int32_t> scol;
+    std::vector<double> sval;
+    {
+        const int64_t ns = (n + SELL_C - 1) / SELL_C;
+        slice_step.resize((size_t)ns + 1, 0);
+        for (int64_t sl = 0; sl < ns; ++sl) {
+            int64_t len = 0;
+            for (int64_t r = sl * SELL_C; r < std::min(n, (sl + 1) * SELL_C); ++r)
+                len = std::max(len, sys.row_ptr[r + 1] - sys.row_ptr[r]);
+            slice_step[(size_t)sl + 1] = slice_step[(size_t)sl] + len;
+        }
+        const int64_t steps = slice_step[(size_t)ns];
+        scol.assign((size_t)steps * SELL_C, 0);
+        sval.assign((size_t)steps * 9 * SELL_C, 0.0);
+        for (int64_t sl = 0; sl < ns; ++sl)
+            for (int64_t lane = 0; lane < SELL_C; ++lane) {
+                const int64_t r = sl * SELL_C + lane;
+                for (int64_t k = slice_step[(size_t)sl]; k < slice_step[(size_t)sl + 1]; ++k) {
+                    const int64_t kk = k - slice_step[(size_t)sl];
+                    int64_t col = r < n ? r : 0;
+                    const double *blk = nullptr;
+                    if (r < n && kk < sys.row_ptr[r + 1] - sys.row_ptr[r]) {
+                        col = sys.col_idx[sys.row_ptr[r] + kk];
+                        blk = sys.val + 9 * (sys.row_ptr[r] + kk);
+                    }
+                    scol[(size_t)(k * SELL_C + lane)] = (int32_t)col;
+                    for (int j = 0; j < 9; ++j)
+                        sval[(size_t)(k * 9 * SELL_C + j * SELL_C + lane)] = blk ? blk[j] : 0.0;
+                }
+            }
+        h.sell_padded_blocks = steps * SELL_C;
+        h.sell.n_rows = n;
+        h.sell.n_slices = (int32_t)ns;
+    }
+
+    // ---- bounds validation of every launch list and index map ------------------------
+    {
+        auto chk = [](bool ok, const char *what) {
+            if (!ok) fail(HPLMM_E_ARG, std::string("internal plan check failed: ") + what);
+        };
+        auto in = [](int64_t off, int64_t len, int64_t n) { return off >= 0 && off + len <= n; };
+        for (int which = 0; which < 2; ++which) {
+            const TaskLists &tl = which ? h.tl32 : h.tl64;
+            const int64_t an = which ? h.ar32_n : h.ar64_n;
+            for (const auto &t : tl.gemm) {
+                chk(in(t.c_off, TE, an), "gemm output tile");
+                if (t.flags & GF_POST) chk(in(t.post_off, TE, an), "gemm post tile");
+                chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
+                    "gemm pair range");
+            }
+            for (const auto &pr : tl.pairs) chk(in(pr.a_off, TE, an) && in(pr.b_off, TE, an), "gemm operand tile");
+            for (const auto &d : tl.diag) chk(in(d.a_off, TE, an) && in(d.w_off, TE, an) && in(d.wt_off, TE, an), "diag tile");
+            for (const auto &c : tl.copy) chk(in(c.src_off, TE, an) && in(c.dst_off, TE, an), "transpose tile");
+        }
+        const int64_t low_n = h.smoother_precision == 32 ? h.ar32_n : (h.smoother_precision == 16 ? h.arbf_n : h.ar64_n);
+        const int64_t c_n = h.smoother_precision == 64 ? h.ar64_n : (h.smoother_precision == 32 ? h.ar32_n : h.arbf_n);
+        auto chk_gemv = [&](Range r, int64_t an, int64_t xl, int64_t yl, const char *what) {
+            for (int64_t i = r.start; i < r.start + r.count; ++i) {
+                const GemvTask &t = h.vtasks[(size_t)i];
+                chk(in(t.y_off, TS, yl), what);
+                chk(t.pair_start >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)h.vpairs.size(), what);
+                for (int32_t q = 0; q < t.pair_count; ++q) {
+                    const GemvPair &pr = h.vpairs[(size_t)(t.pair_start + q)];
+                    chk(in(pr.t_off, TE, an) && in(pr.x_off, TS, xl), what);
+                }
+            }
+        };
+        chk_gemv(h.gset.gemv_W, low_n, h.gset.vec_len, h.gset.vec_len, "grain W gemv");
+        chk_gemv(h.gset.gemv_Wt, low_n, h.gset.vec_len, h.gset.vec_len, "grain Wt gemv");
+        chk_gemv(h.cset.gemv_W, c_n, h.cset.vec_len, h.cset.vec_len, "contact W gemv");
+        chk_gemv(h.cset.gemv_Wt, c_n, h.cset.vec_len, h.cset.vec_len, "contact Wt gemv");
+        chk_gemv(h.sset.gemv_W, h.ar64_n, h.cvec_len, h.cvec_len, "coarse W gemv");
+        chk_gemv(h.sset.gemv_Wt, h.ar64_n, h.cvec_len, h.cvec_len, "coarse Wt gemv");
+        chk_gemv(h.gemv_XT, h.ar64_n, h.gset.vec_len, h.gcol_len, "restriction gemv");
+        chk_gemv(h.gemv_X, h.ar64_n, h.gcol_len, h.gset.vec_len, "prolongation gemv");
+        for (auto v : g_slot_dof) chk(v >= -1 && v < h.N, "grain slot map");
+        for (auto v : g_dof_slot) chk(v >= -1 && v < h.gset.vec_len, "grain dof map");
+        for (auto v : gcol_upos) chk(v >= -1 && v < h.cvec_len, "grain column map");
+        for (auto v : c_slot_dof) chk(v >= -1 && v < h.N, "contact slot map");
+        for (auto v : c_dof_slot) chk(v >= 0 && v < h.cset.vec_len, "contact dof map");
+        for (auto v : fpos) chk(v >= 0 && v < h.cvec_len, "coarse position map");
+        for (auto v : tslot) chk(v >= 0 && v < h.gcol_len, "restriction slot map");
+        for (auto v : corr_koff) chk(in(v, 1, h.ar64_n), "correction pivot offset");
+        for (auto v : h.pad_ones_g) chk(in(v, 1, h.ar64_n), "grain padding");
+        for (auto v : h.pad_ones_c) chk(in(v, 1, h.ar64_n), "contact padding");
+        for (auto v : h.pad_ones_s) chk(in(v, 1, h.ar64_n), "coarse padding");
+        for (auto v : scol) chk(v >= 0 && v < n, "SELL column");
+        for (const auto &e : edges) chk(e.blk >= 0 && e.blk < h.nnzb, "coarse edge block");
+        for (const auto &k : krefs) chk(in(k.koff, 1, h.ar64_n), "coarse K reference");
+        for (const auto &w : abar) chk(w.m >= 0 && w.m < nG && w.lcol0 >= 0 && w.lcol0 < h.gm_k[(size_t)w.m], "abar work");
+        for (int64_t m = 0; m < nG; ++m) {
+            chk(in(h.gm_roff[(size_t)m], h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE, h.ar64_n), "R region");
+            chk(in(h.gm_koff[(size_t)m], tri_tiles(h.gm_ntc[(size_t)m]) * TE, h.ar64_n), "K region");
+        }
+        chk(in(h.gset.a_base, h.gset.region, h.ar64_n), "grain region");
+        chk(in(h.sset.a_base, h.sset.region, h.ar64_n), "coarse region");
+        chk(h.n_coarse <= h.cvec_len, "coarse vector length");
+    }
+    if (dry_run) return;
+    // ---- uploads --------------------------------------------------------------------------
+    std::vector<int64_t> rp(sys.row_ptr, sys.row_ptr + n + 1);
+    std::vector<int32_t> ci(sys.col_idx, sys.col_idx + h.nnzb);
+    std::vector<double> va(sys.val, sys.val + 9 * h.nnzb);
+    h.csr.n_nodes = n;
+    h.csr.row_ptr = h.upload(rp, s);
+    h.csr.col = h.upload(ci, s);
+    h.csr.val = h.upload(va, s);
+    h.sell.slice_step = h.upload(slice_step, s);
+    h.sell.col = h.upload(scol, s);
+    h.sell.val = h.upload(sval, s);
+    std::vector<double> bvec((size_t)h.N, 0.0);
+    if (sys.rhs) std::memcpy(bvec.data(), sys.rhs, sizeof(double) * (size_t)h.N);
+    h.d_b = h.upload(bvec, s);
+    // coarse maps
+    h.cm.n_mortar = h.n_mortar;
+    h.cm.n_coarse = h.n_coarse;
+    h.cm.fpos = h.upload(fpos, s);
+    h.cm.q_iface = h.upload(q_iface, s);
+    h.cm.q_local = h.upload(q_local, s);
+    std::vector<int64_t> ip(part.iface_ptr, part.iface_ptr + part.n_ifaces + 1);
+    std::vector<int32_t> inodes(part.iface_nodes, part.iface_nodes + (part.n_ifaces ? part.iface_ptr[part.n_ifaces] : 0));
+    h.cm.iface_ptr = h.upload(ip, s);
+    h.cm.iface_nodes = h.upload(inodes, s);
+    h.cm.iface_hoff = h.upload(iface_hoff, s);
+    h.cm.iface_nu = h.upload(iface_nu, s);
+    h.cm.iface_moff = h.upload(iface_moff, s);
+    h.cm.H = h.upload(h.h_H, s);
+    h.cm.tptr = h.upload(tptr, s);
+    h.cm.tslot = h.upload(tslot, s);
+    h.corr_d = h.dalloc<double>(h.n_corr);
+    h.cm.corr_d = h.corr_d;
+    h.cm.node_iface = h.upload(node_iface, s);
+    h.cm.node_irow = h.upload(node_irow, s);
+    h.d_corr_koff = h.upload(corr_koff, s);
+    // grains
+    h.gg.node_gmat = h.upload(node_gmat, s);
+    h.gg.node_local = h.upload(node_local, s);
+    std::vector<int64_t> aoff(nG);
+    std::vector<int32_t> nt32(nG), corrcol(nG);
+    for (int64_t m = 0; m < nG; ++m) {
+        aoff[(size_t)m] = h.gset.a_base + h.gset.rel[m];
+        nt32[(size_t)m] = (int32_t)h.gset.nt[m];
+        corrcol[(size_t)m] = h.gm_corr[(size_t)m] >= 0 ? h.gm_k[(size_t)m] : -1;
+    }
+    h.gg.mat_aoff = h.upload(aoff, s);
+    h.gg.mat_roff = h.upload(h.gm_roff, s);
+    h.gg.mat_nt = h.upload(nt32, s);
+    h.gg.mat_corrcol = h.upload(corrcol, s);
+    h.n_abar = (int64_t)abar.size();
+    h.d_abar = h.upload(abar, s);
+    h.d_g_slot_dof = h.upload(g_slot_dof, s);
+    h.d_g_dof_slot = h.upload(g_dof_slot, s);
+    h.d_gcol_upos = h.upload(gcol_upos, s);
+    h.d_pad_g = h.upload(h.pad_ones_g, s);
+    // contacts
+    std::vector<int64_t> caoff(h.cset.n.size());
+    for (size_t m = 0; m < h.cset.n.size(); ++m) caoff[m] = (lowp ? h.c_stage_base : h.cset.a_base) + h.cset.rel[m];
+    h.cg.mat_aoff = h.upload(caoff, s);
+    h.cg.item_node = h.upload(item_node, s);
+    h.cg.item_mat = h.upload(item_mat, s);
+    h.cg.item_local = h.upload(item_local, s);
+    h.cg.node_cptr = h.upload(cn_cnt, s);
+    h.cg.node_cmat = h.upload(node_cmat, s);
+    h.cg.node_cloc = h.upload(node_cloc, s);
+    h.n_citems = (int64_t)item_node.size();
+    h.d_c_slot_dof = h.upload(c_slot_dof, s);
+    h.d_c_dof_ptr = h.upload(c_dof_ptr, s);
+    h.d_c_dof_slot = h.upload(c_dof_slot, s);
+    h.d_pad_c = h.upload(h.pad_ones_c, s);
+    // coarse
+    h.n_pairs = (int64_t)pairs.size();
+    h.d_pairs = h.upload(pairs, s);
+    h.d_edges = h.upload(edges, s);
+    h.d_krefs = h.upload(krefs, s);
+    h.d_pad_s = h.upload(h.pad_ones_s, s);
+    // task lists
+    for (TaskLists *tl : {&h.tl64, &h.tl32}) {
+        tl->d_gemm = h.upload(tl->gemm, s);
+        tl->d_pairs = h.upload(tl->pairs, s);
+        tl->d_diag = h.upload(tl->diag, s);
+        tl->d_copy = h.upload(tl->copy, s);
+    }
+    h.d_vtasks = h.upload(h.vtasks, s);
+    h.d_vpairs = h.upload(h.vpairs, s);
+    // arenas and vectors
+    h.ar64 = h.dalloc<double>(h.ar64_n);
+    if (h.ar32_n) h.ar32 = h.dalloc<float>(h.ar32_n);
+    if (h.arbf_n) h.arbf = h.dalloc<uint16_t>(h.arbf_n);
+    h.gx = h.dalloc<double>(h.gset.vec_len);
+    h.gt = h.dalloc<double>(h.gset.vec_len);
+    h.gy = h.dalloc<double>(h.gset.vec_len);
+    h.gc_t = h.dalloc<double>(h.gcol_len);
+    h.gc_u = h.dalloc<double>(h.gcol_len);
+    h.cx = h.dalloc<double>(h.cset.vec_len);
+    h.ct = h.dalloc<double>(h.cset.vec_len);
+    h.cy = h.dalloc<double>(h.cset.vec_len);
+    h.sf = h.dalloc<double>(h.cvec_len);
+    h.st = h.dalloc<double>(h.cvec_len);
+    h.su = h.dalloc<double>(h.cvec_len);
+    if (h.cvec_len > 0) {
+        (void)hipMemsetAsync(h.sf, 0, sizeof(double) * (size_t)h.cvec_len, s);
+        (void)hipMemsetAsync(h.st, 0, sizeof(double) * (size_t)h.cvec_len, s);
+        (void)hipMemsetAsync(h.su, 0, sizeof(double) * (size_t)h.cvec_len, s);
+    }
+    h.z1 = h.dalloc<double>(h.N);
+    h.z2 = h.dalloc<double>(h.N);
+    h.r1 = h.dalloc<double>(h.N);
+    h.r2 = h.dalloc<double>(h.N);
+    h.tmpN = h.dalloc<double>(h.N);
+    h.d_flag = h.dalloc<int32_t>(2);
+    if (hipStreamSynchronize(s) != hipSuccess) fail(HPLMM_E_HIP, "upload failed");
+}
+
+}  // namespace hplmm

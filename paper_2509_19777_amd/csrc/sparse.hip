@@ -1,0 +1,459 @@
+// Sparse, gather/scatter, coarse-assembly and Krylov kernels for gfx950.
+//
+// Every kernel writes each output element from exactly one thread and sums
+// in a fixed order, so results are bitwise reproducible run to run (no
+// floating-point atomics).
+#include <hip/hip_runtime.h>
+
+#include "dense.h"
+#include "sparse.h"
+
+namespace hplmm {
+
+static inline unsigned blocks_for(int64_t n, int per) { return (unsigned)((n + per - 1) / per); }
+
+// ---- SpMV (SELL-64, one wavefront per slice, one lane per node row) ---------
+__global__ void __launch_bounds__(256) spmv_kernel(int64_t n_rows, int32_t n_slices,
+                                                   const int64_t *__restrict__ slice_step,
+                                                   const int32_t *__restrict__ col,
+                                                   const double *__restrict__ val,
+                                                   const double *__restrict__ x,
+                                                   const double *__restrict__ r, double *__restrict__ y) {
+    const int lane = threadIdx.x & 63;
+    const int slice = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (slice >= n_slices) return;
+    const int64_t st = slice_step[slice], en = slice_step[slice + 1];
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int64_t k = st; k < en; ++k) {
+        const int64_t c = col[k * SELL_C + lane];
+        const double *v = val + k * (9 * SELL_C) + lane;
+        const double x0 = x[3 * c], x1 = x[3 * c + 1], x2 = x[3 * c + 2];
+        a0 += v[0] * x0 + v[64] * x1 + v[128] * x2;
+        a1 += v[192] * x0 + v[256] * x1 + v[320] * x2;
+        a2 += v[384] * x0 + v[448] * x1 + v[512] * x2;
+    }
+    const int64_t row = (int64_t)slice * SELL_C + lane;
+    if (row < n_rows) {
+        if (r) {
+            y[3 * row] = r[3 * row] - a0;
+            y[3 * row + 1] = r[3 * row + 1] - a1;
+            y[3 * row + 2] = r[3 * row + 2] - a2;
+        } else {
+            y[3 * row] = a0;
+            y[3 * row + 1] = a1;
+            y[3 * row + 2] = a2;
+        }
+    }
+}
+
+void launch_spmv(const SellMatrix &A, const double *x, const double *r, double *y, hipStream_t s) {
+    hipLaunchKernelGGL(spmv_kernel, dim3(blocks_for(A.n_slices, 4)), dim3(256), 0, s, A.n_rows, A.n_slices,
+                       A.slice_step, A.col, A.val, x, r, y);
+}
+
+// ---- gathers / combination ----------------------------------------------------
+__global__ void gather_kernel(const int64_t *__restrict__ map, const double *__restrict__ src,
+                              double *__restrict__ dst, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int64_t m = map[i];
+    dst[i] = m >= 0 ? src[m] : 0.0;
+}
+void launch_gather(const int64_t *map, const double *src, double *dst, int64_t n, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, map, src, dst, n);
+}
+
+__global__ void combine_kernel(int64_t n, const double *__restrict__ base, const int64_t *__restrict__ gslot,
+                               const double *__restrict__ g, const int64_t *__restrict__ cptr,
+                               const int64_t *__restrict__ cslot, const double *__restrict__ c,
+                               double *__restrict__ out) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= n) return;
+    double s = base ? base[d] : 0.0;
+    if (gslot) {
+        const int64_t q = gslot[d];
+        if (q >= 0) s += g[q];
+    }
+    if (cptr) {
+        double t = 0.0;
+        for (int64_t p = cptr[d]; p < cptr[d + 1]; ++p) t += c[cslot[p]];
+        s += t;
+    }
+    out[d] = s;
+}
+void launch_combine(int64_t n, const double *base, const int64_t *gslot, const double *g, const int64_t *cptr,
+                    const int64_t *cslot, const double *c, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(combine_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, n, base, gslot, g, cptr, cslot,
+                       c, out);
+}
+
+// ---- restriction / prolongation ------------------------------------------------
+__global__ void coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r, const double *__restrict__ t,
+                                  double *__restrict__ f) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= m.n_coarse) return;
+    double s = 0.0;
+    if (q < m.n_mortar) {
+        const int32_t c = m.q_iface[q];
+        const int32_t lq = m.q_local[q];
+        const int32_t nu = m.iface_nu[c];
+        const int32_t a = lq / 3, d = lq % 3;
+        const double *H = m.H + m.iface_hoff[c];
+        const int64_t p0 = m.iface_ptr[c], p1 = m.iface_ptr[c + 1];
+        for (int64_t p = p0; p < p1; ++p) s += H[(p - p0) * nu + a] * r[3 * (int64_t)m.iface_nodes[p] + d];
+    }
+    double g = 0.0;
+    for (int64_t p = m.tptr[q]; p < m.tptr[q + 1]; ++p) g += t[m.tslot[p]];
+    f[m.fpos[q]] = s + g;
+}
+void launch_coarse_rhs(const CoarseMaps &m, const double *r, const double *t, double *f, hipStream_t s) {
+    if (m.n_coarse <= 0) return;
+    hipLaunchKernelGGL(coarse_rhs_kernel, dim3(blocks_for(m.n_coarse, 256)), dim3(256), 0, s, m, r, t, f);
+}
+
+__global__ void corr_solve_kernel(CoarseMaps m, const double *__restrict__ f, double *__restrict__ u) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t q = m.n_mortar + j;
+    if (q >= m.n_coarse) return;
+    u[m.fpos[q]] = f[m.fpos[q]] / m.corr_d[j];
+}
+void launch_corr_solve(const CoarseMaps &m, const double *f, double *u, hipStream_t s) {
+    const int64_t nc = m.n_coarse - m.n_mortar;
+    if (nc <= 0) return;
+    hipLaunchKernelGGL(corr_solve_kernel, dim3(blocks_for(nc, 256)), dim3(256), 0, s, m, f, u);
+}
+
+__global__ void prolong_nodes_kernel(CoarseMaps m, int64_t n_nodes, const int64_t *__restrict__ gslot,
+                                     const double *__restrict__ zl, const double *__restrict__ u,
+                                     double *__restrict__ z) {
+    const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (d >= 3 * n_nodes) return;
+    const int64_t q = gslot[d];
+    if (q >= 0) {
+        z[d] = zl[q];
+        return;
+    }
+    const int64_t v = d / 3;
+    const int g = (int)(d - 3 * v);
+    const int32_t c = m.node_iface[v];
+    double s = 0.0;
+    if (c >= 0) {
+        const int32_t nu = m.iface_nu[c];
+        const double *H = m.H + m.iface_hoff[c] + (int64_t)m.node_irow[v] * nu;
+        const int64_t mo = m.iface_moff[c];
+        for (int a = 0; a < nu; ++a) s += H[a] * u[m.fpos[mo + 3 * a + g]];
+    }
+    z[d] = s;
+}
+void launch_prolong_nodes(const CoarseMaps &m, int64_t n_nodes, const int64_t *gslot, const double *zl,
+                          const double *u, double *z, hipStream_t s) {
+    hipLaunchKernelGGL(prolong_nodes_kernel, dim3(blocks_for(3 * n_nodes, 256)), dim3(256), 0, s, m, n_nodes,
+                       gslot, zl, u, z);
+}
+
+// ---- set-up gathers ------------------------------------------------------------
+__device__ __forceinline__ int64_t tile_elem(int64_t r, int64_t c) {
+    // element (r, c) inside packed lower tiles (caller ensures r/64 >= c/64)
+    const int64_t I = r >> 6, J = c >> 6;
+    return tri_index(I, J) * TE + (c & 63) * TS + (r & 63);
+}
+__device__ __forceinline__ int64_t rect_elem(int64_t r, int64_t c, int64_t nt) {
+    // element (r, c) of a tile grid stored tile-column-major (tile (I, C) at C*nt + I)
+    return ((c >> 6) * nt + (r >> 6)) * TE + (c & 63) * TS + (r & 63);
+}
+
+__global__ void gather_grain_kernel(FineCsr A, GrainGather g, const double *__restrict__ b,
+                                    double *__restrict__ arena) {
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= A.n_nodes) return;
+    const int32_t m = g.node_gmat[v];
+    if (m < 0) return;
+    const int64_t lv = g.node_local[v];
+    double *T = arena + g.mat_aoff[m];
+    for (int64_t p = A.row_ptr[v]; p < A.row_ptr[v + 1]; ++p) {
+        const int32_t w = A.col[p];
+        if (g.node_gmat[w] != m) continue;
+        const int64_t lw = g.node_local[w];
+        for (int gi = 0; gi < 3; ++gi)
+            for (int di = 0; di < 3; ++di) {
+                const int64_t r = 3 * lv + gi, c = 3 * lw + di;
+                if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p + 3 * gi + di];
+            }
+    }
+    const int32_t cc = g.mat_corrcol[m];
+    if (cc >= 0 && b) {
+        double *R = arena + g.mat_roff[m];
+        for (int gi = 0; gi < 3; ++gi) R[rect_elem(3 * lv + gi, cc, g.mat_nt[m])] = b[3 * v + gi];
+    }
+}
+void launch_gather_grain_blocks(const FineCsr &A, const GrainGather &g, const double *b, double *arena,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(gather_grain_kernel, dim3(blocks_for(A.n_nodes, 128)), dim3(128), 0, s, A, g, b, arena);
+}
+
+template <class T>
+__global__ void set_ones_kernel(const int64_t *__restrict__ off, int64_t n, T *__restrict__ arena) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) arena[off[i]] = T(1);
+}
+void launch_set_ones(const int64_t *off, int64_t n, double *arena, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(set_ones_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, off, n, arena);
+}
+template <class T>
+void launch_set_ones_t(const int64_t *off, int64_t n, T *arena, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(set_ones_kernel<T>, dim3(blocks_for(n, 256)), dim3(256), 0, s, off, n, arena);
+}
+template void launch_set_ones_t<float>(const int64_t *, int64_t, float *, hipStream_t);
+template void launch_set_ones_t<double>(const int64_t *, int64_t, double *, hipStream_t);
+
+__global__ void gather_abar_kernel(FineCsr A, const AbarWork *__restrict__ work, int64_t nwork, CoarseMaps cm,
+                                   GrainGather g, double *__restrict__ arena) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nwork) return;
+    const AbarWork wk = work[i];
+    const int32_t nu = cm.iface_nu[wk.c];
+    const double *H = cm.H + cm.iface_hoff[wk.c];
+    double *R = arena + g.mat_roff[wk.m];
+    const int64_t nt = g.mat_nt[wk.m];
+    for (int a = 0; a < nu; ++a) {
+        double acc[9];
+        for (int j = 0; j < 9; ++j) acc[j] = 0.0;
+        for (int64_t p = A.row_ptr[wk.v]; p < A.row_ptr[wk.v + 1]; ++p) {
+            const int32_t w = A.col[p];
+            if (cm.node_iface[w] != wk.c) continue;
+            const double h = H[(int64_t)cm.node_irow[w] * nu + a];
+            for (int j = 0; j < 9; ++j) acc[j] += A.val[9 * p + j] * h;
+        }
+        for (int gi = 0; gi < 3; ++gi)
+            for (int di = 0; di < 3; ++di)
+                R[rect_elem(3 * (int64_t)wk.lrow + gi, wk.lcol0 + 3 * a + di, nt)] = -acc[3 * gi + di];
+    }
+}
+void launch_gather_abar(const FineCsr &A, const AbarWork *work, int64_t nwork, const CoarseMaps &cm,
+                        const GrainGather &g, double *arena, hipStream_t s) {
+    if (nwork <= 0) return;
+    hipLaunchKernelGGL(gather_abar_kernel, dim3(blocks_for(nwork, 128)), dim3(128), 0, s, A, work, nwork, cm, g,
+                       arena);
+}
+
+__global__ void gather_contact_kernel(FineCsr A, ContactGather cg, int64_t nitems, double *__restrict__ arena) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nitems) return;
+    const int32_t v = cg.item_node[i], m = cg.item_mat[i];
+    const int64_t lv = cg.item_local[i];
+    double *T = arena + cg.mat_aoff[m];
+    for (int64_t p = A.row_ptr[v]; p < A.row_ptr[v + 1]; ++p) {
+        const int32_t w = A.col[p];
+        int64_t lw = -1;
+        for (int64_t q = cg.node_cptr[w]; q < cg.node_cptr[w + 1]; ++q)
+            if (cg.node_cmat[q] == m) {
+                lw = cg.node_cloc[q];
+                break;
+            }
+        if (lw < 0) continue;
+        for (int gi = 0; gi < 3; ++gi)
+            for (int di = 0; di < 3; ++di) {
+                const int64_t r = 3 * lv + gi, c = 3 * lw + di;
+                if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p + 3 * gi + di];
+            }
+    }
+}
+void launch_gather_contact_blocks(const FineCsr &A, const ContactGather &c, int64_t nitems, double *arena,
+                                  hipStream_t s) {
+    if (nitems <= 0) return;
+    hipLaunchKernelGGL(gather_contact_kernel, dim3(blocks_for(nitems, 128)), dim3(128), 0, s, A, c, nitems, arena);
+}
+
+// ---- coarse Galerkin assembly ----------------------------------------------------
+__global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *__restrict__ pairs,
+                                                             const CoarseEdge *__restrict__ edges,
+                                                             const CoarseKRef *__restrict__ krefs, CoarseMaps cm,
+                                                             const double *__restrict__ bval,
+                                                             const double *__restrict__ karena,
+                                                             double *__restrict__ S) {
+    const CoarsePair pr = pairs[blockIdx.x];
+    const int32_t nu1 = cm.iface_nu[pr.c], nu2 = cm.iface_nu[pr.c2];
+    const int n1 = 3 * nu1, n2 = 3 * nu2;
+    const double *H1 = cm.H + cm.iface_hoff[pr.c];
+    const double *H2 = cm.H + cm.iface_hoff[pr.c2];
+    const int64_t mo1 = cm.iface_moff[pr.c], mo2 = cm.iface_moff[pr.c2];
+    for (int e = threadIdx.x; e < n1 * n2; e += 64) {
+        const int i = e / n2, j = e - (e / n2) * n2;
+        const int a = i / 3, gi = i % 3, bb = j / 3, di = j % 3;
+        double acc = 0.0;
+        for (int32_t k = 0; k < pr.e_count; ++k) {
+            const CoarseEdge ed = edges[pr.e_start + k];
+            acc += H1[(int64_t)ed.rv * nu1 + a] * H2[(int64_t)ed.rw * nu2 + bb] * bval[9 * ed.blk + 3 * gi + di];
+        }
+        double kk = 0.0;
+        for (int32_t k = 0; k < pr.k_count; ++k) {
+            const CoarseKRef kr = krefs[pr.k_start + k];
+            int64_t R = kr.lc + i, C = kr.lc2 + j;
+            if (R < C) {
+                const int64_t t = R;
+                R = C;
+                C = t;
+            }
+            kk += karena[kr.koff + tile_elem(R, C)];
+        }
+        const double val = acc - kk;
+        const int64_t p = mo1 + i, q = mo2 + j;
+        if ((p >> 6) > (q >> 6)) {
+            S[tile_elem(p, q)] = val;
+        } else if ((p >> 6) == (q >> 6)) {
+            S[tile_elem(p, q)] = val;
+            if (pr.c != pr.c2) S[tile_elem(q, p)] = val;
+        }
+    }
+}
+void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const CoarseEdge *edges,
+                            const CoarseKRef *krefs, const CoarseMaps &cm, const double *bsr_val,
+                            const double *karena, double *sarena, int64_t s_off, hipStream_t s) {
+    if (npairs <= 0) return;
+    hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)npairs), dim3(64), 0, s, pairs, edges, krefs, cm,
+                       bsr_val, karena, sarena + s_off);
+}
+
+__global__ void gather_scalar_kernel(const int64_t *__restrict__ off, int64_t n, const double *__restrict__ src,
+                                     double *__restrict__ dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[off[i]];
+}
+void launch_gather_scalar(const int64_t *off, int64_t n, const double *src, double *dst, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_scalar_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, off, n, src, dst);
+}
+
+// ---- conversions ------------------------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__global__ void cvt_f64_f32_kernel(const double *__restrict__ s, float *__restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = (float)s[i];
+}
+__global__ void cvt_f32_bf16_kernel(const float *__restrict__ s, uint16_t *__restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = f32_to_bf16_rne(s[i]);
+}
+__global__ void cvt_f64_bf16_kernel(const double *__restrict__ s, uint16_t *__restrict__ d, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) d[i] = f32_to_bf16_rne((float)s[i]);
+}
+void launch_convert_f64_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_f64_f32_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+void launch_convert_f32_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_f32_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+void launch_convert_f64_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s) {
+    if (n > 0) hipLaunchKernelGGL(cvt_f64_bf16_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, src, dst, n);
+}
+
+// ---- Krylov --------------------------------------------------------------------------
+int32_t multidot_blocks(int64_t n) {
+    int64_t b = (n + 4095) / 4096;
+    if (b > 512) b = 512;
+    if (b < 1) b = 1;
+    return (int32_t)b;
+}
+
+__device__ __forceinline__ double block_sum_256(double v, double *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    __syncthreads();
+    if (lane == 0) sh[w] = v;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, int64_t ld, int32_t k,
+                                                       const double *__restrict__ w, int64_t n,
+                                                       double *__restrict__ part) {
+    __shared__ double sh[4];
+    const int64_t nb = gridDim.x;
+    const int64_t chunk = (n + nb - 1) / nb;
+    const int64_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    for (int32_t j = 0; j < k; ++j) {
+        const double *v = V + j * ld;
+        double s = 0.0;
+        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += w[i] * v[i];
+        s = block_sum_256(s, sh);
+        if (threadIdx.x == 0) part[blockIdx.x * (int64_t)k + j] = s;
+    }
+}
+void launch_multidot(const double *V, int64_t ld, int32_t k, const double *w, int64_t n, double *part,
+                     int32_t nblocks, hipStream_t s) {
+    hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(256), 0, s, V, ld, k, w, n, part);
+}
+
+__global__ void reduce_parts_kernel(const double *__restrict__ part, int32_t nb, int32_t k, double *__restrict__ out,
+                                    int32_t acc) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= k) return;
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * k + j];
+    out[j] = acc ? out[j] + s : s;
+}
+void launch_reduce_parts(const double *part, int32_t nblocks, int32_t k, double *out, int32_t acc, hipStream_t s) {
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(k, 64)), dim3(64), 0, s, part, nblocks, k, out, acc);
+}
+
+__global__ void sub_comb_kernel(const double *__restrict__ V, int64_t ld, int32_t k, const double *__restrict__ h,
+                                double *__restrict__ w, int64_t n) {
+    __shared__ double hs[128];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int32_t j = 0; j < k; ++j) s += V[j * ld + i] * hs[j];
+    w[i] -= s;
+}
+void launch_subtract_combination(const double *V, int64_t ld, int32_t k, const double *h, double *w, int64_t n,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(sub_comb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, V, ld, k, h, w, n);
+}
+
+__global__ void add_comb_kernel(const double *__restrict__ Z, int64_t ld, int32_t k, const double *__restrict__ y,
+                                double *__restrict__ x, int64_t n) {
+    __shared__ double ys[128];
+    for (int j = threadIdx.x; j < k; j += blockDim.x) ys[j] = y[j];
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int32_t j = 0; j < k; ++j) s += Z[j * ld + i] * ys[j];
+    x[i] += s;
+}
+void launch_add_combination(const double *Z, int64_t ld, int32_t k, const double *y, double *x, int64_t n,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(add_comb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Z, ld, k, y, x, n);
+}
+
+__global__ void normalize_kernel(const double *__restrict__ w, const double *__restrict__ nrm2,
+                                 double *__restrict__ v, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double nr = sqrt(nrm2[0]);
+    v[i] = nr > 0.0 ? w[i] / nr : 0.0;
+}
+void launch_normalize(const double *w, const double *nrm2, double *v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(normalize_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, w, nrm2, v, n);
+}
+
+__global__ void axpby_kernel(double a, const double *__restrict__ x, double b, const double *__restrict__ y,
+                             double *__restrict__ out, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = a * x[i] + (y ? b * y[i] : 0.0);
+}
+void launch_axpby(double a, const double *x, double b, const double *y, double *out, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(axpby_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, a, x, b, y, out, n);
+}
+
+}  // namespace hplmm

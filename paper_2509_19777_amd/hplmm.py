@@ -1,0 +1,356 @@
+"""ctypes binding of libhplmm (argument marshalling only).
+
+Every computation happens in the native library: Q1 assembly, partitioning
+and mortar placement on the host (C++), set-up, preconditioner application
+and FGMRES on the GPU (HIP).  PyTorch only provides device memory and the
+stream.  The binding raises if the library is missing: there is no fallback.
+
+torch is imported before the library is loaded so that the library binds to
+the HIP runtime torch already loaded (both carry the soname libamdhip64.so.7).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libhplmm.so")
+
+i32, i64, f64, u8 = C.c_int32, C.c_int64, C.c_double, C.c_uint8
+P = C.POINTER
+
+
+class HplmmSystem(C.Structure):
+    _fields_ = [("n_nodes", i64), ("nnzb", i64), ("row_ptr", P(i64)), ("col_idx", P(i32)),
+                ("val", P(f64)), ("rhs", P(f64)), ("node_xyz", P(i32))]
+
+
+class HplmmPartition(C.Structure):
+    _fields_ = [("n_nodes", i64), ("n_grains", i32), ("node_grain", P(i32)), ("n_ifaces", i32), ("iface_ptr", P(i64)),
+                ("iface_nodes", P(i32)), ("n_contacts", i32), ("contact_ptr", P(i64)),
+                ("contact_nodes", P(i32))]
+
+
+class HplmmMortar(C.Structure):
+    _fields_ = [("n", i32), ("beta", f64)]
+
+
+class HplmmOptions(C.Structure):
+    _fields_ = [("smoother_precision", i32)]
+
+
+class HplmmSolveInfo(C.Structure):
+    _fields_ = [("iters", i32), ("rel_res_true", f64), ("t_solve_ms", f64), ("res_hist", P(f64)),
+                ("res_hist_cap", i32), ("res_hist_len", i32)]
+
+
+EXPORTS = {
+    "hplmm_assemble_voxels": (i32, [i32, i32, i32, P(u8), P(f64), f64, P(f64), P(HplmmSystem)]),
+    "hplmm_system_free": (None, [P(HplmmSystem)]),
+    "hplmm_partition_from_voxels": (i32, [i32, i32, i32, P(u8), P(i32), i32, i32, P(HplmmPartition)]),
+    "hplmm_partition_free": (None, [P(HplmmPartition)]),
+    "hplmm_place_mortars": (i32, [P(i32), i32, i32, P(i32)]),
+    "hplmm_plan": (i32, [P(HplmmSystem), P(HplmmPartition), P(HplmmMortar), P(HplmmOptions), C.c_void_p,
+                         P(C.c_void_p)]),
+    "hplmm_plan_check": (i32, [P(HplmmSystem), P(HplmmPartition), P(HplmmMortar), P(HplmmOptions), P(i64)]),
+    "hplmm_setup": (i32, [C.c_void_p, C.c_void_p]),
+    "hplmm_apply": (i32, [C.c_void_p, i32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_spmv": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_solve": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, f64, i32, i32, i32, P(HplmmSolveInfo),
+                          C.c_void_p]),
+    "hplmm_query": (i32, [C.c_void_p, i32, C.c_void_p, i64, P(i64)]),
+    "hplmm_destroy": (None, [C.c_void_p]),
+    "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
+    "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
+    "hplmm_debug_read_arena": (i32, [C.c_void_p, i32, i64, i64, C.c_void_p]),
+    "hplmm_debug_grain_layout": (i32, [C.c_void_p, P(i64), i64]),
+    "hplmm_last_error": (C.c_char_p, []),
+}
+
+STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_PARTITION", -3: "E_NOT_SPD",
+          -4: "E_SINGULAR_COARSE", -5: "E_HIP", -6: "E_OOM", -7: "E_NONFINITE", -8: "E_STATE"}
+
+_lib = None
+
+
+class HplmmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"hplmm {STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lib():
+    """Load libhplmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with python -m paper_2509_19777_amd.build")
+        L = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code < 0:
+        raise HplmmError(code, lib().hplmm_last_error().decode())
+    return code
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(P(ct))
+
+
+# ---- host-side problem construction ---------------------------------------------
+class System:
+    """Assembled fine system (numpy copies of the library's arrays)."""
+
+    def __init__(self, n_nodes, row_ptr, col_idx, val, rhs, node_xyz):
+        self.n_nodes = int(n_nodes)
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self.val = np.ascontiguousarray(val, dtype=np.float64).reshape(-1)
+        self.rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        self.node_xyz = np.ascontiguousarray(node_xyz, dtype=np.int32).reshape(-1)
+
+    @property
+    def nnzb(self):
+        return int(self.row_ptr[-1])
+
+    def c_struct(self):
+        return HplmmSystem(self.n_nodes, self.nnzb, _ptr(self.row_ptr, i64), _ptr(self.col_idx, i32),
+                           _ptr(self.val, f64), _ptr(self.rhs, f64), _ptr(self.node_xyz, i32))
+
+    def to_scipy(self):
+        """Scalar CSR matrix (for tests)."""
+        import scipy.sparse as sp
+        n = self.n_nodes
+        blocks = self.val.reshape(-1, 3, 3)
+        return sp.bsr_matrix((blocks, self.col_idx, self.row_ptr), shape=(3 * n, 3 * n)).tocsr()
+
+
+def assemble_voxels(problem):
+    """Q1 assembly of a synth.Problem by the library (host only)."""
+    nz, ny, nx = problem.solid.shape
+    solid = np.ascontiguousarray(problem.solid, dtype=np.uint8)
+    E = np.ascontiguousarray(problem.E, dtype=np.float64)
+    t = np.ascontiguousarray(problem.traction, dtype=np.float64)
+    out = HplmmSystem()
+    _check(lib().hplmm_assemble_voxels(nx, ny, nz, _ptr(solid, u8), _ptr(E, f64), float(problem.nu),
+                                       _ptr(t, f64), C.byref(out)))
+    try:
+        n, nb = out.n_nodes, out.nnzb
+        sysm = System(n, np.ctypeslib.as_array(out.row_ptr, (n + 1,)).copy(),
+                      np.ctypeslib.as_array(out.col_idx, (nb,)).copy(),
+                      np.ctypeslib.as_array(out.val, (9 * nb,)).copy(),
+                      np.ctypeslib.as_array(out.rhs, (3 * n,)).copy(),
+                      np.ctypeslib.as_array(out.node_xyz, (3 * n,)).copy())
+    finally:
+        lib().hplmm_system_free(C.byref(out))
+    return sysm
+
+
+class Partition:
+    """Grains, interfaces and contact grids (numpy arrays)."""
+
+    def __init__(self, n_grains, node_grain, iface_ptr, iface_nodes, contact_ptr, contact_nodes):
+        self.n_grains = int(n_grains)
+        self.node_grain = np.ascontiguousarray(node_grain, dtype=np.int32)
+        self.iface_ptr = np.ascontiguousarray(iface_ptr, dtype=np.int64)
+        self.iface_nodes = np.ascontiguousarray(iface_nodes, dtype=np.int32)
+        self.contact_ptr = np.ascontiguousarray(contact_ptr, dtype=np.int64)
+        self.contact_nodes = np.ascontiguousarray(contact_nodes, dtype=np.int32)
+
+    @property
+    def n_ifaces(self):
+        return self.iface_ptr.size - 1
+
+    @property
+    def n_contacts(self):
+        return self.contact_ptr.size - 1
+
+    def iface(self, c):
+        return self.iface_nodes[self.iface_ptr[c]:self.iface_ptr[c + 1]]
+
+    def contact(self, c):
+        return self.contact_nodes[self.contact_ptr[c]:self.contact_ptr[c + 1]]
+
+    def c_struct(self):
+        return HplmmPartition(self.node_grain.size, self.n_grains, _ptr(self.node_grain, i32), self.n_ifaces, _ptr(self.iface_ptr, i64),
+                              _ptr(self.iface_nodes, i32), self.n_contacts, _ptr(self.contact_ptr, i64),
+                              _ptr(self.contact_nodes, i32))
+
+
+def partition_from_voxels(problem, w_zeta=None):
+    nz, ny, nx = problem.solid.shape
+    solid = np.ascontiguousarray(problem.solid, dtype=np.uint8)
+    lab = np.ascontiguousarray(np.where(problem.solid > 0, problem.labels, 0), dtype=np.int32)
+    w = problem.w_zeta if w_zeta is None else w_zeta
+    out = HplmmPartition()
+    _check(lib().hplmm_partition_from_voxels(nx, ny, nz, _ptr(solid, u8), _ptr(lab, i32), int(problem.n_grains),
+                                             int(w), C.byref(out)))
+    try:
+        n = out.n_nodes
+        nI, nC = out.n_ifaces, out.n_contacts
+        ip = np.ctypeslib.as_array(out.iface_ptr, (nI + 1,)).copy()
+        cp = np.ctypeslib.as_array(out.contact_ptr, (nC + 1,)).copy()
+        part = Partition(out.n_grains, np.ctypeslib.as_array(out.node_grain, (n,)).copy(), ip,
+                         np.ctypeslib.as_array(out.iface_nodes, (max(int(ip[-1]), 1),)).copy()[:ip[-1]],
+                         cp, np.ctypeslib.as_array(out.contact_nodes, (max(int(cp[-1]), 1),)).copy()[:cp[-1]])
+    finally:
+        lib().hplmm_partition_free(C.byref(out))
+    return part
+
+
+def place_mortars(xyz, n):
+    xyz = np.ascontiguousarray(xyz, dtype=np.int32).reshape(-1)
+    N = xyz.size // 3
+    out = np.zeros(min(n, N), dtype=np.int32)
+    _check(lib().hplmm_place_mortars(_ptr(xyz, i32), N, int(n), _ptr(out, i32)))
+    return out.tolist()
+
+
+def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64):
+    """Host-only symbolic phase plus bounds check of every launch list."""
+    s, p = system.c_struct(), part.c_struct()
+    m = HplmmMortar(int(n_mortar), float(beta))
+    o = HplmmOptions(int(smoother_precision))
+    out = np.zeros(16, dtype=np.int64)
+    _check(lib().hplmm_plan_check(C.byref(s), C.byref(p), C.byref(m), C.byref(o), _ptr(out, i64)))
+    keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
+            "grain_mats", "ar64", "ar32", "arbf", "tile_tasks", "tile_pairs", "gemv_tasks", "gemv_pairs"]
+    return dict(zip(keys, (int(x) for x in out)))
+
+
+# ---- device solver --------------------------------------------------------------------
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t):
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """hPLMM-preconditioned FGMRES on the current GPU.
+
+    plan(...) runs the symbolic phase and uploads the inputs; setup() runs the
+    numeric set-up on the device; apply/spmv/solve operate on float64 CUDA
+    tensors of length 3*n_nodes.
+    """
+
+    def __init__(self, system: System, part: Partition, n_mortar=2, beta=4.0, smoother_precision=64):
+        if not torch.cuda.is_available():
+            raise RuntimeError("hplmm.Solver needs a GPU")
+        self.system, self.part = system, part
+        self._keep = (system.c_struct(), part.c_struct())
+        h = C.c_void_p()
+        m = HplmmMortar(int(n_mortar), float(beta))
+        o = HplmmOptions(int(smoother_precision))
+        _check(lib().hplmm_plan(C.byref(self._keep[0]), C.byref(self._keep[1]), C.byref(m), C.byref(o), _stream(),
+                                C.byref(h)))
+        self.h = h
+        self.N = 3 * system.n_nodes
+        self.b = torch.from_numpy(system.rhs).cuda()
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is not None and h.value:
+            lib().hplmm_destroy(h)
+            self.h = None
+
+    def setup(self):
+        _check(lib().hplmm_setup(self.h, _stream()))
+
+    def apply(self, r, which=0, out=None):
+        z = torch.empty_like(r) if out is None else out
+        _check(lib().hplmm_apply(self.h, int(which), _dptr(r), _dptr(z), _stream()))
+        return z
+
+    def spmv(self, x, out=None):
+        y = torch.empty_like(x) if out is None else out
+        _check(lib().hplmm_spmv(self.h, _dptr(x), _dptr(y), _stream()))
+        return y
+
+    def solve(self, b=None, x0=None, rtol=1e-8, restart=50, maxit=300, fixed_iters=0, hist_cap=1024):
+        b = self.b if b is None else b
+        x = torch.zeros_like(b) if x0 is None else x0.clone()
+        hist = np.zeros(hist_cap)
+        info = HplmmSolveInfo(0, 0.0, 0.0, _ptr(hist, f64), hist_cap, 0)
+        code = _check(lib().hplmm_solve(self.h, _dptr(b), _dptr(x), float(rtol), int(restart), int(maxit),
+                                        int(fixed_iters), C.byref(info), _stream()))
+        return x, {"status": STATUS[code], "iters": info.iters, "rel_res": info.rel_res_true,
+                   "t_solve_ms": info.t_solve_ms, "history": hist[:info.res_hist_len].copy()}
+
+    def query(self, what, dtype):
+        need = i64(0)
+        _check(lib().hplmm_query(self.h, int(what), None, 0, C.byref(need)))
+        buf = np.zeros(max(int(need.value), 1), dtype=np.uint8)
+        _check(lib().hplmm_query(self.h, int(what), buf.ctypes.data_as(C.c_void_p), buf.size, C.byref(need)))
+        return buf[:need.value].view(dtype)
+
+    def sizes(self):
+        keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
+                "grain_mats", "max_grain_dofs", "max_contact_dofs", "sell_slices", "sell_padded_blocks"]
+        v = self.query(0, np.int64)
+        return dict(zip(keys, (int(x) for x in v)))
+
+    def coarse_matrix(self):
+        n = self.sizes()["n_coarse"]
+        return self.query(4, np.float64).reshape(n, n)
+
+    def setup_times_ms(self):
+        v = self.query(5, np.float64)
+        return {"grains": v[0], "contacts": v[1], "coarse": v[2], "total": v[3]}
+
+
+# ---- test hooks ---------------------------------------------------------------
+def _vp(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def debug_tile_gemm(A, B, C_, flags, P_=None):
+    """One tile task on CUDA tensors: A, B (npairs, 64, 64) as column-major tiles
+    (i.e. tensors holding the transposed tile), C_ (64, 64) updated in place."""
+    prec = 64 if A.dtype == torch.float64 else 32
+    _check(lib().hplmm_debug_tile_gemm(prec, _vp(A), _vp(B), int(A.shape[0]), _vp(P_), _vp(C_), int(flags),
+                                       _stream()))
+
+
+def debug_diag(A):
+    prec = 64 if A.dtype == torch.float64 else 32
+    W = torch.empty_like(A)
+    Wt = torch.empty_like(A)
+    _check(lib().hplmm_debug_diag(prec, _vp(A), _vp(W), _vp(Wt), _stream()))
+    return A, W, Wt
+
+
+def debug_setup_stage(solver, stage):
+    _check(lib().hplmm_debug_setup_stage(solver.h, int(stage), _stream()))
+
+
+def debug_read_arena(solver, arena, off, count):
+    dt = {0: np.float64, 1: np.float32, 2: np.uint16}[arena]
+    out = np.zeros(int(count), dtype=dt)
+    _check(lib().hplmm_debug_read_arena(solver.h, int(arena), int(off), int(count), out.ctypes.data_as(C.c_void_p)))
+    return out
+
+
+def debug_grain_layout(solver):
+    nm = solver.sizes()["grain_mats"]
+    out = np.zeros(11 * nm, dtype=np.int64)
+    _check(lib().hplmm_debug_grain_layout(solver.h, _ptr(out, i64), out.size))
+    return out.reshape(nm, 11)
+
+
+def build_problem(problem, w_zeta=None):
+    """Assemble and partition a synth.Problem with the library (host only)."""
+    return assemble_voxels(problem), partition_from_voxels(problem, w_zeta)

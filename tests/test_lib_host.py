@@ -1,0 +1,135 @@
+"""Host-side parts of libhplmm (no GPU needed): the library loads and exports
+every symbol its headers declare; its Q1 assembly, partition (reading R1/R5)
+and mortar placement (Eq. 7, reading R7) agree with the oracle."""
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2509_19777_amd import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2509_19777_amd", "_lib", "libhplmm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libhplmm.so not built")
+
+
+def _declared_symbols():
+    names = set()
+    for hdr in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(hdr).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(hplmm_[a-z_0-9]+)\s*\(", text))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    import subprocess
+    names = _declared_symbols()
+    assert len(names) >= 12
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\b(hplmm_[a-z_0-9]+)\b", out))
+    assert names <= exported, names - exported
+    L = ctypes.CDLL(LIB)
+    for n in names:
+        getattr(L, n)
+
+
+@pytest.fixture(scope="module")
+def hp():
+    from paper_2509_19777_amd import hplmm
+    return hplmm
+
+
+@pytest.mark.parametrize("seed", [1, 4])
+def test_assembly_matches_oracle(hp, seed):
+    from oracle import fem
+    p = synth.config_pores(12, 4, seed=seed)
+    p.E = np.where(p.solid > 0, np.exp(np.random.default_rng(seed).standard_normal(p.solid.shape)), 0.0)
+    sysm = hp.assemble_voxels(p)
+    A, b, mesh = fem.assemble(p)
+    assert sysm.n_nodes == mesh.n
+    assert np.array_equal(sysm.node_xyz.reshape(-1, 3), mesh.xyz)
+    Al = sysm.to_scipy()
+    d = abs(Al - A)
+    assert d.max() <= 1e-14 * abs(A).max()
+    assert np.array_equal(np.sort(Al.indices), np.sort(A.indices)) or Al.nnz >= A.nnz
+    assert np.allclose(sysm.rhs, b, rtol=0, atol=1e-15)
+
+
+def test_partition_matches_oracle(hp):
+    from oracle import fem, partition
+    for p in (synth.config_pores(16, 4, seed=1), synth.config_block(8, 8, 8, 4)):
+        A, b, mesh = fem.assemble(p)
+        P = partition.classify(p, mesh)
+        partition.contact_grids(P, mesh, p.w_zeta)
+        lp = hp.partition_from_voxels(p)
+        assert np.array_equal(lp.node_grain, P.node_grain)
+        assert lp.n_ifaces == len(P.iface_nodes)
+        for c in range(lp.n_ifaces):
+            assert np.array_equal(lp.iface(c), P.iface_nodes[c])
+            assert np.array_equal(lp.contact(c), P.contact_nodes[c])
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 6])
+def test_mortar_ids_match_oracle_exactly(hp, n):
+    from oracle import fem, mortar, partition
+    p = synth.config_pores(16, 4, seed=1)
+    A, b, mesh = fem.assemble(p)
+    P = partition.classify(p, mesh)
+    for nodes in P.iface_nodes:
+        xyz = mesh.xyz[nodes]
+        assert hp.place_mortars(xyz, n) == mortar.place_mortars(xyz, min(n, len(nodes)))
+
+
+def test_mortar_ids_random_point_sets(hp):
+    from oracle import mortar
+    rng = np.random.default_rng(5)
+    for trial in range(20):
+        pts = np.unique(rng.integers(0, 12, size=(rng.integers(5, 60), 3)), axis=0)
+        if trial % 2:
+            pts[:, 2] = 3
+            pts = np.unique(pts, axis=0)
+        for n in (2, 4, 5):
+            assert hp.place_mortars(pts, n) == mortar.place_mortars(pts, min(n, len(pts)))
+
+
+def test_invalid_inputs_raise(hp):
+    p = synth.config_pores(8, 4, seed=2)
+    bad = synth.Problem(solid=p.solid, E=p.E, nu=0.7, labels=p.labels, n_grains=p.n_grains)
+    with pytest.raises(hp.HplmmError) as e:
+        hp.assemble_voxels(bad)
+    assert e.value.code == -1
+    lab = p.labels.copy()
+    lab[p.solid > 0] = p.n_grains + 3
+    bad2 = synth.Problem(solid=p.solid, E=p.E, nu=0.3, labels=lab, n_grains=p.n_grains)
+    with pytest.raises(hp.HplmmError):
+        hp.partition_from_voxels(bad2)
+
+
+@pytest.mark.parametrize("prec", [64, 32, 16])
+def test_plan_check_bounds(hp, prec):
+    """The symbolic phase validates every launch list against its buffers."""
+    for p in (synth.config_pores(16, 4, seed=1), synth.config_block(8, 8, 8, 4),
+              synth.config_pores(12, 4, seed=3, n_mortar=4)):
+        sysm, part = hp.build_problem(p)
+        s = hp.plan_check(sysm, part, p.n_mortar, 4.0, prec)
+        assert s["n_nodes"] == sysm.n_nodes and s["tile_tasks"] > 0
+
+
+def test_plan_rejects_coupled_grains(hp):
+    p = synth.config_block(8, 8, 8, 4)
+    sysm, part = hp.build_problem(p)
+    ng = part.node_grain.copy()
+    # relabel one interface node as interior of a grain it couples to and its
+    # neighbour as interior of another grain: A then couples two interiors
+    c0 = part.iface(0)
+    ng[c0] = 0
+    bad = hp.Partition(part.n_grains, ng, part.iface_ptr[:1].copy(), part.iface_nodes[:0].copy(),
+                       part.contact_ptr, part.contact_nodes)
+    with pytest.raises(hp.HplmmError) as e:
+        hp.plan_check(sysm, bad)
+    assert e.value.code == -2
