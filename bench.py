@@ -1,0 +1,199 @@
+"""Benchmark: hPLMM set-up + FGMRES solve to a 1e-8 relative residual on the
+64^3 headline workload, one MI355X.
+
+A step is one pass of the whole hot path on one load case: the numeric
+set-up on the device (grain and contact-grid factorisations, basis, Galerkin
+coarse operator and its factor) followed by the preconditioned FGMRES solve
+from x0 = 0.  Inputs (matrix, load, partition, plans) are resident in HBM
+before the timed region.
+
+Prints one JSON line (see the repository's design notes for the fields).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GMRES time-to-1e-8 residual (setup+solve) & SpMV/apply HBM GB/s, 64^3 case"
+HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
+FP64_MFMA_TFLOPS = 78.6         # MI355X dense FP64 matrix peak
+FP32_MFMA_TFLOPS = 157.3
+KERNEL_NAMES = {
+    "tile_gemm": "tile_gemm_kernel<double>",
+    "gemv_smoother": "gemv_kernel (grain + contact smoother)",
+    "gemv_coarse": "gemv_kernel (coarse solve)",
+    "gemv_basis": "gemv_kernel (restriction / prolongation)",
+    "spmv": "spmv_kernel",
+    "diag": "diag_kernel<double>",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=64, help="voxels per side")
+    ap.add_argument("--box", type=int, default=8)
+    ap.add_argument("--mortar", type=int, default=2)
+    ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="skip the SpMV/apply bandwidth loops")
+    return ap.parse_args()
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
+        sys.exit(2)
+    import torch
+    from paper_2509_19777_amd import hplmm as hp, synth
+
+    torch.cuda.set_device(0)
+    t0 = time.perf_counter()
+    prob = synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar)
+    sysm, part = hp.build_problem(prob)
+    S = hp.Solver(sysm, part, n_mortar=a.mortar, smoother_precision=a.precision)
+    t_plan = time.perf_counter() - t0
+    sizes = S.sizes()
+    print(f"# plan done in {t_plan:.1f} s: {sizes}", file=sys.stderr, flush=True)
+
+    def step():
+        S.setup()
+        x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
+        return x, info
+
+    for _ in range(a.warmup):
+        step()
+    # timed region: every kernel class timed live with HIP events on its stream
+    S.profile(S.PROF_CLASSES)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    infos = []
+    for _ in range(a.steps):
+        x, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ms = (t2 - t1) * 1e3 / a.steps
+    prof = S.profile_results()
+    S.profile([])
+    setup_ms = S.setup_times_ms()
+    # the same steps without events, for reference
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    for _ in range(a.steps):
+        step()
+    torch.cuda.synchronize()
+    ms_unprof = (time.perf_counter() - t3) * 1e3 / a.steps
+    print(f"# step {ms:.1f} ms, iters {infos[-1]['iters']}, rel_res {infos[-1]['rel_res']:.2e}, "
+          f"setup {setup_ms}", file=sys.stderr, flush=True)
+    # roofline of the dominant kernel class over the timed region
+    kclasses = [k for k in KERNEL_NAMES if prof[k]["launches"] > 0]
+    dom = max(kclasses, key=lambda k: prof[k]["ms"])
+    d = prof[dom]
+    if dom == "tile_gemm":
+        ach = d["units"] / (d["ms"] * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / FP64_MFMA_TFLOPS, 4)}
+    else:
+        ach = d["units"] / (d["ms"] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4)}
+    roof.update({"kernel": KERNEL_NAMES[dom], "launches": d["launches"], "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 3),
+                 "units_per_launch": d["units"] / d["launches"], "traffic": traffic_for(dom)})
+    spmv_gbs = prof["spmv"]["units"] / (prof["spmv"]["ms"] * 1e-3) / 1e9 if prof["spmv"]["ms"] else None
+    apply_gbs = prof["apply"]["units"] / (prof["apply"]["ms"] * 1e-3) / 1e9 if prof["apply"]["ms"] else None
+    breakdown = {k: {"ms_per_step": round(v["ms"] / a.steps, 3), "launches_per_step": v["launches"] // a.steps}
+                 for k, v in prof.items() if v["launches"]}
+    out = {
+        "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if a.precision == 64 else f"f64+{'f32' if a.precision == 32 else 'bf16'}-smoother",
+        "data": "synthetic",
+        "config": {"workload": f"grf{a.n}^3 solid 0.6, lognormal E, {a.box}^3-voxel boxes, n={a.mortar}, FGMRES(50) to 1e-8",
+                   "dofs": 3 * sizes["n_nodes"], "subdomains": sizes["grain_mats"], "coarse_dofs": sizes["n_coarse"]},
+        "iters": infos[-1]["iters"], "rel_res_true": infos[-1]["rel_res"],
+        "setup_ms": {k: round(float(v), 3) for k, v in setup_ms.items()},
+        "solve_ms": round(float(np.mean([i["t_solve_ms"] for i in infos])), 3),
+        "ms_per_step_without_profiler_events": round(ms_unprof, 3),
+        "spmv_gbs": None if spmv_gbs is None else round(spmv_gbs, 1),
+        "apply_gbs": None if apply_gbs is None else round(apply_gbs, 1),
+        "apply_algorithmic_bytes": S.algorithmic_bytes()["apply"],
+        "spmv_algorithmic_bytes": S.algorithmic_bytes()["spmv"],
+        "kernel_breakdown": breakdown,
+        "roofline": roof,
+        "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"]),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def traffic_for(dom):
+    """HBM bytes per launch of the dominant kernel class from the committed
+    rocprofv3 counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+        rec = t.get(dom)
+        if not rec or rec.get("source_sha256") != _source_hash():
+            return None
+        return rec.get("bytes_per_launch")
+    except Exception:
+        return None
+
+
+def _source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("dense.hip", "sparse.hip"):
+        h.update(open(os.path.join(ROOT, "paper_2509_19777_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
+def cpu_baseline(a, gpu_iters, gpu_dofs):
+    """The oracle, untuned, on a bounded sample of the same workload: the lower
+    24^3 corner of the same 64^3 fields with the same 8^3 boxes, solved to
+    1e-8 (assembly excluded, as on the GPU).  Its set-up time is scaled by the
+    subdomain-count ratio and its solve time by (dof ratio) x (GPU iteration
+    count / oracle iteration count)."""
+    try:
+        import threadpoolctl
+        threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
+    except Exception:
+        threads = None
+    from oracle import fem, gmres, hplmm as oh
+    from paper_2509_19777_amd import synth
+    full = synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar)
+    sub = synth.crop(full, 24, box=a.box)
+    A, b, mesh = fem.assemble(sub)
+    t0 = time.perf_counter()
+    H = oh.HPLMM(sub, A=A, b=b, mesh=mesh, n=a.mortar)
+    t1 = time.perf_counter()
+    r = gmres.gmres(A, b, H.apply, tol=1e-8, restart=50, maxit=300, flexible=True)
+    t2 = time.perf_counter()
+    n_sub = sum(1 for g in H.part.grain_nodes if len(g))
+    full_grains = len(np.unique(full.labels[full.solid > 0]))
+    setup_ms = (t1 - t0) * 1e3 * full_grains / n_sub
+    solve_ms = (t2 - t1) * 1e3 * (gpu_dofs / A.shape[0]) * (gpu_iters / max(r.iters, 1))
+    return {"value": round(setup_ms + solve_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
+            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on the 24^3 corner crop of the same fields "
+                       f"({A.shape[0]} dofs, {n_sub} subdomains, {r.iters} iterations, set-up "
+                       f"{(t1 - t0):.2f} s, solve {(t2 - t1):.2f} s); set-up scaled x{full_grains / n_sub:.1f} "
+                       f"(subdomains), solve scaled x{gpu_dofs / A.shape[0]:.1f} (dofs) "
+                       f"x{gpu_iters / max(r.iters, 1):.2f} (iterations)"),
+            "setup_ms": round(setup_ms, 1), "solve_ms": round(solve_ms, 1)}
+
+
+if __name__ == "__main__":
+    main()

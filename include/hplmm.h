@@ -209,9 +209,22 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *            mortar block then the correction diagonal
  *   5 setup phase times in ms: double[4] = {grains, contacts, coarse, total}
  *   6 device bytes held: int64[1]
+ *   7 profiler totals (see hplmm_profile)
+ *   8 algorithmic bytes: double[2] = {one application of M^-1, one SpMV}
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);
+
+/* Built-in kernel profiler: when bit c of mask is set, HIP events are
+ * recorded on the launch stream around every launch of kernel class c:
+ *   0 set-up tile contractions, 1 diagonal-tile factorisations, 2 smoother
+ *   GEMVs, 3 coarse-solve GEMVs, 4 restriction/prolongation GEMVs, 5 fine
+ *   SpMV, 6 whole applications of M^-1.
+ * Query 7 returns double[3*7] = per class {launches, total ms, total
+ * algorithmic units} (flops for class 0, tiles for 1, bytes otherwise) over
+ * all launches since the last hplmm_profile call, which clears them.  mask = 0 turns the
+ * profiler off (no events are recorded). */
+hplmm_status hplmm_profile(hplmm_handle *h, int32_t mask);
 
 void        hplmm_destroy(hplmm_handle *h);
 const char *hplmm_last_error(void);

@@ -18,15 +18,57 @@ static void hip_check(hipError_t e, const char *what) {
     if (e != hipSuccess) fail(HPLMM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Built-in profiler: HIP events recorded on the launch stream around every
+// launch of the enabled kernel classes.
+struct ProfScope {
+    Profiler &p;
+    int32_t cls;
+    double units;
+    hipStream_t s;
+    size_t ev = 0;
+    bool on;
+    ProfScope(Handle &h, int32_t c, double u, hipStream_t st) : p(h.prof), cls(c), units(u), s(st) {
+        on = (p.mask >> c) & 1;
+        if (!on) return;
+        while (p.used + 2 > p.pool.size()) {
+            hipEvent_t e;
+            hip_check(hipEventCreate(&e), "hipEventCreate");
+            p.pool.push_back(e);
+        }
+        ev = p.used;
+        p.used += 2;
+        hip_check(hipEventRecord(p.pool[ev], s), "event");
+    }
+    ~ProfScope() {
+        if (!on) return;
+        (void)hipEventRecord(p.pool[ev + 1], s);
+        p.recs.push_back({cls, ev, units});
+    }
+};
+
 template <class T>
-static void run_program(const TaskLists &tl, T *arena, const std::vector<Launch> &prog, int32_t *flag, hipStream_t s) {
+static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vector<Launch> &prog, int32_t *flag,
+                        hipStream_t s) {
     for (const Launch &L : prog) {
         switch (L.kind) {
-            case LK_DIAG: launch_diag<T>(arena, arena, arena, tl.d_diag + L.start, L.count, flag, s); break;
-            case LK_GEMM: launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s); break;
+            case LK_DIAG: {
+                ProfScope ps(h, PC_DIAG, (double)L.count, s);
+                launch_diag<T>(arena, arena, arena, tl.d_diag + L.start, L.count, flag, s);
+                break;
+            }
+            case LK_GEMM: {
+                ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
+                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s);
+                break;
+            }
             case LK_TRANSPOSE: launch_tile_transpose<T>(arena, arena, tl.d_copy + L.start, L.count, s); break;
         }
     }
+}
+
+static void spmv(Handle &h, const double *x, const double *r, double *y, hipStream_t s) {
+    ProfScope ps(h, PC_SPMV, h.spmv_bytes + (r ? 24.0 * h.n_nodes : 0.0), s);
+    launch_spmv(h.sell, x, r, y, s);
 }
 
 static void zero(void *p, int64_t bytes, hipStream_t s) {
@@ -54,12 +96,12 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
     }
-    run_program<double>(h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
+    run_program<double>(h, h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
     if (stage < 2) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
     }
-    run_program<double>(h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
+    run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
     if (stage < 3) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -78,13 +120,13 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
         zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
-        run_program<double>(h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s);
+        run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s);
     } else {
         zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
         launch_convert_f64_f32(h.ar64 + h.c_stage_base, h.ar32 + h.cset.a_base, h.cset.region, s);
-        run_program<float>(h.tl32, h.ar32, h.cset.factor_prog, h.d_flag, s);
+        run_program<float>(h, h.tl32, h.ar32, h.cset.factor_prog, h.d_flag, s);
         if (h.smoother_precision == 16) {
             launch_convert_f32_bf16(h.ar32 + h.cset.w_base, h.arbf + h.cset.low_w_base, h.cset.region, s);
             launch_convert_f32_bf16(h.ar32 + h.cset.wt_base, h.arbf + h.cset.low_wt_base, h.cset.region, s);
@@ -97,7 +139,7 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
         launch_coarse_assemble(h.d_pairs, h.n_pairs, h.d_edges, h.d_krefs, h.cm, h.csr.val, h.ar64, h.ar64,
                                h.sset.a_base, s);
         launch_set_ones(h.d_pad_s, (int64_t)h.pad_ones_s.size(), h.ar64, s);
-        run_program<double>(h.tl64, h.ar64, h.sset.factor_prog, h.d_flag, s);
+        run_program<double>(h, h.tl64, h.ar64, h.sset.factor_prog, h.d_flag, s);
     }
     hip_check(hipEventRecord(ev[3], s), "event");
     hip_check(hipGetLastError(), "kernel launch");
@@ -125,8 +167,10 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
     h.ready = true;
 }
 
-static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, double *y, hipStream_t s) {
+static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, double *y, hipStream_t s,
+                     int32_t cls = PC_GEMV_SMOOTH) {
     if (r.count == 0) return;
+    ProfScope ps(h, cls, r.bytes, s);
     const GemvTask *t = h.d_vtasks + r.start;
     if (!smoother_low || h.smoother_precision == 64)
         launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s);
@@ -141,7 +185,11 @@ static void contact_solve(Handle &h, const double *rr, hipStream_t s) {
     launch_gather(h.d_c_slot_dof, rr, h.cx, h.cset.vec_len, s);
     const bool low = h.smoother_precision != 64;
     if (h.smoother_precision == 32) {
-        launch_gemv<float>(h.ar32, h.cx, h.ct, h.d_vtasks + h.cset.gemv_W.start, h.d_vpairs, h.cset.gemv_W.count, s);
+        {
+            ProfScope ps(h, PC_GEMV_SMOOTH, h.cset.gemv_W.bytes, s);
+            launch_gemv<float>(h.ar32, h.cx, h.ct, h.d_vtasks + h.cset.gemv_W.start, h.d_vpairs, h.cset.gemv_W.count, s);
+        }
+        ProfScope ps(h, PC_GEMV_SMOOTH, h.cset.gemv_Wt.bytes, s);
         launch_gemv<float>(h.ar32, h.ct, h.cy, h.d_vtasks + h.cset.gemv_Wt.start, h.d_vpairs, h.cset.gemv_Wt.count, s);
     } else {
         gemv_set(h, h.cset.gemv_W, low, h.cx, h.ct, s);
@@ -159,18 +207,19 @@ static void grain_solve(Handle &h, const double *rr, hipStream_t s) {
 // z1 = M_G^-1 r = P^ (P^T A P^)^-1 P^T r   (Eq. 18)
 static void coarse_apply(Handle &h, const double *r, double *z, hipStream_t s) {
     launch_gather(h.d_g_slot_dof, r, h.gx, h.gset.vec_len, s);
-    gemv_set(h, h.gemv_XT, false, h.gx, h.gc_t, s);
+    gemv_set(h, h.gemv_XT, false, h.gx, h.gc_t, s, PC_GEMV_BASIS);
     launch_coarse_rhs(h.cm, r, h.gc_t, h.sf, s);
-    gemv_set(h, h.sset.gemv_W, false, h.sf, h.st, s);
-    gemv_set(h, h.sset.gemv_Wt, false, h.st, h.su, s);
+    gemv_set(h, h.sset.gemv_W, false, h.sf, h.st, s, PC_GEMV_COARSE);
+    gemv_set(h, h.sset.gemv_Wt, false, h.st, h.su, s, PC_GEMV_COARSE);
     launch_corr_solve(h.cm, h.sf, h.su, s);
     launch_gather(h.d_gcol_upos, h.su, h.gc_u, h.gcol_len, s);
-    gemv_set(h, h.gemv_X, false, h.gc_u, h.gy, s);
+    gemv_set(h, h.gemv_X, false, h.gc_u, h.gy, s, PC_GEMV_BASIS);
     launch_prolong_nodes(h.cm, h.n_nodes, h.d_g_dof_slot, h.gy, h.su, z, s);
 }
 
 static void apply_op(Handle &h, int32_t which, const double *r, double *z, hipStream_t s) {
     const int64_t N = h.N;
+    ProfScope ps(h, PC_APPLY, which == 0 ? h.apply_bytes : 0.0, s);
     switch (which) {
         case 1:
             coarse_apply(h, r, z, s);
@@ -187,7 +236,7 @@ static void apply_op(Handle &h, int32_t which, const double *r, double *z, hipSt
             // M_CG^-1 r = M_zeta^-1 r + M_g^-1 (r - A M_zeta^-1 r)   (Eq. 25)
             contact_solve(h, r, s);
             launch_combine(N, nullptr, nullptr, nullptr, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, h.z2, s);
-            launch_spmv(h.sell, h.z2, r, h.r2, s);
+            spmv(h, h.z2, r, h.r2, s);
             grain_solve(h, h.r2, s);
             launch_combine(N, h.z2, h.d_g_dof_slot, h.gy, nullptr, nullptr, nullptr, z, s);
             return;
@@ -195,10 +244,10 @@ static void apply_op(Handle &h, int32_t which, const double *r, double *z, hipSt
         case 0: {
             // M^-1 r = M_G^-1 r + M_CG^-1 (r - A M_G^-1 r)   (Eq. 16)
             coarse_apply(h, r, h.z1, s);
-            launch_spmv(h.sell, h.z1, r, h.r1, s);
+            spmv(h, h.z1, r, h.r1, s);
             contact_solve(h, h.r1, s);
             launch_combine(N, nullptr, nullptr, nullptr, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, h.z2, s);
-            launch_spmv(h.sell, h.z2, h.r1, h.r2, s);
+            spmv(h, h.z2, h.r1, h.r2, s);
             grain_solve(h, h.r2, s);
             launch_combine(N, h.z1, h.d_g_dof_slot, h.gy, h.d_c_dof_ptr, h.d_c_dof_slot, h.cy, z, s);
             return;
@@ -247,7 +296,7 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
     }
     std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), hv(m + 2);
     while (!conv && it < limit) {
-        launch_spmv(h.sell, x, b, h.V, s);       // r0 = b - A x
+        spmv(h, x, b, h.V, s);       // r0 = b - A x
         const double beta = std::sqrt(device_dot(h, h.V, h.V, h.hbuf, s));
         rel = beta / bnorm;
         if (!std::isfinite(beta)) fail(HPLMM_E_NONFINITE, "non-finite residual");
@@ -263,7 +312,7 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
         for (; j < m && it < limit; ++j) {
             double *vj = h.V + (int64_t)j * N, *zj = h.Z + (int64_t)j * N;
             apply_op(h, 0, vj, zj, s);
-            launch_spmv(h.sell, zj, nullptr, h.w, s);
+            spmv(h, zj, nullptr, h.w, s);
             // classical Gram-Schmidt, twice
             launch_multidot(h.V, N, j + 1, h.w, N, h.part, h.kr_blocks, s);
             launch_reduce_parts(h.part, h.kr_blocks, j + 1, h.hbuf, 0, s);
@@ -310,7 +359,7 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
         }
         hip_check(hipMemcpyAsync(h.ydev, y.data(), sizeof(double) * (size_t)k, hipMemcpyHostToDevice, s), "copy y");
         launch_add_combination(h.Z, N, k, h.ydev, x, N, s);
-        launch_spmv(h.sell, x, b, h.w, s);
+        spmv(h, x, b, h.w, s);
         rel = std::sqrt(device_dot(h, h.w, h.w, h.hbuf, s)) / bnorm;
         if (fixed <= 0 && rel < rtol) conv = true;
     }
@@ -400,7 +449,7 @@ extern "C" hplmm_status hplmm_spmv(hplmm_handle *hh, const double *x, double *y,
     return guarded([&]() -> hplmm_status {
         if (!hh || !x || !y) fail(HPLMM_E_ARG, "NULL argument");
         if (x == y) fail(HPLMM_E_ARG, "x and y must not alias");
-        launch_spmv(hh->h.sell, x, nullptr, y, as_stream(stream));
+        spmv(hh->h, x, nullptr, y, as_stream(stream));
         hip_check(hipGetLastError(), "kernel launch");
         return HPLMM_OK;
     });
@@ -471,11 +520,40 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 break;
             }
             case 5: put(h.t_setup_ms, sizeof(h.t_setup_ms)); break;
+            case 7: {
+                hip_check(hipDeviceSynchronize(), "sync");
+                std::vector<double> acc(3 * PC_COUNT, 0.0);
+                for (const auto &rc : h.prof.recs) {
+                    float ms = 0.f;
+                    hip_check(hipEventElapsedTime(&ms, h.prof.pool[rc.ev], h.prof.pool[rc.ev + 1]), "elapsed");
+                    acc[(size_t)(3 * rc.cls)] += 1.0;
+                    acc[(size_t)(3 * rc.cls + 1)] += ms;
+                    acc[(size_t)(3 * rc.cls + 2)] += rc.units;
+                }
+                put(acc.data(), sizeof(double) * acc.size());
+                break;
+            }
+            case 8: {
+                const double v[2] = {h.apply_bytes, h.spmv_bytes};
+                put(v, sizeof(v));
+                break;
+            }
             case 6: put(&h.dev_bytes, sizeof(int64_t)); break;
             default: fail(HPLMM_E_ARG, "unknown query");
         }
         if (needed) *needed = (int64_t)buf.size();
         if (out && cap > 0) std::memcpy(out, buf.data(), (size_t)std::min<int64_t>(cap, (int64_t)buf.size()));
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_profile(hplmm_handle *hh, int32_t mask) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        hip_check(hipDeviceSynchronize(), "sync");
+        hh->h.prof.mask = mask;
+        hh->h.prof.recs.clear();
+        hh->h.prof.used = 0;
         return HPLMM_OK;
     });
 }

@@ -17,6 +17,31 @@ struct Launch {
     int32_t kind;
     int64_t start;
     int64_t count;
+    double flops = 0.0;   // algorithmic flops of the launch (2*64^3 per tile product)
+};
+
+// Kernel classes timed by the built-in profiler.
+enum ProfClass : int32_t {
+    PC_TILE_GEMM = 0,     // set-up tile contractions (units: flops)
+    PC_DIAG = 1,          // diagonal-tile factorisations (units: tiles)
+    PC_GEMV_SMOOTH = 2,   // smoother GEMVs, grain + contact (units: bytes)
+    PC_GEMV_COARSE = 3,   // coarse solve GEMVs (units: bytes)
+    PC_GEMV_BASIS = 4,    // restriction / prolongation GEMVs (units: bytes)
+    PC_SPMV = 5,          // fine SpMV (units: bytes)
+    PC_APPLY = 6,         // one whole preconditioner application (units: bytes)
+    PC_COUNT = 7
+};
+
+struct Profiler {
+    int32_t mask = 0;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec {
+        int32_t cls;
+        size_t ev;
+        double units;
+    };
+    std::vector<Rec> recs;
 };
 
 // Host-side task lists of one element type (uploaded once).
@@ -33,6 +58,7 @@ struct TaskLists {
 
 struct Range {
     int64_t start = 0, count = 0;
+    double bytes = 0.0;   // algorithmic bytes read and written by the launch
 };
 
 // A batch of symmetric positive definite matrices stored as packed lower
@@ -144,6 +170,8 @@ struct Handle {
 
     // timings
     double t_setup_ms[4] = {0, 0, 0, 0};
+    Profiler prof;
+    double apply_bytes = 0.0, spmv_bytes = 0.0;
 
     template <class T>
     T *dalloc(int64_t n) {
@@ -162,6 +190,7 @@ struct Handle {
         return p;
     }
     ~Handle() {
+        for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }
 };

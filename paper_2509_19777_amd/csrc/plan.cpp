@@ -131,6 +131,27 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
+// Algorithmic flops of every GEMM launch: 2*64^3 per tile product.
+void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
+    for (Launch &L : prog) {
+        if (L.kind != LK_GEMM) continue;
+        double f = 0.0;
+        for (int64_t i = L.start; i < L.start + L.count; ++i) {
+            const GemmTask &t = tl.gemm[(size_t)i];
+            f += (double)t.pair_count + ((t.flags & GF_POST) ? 1.0 : 0.0);
+        }
+        L.flops = f * 2.0 * TS * TS * TS;
+    }
+}
+
+// Algorithmic bytes of a GEMV launch: every tile and x segment read, y written.
+double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
+    double b = 0.0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i)
+        b += (double)vt[(size_t)i].pair_count * (TE * elem + TS * 8.0) + TS * 8.0;
+    return b;
+}
+
 void layout_set(DenseSet &ds) {
     ds.rel.resize(ds.n.size());
     ds.nt.resize(ds.n.size());
@@ -475,6 +496,30 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             }
         }
         h.gemv_X.count = (int64_t)h.vtasks.size() - h.gemv_X.start;
+    }
+    fill_flops(h.gset.factor_prog, h.tl64);
+    fill_flops(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
+    fill_flops(h.sset.factor_prog, h.tl64);
+    fill_flops(h.basis_prog, h.tl64);
+    {
+        const double ge = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
+        h.gset.gemv_W.bytes = gemv_bytes(h.vtasks, h.gset.gemv_W, ge);
+        h.gset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.gset.gemv_Wt, ge);
+        h.cset.gemv_W.bytes = gemv_bytes(h.vtasks, h.cset.gemv_W, ge);
+        h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
+        h.sset.gemv_W.bytes = gemv_bytes(h.vtasks, h.sset.gemv_W, 8.0);
+        h.sset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.sset.gemv_Wt, 8.0);
+        h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
+        h.gemv_X.bytes = gemv_bytes(h.vtasks, h.gemv_X, 8.0);
+        // fine SpMV: 72 B of values + 4 B of index per stored block, x read and
+        // y written once, row pointer
+        h.spmv_bytes = (double)h.nnzb * 76.0 + (double)n * (24.0 + 24.0 + 8.0);
+        // one application of M^-1 (Eq. 16): the operators above once each, two
+        // residual SpMVs (which also read r), and the vector gathers/combines
+        h.apply_bytes = h.gset.gemv_W.bytes + h.gset.gemv_Wt.bytes + h.cset.gemv_W.bytes +
+                        h.cset.gemv_Wt.bytes + h.sset.gemv_W.bytes + h.sset.gemv_Wt.bytes +
+                        h.gemv_XT.bytes + h.gemv_X.bytes + 2.0 * (h.spmv_bytes + 24.0 * n) +
+                        8.0 * (6.0 * h.N + 3.0 * (double)h.gset.vec_len + 2.0 * (double)h.cset.vec_len);
     }
     pad_ones(h.gset, h.pad_ones_g, h.gset.a_base);
     pad_ones(h.cset, h.pad_ones_c, lowp ? h.c_stage_base : h.cset.a_base);

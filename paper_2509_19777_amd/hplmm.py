@@ -63,6 +63,7 @@ EXPORTS = {
                           C.c_void_p]),
     "hplmm_query": (i32, [C.c_void_p, i32, C.c_void_p, i64, P(i64)]),
     "hplmm_destroy": (None, [C.c_void_p]),
+    "hplmm_profile": (i32, [C.c_void_p, i32]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
@@ -306,6 +307,24 @@ class Solver:
     def coarse_matrix(self):
         n = self.sizes()["n_coarse"]
         return self.query(4, np.float64).reshape(n, n)
+
+    PROF_CLASSES = ["tile_gemm", "diag", "gemv_smoother", "gemv_coarse", "gemv_basis", "spmv", "apply"]
+
+    def profile(self, classes):
+        """Enable event timing for the named kernel classes (empty: off)."""
+        mask = 0
+        for c in classes:
+            mask |= 1 << self.PROF_CLASSES.index(c)
+        _check(lib().hplmm_profile(self.h, mask))
+
+    def profile_results(self):
+        v = self.query(7, np.float64).reshape(-1, 3)
+        return {name: {"launches": int(v[i, 0]), "ms": float(v[i, 1]), "units": float(v[i, 2])}
+                for i, name in enumerate(self.PROF_CLASSES)}
+
+    def algorithmic_bytes(self):
+        v = self.query(8, np.float64)
+        return {"apply": float(v[0]), "spmv": float(v[1])}
 
     def setup_times_ms(self):
         v = self.query(5, np.float64)

@@ -188,6 +188,17 @@ def config_block(nx: int, ny: int, nz: int, box: int, E: float = 1.0, nu: float 
                    w_zeta=w_zeta, traction=tuple(traction))
 
 
+def crop(problem: Problem, n: int, box: int = None) -> Problem:
+    """The lower-corner n^3 sub-cube of a problem's fields (same plane z = 0
+    clamped), re-filtered to components touching z = 0 and re-partitioned into
+    boxes of the same size."""
+    box = box or int(round(problem.solid.shape[0] / max(1, round(problem.n_grains ** (1 / 3)))))
+    solid = problem.solid[:n, :n, :n].copy()
+    E = problem.E[:n, :n, :n].copy()
+    return _finish(solid, E, problem.nu, box, f"{problem.name}_crop{n}", n_mortar=problem.n_mortar,
+                   w_zeta=problem.w_zeta, traction=tuple(problem.traction))
+
+
 def random_vector(n: int, seed: int) -> np.ndarray:
     """Standard-normal float64 test vector."""
     return np.random.default_rng(seed).standard_normal(n)
