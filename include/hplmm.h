@@ -155,7 +155,8 @@ hplmm_status hplmm_plan(const hplmm_system *sys, const hplmm_partition *part,
  * they address, without touching a device.  sizes (may be NULL) receives
  * int64[16] = {n_nodes, nnzb, n_grains, n_ifaces, n_contacts, n_mortar_dofs,
  * n_corr, n_coarse, grain_mats, f64 arena elements, f32 arena elements, bf16
- * arena elements, f64 tile tasks, f64 tile pairs, gemv tasks, gemv pairs}. */
+ * arena elements, f64 tile tasks, coarse fronts, coarse levels, largest front
+ * (dofs)}. */
 hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_partition *part,
                               const hplmm_mortar *mortar, const hplmm_options *opt, int64_t *sizes);
 
@@ -200,7 +201,8 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
 /* Introspection for tests and benchmarks.  what:
  *   0 sizes: int64[16] = {n_nodes, nnzb, n_grains, n_ifaces, n_contacts,
  *            n_mortar_dofs, n_corr, n_coarse, grain_mats, max_grain_dofs,
- *            max_contact_dofs, sell_slices, sell_padded_blocks, 0, 0, 0}
+ *            max_contact_dofs, sell_slices, sell_padded_blocks, coarse_fronts,
+ *            coarse_levels, max_front_dofs}
  *   1 mortar node ids: int32 per interface, concatenated in interface order
  *            (nu_c entries each, local indices into the interface's nodes)
  *   2 Gaussian weights: float64, per interface row-major N_c x nu_c

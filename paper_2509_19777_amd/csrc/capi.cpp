@@ -135,11 +135,20 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
     hip_check(hipEventRecord(ev[2], s), "event");
     // ---- coarse operator P^T A P (Eq. 18) and its factorisation ----
     if (h.n_mortar > 0) {
-        zero(h.ar64 + h.sset.a_base, sizeof(double) * h.sset.region, s);
+        // assemble every front, then factor level by level from the leaves,
+        // adding each child's update matrix into its parent first
+        CoarseMF &mf = h.mf;
+        zero(h.ar64 + mf.a_base, sizeof(double) * mf.region, s);
         launch_coarse_assemble(h.d_pairs, h.n_pairs, h.d_edges, h.d_krefs, h.cm, h.csr.val, h.ar64, h.ar64,
-                               h.sset.a_base, s);
-        launch_set_ones(h.d_pad_s, (int64_t)h.pad_ones_s.size(), h.ar64, s);
-        run_program<double>(h, h.tl64, h.ar64, h.sset.factor_prog, h.d_flag, s);
+                               h.pair_vals, s);
+        launch_set_ones(mf.d_pad, (int64_t)mf.pad_ones.size(), h.ar64, s);
+        for (int32_t l = mf.n_levels - 1; l >= 0; --l) {
+            for (int sd = 0; sd < 2; ++sd) {
+                const Range r = mf.ext_rows[sd][(size_t)l];
+                launch_extend_add(mf.d_rows + r.start, r.count, mf.d_maps, h.ar64, s);
+            }
+            run_program<double>(h, h.tl64, h.ar64, mf.factor_prog[(size_t)l], h.d_flag, s);
+        }
     }
     hip_check(hipEventRecord(ev[3], s), "event");
     hip_check(hipGetLastError(), "kernel launch");
@@ -180,6 +189,36 @@ static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, dou
         launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s);
 }
 
+static void gemv64(Handle &h, Range r, const double *x, double *y, const double *base, int32_t neg,
+                   hipStream_t s) {
+    if (r.count == 0) return;
+    launch_gemv<double>(h.ar64, x, y, h.d_vtasks + r.start, h.d_vpairs, r.count, s, base, neg);
+}
+
+// u = S^-1 f for the mortar block of the coarse operator with the
+// multifrontal factor: forward sweep from the leaves (y = W11 w, then the
+// boundary part w_b -= L21 y is added into the parent), backward sweep from
+// the root (x = W11^T (y - L21^T x_b), x_b taken from the parent).
+static void coarse_solve(Handle &h, const double *f, double *u, hipStream_t s) {
+    CoarseMF &mf = h.mf;
+    if (mf.n_fronts == 0) return;
+    ProfScope ps(h, PC_GEMV_COARSE, 2.0 * mf.factor_bytes, s);
+    launch_gather(mf.d_init_map, f, mf.WV, mf.vec_len, s);
+    for (int32_t l = mf.n_levels - 1; l >= 0; --l) {
+        const Range ve = mf.vec_ext[(size_t)l];
+        launch_gather_add(mf.d_va_dst + ve.start, mf.d_va_ptr + ve.start, mf.d_va_src, ve.count, mf.WV, mf.WV, s);
+        gemv64(h, mf.fwd_W[(size_t)l], mf.WV, mf.YV, nullptr, 0, s);
+        gemv64(h, mf.fwd_L21[(size_t)l], mf.YV, mf.WV, mf.WV, 1, s);
+    }
+    for (int32_t l = 0; l < mf.n_levels; ++l) {
+        const Range cp = mf.bwd_copy[(size_t)l];
+        launch_copy_idx(mf.d_cp_dst + cp.start, mf.d_cp_src + cp.start, cp.count, mf.XV, mf.XV, s);
+        gemv64(h, mf.bwd_LT21[(size_t)l], mf.XV, mf.ZV, mf.YV, 1, s);
+        gemv64(h, mf.bwd_Wt[(size_t)l], mf.ZV, mf.XV, nullptr, 0, s);
+    }
+    launch_copy_idx(mf.d_out_dst, mf.d_out_src, (int64_t)mf.out_dst.size(), mf.XV, u, s);
+}
+
 // Contact-grid smoother (reduced precision applies to the stored operators).
 static void contact_solve(Handle &h, const double *rr, hipStream_t s) {
     launch_gather(h.d_c_slot_dof, rr, h.cx, h.cset.vec_len, s);
@@ -209,8 +248,7 @@ static void coarse_apply(Handle &h, const double *r, double *z, hipStream_t s) {
     launch_gather(h.d_g_slot_dof, r, h.gx, h.gset.vec_len, s);
     gemv_set(h, h.gemv_XT, false, h.gx, h.gc_t, s, PC_GEMV_BASIS);
     launch_coarse_rhs(h.cm, r, h.gc_t, h.sf, s);
-    gemv_set(h, h.sset.gemv_W, false, h.sf, h.st, s, PC_GEMV_COARSE);
-    gemv_set(h, h.sset.gemv_Wt, false, h.st, h.su, s, PC_GEMV_COARSE);
+    coarse_solve(h, h.sf, h.su, s);
     launch_corr_solve(h.cm, h.sf, h.su, s);
     launch_gather(h.d_gcol_upos, h.su, h.gc_u, h.gcol_len, s);
     gemv_set(h, h.gemv_X, false, h.gc_u, h.gy, s, PC_GEMV_BASIS);
@@ -415,10 +453,12 @@ extern "C" hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_pa
         Handle h;
         build_plan(h, *sys, *part, *mortar, o, nullptr, true);
         if (sizes) {
+            int64_t mx_f = 0;
+            for (int32_t t = 0; t < h.mf.n_fronts; ++t) mx_f = std::max(mx_f, h.mf.d[(size_t)t] + h.mf.u[(size_t)t]);
             int64_t v[16] = {h.n_nodes, h.nnzb, h.n_grains, h.n_ifaces, h.n_contacts, h.n_mortar, h.n_corr,
                              h.n_coarse, (int64_t)h.gset.n.size(), h.ar64_n, h.ar32_n, h.arbf_n,
-                             (int64_t)h.tl64.gemm.size(), (int64_t)h.tl64.pairs.size(), (int64_t)h.vtasks.size(),
-                             (int64_t)h.vpairs.size()};
+                             (int64_t)h.tl64.gemm.size(), h.mf.n_fronts, h.mf.n_levels, mx_f};
+            (void)h.tl64.pairs.size();
             std::memcpy(sizes, v, sizeof(v));
         }
         return HPLMM_OK;
@@ -481,9 +521,11 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 int64_t mx_g = 0, mx_c = 0;
                 for (auto v : h.gset.n) mx_g = std::max(mx_g, v);
                 for (auto v : h.cset.n) mx_c = std::max(mx_c, v);
+                int64_t mx_f = 0;
+                for (int32_t t = 0; t < h.mf.n_fronts; ++t) mx_f = std::max(mx_f, h.mf.d[(size_t)t] + h.mf.u[(size_t)t]);
                 int64_t v[16] = {h.n_nodes, h.nnzb, h.n_grains, h.n_ifaces, h.n_contacts, h.n_mortar, h.n_corr,
                                  h.n_coarse, (int64_t)h.gset.n.size(), mx_g, mx_c, h.sell.n_slices,
-                                 h.sell_padded_blocks, 0, 0, 0};
+                                 h.sell_padded_blocks, h.mf.n_fronts, h.mf.n_levels, mx_f};
                 put(v, sizeof(v));
                 break;
             }
@@ -493,29 +535,29 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
             case 4: {
                 if (!h.ready) fail(HPLMM_E_STATE, "hplmm_setup has not completed");
                 const int64_t nc = h.n_coarse;
-                // The coarse factor overwrote S; rebuild S = L L^T on the host from
-                // the lower tiles of L, and append the correction diagonal.
-                std::vector<double> Ltiles((size_t)h.sset.region);
-                if (h.sset.region)
-                    hip_check(hipMemcpy(Ltiles.data(), h.ar64 + h.sset.a_base, sizeof(double) * Ltiles.size(),
-                                        hipMemcpyDeviceToHost), "copy");
-                std::vector<double> cd((size_t)h.n_corr);
+                if (nc > 8000) fail(HPLMM_E_ARG, "coarse matrix too large to return densely");
+                std::vector<double> vals((size_t)h.n_pair_vals), cd((size_t)h.n_corr);
+                if (h.n_pair_vals)
+                    hip_check(hipMemcpy(vals.data(), h.pair_vals, sizeof(double) * vals.size(), hipMemcpyDeviceToHost), "copy");
                 if (h.n_corr)
                     hip_check(hipMemcpy(cd.data(), h.corr_d, sizeof(double) * cd.size(), hipMemcpyDeviceToHost), "copy");
-                const int64_t nm = h.n_mortar;
-                std::vector<double> L((size_t)(nm * nm), 0.0);
-                for (int64_t r = 0; r < nm; ++r)
-                    for (int64_t c = 0; c <= r; ++c)
-                        L[(size_t)(r * nm + c)] =
-                            Ltiles[(size_t)(tri_index(r / TS, c / TS) * TE + (c % TS) * TS + (r % TS))];
+                std::vector<int32_t> nu((size_t)h.n_ifaces);
+                std::vector<int64_t> mo((size_t)h.n_ifaces);
+                hip_check(hipMemcpy(nu.data(), h.cm.iface_nu, sizeof(int32_t) * nu.size(), hipMemcpyDeviceToHost), "copy");
+                hip_check(hipMemcpy(mo.data(), h.cm.iface_moff, sizeof(int64_t) * mo.size(), hipMemcpyDeviceToHost), "copy");
                 std::vector<double> S((size_t)(nc * nc), 0.0);
-                for (int64_t r = 0; r < nm; ++r)
-                    for (int64_t c = 0; c <= r; ++c) {
-                        double t = 0.0;
-                        for (int64_t k = 0; k <= c; ++k) t += L[(size_t)(r * nm + k)] * L[(size_t)(c * nm + k)];
-                        S[(size_t)(r * nc + c)] = S[(size_t)(c * nc + r)] = t;
-                    }
-                for (int64_t j = 0; j < h.n_corr; ++j) S[(size_t)((nm + j) * nc + nm + j)] = cd[(size_t)j];
+                for (const auto &pr : h.h_pairs) {
+                    const int n1 = 3 * nu[(size_t)pr.c], n2 = 3 * nu[(size_t)pr.c2];
+                    for (int i = 0; i < n1; ++i)
+                        for (int j = 0; j < n2; ++j) {
+                            const int64_t p = mo[(size_t)pr.c] + i, q = mo[(size_t)pr.c2] + j;
+                            const double v = vals[(size_t)(pr.v_off + (int64_t)i * n2 + j)];
+                            if (pr.c == pr.c2 && i < j) continue;
+                            S[(size_t)(p * nc + q)] = v;
+                            S[(size_t)(q * nc + p)] = v;
+                        }
+                }
+                for (int64_t j = 0; j < h.n_corr; ++j) S[(size_t)((h.n_mortar + j) * nc + h.n_mortar + j)] = cd[(size_t)j];
                 put(S.data(), sizeof(double) * S.size());
                 break;
             }

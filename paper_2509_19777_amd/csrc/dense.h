@@ -53,7 +53,7 @@ struct DiagTask {
     int32_t pad;
 };
 
-// Tiled matrix-vector product: y[y_off .. +64) (+)= sum_p T_p x[x_off_p .. +64)
+// Tiled matrix-vector product: y[y_off .. +64) = [base[y_off ..] +/-] sum_p T_p x[x_off_p .. +64)
 struct GemvTask {
     int64_t y_off;
     int32_t pair_start;
@@ -81,8 +81,10 @@ void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int
 template <class T>
 void launch_tile_transpose(T *arena_src, T *arena_dst, const CopyTask *tasks, int64_t ntasks,
                            hipStream_t s);
+// y = (base ? base : 0) + (neg ? -1 : 1) * sum; base may equal y.
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
-                 const GemvPair *pairs, int64_t ntasks, hipStream_t s);
+                 const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
+                 int32_t neg = 0);
 
 }  // namespace hplmm

@@ -268,8 +268,9 @@ struct Vec16<uint16_t> {   // bfloat16 storage
 
 template <class T>
 __global__ void __launch_bounds__(256) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
-                                                   double *__restrict__ y, const GemvTask *__restrict__ tasks,
-                                                   const GemvPair *__restrict__ pairs) {
+                                                   double *y, const GemvTask *__restrict__ tasks,
+                                                   const GemvPair *__restrict__ pairs, const double *base,
+                                                   int32_t neg) {
     constexpr int R = Vec16<T>::R;          // rows per lane
     constexpr int LPC = TS / R;             // lanes per column
     __shared__ double red[4 * R * TS];
@@ -298,6 +299,8 @@ __global__ void __launch_bounds__(256) gemv_kernel(const T *__restrict__ arena, 
     if (threadIdx.x < TS) {
         double s = 0.0;
         for (int q = 0; q < 4 * R; ++q) s += red[q * TS + threadIdx.x];
+        if (neg) s = -s;
+        if (base) s += base[tk.y_off + threadIdx.x];
         y[tk.y_off + threadIdx.x] = s;
     }
 }
@@ -322,9 +325,9 @@ void launch_tile_transpose(T *src, T *dst, const CopyTask *tasks, int64_t ntasks
 }
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const GemvPair *pairs,
-                 int64_t ntasks, hipStream_t s) {
+                 int64_t ntasks, hipStream_t s, const double *base, int32_t neg) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(gemv_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs);
+    hipLaunchKernelGGL(gemv_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs, base, neg);
 }
 
 template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);
@@ -334,10 +337,10 @@ template void launch_diag<float>(float *, float *, float *, const DiagTask *, in
 template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);
 template void launch_tile_transpose<float>(float *, float *, const CopyTask *, int64_t, hipStream_t);
 template void launch_gemv<double>(const double *, const double *, double *, const GemvTask *, const GemvPair *,
-                                  int64_t, hipStream_t);
+                                  int64_t, hipStream_t, const double *, int32_t);
 template void launch_gemv<float>(const float *, const double *, double *, const GemvTask *, const GemvPair *,
-                                 int64_t, hipStream_t);
+                                 int64_t, hipStream_t, const double *, int32_t);
 template void launch_gemv<uint16_t>(const uint16_t *, const double *, double *, const GemvTask *,
-                                    const GemvPair *, int64_t, hipStream_t);
+                                    const GemvPair *, int64_t, hipStream_t, const double *, int32_t);
 
 }  // namespace hplmm

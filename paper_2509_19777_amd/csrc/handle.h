@@ -73,6 +73,37 @@ struct DenseSet {
     int64_t vec_len = 0;               // local vector length (sum nt*64)
     std::vector<int64_t> voff;         // local vector offset per matrix
     int64_t low_w_base = 0, low_wt_base = 0;   // offsets in the reduced-precision arena
+    std::vector<int64_t> nt_own;       // tiles factored per matrix (partial factorisation); empty = nt
+};
+
+// Multifrontal Cholesky of the coarse operator on a nested-dissection tree of
+// interfaces.  Front t holds its own interfaces' dofs (padded to nt_d tiles)
+// followed by its boundary dofs (padded to nt_u tiles) as packed lower tiles;
+// its first nt_d tile columns are factored, leaving the update matrix in the
+// boundary block.  Level 0 is the root.
+struct CoarseMF {
+    int32_t n_fronts = 0, n_levels = 0;
+    std::vector<int32_t> parent, level, side;
+    std::vector<int64_t> d, u, nt_d, nt_u, rel, ltrel, voff;
+    std::vector<std::vector<int32_t>> own, bnd;
+    std::vector<int32_t> iface_front;
+    std::vector<int64_t> iface_pos;           // position inside its owner front
+    int64_t region = 0, lt_region = 0, vec_len = 0;
+    int64_t a_base = 0, w_base = 0, wt_base = 0, lt_base = 0;
+    std::vector<std::vector<Launch>> factor_prog;   // per level
+    std::vector<Range> ext_rows[2];                 // per level: extend-add rows (left / right children)
+    std::vector<Range> vec_ext, bwd_copy;           // per level
+    std::vector<Range> fwd_W, fwd_L21, bwd_LT21, bwd_Wt;
+    std::vector<ExtendRow> rows;
+    std::vector<int32_t> maps;
+    std::vector<int64_t> va_dst, va_ptr, va_src, cp_dst, cp_src, init_map, out_dst, out_src;
+    std::vector<int64_t> pad_ones;
+    ExtendRow *d_rows = nullptr;
+    int32_t *d_maps = nullptr;
+    int64_t *d_va_dst = nullptr, *d_va_ptr = nullptr, *d_va_src = nullptr, *d_cp_dst = nullptr, *d_cp_src = nullptr;
+    int64_t *d_init_map = nullptr, *d_out_dst = nullptr, *d_out_src = nullptr, *d_pad = nullptr;
+    double *WV = nullptr, *YV = nullptr, *ZV = nullptr, *XV = nullptr;
+    double flops = 0.0, factor_bytes = 0.0;
 };
 
 struct Handle {
@@ -130,7 +161,11 @@ struct Handle {
 
     // coarse
     DenseSet sset;
+    CoarseMF mf;
     int64_t cvec_len = 0;
+    double *pair_vals = nullptr;
+    int64_t n_pair_vals = 0;
+    std::vector<CoarsePair> h_pairs;
     CoarsePair *d_pairs = nullptr;
     int64_t n_pairs = 0;
     CoarseEdge *d_edges = nullptr;

@@ -2,6 +2,8 @@
 // W and reduction Q (Eqs. 20-21), the column layout of P (Eq. 23), contact
 // grids (Eq. 26), device data layout and all launch task lists.
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -50,58 +52,69 @@ std::vector<double> gaussian_weights(const std::vector<int32_t> &xyz, int32_t N,
 }
 
 // Append the factorisation program of a dense set: blocked right-looking
-// Cholesky (diagonal tile, panel L_ik = A_ik L_kk^-T, trailing update),
-// then the triangular inverse W = L^-1 by diagonals, then Wt = W^T tiles.
-void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id) {
+// Cholesky (diagonal tile, panel L_ik = A_ik L_kk^-T, trailing update) of the
+// first nt_own tile columns (all of them for a full factorisation; a partial
+// factorisation leaves the Schur complement in the trailing block), then the
+// triangular inverse W = L^-1 of the factored block by diagonals, then its
+// transposed tiles Wt = W^T.
+void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vector<Launch> *out = nullptr,
+                          const std::vector<int64_t> *ids = nullptr) {
+    std::vector<Launch> &prog = out ? *out : ds.factor_prog;
     const int64_t nm = (int64_t)ds.n.size();
-    int64_t maxnt = 0;
-    for (auto t : ds.nt) maxnt = std::max(maxnt, t);
+    auto own = [&](int64_t m) { return ds.nt_own.empty() ? ds.nt[m] : ds.nt_own[m]; };
+    int64_t maxk = 0;
+    for (int64_t m = 0; m < nm; ++m) maxk = std::max(maxk, own(m));
     auto A = [&](int64_t m, int64_t I, int64_t J) { return ds.a_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
-    for (int64_t k = 0; k < maxnt; ++k) {
+    auto id = [&](int64_t m) { return (int32_t)(set_id * (1 << 26) + (ids ? (*ids)[m] : m)); };
+    for (int64_t k = 0; k < maxk; ++k) {
         Launch d{LK_DIAG, (int64_t)tl.diag.size(), 0};
         for (int64_t m = 0; m < nm; ++m)
-            if (ds.nt[m] > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), (int32_t)(set_id * (1 << 26) + m), 0});
+            if (own(m) > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0});
         d.count = (int64_t)tl.diag.size() - d.start;
-        ds.factor_prog.push_back(d);
+        prog.push_back(d);
         Launch p{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nm; ++m)
+        for (int64_t m = 0; m < nm; ++m) {
+            if (own(m) <= k) continue;
             for (int64_t i = k + 1; i < ds.nt[m]; ++i) {
                 tl.gemm.push_back({A(m, i, k), -1, (int32_t)tl.pairs.size(), 1, 0, 0});
                 tl.pairs.push_back({A(m, i, k), Wt(m, k, k)});
             }
+        }
         p.count = (int64_t)tl.gemm.size() - p.start;
-        if (p.count) ds.factor_prog.push_back(p);
+        if (p.count) prog.push_back(p);
         Launch u{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nm; ++m)
+        for (int64_t m = 0; m < nm; ++m) {
+            if (own(m) <= k) continue;
             for (int64_t i = k + 1; i < ds.nt[m]; ++i)
                 for (int64_t j = k + 1; j <= i; ++j) {
                     tl.gemm.push_back({A(m, i, j), -1, (int32_t)tl.pairs.size(), 1,
                                        GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
                     tl.pairs.push_back({A(m, i, k), A(m, j, k)});
                 }
+        }
         u.count = (int64_t)tl.gemm.size() - u.start;
-        if (u.count) ds.factor_prog.push_back(u);
+        if (u.count) prog.push_back(u);
     }
     // W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj, computed for i - j = 1, 2, ...
-    for (int64_t d = 1; d < maxnt; ++d) {
+    for (int64_t d = 1; d < maxk; ++d) {
         Launch t{LK_GEMM, (int64_t)tl.gemm.size(), 0};
         for (int64_t m = 0; m < nm; ++m)
-            for (int64_t j = 0; j + d < ds.nt[m]; ++j) {
+            for (int64_t j = 0; j + d < own(m); ++j) {
                 const int64_t i = j + d;
                 tl.gemm.push_back({W(m, i, j), W(m, i, i), (int32_t)tl.pairs.size(), (int32_t)d, GF_POST | GF_NEGATE, 0});
                 for (int64_t k = j; k < i; ++k) tl.pairs.push_back({A(m, i, k), W(m, k, j)});
             }
         t.count = (int64_t)tl.gemm.size() - t.start;
-        if (t.count) ds.factor_prog.push_back(t);
+        if (t.count) prog.push_back(t);
     }
     Launch c{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
     for (int64_t m = 0; m < nm; ++m)
-        for (int64_t i = 0; i < ds.nt[m]; ++i)
+        for (int64_t i = 0; i < own(m); ++i)
             for (int64_t j = 0; j < i; ++j) tl.copy.push_back({W(m, i, j), Wt(m, i, j)});
     c.count = (int64_t)tl.copy.size() - c.start;
-    if (c.count) ds.factor_prog.push_back(c);
+    if (c.count) prog.push_back(c);
 }
 
 // Apply-time GEMV task lists y = W x and y = W^T x of a dense set.
@@ -174,6 +187,375 @@ void pad_ones(const DenseSet &ds, std::vector<int64_t> &out, int64_t a_base) {
             out.push_back(a_base + ds.rel[m] + tri_index(r / TS, r / TS) * TE + (r % TS) * TS + (r % TS));
 }
 
+
+// ---- multifrontal coarse factorisation: symbolic phase ----------------------------
+// Nested dissection of the interface graph (two interfaces are adjacent when
+// the coarse operator couples them) by recursive coordinate bisection of the
+// interface centroids; each bisection's separator is the boundary layer of
+// the side with fewer dofs.  Subsets of at most kLeafDofs dofs become leaves.
+constexpr int64_t kLeafDofs = 192;
+
+struct NDCtx {
+    const std::vector<std::vector<int32_t>> &adj;
+    const std::vector<std::array<double, 3>> &cen;
+    const std::vector<int32_t> &dofs;
+    CoarseMF &mf;
+    std::vector<int32_t> mark;
+};
+
+int32_t nd_build(NDCtx &x, std::vector<int32_t> I, int32_t par, int32_t side, int32_t depth) {
+    CoarseMF &mf = x.mf;
+    const int32_t t = mf.n_fronts++;
+    mf.parent.push_back(par);
+    mf.side.push_back(side);
+    mf.level.push_back(depth);
+    mf.own.emplace_back();
+    mf.bnd.emplace_back();
+    int64_t tot = 0;
+    for (int32_t c : I) tot += x.dofs[(size_t)c];
+    if (tot <= kLeafDofs || I.size() <= 2) {
+        std::sort(I.begin(), I.end());
+        mf.own[(size_t)t] = I;
+        return t;
+    }
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t c : I)
+        for (int d = 0; d < 3; ++d) {
+            lo[d] = std::min(lo[d], x.cen[(size_t)c][d]);
+            hi[d] = std::max(hi[d], x.cen[(size_t)c][d]);
+        }
+    int ax = 0;
+    for (int d = 1; d < 3; ++d)
+        if (hi[d] - lo[d] > hi[ax] - lo[ax]) ax = d;
+    std::stable_sort(I.begin(), I.end(), [&](int32_t a, int32_t b) {
+        if (x.cen[(size_t)a][ax] != x.cen[(size_t)b][ax]) return x.cen[(size_t)a][ax] < x.cen[(size_t)b][ax];
+        return a < b;
+    });
+    const size_t half = I.size() / 2;
+    std::vector<int32_t> L(I.begin(), I.begin() + (long)half), R(I.begin() + (long)half, I.end());
+    // mark: 1 = left, 2 = right
+    for (int32_t c : L) x.mark[(size_t)c] = 1;
+    for (int32_t c : R) x.mark[(size_t)c] = 2;
+    std::vector<int32_t> sepL, sepR;
+    int64_t dL = 0, dR = 0;
+    for (int32_t c : L)
+        for (int32_t e : x.adj[(size_t)c])
+            if (x.mark[(size_t)e] == 2) {
+                sepL.push_back(c);
+                dL += x.dofs[(size_t)c];
+                break;
+            }
+    for (int32_t c : R)
+        for (int32_t e : x.adj[(size_t)c])
+            if (x.mark[(size_t)e] == 1) {
+                sepR.push_back(c);
+                dR += x.dofs[(size_t)c];
+                break;
+            }
+    for (int32_t c : I) x.mark[(size_t)c] = 0;
+    std::vector<int32_t> sep = dL <= dR ? sepL : sepR;
+    std::vector<int32_t> &from = dL <= dR ? L : R;
+    for (int32_t c : sep) x.mark[(size_t)c] = 3;
+    from.erase(std::remove_if(from.begin(), from.end(), [&](int32_t c) { return x.mark[(size_t)c] == 3; }), from.end());
+    for (int32_t c : sep) x.mark[(size_t)c] = 0;
+    std::sort(sep.begin(), sep.end());
+    mf.own[(size_t)t] = sep;
+    if (!L.empty()) nd_build(x, L, t, 0, depth + 1);
+    if (!R.empty()) nd_build(x, R, t, 1, depth + 1);
+    return t;
+}
+
+void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
+                     const std::vector<int32_t> &iface_nu, const std::vector<int64_t> &iface_moff,
+                     std::vector<CoarsePair> &pairs, int64_t &off64) {
+    CoarseMF &mf = h.mf;
+    const int32_t nI = part.n_ifaces;
+    if (h.n_mortar == 0 || nI == 0) return;
+    std::vector<std::vector<int32_t>> adj((size_t)nI);
+    for (const auto &pr : pairs)
+        if (pr.c != pr.c2) {
+            adj[(size_t)pr.c].push_back(pr.c2);
+            adj[(size_t)pr.c2].push_back(pr.c);
+        }
+    for (auto &a : adj) {
+        std::sort(a.begin(), a.end());
+        a.erase(std::unique(a.begin(), a.end()), a.end());
+    }
+    std::vector<std::array<double, 3>> cen((size_t)nI);
+    std::vector<int32_t> dofs((size_t)nI);
+    for (int32_t c = 0; c < nI; ++c) {
+        double s[3] = {0, 0, 0};
+        const int64_t p0 = part.iface_ptr[c], p1 = part.iface_ptr[c + 1];
+        for (int64_t q = p0; q < p1; ++q)
+            for (int d = 0; d < 3; ++d) s[d] += sys.node_xyz[3 * (int64_t)part.iface_nodes[q] + d];
+        for (int d = 0; d < 3; ++d) cen[(size_t)c][d] = s[d] / (double)(p1 - p0);
+        dofs[(size_t)c] = 3 * iface_nu[(size_t)c];
+    }
+    NDCtx x{adj, cen, dofs, mf, std::vector<int32_t>((size_t)nI, 0)};
+    std::vector<int32_t> all((size_t)nI);
+    std::iota(all.begin(), all.end(), 0);
+    nd_build(x, all, -1, 0, 0);
+    const int32_t nf = mf.n_fronts;
+    // children lists
+    std::vector<std::array<int32_t, 2>> child((size_t)nf, {-1, -1});
+    for (int32_t t = 0; t < nf; ++t)
+        if (mf.parent[(size_t)t] >= 0) child[(size_t)mf.parent[(size_t)t]][(size_t)mf.side[(size_t)t]] = t;
+    // owners
+    mf.iface_front.assign((size_t)nI, -1);
+    for (int32_t t = 0; t < nf; ++t)
+        for (int32_t c : mf.own[(size_t)t]) mf.iface_front[(size_t)c] = t;
+    for (int32_t c = 0; c < nI; ++c)
+        if (mf.iface_front[(size_t)c] < 0) fail(HPLMM_E_ARG, "internal: interface missing from the dissection");
+    // symbolic boundaries in postorder (children have larger ids than parents,
+    // so decreasing ids visit every child before its parent)
+    std::vector<uint8_t> elim((size_t)nI, 0);
+    std::vector<int32_t> stamp((size_t)nI, -1);
+    for (int32_t t = nf - 1; t >= 0; --t) {
+        std::vector<int32_t> cand;
+        for (int32_t c : mf.own[(size_t)t]) stamp[(size_t)c] = t;
+        auto consider = [&](int32_t e) {
+            if (elim[(size_t)e] || stamp[(size_t)e] == t) return;
+            stamp[(size_t)e] = t;
+            cand.push_back(e);
+        };
+        for (int32_t c : mf.own[(size_t)t])
+            for (int32_t e : adj[(size_t)c]) consider(e);
+        for (int s = 0; s < 2; ++s)
+            if (child[(size_t)t][s] >= 0)
+                for (int32_t e : mf.bnd[(size_t)child[(size_t)t][s]]) consider(e);
+        std::sort(cand.begin(), cand.end());
+        mf.bnd[(size_t)t] = cand;
+        for (int32_t c : mf.own[(size_t)t]) elim[(size_t)c] = 1;
+    }
+    if (!mf.bnd[0].empty()) fail(HPLMM_E_ARG, "internal: root front has a boundary");
+    // sizes, positions, storage
+    mf.d.resize(nf);
+    mf.u.resize(nf);
+    mf.nt_d.resize(nf);
+    mf.nt_u.resize(nf);
+    mf.rel.resize(nf);
+    mf.ltrel.resize(nf);
+    mf.voff.resize(nf);
+    mf.iface_pos.assign((size_t)nI, -1);
+    std::vector<std::unordered_map<int32_t, int64_t>> pos((size_t)nf);
+    int64_t off = 0, lt = 0, vo = 0;
+    for (int32_t t = 0; t < nf; ++t) {
+        int64_t d = 0, u = 0;
+        for (int32_t c : mf.own[(size_t)t]) {
+            pos[(size_t)t][c] = d;
+            mf.iface_pos[(size_t)c] = d;
+            d += dofs[(size_t)c];
+        }
+        const int64_t ntd = ceil_tiles(d);
+        for (int32_t c : mf.bnd[(size_t)t]) {
+            pos[(size_t)t][c] = ntd * TS + u;
+            u += dofs[(size_t)c];
+        }
+        const int64_t ntu = ceil_tiles(u);
+        mf.d[(size_t)t] = d;
+        mf.u[(size_t)t] = u;
+        mf.nt_d[(size_t)t] = ntd;
+        mf.nt_u[(size_t)t] = ntu;
+        mf.rel[(size_t)t] = off;
+        off += tri_tiles(ntd + ntu) * TE;
+        mf.ltrel[(size_t)t] = lt;
+        lt += ntd * ntu * TE;
+        mf.voff[(size_t)t] = vo;
+        vo += (ntd + ntu) * TS;
+    }
+    mf.region = off;
+    mf.lt_region = lt;
+    mf.vec_len = vo;
+    mf.a_base = off64;
+    off64 += off;
+    mf.w_base = off64;
+    off64 += off;
+    mf.wt_base = off64;
+    off64 += off;
+    mf.lt_base = off64;
+    off64 += lt;
+    int32_t nl = 0;
+    for (int32_t t = 0; t < nf; ++t) nl = std::max(nl, mf.level[(size_t)t] + 1);
+    mf.n_levels = nl;
+    std::vector<std::vector<int32_t>> at((size_t)nl);
+    for (int32_t t = 0; t < nf; ++t) at[(size_t)mf.level[(size_t)t]].push_back(t);
+    // extend-add maps: child boundary dof -> parent front position
+    std::vector<int64_t> map_off((size_t)nf, -1);
+    for (int32_t t = 0; t < nf; ++t) {
+        const int32_t par = mf.parent[(size_t)t];
+        if (par < 0) continue;
+        map_off[(size_t)t] = (int64_t)mf.maps.size();
+        for (int32_t c : mf.bnd[(size_t)t]) {
+            auto it = pos[(size_t)par].find(c);
+            if (it == pos[(size_t)par].end()) fail(HPLMM_E_ARG, "internal: boundary interface missing from the parent front");
+            for (int32_t j = 0; j < dofs[(size_t)c]; ++j) mf.maps.push_back((int32_t)(it->second + j));
+        }
+    }
+    auto A = [&](int32_t t, int64_t I, int64_t J) { return mf.a_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
+    auto W = [&](int32_t t, int64_t I, int64_t J) { return mf.w_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
+    auto Wt = [&](int32_t t, int64_t I, int64_t J) { return mf.wt_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
+    auto LT = [&](int32_t t, int64_t I, int64_t J) {  // I boundary tile (0-based), J own tile
+        return mf.lt_base + mf.ltrel[(size_t)t] + (I * mf.nt_d[(size_t)t] + J) * TE;
+    };
+    mf.factor_prog.assign((size_t)nl, {});
+    for (int s = 0; s < 2; ++s) mf.ext_rows[s].assign((size_t)nl, Range{});
+    mf.vec_ext.assign((size_t)nl, Range{});
+    mf.bwd_copy.assign((size_t)nl, Range{});
+    mf.fwd_W.assign((size_t)nl, Range{});
+    mf.fwd_L21.assign((size_t)nl, Range{});
+    mf.bwd_LT21.assign((size_t)nl, Range{});
+    mf.bwd_Wt.assign((size_t)nl, Range{});
+    mf.va_ptr.push_back(0);
+    for (int32_t l = 0; l < nl; ++l) {
+        // factorisation of this level's fronts
+        DenseSet lv;
+        std::vector<int64_t> ids;
+        for (int32_t t : at[(size_t)l]) {
+            lv.n.push_back(mf.d[(size_t)t] + mf.u[(size_t)t]);
+            lv.nt.push_back(mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t]);
+            lv.nt_own.push_back(mf.nt_d[(size_t)t]);
+            lv.rel.push_back(mf.rel[(size_t)t]);
+            ids.push_back(t);
+        }
+        lv.a_base = mf.a_base;
+        lv.w_base = mf.w_base;
+        lv.wt_base = mf.wt_base;
+        build_factor_program(lv, h.tl64, 2, &mf.factor_prog[(size_t)l], &ids);
+        Launch c{LK_TRANSPOSE, (int64_t)h.tl64.copy.size(), 0};
+        for (int32_t t : at[(size_t)l])
+            for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I)
+                for (int64_t J = 0; J < mf.nt_d[(size_t)t]; ++J)
+                    h.tl64.copy.push_back({A(t, mf.nt_d[(size_t)t] + I, J), LT(t, I, J)});
+        c.count = (int64_t)h.tl64.copy.size() - c.start;
+        if (c.count) mf.factor_prog[(size_t)l].push_back(c);
+        // extend-add of the children (level l+1) into this level's fronts
+        for (int s = 0; s < 2; ++s) {
+            Range r{(int64_t)mf.rows.size(), 0};
+            for (int32_t t : at[(size_t)l]) {
+                const int32_t ch = child[(size_t)t][s];
+                if (ch < 0) continue;
+                for (int64_t rr = 0; rr < mf.u[(size_t)ch]; ++rr)
+                    mf.rows.push_back({mf.a_base + mf.rel[(size_t)ch], mf.a_base + mf.rel[(size_t)t],
+                                       map_off[(size_t)ch], (int32_t)mf.nt_d[(size_t)ch], (int32_t)rr});
+            }
+            r.count = (int64_t)mf.rows.size() - r.start;
+            mf.ext_rows[s][(size_t)l] = r;
+        }
+        // forward vector extend-add: parent slot <- sum of child boundary slots
+        {
+            Range r{(int64_t)mf.va_dst.size(), 0};
+            for (int32_t t : at[(size_t)l]) {
+                std::map<int64_t, std::vector<int64_t>> src;
+                for (int s = 0; s < 2; ++s) {
+                    const int32_t ch = child[(size_t)t][s];
+                    if (ch < 0) continue;
+                    for (int64_t rr = 0; rr < mf.u[(size_t)ch]; ++rr)
+                        src[mf.maps[(size_t)(map_off[(size_t)ch] + rr)]].push_back(
+                            mf.voff[(size_t)ch] + mf.nt_d[(size_t)ch] * TS + rr);
+                }
+                for (auto &kv : src) {
+                    mf.va_dst.push_back(mf.voff[(size_t)t] + kv.first);
+                    for (int64_t q : kv.second) mf.va_src.push_back(q);
+                    mf.va_ptr.push_back((int64_t)mf.va_src.size());
+                }
+            }
+            r.count = (int64_t)mf.va_dst.size() - r.start;
+            mf.vec_ext[(size_t)l] = r;
+        }
+        // backward: this level's boundary values from the parent front
+        {
+            Range r{(int64_t)mf.cp_dst.size(), 0};
+            for (int32_t t : at[(size_t)l]) {
+                const int32_t par = mf.parent[(size_t)t];
+                if (par < 0) continue;
+                for (int64_t rr = 0; rr < mf.u[(size_t)t]; ++rr) {
+                    mf.cp_dst.push_back(mf.voff[(size_t)t] + mf.nt_d[(size_t)t] * TS + rr);
+                    mf.cp_src.push_back(mf.voff[(size_t)par] + mf.maps[(size_t)(map_off[(size_t)t] + rr)]);
+                }
+            }
+            r.count = (int64_t)mf.cp_dst.size() - r.start;
+            mf.bwd_copy[(size_t)l] = r;
+        }
+        // GEMV lists of the solve
+        auto &vt = h.vtasks;
+        auto &vp = h.vpairs;
+        mf.fwd_W[(size_t)l].start = (int64_t)vt.size();
+        for (int32_t t : at[(size_t)l])
+            for (int64_t I = 0; I < mf.nt_d[(size_t)t]; ++I) {
+                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)(I + 1)});
+                for (int64_t J = 0; J <= I; ++J) vp.push_back({W(t, I, J), mf.voff[(size_t)t] + J * TS});
+            }
+        mf.fwd_W[(size_t)l].count = (int64_t)vt.size() - mf.fwd_W[(size_t)l].start;
+        mf.fwd_L21[(size_t)l].start = (int64_t)vt.size();
+        for (int32_t t : at[(size_t)l]) {
+            const int64_t nd = mf.nt_d[(size_t)t];
+            if (nd == 0) continue;
+            for (int64_t I = nd; I < nd + mf.nt_u[(size_t)t]; ++I) {
+                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)nd});
+                for (int64_t J = 0; J < nd; ++J) vp.push_back({A(t, I, J), mf.voff[(size_t)t] + J * TS});
+            }
+        }
+        mf.fwd_L21[(size_t)l].count = (int64_t)vt.size() - mf.fwd_L21[(size_t)l].start;
+        mf.bwd_LT21[(size_t)l].start = (int64_t)vt.size();
+        for (int32_t t : at[(size_t)l]) {
+            const int64_t nd = mf.nt_d[(size_t)t], nu = mf.nt_u[(size_t)t];
+            for (int64_t J = 0; J < nd; ++J) {
+                vt.push_back({mf.voff[(size_t)t] + J * TS, (int32_t)vp.size(), (int32_t)nu});
+                for (int64_t I = 0; I < nu; ++I) vp.push_back({LT(t, I, J), mf.voff[(size_t)t] + (nd + I) * TS});
+            }
+        }
+        mf.bwd_LT21[(size_t)l].count = (int64_t)vt.size() - mf.bwd_LT21[(size_t)l].start;
+        mf.bwd_Wt[(size_t)l].start = (int64_t)vt.size();
+        for (int32_t t : at[(size_t)l]) {
+            const int64_t nd = mf.nt_d[(size_t)t];
+            for (int64_t I = 0; I < nd; ++I) {
+                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)(nd - I)});
+                for (int64_t J = I; J < nd; ++J) vp.push_back({Wt(t, J, I), mf.voff[(size_t)t] + J * TS});
+            }
+        }
+        mf.bwd_Wt[(size_t)l].count = (int64_t)vt.size() - mf.bwd_Wt[(size_t)l].start;
+    }
+    // right-hand side in, solution out
+    mf.init_map.assign((size_t)mf.vec_len, -1);
+    for (int32_t c = 0; c < nI; ++c) {
+        const int32_t t = mf.iface_front[(size_t)c];
+        for (int32_t j = 0; j < dofs[(size_t)c]; ++j) {
+            const int64_t slot = mf.voff[(size_t)t] + mf.iface_pos[(size_t)c] + j;
+            mf.init_map[(size_t)slot] = iface_moff[(size_t)c] + j;
+            mf.out_dst.push_back(iface_moff[(size_t)c] + j);
+            mf.out_src.push_back(slot);
+        }
+    }
+    for (int32_t t = 0; t < nf; ++t)
+        for (int64_t r = mf.d[(size_t)t]; r < mf.nt_d[(size_t)t] * TS; ++r)
+            mf.pad_ones.push_back(A(t, r / TS, r / TS) + (r % TS) * TS + (r % TS));
+    // the coarse Galerkin pairs go to the front that eliminates the earlier interface
+    int64_t voffp = 0;
+    for (auto &pr : pairs) {
+        int32_t t1 = mf.iface_front[(size_t)pr.c], t2 = mf.iface_front[(size_t)pr.c2];
+        int32_t t = t1;
+        if (t1 != t2) {
+            // the deeper front must have the other interface on its boundary
+            t = mf.level[(size_t)t1] >= mf.level[(size_t)t2] ? t1 : t2;
+        }
+        auto i1 = pos[(size_t)t].find(pr.c), i2 = pos[(size_t)t].find(pr.c2);
+        if (i1 == pos[(size_t)t].end() || i2 == pos[(size_t)t].end())
+            fail(HPLMM_E_ARG, "internal: coarse coupling outside its front");
+        pr.f_off = mf.a_base + mf.rel[(size_t)t];
+        pr.pos1 = (int32_t)i1->second;
+        pr.pos2 = (int32_t)i2->second;
+        pr.v_off = voffp;
+        voffp += 9 * (int64_t)iface_nu[(size_t)pr.c] * iface_nu[(size_t)pr.c2];
+    }
+    h.n_pair_vals = voffp;
+    for (int32_t l = 0; l < nl; ++l) fill_flops(mf.factor_prog[(size_t)l], h.tl64);
+    for (int32_t l = 0; l < nl; ++l)
+        for (const Launch &L : mf.factor_prog[(size_t)l]) mf.flops += L.flops;
+    for (int32_t t = 0; t < nf; ++t) {
+        const double dd = (double)mf.d[(size_t)t], uu = (double)mf.u[(size_t)t];
+        mf.factor_bytes += 8.0 * (dd * (dd + 1) / 2 + dd * uu);
+    }
+}
 }  // namespace
 
 void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
@@ -343,8 +725,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     // ---- layout ------------------------------------------------------------------
     layout_set(h.gset);
     layout_set(h.cset);
-    if (h.n_mortar > 0) h.sset.n.push_back(h.n_mortar);
-    layout_set(h.sset);
+    layout_set(h.sset);   // the coarse operator is factored by the multifrontal plan below
     int64_t off64 = 0, off32 = 0, offbf = 0;
     auto take64 = [&](int64_t k) { const int64_t o = off64; off64 += k; return o; };
     h.gset.a_base = take64(h.gset.region);
@@ -525,7 +906,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     pad_ones(h.cset, h.pad_ones_c, lowp ? h.c_stage_base : h.cset.a_base);
     pad_ones(h.sset, h.pad_ones_s, h.sset.a_base);
     // ---- index maps ------------------------------------------------------------------
-    const int64_t s_pad = h.sset.vec_len;   // corrections follow the padded mortar block
+    const int64_t s_pad = h.n_mortar;   // corrections follow the mortar dofs
     h.cvec_len = s_pad + h.n_corr;
     std::vector<int64_t> fpos((size_t)h.n_coarse);
     for (int64_t q = 0; q < h.n_mortar; ++q) fpos[(size_t)q] = q;
@@ -658,6 +1039,15 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             pairs.push_back(pr);
         }
     }
+    // ---- multifrontal coarse factorisation plan ---------------------------------------
+    build_coarse_mf(h, sys, part, iface_nu, iface_moff, pairs, off64);
+    h.ar64_n = off64;
+    h.h_pairs = pairs;
+    {
+        // one application also runs the coarse forward and backward sweeps over
+        // the front factors (W11 and L21, then L21^T and W11^T) and their vectors
+        h.apply_bytes += 2.0 * h.mf.factor_bytes + 8.0 * 8.0 * (double)h.mf.vec_len;
+    }
     // ---- SELL-64 fine matrix ---------------------------------------------------------
     std::vector<int64_t> slice_step;
     std::vector<int32_t> scol;
@@ -757,6 +1147,49 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         chk(in(h.gset.a_base, h.gset.region, h.ar64_n), "grain region");
         chk(in(h.sset.a_base, h.sset.region, h.ar64_n), "coarse region");
         chk(h.n_coarse <= h.cvec_len, "coarse vector length");
+        {
+            const CoarseMF &mf = h.mf;
+            for (const auto &r : mf.rows) {
+                chk(in(r.child_off, 1, h.ar64_n) && in(r.parent_off, 1, h.ar64_n), "extend-add fronts");
+                chk(r.map_off >= 0 && r.map_off + r.r < (int64_t)mf.maps.size(), "extend-add map");
+            }
+            for (int32_t t = 0; t < mf.n_fronts; ++t) {
+                const int64_t nt = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
+                chk(in(mf.a_base + mf.rel[(size_t)t], tri_tiles(nt) * TE, h.ar64_n), "front tiles");
+                chk(in(mf.lt_base + mf.ltrel[(size_t)t], mf.nt_d[(size_t)t] * mf.nt_u[(size_t)t] * TE, h.ar64_n),
+                    "front L21^T tiles");
+            }
+            // every extend-add position lies inside the parent front
+            std::unordered_map<int64_t, int64_t> front_nt;
+            for (int32_t t = 0; t < mf.n_fronts; ++t)
+                front_nt[mf.a_base + mf.rel[(size_t)t]] = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
+            for (const auto &r : mf.rows) {
+                auto it = front_nt.find(r.parent_off), ic = front_nt.find(r.child_off);
+                chk(it != front_nt.end() && ic != front_nt.end(), "extend-add front offsets");
+                chk(r.nt_d * TS + r.r < ic->second * TS, "extend-add child row");
+                chk(mf.maps[(size_t)(r.map_off + r.r)] < it->second * TS, "extend-add parent position");
+            }
+            for (auto v : mf.maps) chk(v >= 0, "extend-add position");
+            for (auto v : mf.va_dst) chk(in(v, 1, mf.vec_len), "front vector extend-add");
+            for (auto v : mf.va_src) chk(in(v, 1, mf.vec_len), "front vector extend-add source");
+            for (auto v : mf.cp_dst) chk(in(v, 1, mf.vec_len), "front vector copy");
+            for (auto v : mf.cp_src) chk(in(v, 1, mf.vec_len), "front vector copy source");
+            for (auto v : mf.init_map) chk(v >= -1 && v < h.cvec_len, "front right-hand side map");
+            for (auto v : mf.out_dst) chk(in(v, 1, h.cvec_len), "coarse solution map");
+            for (auto v : mf.out_src) chk(in(v, 1, mf.vec_len), "coarse solution source");
+            for (auto v : mf.pad_ones) chk(in(v, 1, h.ar64_n), "front padding");
+            for (int32_t l = 0; l < mf.n_levels; ++l) {
+                chk_gemv(mf.fwd_W[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front forward W");
+                chk_gemv(mf.fwd_L21[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front forward L21");
+                chk_gemv(mf.bwd_LT21[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front backward L21^T");
+                chk_gemv(mf.bwd_Wt[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front backward W^T");
+            }
+            for (const auto &pr : pairs) {
+                chk(in(pr.f_off, 1, h.ar64_n), "coarse pair front");
+                chk(pr.v_off >= 0 && pr.v_off + 9 * (int64_t)iface_nu[(size_t)pr.c] * iface_nu[(size_t)pr.c2] <= h.n_pair_vals,
+                    "coarse pair values");
+            }
+        }
     }
     if (dry_run) return;
     // ---- uploads --------------------------------------------------------------------------
@@ -835,6 +1268,29 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.d_edges = h.upload(edges, s);
     h.d_krefs = h.upload(krefs, s);
     h.d_pad_s = h.upload(h.pad_ones_s, s);
+    h.pair_vals = h.dalloc<double>(h.n_pair_vals);
+    {
+        CoarseMF &mf = h.mf;
+        mf.d_rows = h.upload(mf.rows, s);
+        mf.d_maps = h.upload(mf.maps, s);
+        mf.d_va_dst = h.upload(mf.va_dst, s);
+        mf.d_va_ptr = h.upload(mf.va_ptr, s);
+        mf.d_va_src = h.upload(mf.va_src, s);
+        mf.d_cp_dst = h.upload(mf.cp_dst, s);
+        mf.d_cp_src = h.upload(mf.cp_src, s);
+        mf.d_init_map = h.upload(mf.init_map, s);
+        mf.d_out_dst = h.upload(mf.out_dst, s);
+        mf.d_out_src = h.upload(mf.out_src, s);
+        mf.d_pad = h.upload(mf.pad_ones, s);
+        mf.WV = h.dalloc<double>(mf.vec_len);
+        mf.YV = h.dalloc<double>(mf.vec_len);
+        mf.ZV = h.dalloc<double>(mf.vec_len);
+        mf.XV = h.dalloc<double>(mf.vec_len);
+        // padding slots of the front vectors are never written and must read as 0
+        for (double *v : {mf.WV, mf.YV, mf.ZV, mf.XV})
+            if (mf.vec_len > 0 && hipMemsetAsync(v, 0, sizeof(double) * (size_t)mf.vec_len, s) != hipSuccess)
+                fail(HPLMM_E_HIP, "hipMemsetAsync failed");
+    }
     // task lists
     for (TaskLists *tl : {&h.tl64, &h.tl32}) {
         tl->d_gemm = h.upload(tl->gemm, s);

@@ -108,13 +108,19 @@ struct ContactGather {
 void launch_gather_contact_blocks(const FineCsr &A, const ContactGather &c, int64_t nitems, double *arena,
                                   hipStream_t s);
 
-// Coarse Galerkin assembly: one wavefront per interface pair (c >= c').
+// Coarse Galerkin assembly: one wavefront per interface pair (c >= c').  The
+// block is written into the multifrontal front that first eliminates one of
+// the two interfaces (packed lower tiles at f_off, rows pos1.. for c and
+// pos2.. for c2), and its values are also kept at v_off in a flat list.
 struct CoarsePair {
     int32_t c, c2;
     int64_t e_start;             // edges: BSR block index, row of v in c, row of w in c2
     int32_t e_count;
     int32_t k_count;
-    int64_t k_start;             // grains sharing both: (K tile-arena offset base m, lcol of c, lcol of c2, ntc)
+    int64_t k_start;             // grains sharing both interfaces (K references)
+    int64_t f_off;               // front tile-arena offset
+    int32_t pos1, pos2;          // positions of c and c2 inside the front
+    int64_t v_off;               // offset of the (3 nu_c x 3 nu_c2) block in the value list
 };
 struct CoarseEdge {
     int64_t blk;
@@ -126,7 +132,26 @@ struct CoarseKRef {
 };
 void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const CoarseEdge *edges,
                             const CoarseKRef *krefs, const CoarseMaps &cm, const double *bsr_val,
-                            const double *karena, double *sarena, int64_t s_off, hipStream_t s);
+                            const double *karena, double *farena, double *vals, hipStream_t s);
+
+// Multifrontal extend-add of update matrices: work item = (child front tile
+// offset, child own tiles nt_d, parent front tile offset, boundary row r, map
+// offset); the child's boundary block row r (columns 0..r) is added into the
+// parent at positions map[r], map[s].
+struct ExtendRow {
+    int64_t child_off;
+    int64_t parent_off;
+    int64_t map_off;
+    int32_t nt_d;
+    int32_t r;
+};
+void launch_extend_add(const ExtendRow *rows, int64_t nrows, const int32_t *maps, double *arena, hipStream_t s);
+// dst[dst_idx[i]] += sum_{q in [ptr[i], ptr[i+1])} src[src_idx[q]], i < n
+void launch_gather_add(const int64_t *dst_idx, const int64_t *ptr, const int64_t *src_idx, int64_t n,
+                       const double *src, double *dst, hipStream_t s);
+// dst[dst_idx[i]] = src[src_idx[i]], i < n
+void launch_copy_idx(const int64_t *dst_idx, const int64_t *src_idx, int64_t n, const double *src, double *dst,
+                     hipStream_t s);
 // corr_d[j] = karena[koff[j]]
 void launch_gather_scalar(const int64_t *off, int64_t n, const double *src, double *dst, hipStream_t s);
 

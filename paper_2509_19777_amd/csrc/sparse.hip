@@ -268,18 +268,35 @@ void launch_gather_contact_blocks(const FineCsr &A, const ContactGather &c, int6
 }
 
 // ---- coarse Galerkin assembly ----------------------------------------------------
+// element (r, c) of a symmetric front stored as packed lower tiles: the value
+// goes to (max, min) by tile; inside a diagonal tile both triangles are kept
+__device__ __forceinline__ void sym_put(double *F, int64_t r, int64_t c, double v, bool mirror_same_tile, bool add) {
+    if ((r >> 6) < (c >> 6)) {
+        const int64_t t = r;
+        r = c;
+        c = t;
+    }
+    if ((r >> 6) > (c >> 6)) {
+        if (add) F[tile_elem(r, c)] += v; else F[tile_elem(r, c)] = v;
+    } else {
+        if (add) F[tile_elem(r, c)] += v; else F[tile_elem(r, c)] = v;
+        if (mirror_same_tile && r != c) {
+            if (add) F[tile_elem(c, r)] += v; else F[tile_elem(c, r)] = v;
+        }
+    }
+}
+
 __global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *__restrict__ pairs,
                                                              const CoarseEdge *__restrict__ edges,
                                                              const CoarseKRef *__restrict__ krefs, CoarseMaps cm,
                                                              const double *__restrict__ bval,
                                                              const double *__restrict__ karena,
-                                                             double *__restrict__ S) {
+                                                             double *__restrict__ F, double *__restrict__ vals) {
     const CoarsePair pr = pairs[blockIdx.x];
     const int32_t nu1 = cm.iface_nu[pr.c], nu2 = cm.iface_nu[pr.c2];
     const int n1 = 3 * nu1, n2 = 3 * nu2;
     const double *H1 = cm.H + cm.iface_hoff[pr.c];
     const double *H2 = cm.H + cm.iface_hoff[pr.c2];
-    const int64_t mo1 = cm.iface_moff[pr.c], mo2 = cm.iface_moff[pr.c2];
     for (int e = threadIdx.x; e < n1 * n2; e += 64) {
         const int i = e / n2, j = e - (e / n2) * n2;
         const int a = i / 3, gi = i % 3, bb = j / 3, di = j % 3;
@@ -300,21 +317,64 @@ __global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *_
             kk += karena[kr.koff + tile_elem(R, C)];
         }
         const double val = acc - kk;
-        const int64_t p = mo1 + i, q = mo2 + j;
-        if ((p >> 6) > (q >> 6)) {
-            S[tile_elem(p, q)] = val;
-        } else if ((p >> 6) == (q >> 6)) {
-            S[tile_elem(p, q)] = val;
-            if (pr.c != pr.c2) S[tile_elem(q, p)] = val;
-        }
+        vals[pr.v_off + e] = val;
+        // S[p][q] for p in c, q in c2; a diagonal block (c == c2) is written from
+        // its lower triangle only, so both triangles hold identical values
+        if (pr.c != pr.c2 || i >= j) sym_put(F + pr.f_off, pr.pos1 + i, pr.pos2 + j, val, true, false);
     }
 }
 void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const CoarseEdge *edges,
                             const CoarseKRef *krefs, const CoarseMaps &cm, const double *bsr_val,
-                            const double *karena, double *sarena, int64_t s_off, hipStream_t s) {
+                            const double *karena, double *farena, double *vals, hipStream_t s) {
     if (npairs <= 0) return;
     hipLaunchKernelGGL(coarse_assemble_kernel, dim3((unsigned)npairs), dim3(64), 0, s, pairs, edges, krefs, cm,
-                       bsr_val, karena, sarena + s_off);
+                       bsr_val, karena, farena, vals);
+}
+
+// ---- multifrontal extend-add ---------------------------------------------------------
+__global__ void __launch_bounds__(64) extend_add_kernel(const ExtendRow *__restrict__ rows,
+                                                        const int32_t *__restrict__ maps, double *arena) {
+    const ExtendRow w = rows[blockIdx.x];
+    const int64_t base = (int64_t)w.nt_d * TS;
+    const double *C = arena + w.child_off;
+    double *P = arena + w.parent_off;
+    const int32_t *map = maps + w.map_off;
+    const int64_t pr = map[w.r];
+    for (int s = threadIdx.x; s <= w.r; s += 64) {
+        const double v = C[tile_elem(base + w.r, base + s)];
+        // (r, s) with r >= s of the child; same-tile mirror of the parent is
+        // written explicitly unless r == s
+        sym_put(P, pr, map[s], v, true, true);
+    }
+}
+void launch_extend_add(const ExtendRow *rows, int64_t nrows, const int32_t *maps, double *arena, hipStream_t s) {
+    if (nrows <= 0) return;
+    hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)nrows), dim3(64), 0, s, rows, maps, arena);
+}
+
+__global__ void gather_add_kernel(const int64_t *__restrict__ dst_idx, const int64_t *__restrict__ ptr,
+                                  const int64_t *__restrict__ src_idx, int64_t n, const double *src, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t q = ptr[i]; q < ptr[i + 1]; ++q) s += src[src_idx[q]];
+    dst[dst_idx[i]] += s;
+}
+void launch_gather_add(const int64_t *dst_idx, const int64_t *ptr, const int64_t *src_idx, int64_t n,
+                       const double *src, double *dst, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(gather_add_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst_idx, ptr, src_idx, n, src, dst);
+}
+
+__global__ void copy_idx_kernel(const int64_t *__restrict__ dst_idx, const int64_t *__restrict__ src_idx, int64_t n,
+                                const double *src, double *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[dst_idx[i]] = src[src_idx[i]];
+}
+void launch_copy_idx(const int64_t *dst_idx, const int64_t *src_idx, int64_t n, const double *src, double *dst,
+                     hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(copy_idx_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, dst_idx, src_idx, n, src, dst);
 }
 
 __global__ void gather_scalar_kernel(const int64_t *__restrict__ off, int64_t n, const double *__restrict__ src,

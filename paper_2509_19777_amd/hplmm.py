@@ -226,7 +226,7 @@ def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64):
     out = np.zeros(16, dtype=np.int64)
     _check(lib().hplmm_plan_check(C.byref(s), C.byref(p), C.byref(m), C.byref(o), _ptr(out, i64)))
     keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
-            "grain_mats", "ar64", "ar32", "arbf", "tile_tasks", "tile_pairs", "gemv_tasks", "gemv_pairs"]
+            "grain_mats", "ar64", "ar32", "arbf", "tile_tasks", "coarse_fronts", "coarse_levels", "max_front_dofs"]
     return dict(zip(keys, (int(x) for x in out)))
 
 
@@ -300,7 +300,8 @@ class Solver:
 
     def sizes(self):
         keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
-                "grain_mats", "max_grain_dofs", "max_contact_dofs", "sell_slices", "sell_padded_blocks"]
+                "grain_mats", "max_grain_dofs", "max_contact_dofs", "sell_slices", "sell_padded_blocks",
+                "coarse_fronts", "coarse_levels", "max_front_dofs"]
         v = self.query(0, np.int64)
         return dict(zip(keys, (int(x) for x in v)))
 
