@@ -23,16 +23,17 @@ def _torch():
     return torch
 
 
-@pytest.fixture(scope="module")
-def case16():
+@pytest.fixture(scope="module", params=[2, 4])
+def case16(request):
     torch = _torch()
     from oracle import fem, hplmm as oh
     from paper_2509_19777_amd import hplmm as hp
+    n = request.param
     p = synth.config_pores(16, 4, seed=1)
     A, b, mesh = fem.assemble(p)
-    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=2)
+    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=n)
     sysm, part = hp.build_problem(p)
-    S = hp.Solver(sysm, part, n_mortar=2)
+    S = hp.Solver(sysm, part, n_mortar=n)
     S.setup()
     torch.cuda.synchronize()
     return p, A, b, mesh, H, S
