@@ -19,7 +19,9 @@ extern "C" {
  * C (op)= alpha [P] sum_p op(A_p) op(B_p) with 64x64 column-major tiles.
  * A_dev, B_dev: npairs tiles each, consecutive; C_dev: one tile; P_dev: one
  * tile or NULL; flags: bit0 transpose A, bit1 transpose B, bit2 accumulate
- * into C, bit3 alpha = -1, bit4 left-multiply by P.  precision 64 or 32 selects
+ * into C, bit3 alpha = -1, bit4 left-multiply by P (C = alpha P S), bit5
+ * right-multiply by P (C = ([C +] alpha S) P); bits 4 and 5 exclude each other
+ * and need P.  npairs may be 0 only with bit5.  precision 64 or 32 selects
  * float64 or float32 tiles (all buffers of that type). */
 hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A_dev, const void *B_dev, int32_t npairs,
                                    const void *P_dev, void *C_dev, int32_t flags, void *stream);

@@ -610,8 +610,12 @@ extern "C" void hplmm_destroy(hplmm_handle *hh) {
 extern "C" hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A, const void *B, int32_t npairs,
                                               const void *Pm, void *Cm, int32_t flags, void *stream) {
     return guarded([&]() -> hplmm_status {
-        if (!A || !B || !Cm || npairs < 1 || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
-        if ((flags & GF_POST) && !Pm) fail(HPLMM_E_ARG, "P needed");
+        if (!A || !B || !Cm || npairs < 0 || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
+        if (flags & ~(GF_TRANS_A | GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST | GF_POST_RIGHT))
+            fail(HPLMM_E_ARG, "unknown flag");
+        if ((flags & GF_POST) && (flags & GF_POST_RIGHT)) fail(HPLMM_E_ARG, "GF_POST and GF_POST_RIGHT exclude each other");
+        if ((flags & (GF_POST | GF_POST_RIGHT)) && !Pm) fail(HPLMM_E_ARG, "P needed");
+        if (npairs == 0 && !(flags & GF_POST_RIGHT)) fail(HPLMM_E_ARG, "no pairs");
         hipStream_t s = as_stream(stream);
         const size_t es = precision == 64 ? 8 : 4;
         // gather everything into one scratch arena: [A tiles][B tiles][P][C]
@@ -629,9 +633,10 @@ extern "C" hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A, 
         GemmTask *dt = nullptr;
         GemmPair *dp = nullptr;
         hip_check(hipMalloc(&dt, sizeof(t)), "hipMalloc");
-        hip_check(hipMalloc(&dp, sizeof(GemmPair) * pr.size()), "hipMalloc");
+        hip_check(hipMalloc(&dp, sizeof(GemmPair) * std::max<size_t>(1, pr.size())), "hipMalloc");
         hip_check(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s), "copy");
-        hip_check(hipMemcpyAsync(dp, pr.data(), sizeof(GemmPair) * pr.size(), hipMemcpyHostToDevice, s), "copy");
+        if (!pr.empty())
+            hip_check(hipMemcpyAsync(dp, pr.data(), sizeof(GemmPair) * pr.size(), hipMemcpyHostToDevice, s), "copy");
         if (precision == 64)
             launch_tile_gemm<double>((double *)ar, dt, dp, 1, s);
         else

@@ -26,9 +26,10 @@ enum GemmFlags : int32_t {
     GF_ACCUM = 4,       // C += alpha * sum (else C = alpha * sum)
     GF_NEGATE = 8,      // alpha = -1 (else +1)
     GF_POST = 16,       // C = alpha * P * sum, P = tile at post_off (no accumulate)
+    GF_POST_RIGHT = 32, // C = ([C +] alpha * sum) * P, P = tile at post_off
 };
 
-// One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p).
+// One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p) [* P].
 struct GemmTask {
     int64_t c_off;
     int64_t post_off;

@@ -38,36 +38,44 @@ struct Mfma<float> {
 
 constexpr int LD = TS + 1;  // padded LDS row length (elements)
 
-// Load a column-major 64x64 tile into LDS as S[k][m] = op(tile)[m][k].
+// One 64x64 tile held across the 256 threads of a work-group: thread t keeps
+// stored elements t, t + 256, ... (coalesced global loads).
 template <class T>
-__device__ __forceinline__ void load_op_tile(T *S, const T *__restrict__ src, bool trans) {
-    const int t = threadIdx.x;
-#pragma unroll 4
+struct TileRegs {
+    T v[TE / 256];
+};
+
+template <class T>
+__device__ __forceinline__ void fetch_tile(TileRegs<T> &r, const T *__restrict__ src) {
+#pragma unroll
+    for (int q = 0; q < TE / 256; ++q) r.v[q] = src[threadIdx.x + 256 * q];
+}
+
+// Stage into LDS as S[k][m] = op(tile)[m][k]  (A operand).
+template <class T>
+__device__ __forceinline__ void stage_A(T *S, const TileRegs<T> &r, bool trans) {
+#pragma unroll
     for (int q = 0; q < TE / 256; ++q) {
-        const int e = t + 256 * q;
-        const T v = src[e];
-        // element e of the stored tile is (row e%64, col e/64)
-        const int r = e & (TS - 1), c = e >> 6;
+        const int e = threadIdx.x + 256 * q;
+        const int rr = e & (TS - 1), c = e >> 6;   // stored element (row rr, col c)
         if (!trans)
-            S[c * LD + r] = v;   // op = identity: m = r, k = c
+            S[c * LD + rr] = r.v[q];
         else
-            S[r * LD + c] = v;   // op = transpose: m = c, k = r
+            S[rr * LD + c] = r.v[q];
     }
 }
 
-// Load B so that S[k][n] = op(B)[k][n].
+// Stage into LDS as S[k][n] = op(tile)[k][n]  (B operand).
 template <class T>
-__device__ __forceinline__ void load_opB_tile(T *S, const T *__restrict__ src, bool trans) {
-    const int t = threadIdx.x;
-#pragma unroll 4
+__device__ __forceinline__ void stage_B(T *S, const TileRegs<T> &r, bool trans) {
+#pragma unroll
     for (int q = 0; q < TE / 256; ++q) {
-        const int e = t + 256 * q;
-        const T v = src[e];
-        const int r = e & (TS - 1), c = e >> 6;
+        const int e = threadIdx.x + 256 * q;
+        const int rr = e & (TS - 1), c = e >> 6;
         if (!trans)
-            S[r * LD + c] = v;   // B[k=r][n=c]
+            S[rr * LD + c] = r.v[q];
         else
-            S[c * LD + r] = v;   // op(B)[k][n] = B[n][k]: n = r, k = c
+            S[c * LD + rr] = r.v[q];
     }
 }
 
@@ -89,6 +97,8 @@ __device__ __forceinline__ void mfma_tile(const T *As, const T *Bs, typename Mfm
     }
 }
 
+// Tile contraction task.  The operands of pair p+1 are fetched into registers
+// while the matrix cores work on pair p from LDS.
 template <class T>
 __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
                                                         const GemmTask *__restrict__ tasks,
@@ -102,26 +112,57 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
     const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
+    TileRegs<T> ra, rb;
+    if (tk.pair_count > 0) {
+        const GemmPair pr = pairs[tk.pair_start];
+        fetch_tile(ra, arena + pr.a_off);
+        fetch_tile(rb, arena + pr.b_off);
+    }
     for (int p = 0; p < tk.pair_count; ++p) {
-        const GemmPair pr = pairs[tk.pair_start + p];
         __syncthreads();
-        load_op_tile(As, arena + pr.a_off, ta);
-        load_opB_tile(Bs, arena + pr.b_off, tb);
+        stage_A(As, ra, ta);
+        stage_B(Bs, rb, tb);
         __syncthreads();
+        if (p + 1 < tk.pair_count) {
+            const GemmPair pr = pairs[tk.pair_start + p + 1];
+            fetch_tile(ra, arena + pr.a_off);
+            fetch_tile(rb, arena + pr.b_off);
+        }
         mfma_tile<T>(As, Bs, acc, lane, wm, wn);
     }
     const int lr = lane & 15, lq = lane >> 4;
+    const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
+    T *C = arena + tk.c_off;
+    const bool post = tk.flags & (GF_POST | GF_POST_RIGHT);
     if (tk.flags & GF_POST) {
-        // C = P * S with S the accumulated sum: S becomes the B operand.
+        // C = alpha P S with S the accumulated sum: S becomes the B operand.
         __syncthreads();
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j)
                 for (int r = 0; r < 4; ++r) {
                     const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
-                    Bs[m * LD + n] = acc[i][j][r];
+                    Bs[m * LD + n] = alpha * acc[i][j][r];
                     acc[i][j][r] = 0;
                 }
-        load_op_tile(As, arena + tk.post_off, false);
+        fetch_tile(ra, arena + tk.post_off);
+        stage_A(As, ra, false);
+        __syncthreads();
+        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+    } else if (tk.flags & GF_POST_RIGHT) {
+        // C = ([C +] alpha S) P: the bracket becomes the A operand.
+        const bool acc_c = tk.flags & GF_ACCUM;
+        __syncthreads();
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 4; ++r) {
+                    const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
+                    T v = alpha * acc[i][j][r];
+                    if (acc_c) v += C[n * TS + m];
+                    As[n * LD + m] = v;
+                    acc[i][j][r] = 0;
+                }
+        fetch_tile(rb, arena + tk.post_off);
+        stage_B(Bs, rb, false);
         __syncthreads();
         mfma_tile<T>(As, Bs, acc, lane, wm, wn);
     }
@@ -134,15 +175,14 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
                 As[n * LD + m] = acc[i][j][r];
             }
     __syncthreads();
-    T *C = arena + tk.c_off;
-    const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
-    const bool accum = (tk.flags & GF_ACCUM) && !(tk.flags & GF_POST);
+    const T a2 = post ? T(1) : alpha;
+    const bool accum = (tk.flags & GF_ACCUM) && !post;
     const int t = threadIdx.x;
 #pragma unroll 4
     for (int q = 0; q < TE / 256; ++q) {
         const int e = t + 256 * q;
         const int m = e & (TS - 1), n = e >> 6;
-        const T v = alpha * As[n * LD + m];
+        const T v = a2 * As[n * LD + m];
         C[e] = accum ? C[e] + v : v;
     }
 }

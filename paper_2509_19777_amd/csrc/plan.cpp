@@ -68,7 +68,21 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
     auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto id = [&](int64_t m) { return (int32_t)(set_id * (1 << 26) + (ids ? (*ids)[m] : m)); };
+    // Left-looking tile Cholesky: step k first subtracts the finished columns
+    // p < k from the diagonal tile, factors it, then forms the panel
+    // L_ik = (A_ik - sum_p L_ip L_kp^T) L_kk^-T in one task per tile.
     for (int64_t k = 0; k < maxk; ++k) {
+        if (k > 0) {
+            Launch u{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+            for (int64_t m = 0; m < nm; ++m) {
+                if (own(m) <= k) continue;
+                tl.gemm.push_back({A(m, k, k), -1, (int32_t)tl.pairs.size(), (int32_t)k,
+                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
+                for (int64_t p = 0; p < k; ++p) tl.pairs.push_back({A(m, k, p), A(m, k, p)});
+            }
+            u.count = (int64_t)tl.gemm.size() - u.start;
+            if (u.count) prog.push_back(u);
+        }
         Launch d{LK_DIAG, (int64_t)tl.diag.size(), 0};
         for (int64_t m = 0; m < nm; ++m)
             if (own(m) > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0});
@@ -78,20 +92,26 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         for (int64_t m = 0; m < nm; ++m) {
             if (own(m) <= k) continue;
             for (int64_t i = k + 1; i < ds.nt[m]; ++i) {
-                tl.gemm.push_back({A(m, i, k), -1, (int32_t)tl.pairs.size(), 1, 0, 0});
-                tl.pairs.push_back({A(m, i, k), Wt(m, k, k)});
+                tl.gemm.push_back({A(m, i, k), Wt(m, k, k), (int32_t)tl.pairs.size(), (int32_t)k,
+                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST_RIGHT, 0});
+                for (int64_t q = 0; q < k; ++q) tl.pairs.push_back({A(m, i, q), A(m, k, q)});
             }
         }
         p.count = (int64_t)tl.gemm.size() - p.start;
         if (p.count) prog.push_back(p);
+    }
+    // Partially factored matrices: Schur complement of the owned columns on
+    // the remaining block, S_ij = A_ij - sum_{p < own} L_ip L_jp^T.
+    {
         Launch u{LK_GEMM, (int64_t)tl.gemm.size(), 0};
         for (int64_t m = 0; m < nm; ++m) {
-            if (own(m) <= k) continue;
-            for (int64_t i = k + 1; i < ds.nt[m]; ++i)
-                for (int64_t j = k + 1; j <= i; ++j) {
-                    tl.gemm.push_back({A(m, i, j), -1, (int32_t)tl.pairs.size(), 1,
+            const int64_t o = own(m);
+            if (o == 0) continue;
+            for (int64_t i = o; i < ds.nt[m]; ++i)
+                for (int64_t j = o; j <= i; ++j) {
+                    tl.gemm.push_back({A(m, i, j), -1, (int32_t)tl.pairs.size(), (int32_t)o,
                                        GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
-                    tl.pairs.push_back({A(m, i, k), A(m, j, k)});
+                    for (int64_t q = 0; q < o; ++q) tl.pairs.push_back({A(m, i, q), A(m, j, q)});
                 }
         }
         u.count = (int64_t)tl.gemm.size() - u.start;
@@ -151,7 +171,7 @@ void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
         double f = 0.0;
         for (int64_t i = L.start; i < L.start + L.count; ++i) {
             const GemmTask &t = tl.gemm[(size_t)i];
-            f += (double)t.pair_count + ((t.flags & GF_POST) ? 1.0 : 0.0);
+            f += (double)t.pair_count + ((t.flags & (GF_POST | GF_POST_RIGHT)) ? 1.0 : 0.0);
         }
         L.flops = f * 2.0 * TS * TS * TS;
     }
@@ -1096,7 +1116,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             const int64_t an = which ? h.ar32_n : h.ar64_n;
             for (const auto &t : tl.gemm) {
                 chk(in(t.c_off, TE, an), "gemm output tile");
-                if (t.flags & GF_POST) chk(in(t.post_off, TE, an), "gemm post tile");
+                if (t.flags & (GF_POST | GF_POST_RIGHT)) chk(in(t.post_off, TE, an), "gemm post tile");
                 chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
                     "gemm pair range");
             }

@@ -337,12 +337,15 @@ def _vp(t):
     return C.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def debug_tile_gemm(A, B, C_, flags, P_=None):
+def debug_tile_gemm(A, B, C_, flags, P_=None, npairs=None):
     """One tile task on CUDA tensors: A, B (npairs, 64, 64) as column-major tiles
-    (i.e. tensors holding the transposed tile), C_ (64, 64) updated in place."""
+    (i.e. tensors holding the transposed tile), C_ (64, 64) updated in place.
+    npairs defaults to A.shape[0]; 0 is allowed with the right-factor flag."""
     prec = 64 if A.dtype == torch.float64 else 32
-    _check(lib().hplmm_debug_tile_gemm(prec, _vp(A), _vp(B), int(A.shape[0]), _vp(P_), _vp(C_), int(flags),
-                                       _stream()))
+    n = int(A.shape[0]) if npairs is None else int(npairs)
+    if n > A.shape[0] or n > B.shape[0]:
+        raise ValueError("npairs exceeds the tiles given")
+    _check(lib().hplmm_debug_tile_gemm(prec, _vp(A), _vp(B), n, _vp(P_), _vp(C_), int(flags), _stream()))
 
 
 def debug_diag(A):

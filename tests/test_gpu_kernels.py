@@ -29,26 +29,33 @@ def _untile(t):
 
 
 @pytest.mark.parametrize("prec", [64, 32])
-@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4 | 8, 2 | 4 | 8, 16 | 8, 1 | 16])
-def test_tile_gemm(prec, flags):
+@pytest.mark.parametrize("npairs", [3, 0])
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4 | 8, 2 | 4 | 8, 16 | 8, 1 | 16, 32, 2 | 4 | 8 | 32, 1 | 8 | 32])
+def test_tile_gemm(prec, flags, npairs):
     torch = _torch()
     from paper_2509_19777_amd import hplmm as hp
     dt = torch.float64 if prec == 64 else torch.float32
-    rng = np.random.default_rng(flags + prec)
-    npairs = 3
-    A = rng.standard_normal((npairs, TS, TS))
-    B = rng.standard_normal((npairs, TS, TS))
+    if npairs == 0 and not flags & 32:
+        pytest.skip("an empty sum is only meaningful with a right factor")
+    rng = np.random.default_rng(flags + prec + npairs)
+    A = rng.standard_normal((max(npairs, 1), TS, TS))
+    B = rng.standard_normal((max(npairs, 1), TS, TS))
     C0 = rng.standard_normal((TS, TS))
     Pm = rng.standard_normal((TS, TS))
-    ref = sum((A[p].T if flags & 1 else A[p]) @ (B[p].T if flags & 2 else B[p]) for p in range(npairs))
+    ref = np.zeros((TS, TS))
+    for p in range(npairs):
+        ref += (A[p].T if flags & 1 else A[p]) @ (B[p].T if flags & 2 else B[p])
     if flags & 16:
         ref = Pm @ ref
     if flags & 8:
         ref = -ref
     if (flags & 4) and not (flags & 16):
         ref = C0 + ref
+    if flags & 32:
+        ref = ref @ Pm
     Ct = _tiles(C0[None], dt)[0].contiguous()
-    hp.debug_tile_gemm(_tiles(A, dt), _tiles(B, dt), Ct, flags, _tiles(Pm[None], dt)[0].contiguous())
+    hp.debug_tile_gemm(_tiles(A, dt)[:npairs] if npairs else _tiles(A, dt), _tiles(B, dt), Ct, flags,
+                       _tiles(Pm[None], dt)[0].contiguous(), npairs=npairs)
     got = _untile(Ct)
     tol = 1e-13 if prec == 64 else 2e-5
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
