@@ -310,8 +310,8 @@ static void ensure_krylov(Handle &h, int32_t restart) {
 }
 
 static double device_dot(Handle &h, const double *a, const double *b, double *dst, hipStream_t s) {
-    launch_multidot(a, 0, 1, b, h.N, h.part, h.kr_blocks, s);
-    launch_reduce_parts(h.part, h.kr_blocks, 1, dst, 0, s);
+    launch_kr_pass(nullptr, 0, 0, nullptr, b, nullptr, h.N, a, 0, 1, h.part, s);
+    launch_kr_reduce(h.part, h.kr_blocks, 1, dst, nullptr, s);
     double v;
     hip_check(hipMemcpyAsync(&v, dst, sizeof(double), hipMemcpyDeviceToHost, s), "copy");
     hip_check(hipStreamSynchronize(s), "sync");
@@ -351,17 +351,17 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
             double *vj = h.V + (int64_t)j * N, *zj = h.Z + (int64_t)j * N;
             apply_op(h, 0, vj, zj, s);
             spmv(h, zj, nullptr, h.w, s);
-            // classical Gram-Schmidt, twice
-            launch_multidot(h.V, N, j + 1, h.w, N, h.part, h.kr_blocks, s);
-            launch_reduce_parts(h.part, h.kr_blocks, j + 1, h.hbuf, 0, s);
-            launch_subtract_combination(h.V, N, j + 1, h.hbuf, h.w, N, s);
-            launch_multidot(h.V, N, j + 1, h.w, N, h.part, h.kr_blocks, s);
-            launch_reduce_parts(h.part, h.kr_blocks, j + 1, h.h2, 0, s);
-            launch_subtract_combination(h.V, N, j + 1, h.h2, h.w, N, s);
-            launch_axpby(1.0, h.hbuf, 1.0, h.h2, h.hbuf, j + 1, s);
-            launch_multidot(h.w, 0, 1, h.w, N, h.part, h.kr_blocks, s);
-            launch_reduce_parts(h.part, h.kr_blocks, 1, h.hbuf + j + 1, 0, s);
-            launch_normalize(h.w, h.hbuf + j + 1, h.V + (int64_t)(j + 1) * N, N, s);
+            // classical Gram-Schmidt, twice: h = V^T w; w -= V h and h2 = V^T w in
+            // one pass; w -= V h2 into v_{j+1} with |w|^2 in one pass; h += h2
+            const int32_t k = j + 1;
+            double *vn = h.V + (int64_t)(j + 1) * N;
+            launch_kr_pass(nullptr, 0, 0, nullptr, h.w, nullptr, N, h.V, N, k, h.part, s);
+            launch_kr_reduce(h.part, h.kr_blocks, k, h.hbuf, nullptr, s);
+            launch_kr_pass(h.V, N, k, h.hbuf, h.w, h.w, N, h.V, N, k, h.part, s);
+            launch_kr_reduce(h.part, h.kr_blocks, k, h.h2, h.hbuf, s);
+            launch_kr_pass(h.V, N, k, h.h2, h.w, vn, N, nullptr, 0, 1, h.part, s);
+            launch_kr_reduce(h.part, h.kr_blocks, 1, h.hbuf + j + 1, nullptr, s);
+            launch_normalize(vn, h.hbuf + j + 1, vn, N, s);
             hip_check(hipMemcpyAsync(hv.data(), h.hbuf, sizeof(double) * (size_t)(j + 2), hipMemcpyDeviceToHost, s), "copy h");
             hip_check(hipStreamSynchronize(s), "step");
             hv[(size_t)j + 1] = std::sqrt(hv[(size_t)j + 1]);

@@ -161,15 +161,15 @@ void launch_convert_f32_bf16(const float *src, uint16_t *dst, int64_t n, hipStre
 void launch_convert_f64_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s);
 
 // ---- Krylov -----------------------------------------------------------------
-// part[b*k + j] = sum over block b's chunk of w . V_j  (V_j = V + j*ld), j < k
-void launch_multidot(const double *V, int64_t ld, int32_t k, const double *w, int64_t n, double *part,
-                     int32_t nblocks, hipStream_t s);
-// out[j] = sum_b part[b*k + j] (fixed order); if acc, out[j] += that
-void launch_reduce_parts(const double *part, int32_t nblocks, int32_t k, double *out, int32_t acc,
-                         hipStream_t s);
-// w -= sum_j V_j h[j]
-void launch_subtract_combination(const double *V, int64_t ld, int32_t k, const double *h, double *w,
-                                 int64_t n, hipStream_t s);
+// One pass over a Krylov basis, per block of rows (multidot_blocks(n) blocks):
+//   x = w - sum_{j < k_sub} hsub[j] V_j  (V_j = V + j*ld; written to wout when
+//   k_sub > 0 and wout is given; wout may equal w)
+//   part[b*k_dot + j] = block b's share of x . D_j (D_j = D + j*ld_d), or of
+//   x . x when D is null (then k_dot must be 1).  k_sub, k_dot <= 128.
+void launch_kr_pass(const double *V, int64_t ld, int32_t k_sub, const double *hsub, const double *w, double *wout,
+                    int64_t n, const double *D, int64_t ld_d, int32_t k_dot, double *part, hipStream_t s);
+// out[j] = sum_b part[b*k + j] in a fixed order; addto[j] += the same if given
+void launch_kr_reduce(const double *part, int32_t nblocks, int32_t k, double *out, double *addto, hipStream_t s);
 // w = w / sqrt(*nrm2) written to v; also copies sqrt(nrm2) to *nrm_out
 void launch_normalize(const double *w, const double *nrm2, double *v, int64_t n, hipStream_t s);
 // x += sum_j Z_j y[j]

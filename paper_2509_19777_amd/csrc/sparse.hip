@@ -416,68 +416,105 @@ void launch_convert_f64_bf16(const double *src, uint16_t *dst, int64_t n, hipStr
 }
 
 // ---- Krylov --------------------------------------------------------------------------
+// Every block owns KR_ROWS * 256 consecutive rows; thread t holds rows
+// base + t + 256 r.  Partial sums are reduced in a fixed order (per thread,
+// wave butterfly, waves 0..3, then blocks in the reduction kernel), so the
+// results are bitwise reproducible.
+constexpr int KR_ROWS = 4;
+constexpr int KR_MAXK = 128;
+
 int32_t multidot_blocks(int64_t n) {
-    int64_t b = (n + 4095) / 4096;
-    if (b > 512) b = 512;
-    if (b < 1) b = 1;
-    return (int32_t)b;
+    const int64_t b = (n + 256 * KR_ROWS - 1) / (256 * KR_ROWS);
+    return (int32_t)(b < 1 ? 1 : b);
 }
 
-__device__ __forceinline__ double block_sum_256(double v, double *sh) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    __syncthreads();
-    if (lane == 0) sh[w] = v;
-    __syncthreads();
-    return sh[0] + sh[1] + sh[2] + sh[3];
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
 }
 
-__global__ void __launch_bounds__(256) multidot_kernel(const double *__restrict__ V, int64_t ld, int32_t k,
-                                                       const double *__restrict__ w, int64_t n,
-                                                       double *__restrict__ part) {
+// One pass over the block's rows of a Krylov basis:
+//   x = w - sum_{j < k_sub} hsub[j] V_j      (k_sub may be 0; x written to wout if given)
+//   part[b * k_dot + j] = sum_rows x . D_j   (D_j = D + j * ld_d), or x . x when D is null
+__global__ void __launch_bounds__(256) kr_pass_kernel(const double *__restrict__ V, int64_t ld, int32_t k_sub,
+                                                      const double *__restrict__ hsub, const double *w,
+                                                      double *wout, int64_t n, const double *__restrict__ D,
+                                                      int64_t ld_d, int32_t k_dot, double *__restrict__ part) {
+    __shared__ double hs[KR_MAXK];
+    __shared__ double red[4][KR_MAXK];
+    for (int j = threadIdx.x; j < k_sub; j += 256) hs[j] = hsub[j];
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * (256 * KR_ROWS) + threadIdx.x;
+    double x[KR_ROWS];
+#pragma unroll
+    for (int r = 0; r < KR_ROWS; ++r) {
+        const int64_t i = base + 256 * r;
+        x[r] = i < n ? w[i] : 0.0;
+    }
+    if (k_sub > 0) {
+        for (int32_t j = 0; j < k_sub; ++j) {
+            const double hj = hs[j];
+            const double *v = V + j * ld;
+#pragma unroll
+            for (int r = 0; r < KR_ROWS; ++r) {
+                const int64_t i = base + 256 * r;
+                if (i < n) x[r] -= hj * v[i];
+            }
+        }
+        if (wout) {
+#pragma unroll
+            for (int r = 0; r < KR_ROWS; ++r) {
+                const int64_t i = base + 256 * r;
+                if (i < n) wout[i] = x[r];
+            }
+        }
+    }
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    for (int32_t j = 0; j < k_dot; ++j) {
+        double sj = 0.0;
+        if (D) {
+            const double *d = D + j * ld_d;
+#pragma unroll
+            for (int r = 0; r < KR_ROWS; ++r) {
+                const int64_t i = base + 256 * r;
+                if (i < n) sj += x[r] * d[i];
+            }
+        } else {
+#pragma unroll
+            for (int r = 0; r < KR_ROWS; ++r) sj += x[r] * x[r];
+        }
+        sj = wave_sum(sj);
+        if (lane == 0) red[wv][j] = sj;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < k_dot; j += 256)
+        part[(int64_t)blockIdx.x * k_dot + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+}
+void launch_kr_pass(const double *V, int64_t ld, int32_t k_sub, const double *hsub, const double *w, double *wout,
+                    int64_t n, const double *D, int64_t ld_d, int32_t k_dot, double *part, hipStream_t s) {
+    hipLaunchKernelGGL(kr_pass_kernel, dim3(multidot_blocks(n)), dim3(256), 0, s, V, ld, k_sub, hsub, w, wout, n, D,
+                       ld_d, k_dot, part);
+}
+
+// out[j] = sum_b part[b * k + j]; addto[j] += the same when addto is given.
+__global__ void __launch_bounds__(256) kr_reduce_kernel(const double *__restrict__ part, int32_t nb, int32_t k,
+                                                        double *__restrict__ out, double *__restrict__ addto) {
     __shared__ double sh[4];
-    const int64_t nb = gridDim.x;
-    const int64_t chunk = (n + nb - 1) / nb;
-    const int64_t i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-    for (int32_t j = 0; j < k; ++j) {
-        const double *v = V + j * ld;
-        double s = 0.0;
-        for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += w[i] * v[i];
-        s = block_sum_256(s, sh);
-        if (threadIdx.x == 0) part[blockIdx.x * (int64_t)k + j] = s;
+    const int j = blockIdx.x;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += 256) v += part[(int64_t)b * k + j];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double t = ((sh[0] + sh[1]) + sh[2]) + sh[3];
+        out[j] = t;
+        if (addto) addto[j] += t;
     }
 }
-void launch_multidot(const double *V, int64_t ld, int32_t k, const double *w, int64_t n, double *part,
-                     int32_t nblocks, hipStream_t s) {
-    hipLaunchKernelGGL(multidot_kernel, dim3(nblocks), dim3(256), 0, s, V, ld, k, w, n, part);
-}
-
-__global__ void reduce_parts_kernel(const double *__restrict__ part, int32_t nb, int32_t k, double *__restrict__ out,
-                                    int32_t acc) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= k) return;
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[(int64_t)b * k + j];
-    out[j] = acc ? out[j] + s : s;
-}
-void launch_reduce_parts(const double *part, int32_t nblocks, int32_t k, double *out, int32_t acc, hipStream_t s) {
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(blocks_for(k, 64)), dim3(64), 0, s, part, nblocks, k, out, acc);
-}
-
-__global__ void sub_comb_kernel(const double *__restrict__ V, int64_t ld, int32_t k, const double *__restrict__ h,
-                                double *__restrict__ w, int64_t n) {
-    __shared__ double hs[128];
-    for (int j = threadIdx.x; j < k; j += blockDim.x) hs[j] = h[j];
-    __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int32_t j = 0; j < k; ++j) s += V[j * ld + i] * hs[j];
-    w[i] -= s;
-}
-void launch_subtract_combination(const double *V, int64_t ld, int32_t k, const double *h, double *w, int64_t n,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL(sub_comb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, V, ld, k, h, w, n);
+void launch_kr_reduce(const double *part, int32_t nblocks, int32_t k, double *out, double *addto, hipStream_t s) {
+    hipLaunchKernelGGL(kr_reduce_kernel, dim3(k), dim3(256), 0, s, part, nblocks, k, out, addto);
 }
 
 __global__ void add_comb_kernel(const double *__restrict__ Z, int64_t ld, int32_t k, const double *__restrict__ y,
@@ -496,8 +533,7 @@ void launch_add_combination(const double *Z, int64_t ld, int32_t k, const double
     hipLaunchKernelGGL(add_comb_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, Z, ld, k, y, x, n);
 }
 
-__global__ void normalize_kernel(const double *__restrict__ w, const double *__restrict__ nrm2,
-                                 double *__restrict__ v, int64_t n) {
+__global__ void normalize_kernel(const double *w, const double *__restrict__ nrm2, double *v, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double nr = sqrt(nrm2[0]);
