@@ -187,64 +187,79 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     }
 }
 
+// Cholesky factor L and inverse W = L^-1 of one 64x64 tile, held in
+// registers: lane r of wave q keeps row r of L and row r of V = W^T at the
+// columns c = q + 4k (k < 16).  Step j uses the unscaled pivot d_j = L_jj:
+// the owners of column j publish it (L and V) through LDS, then every thread
+// subtracts L_rj L_cj / d_j from its trailing entries of L and V_rj L_cj / d_j
+// from V (forward elimination on the identity), and the owners scale column j
+// by 1/sqrt(d_j).  One barrier per step (double-buffered columns).
 template <class T>
 __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restrict__ Wa,
                                                    T *__restrict__ Wta,
                                                    const DiagTask *__restrict__ tasks,
                                                    int32_t *__restrict__ flag) {
-    __shared__ T L[TS * LD];   // L[r*LD + c]
-    __shared__ T W[TS * LD];
+    __shared__ T colL[2][TS];
+    __shared__ T colV[2][TS];
+    __shared__ T S[TS * LD];
     const DiagTask tk = tasks[blockIdx.x];
-    const int t = threadIdx.x;
+    const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
     T *a = A + tk.a_off;
-    for (int e = t; e < TE; e += 256) {
-        const int r = e & (TS - 1), c = e >> 6;
-        L[r * LD + c] = (r >= c) ? a[e] : T(0);
-        W[r * LD + c] = T(0);
+    T Lr[16], Vr[16];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = q + 4 * k;
+        Lr[k] = r >= c ? a[c * TS + r] : T(0);
+        Vr[k] = r == c ? T(1) : T(0);
     }
-    __syncthreads();
-    __shared__ int bad;
-    if (t == 0) bad = 0;
+    bool bad = false;
+#pragma unroll
     for (int j = 0; j < TS; ++j) {
-        if (t == 0) {
-            T d = L[j * LD + j];
-            if (!(d > T(0)) || !(d < T(INFINITY))) {
-                bad = 1;
-                d = T(1);
+        const int buf = j & 1, kj = j >> 2;
+        if (q == (j & 3)) {
+            colL[buf][r] = Lr[kj];
+            colV[buf][r] = Vr[kj];
+        }
+        __syncthreads();
+        T d = colL[buf][j];
+        if (!(d > T(0)) || !(d < T(INFINITY))) {
+            bad = true;
+            d = T(1);
+        }
+        const T inv_d = T(1) / d;
+        const T lrj = colL[buf][r] * inv_d;
+        const T vrj = colV[buf][r] * inv_d;
+#pragma unroll
+        for (int k = 0; k < 16; ++k) {
+            const int c = q + 4 * k;
+            if (c > j) {
+                const T lcj = colL[buf][c];
+                if (r >= c) Lr[k] -= lrj * lcj;
+                Vr[k] -= vrj * lcj;
             }
-            L[j * LD + j] = sqrt(d);
         }
-        __syncthreads();
-        const T piv = L[j * LD + j];
-        if (t > j && t < TS) L[t * LD + j] /= piv;
-        __syncthreads();
-        const int c = j + 1 + (t & 63);
-        if (c < TS) {
-            const T lcj = L[c * LD + j];
-            for (int i = c + (t >> 6); i < TS; i += 4) L[i * LD + c] -= L[i * LD + j] * lcj;
-        }
-        __syncthreads();
-    }
-    // W = L^-1, one column per thread
-    if (t < TS) {
-        const int j = t;
-        W[j * LD + j] = T(1) / L[j * LD + j];
-        for (int i = j + 1; i < TS; ++i) {
-            T s = 0;
-            for (int k = j; k < i; ++k) s += L[i * LD + k] * W[k * LD + j];
-            W[i * LD + j] = -s / L[i * LD + i];
+        if (q == (j & 3)) {
+            const T sc = T(1) / sqrt(d);
+            Lr[kj] *= sc;
+            Vr[kj] *= sc;
         }
     }
-    __syncthreads();
+    // L and W^T = V are stored with coalesced writes; W goes through LDS
     T *w = Wa + tk.w_off;
     T *wt = Wta + tk.wt_off;
-    for (int e = t; e < TE; e += 256) {
-        const int r = e & (TS - 1), c = e >> 6;
-        a[e] = L[r * LD + c];
-        w[e] = W[r * LD + c];
-        wt[e] = W[c * LD + r];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const int c = q + 4 * k;
+        a[c * TS + r] = Lr[k];
+        wt[c * TS + r] = Vr[k];
+        S[r * LD + c] = Vr[k];   // S(r, c) = W(c, r)
     }
-    if (t == 0 && bad) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < TE; e += 256) {
+        const int row = e & (TS - 1), col = e >> 6;
+        w[e] = S[col * LD + row];
+    }
+    if (bad && threadIdx.x == 0) {
         atomicOr(&flag[0], 1);
         atomicMin(&flag[1], tk.id);
     }
