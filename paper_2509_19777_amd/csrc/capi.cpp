@@ -189,16 +189,16 @@ static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, dou
         launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s);
 }
 
-static void gemv64(Handle &h, Range r, const double *x, double *y, const double *base, int32_t neg,
-                   hipStream_t s) {
+// Front sweeps: long rows, few tasks per launch, so 16 wavefronts per task.
+static void gemv_front(Handle &h, Range r, hipStream_t s) {
     if (r.count == 0) return;
-    launch_gemv<double>(h.ar64, x, y, h.d_vtasks + r.start, h.d_vpairs, r.count, s, base, neg);
+    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, 16);
 }
 
 // u = S^-1 f for the mortar block of the coarse operator with the
-// multifrontal factor: forward sweep from the leaves (y = W11 w, then the
-// boundary part w_b -= L21 y is added into the parent), backward sweep from
-// the root (x = W11^T (y - L21^T x_b), x_b taken from the parent).
+// multifrontal factor: forward sweep from the leaves (y = W11 w and
+// w_b -= G w with G = L21 W11, w_b then added into the parent), backward sweep
+// from the root (x = W11^T y - G^T x_b, x_b taken from the parent).
 static void coarse_solve(Handle &h, const double *f, double *u, hipStream_t s) {
     CoarseMF &mf = h.mf;
     if (mf.n_fronts == 0) return;
@@ -207,14 +207,12 @@ static void coarse_solve(Handle &h, const double *f, double *u, hipStream_t s) {
     for (int32_t l = mf.n_levels - 1; l >= 0; --l) {
         const Range ve = mf.vec_ext[(size_t)l];
         launch_gather_add(mf.d_va_dst + ve.start, mf.d_va_ptr + ve.start, mf.d_va_src, ve.count, mf.WV, mf.WV, s);
-        gemv64(h, mf.fwd_W[(size_t)l], mf.WV, mf.YV, nullptr, 0, s);
-        gemv64(h, mf.fwd_L21[(size_t)l], mf.YV, mf.WV, mf.WV, 1, s);
+        gemv_front(h, mf.fwd[(size_t)l], s);
     }
     for (int32_t l = 0; l < mf.n_levels; ++l) {
         const Range cp = mf.bwd_copy[(size_t)l];
         launch_copy_idx(mf.d_cp_dst + cp.start, mf.d_cp_src + cp.start, cp.count, mf.XV, mf.XV, s);
-        gemv64(h, mf.bwd_LT21[(size_t)l], mf.XV, mf.ZV, mf.YV, 1, s);
-        gemv64(h, mf.bwd_Wt[(size_t)l], mf.ZV, mf.XV, nullptr, 0, s);
+        gemv_front(h, mf.bwd[(size_t)l], s);
     }
     launch_copy_idx(mf.d_out_dst, mf.d_out_src, (int64_t)mf.out_dst.size(), mf.XV, u, s);
 }

@@ -54,11 +54,13 @@ struct DiagTask {
     int32_t pad;
 };
 
-// Tiled matrix-vector product: y[y_off .. +64) = [base[y_off ..] +/-] sum_p T_p x[x_off_p .. +64)
+// Tiled matrix-vector product: y[y_off .. +64) = [base[base_off .. +64) +] sum_p T_p x[x_off_p .. +64)
+// (no base term when base_off < 0)
 struct GemvTask {
     int64_t y_off;
     int32_t pair_start;
     int32_t pair_count;
+    int64_t base_off;
 };
 
 struct GemvPair {
@@ -82,10 +84,12 @@ void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int
 template <class T>
 void launch_tile_transpose(T *arena_src, T *arena_dst, const CopyTask *tasks, int64_t ntasks,
                            hipStream_t s);
-// y = (base ? base : 0) + (neg ? -1 : 1) * sum; base may equal y.
+// One work-group per task with `waves` (4 or 16) wavefronts splitting the
+// pairs; base (needed only if some task has base_off >= 0) may alias y when
+// every task reads its base at its own output rows.
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
                  const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
-                 int32_t neg = 0);
+                 int32_t waves = 4);
 
 }  // namespace hplmm

@@ -191,16 +191,63 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
 // registers: lane r of wave q keeps row r of L and row r of V = W^T at the
 // columns c = q + 4k (k < 16).  Step j uses the unscaled pivot d_j = L_jj:
 // the owners of column j publish it (L and V) through LDS, then every thread
-// subtracts L_rj L_cj / d_j from its trailing entries of L and V_rj L_cj / d_j
-// from V (forward elimination on the identity), and the owners scale column j
-// by 1/sqrt(d_j).  One barrier per step (double-buffered columns).
+// subtracts L_rj L_cj / d_j from its entries of L and V_rj L_cj / d_j from V
+// (forward elimination on the identity) for c > j, and the owners scale
+// column j by 1/sqrt(d_j).  Entries above the diagonal of L are never read
+// for the lower part and are masked on store.  One barrier per step
+// (double-buffered columns); the published column is stored permuted
+// (slot (c & 3) * 16 + c / 4) so a thread's 16 values are contiguous.  The
+// 64 steps are unrolled at compile time so every register index is static.
+template <class T, int J>
+struct DiagStep {
+    static __device__ __forceinline__ void run(T (&Lr)[16], T (&Vr)[16], T *colL, T *colV, int r, int q,
+                                               bool &bad) {
+        constexpr int kj = J >> 2, qj = J & 3;
+        T *cl = colL + (J & 1) * TS;
+        T *cv = colV + (J & 1) * TS;
+        const int pr = (r & 3) * 16 + (r >> 2);
+        if (q == qj) {
+            cl[pr] = Lr[kj];
+            cv[pr] = Vr[kj];
+        }
+        __syncthreads();
+        T d = cl[qj * 16 + kj];
+        if (!(d > T(0)) || !(d < T(INFINITY))) {
+            bad = true;
+            d = T(1);
+        }
+        const T inv_d = T(1) / d;
+        const T lrj = cl[pr] * inv_d;
+        const T vrj = cv[pr] * inv_d;
+        const T *cq = cl + q * 16;
+#pragma unroll
+        for (int k = kj; k < 16; ++k) {
+            const T lcj = cq[k];
+            if (k > kj || q > qj) {
+                Lr[k] -= lrj * lcj;
+                Vr[k] -= vrj * lcj;
+            }
+        }
+        if (q == qj) {
+            const T sc = T(1) / sqrt(d);
+            Lr[kj] *= sc;
+            Vr[kj] *= sc;
+        }
+        DiagStep<T, J + 1>::run(Lr, Vr, colL, colV, r, q, bad);
+    }
+};
+template <class T>
+struct DiagStep<T, TS> {
+    static __device__ __forceinline__ void run(T (&)[16], T (&)[16], T *, T *, int, int, bool &) {}
+};
+
 template <class T>
 __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restrict__ Wa,
                                                    T *__restrict__ Wta,
                                                    const DiagTask *__restrict__ tasks,
                                                    int32_t *__restrict__ flag) {
-    __shared__ T colL[2][TS];
-    __shared__ T colV[2][TS];
+    __shared__ T colL[2 * TS];
+    __shared__ T colV[2 * TS];
     __shared__ T S[TS * LD];
     const DiagTask tk = tasks[blockIdx.x];
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -213,44 +260,14 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
         Vr[k] = r == c ? T(1) : T(0);
     }
     bool bad = false;
-#pragma unroll
-    for (int j = 0; j < TS; ++j) {
-        const int buf = j & 1, kj = j >> 2;
-        if (q == (j & 3)) {
-            colL[buf][r] = Lr[kj];
-            colV[buf][r] = Vr[kj];
-        }
-        __syncthreads();
-        T d = colL[buf][j];
-        if (!(d > T(0)) || !(d < T(INFINITY))) {
-            bad = true;
-            d = T(1);
-        }
-        const T inv_d = T(1) / d;
-        const T lrj = colL[buf][r] * inv_d;
-        const T vrj = colV[buf][r] * inv_d;
-#pragma unroll
-        for (int k = 0; k < 16; ++k) {
-            const int c = q + 4 * k;
-            if (c > j) {
-                const T lcj = colL[buf][c];
-                if (r >= c) Lr[k] -= lrj * lcj;
-                Vr[k] -= vrj * lcj;
-            }
-        }
-        if (q == (j & 3)) {
-            const T sc = T(1) / sqrt(d);
-            Lr[kj] *= sc;
-            Vr[kj] *= sc;
-        }
-    }
+    DiagStep<T, 0>::run(Lr, Vr, colL, colV, r, q, bad);
     // L and W^T = V are stored with coalesced writes; W goes through LDS
     T *w = Wa + tk.w_off;
     T *wt = Wta + tk.wt_off;
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
         const int c = q + 4 * k;
-        a[c * TS + r] = Lr[k];
+        a[c * TS + r] = r >= c ? Lr[k] : T(0);
         wt[c * TS + r] = Vr[k];
         S[r * LD + c] = Vr[k];   // S(r, c) = W(c, r)
     }
@@ -321,21 +338,20 @@ struct Vec16<uint16_t> {   // bfloat16 storage
     }
 };
 
-template <class T>
-__global__ void __launch_bounds__(256) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
-                                                   double *y, const GemvTask *__restrict__ tasks,
-                                                   const GemvPair *__restrict__ pairs, const double *base,
-                                                   int32_t neg) {
+template <class T, int NW>
+__global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
+                                                       double *y, const GemvTask *__restrict__ tasks,
+                                                       const GemvPair *__restrict__ pairs, const double *base) {
     constexpr int R = Vec16<T>::R;          // rows per lane
     constexpr int LPC = TS / R;             // lanes per column
-    __shared__ double red[4 * R * TS];
+    __shared__ double red[NW * R * TS];
     const GemvTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int phase = lane / LPC, row0 = (lane % LPC) * R;
     double acc[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) acc[i] = 0.0;
-    for (int p = wave; p < tk.pair_count; p += 4) {
+    for (int p = wave; p < tk.pair_count; p += NW) {
         const GemvPair pr = pairs[tk.pair_start + p];
         const T *tile = arena + pr.t_off;
         const double *xs = x + pr.x_off;
@@ -353,9 +369,8 @@ __global__ void __launch_bounds__(256) gemv_kernel(const T *__restrict__ arena, 
     __syncthreads();
     if (threadIdx.x < TS) {
         double s = 0.0;
-        for (int q = 0; q < 4 * R; ++q) s += red[q * TS + threadIdx.x];
-        if (neg) s = -s;
-        if (base) s += base[tk.y_off + threadIdx.x];
+        for (int q = 0; q < NW * R; ++q) s += red[q * TS + threadIdx.x];
+        if (tk.base_off >= 0) s += base[tk.base_off + threadIdx.x];
         y[tk.y_off + threadIdx.x] = s;
     }
 }
@@ -380,9 +395,14 @@ void launch_tile_transpose(T *src, T *dst, const CopyTask *tasks, int64_t ntasks
 }
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const GemvPair *pairs,
-                 int64_t ntasks, hipStream_t s, const double *base, int32_t neg) {
+                 int64_t ntasks, hipStream_t s, const double *base, int32_t waves) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(gemv_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs, base, neg);
+    if (waves == 16)
+        hipLaunchKernelGGL((gemv_kernel<T, 16>), dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y, tasks, pairs,
+                           base);
+    else
+        hipLaunchKernelGGL((gemv_kernel<T, 4>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
+                           base);
 }
 
 template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);

@@ -89,11 +89,11 @@ struct CoarseMF {
     std::vector<int32_t> iface_front;
     std::vector<int64_t> iface_pos;           // position inside its owner front
     int64_t region = 0, lt_region = 0, vec_len = 0;
-    int64_t a_base = 0, w_base = 0, wt_base = 0, lt_base = 0;
+    int64_t a_base = 0, w_base = 0, wt_base = 0, lt_base = 0, ng_base = 0;
     std::vector<std::vector<Launch>> factor_prog;   // per level
     std::vector<Range> ext_rows[2];                 // per level: extend-add rows (left / right children)
     std::vector<Range> vec_ext, bwd_copy;           // per level
-    std::vector<Range> fwd_W, fwd_L21, bwd_LT21, bwd_Wt;
+    std::vector<Range> fwd, bwd;                    // per level: one GEMV launch each way
     std::vector<ExtendRow> rows;
     std::vector<int32_t> maps;
     std::vector<int64_t> va_dst, va_ptr, va_src, cp_dst, cp_src, init_map, out_dst, out_src;
@@ -102,7 +102,7 @@ struct CoarseMF {
     int32_t *d_maps = nullptr;
     int64_t *d_va_dst = nullptr, *d_va_ptr = nullptr, *d_va_src = nullptr, *d_cp_dst = nullptr, *d_cp_src = nullptr;
     int64_t *d_init_map = nullptr, *d_out_dst = nullptr, *d_out_src = nullptr, *d_pad = nullptr;
-    double *WV = nullptr, *YV = nullptr, *ZV = nullptr, *XV = nullptr;
+    double *V = nullptr, *WV = nullptr, *YV = nullptr, *XV = nullptr;   // WV, YV, XV are views of V
     double flops = 0.0, factor_bytes = 0.0;
 };
 
@@ -160,7 +160,6 @@ struct Handle {
     int64_t *d_c_aoff_stage = nullptr;
 
     // coarse
-    DenseSet sset;
     CoarseMF mf;
     int64_t cvec_len = 0;
     double *pair_vals = nullptr;
@@ -171,8 +170,6 @@ struct Handle {
     CoarseEdge *d_edges = nullptr;
     CoarseKRef *d_krefs = nullptr;
     int64_t *d_corr_koff = nullptr;
-    std::vector<int64_t> pad_ones_s;
-    int64_t *d_pad_s = nullptr;
 
     // arenas
     double *ar64 = nullptr;

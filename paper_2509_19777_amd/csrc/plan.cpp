@@ -148,7 +148,7 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
         for (int64_t I = 0; I < ds.nt[m]; ++I) order.push_back({m, I});
     std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) { return a.second > b.second; });
     for (auto [m, I] : order) {
-        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(I + 1)});
+        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(I + 1), -1});
         for (int64_t J = 0; J <= I; ++J) vp.push_back({w_abs + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS});
     }
     ds.gemv_W.count = (int64_t)vt.size() - ds.gemv_W.start;
@@ -157,7 +157,7 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     });
     ds.gemv_Wt.start = (int64_t)vt.size();
     for (auto [m, I] : order) {
-        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(ds.nt[m] - I)});
+        vt.push_back({ds.voff[m] + I * TS, (int32_t)vp.size(), (int32_t)(ds.nt[m] - I), -1});
         for (int64_t J = I; J < ds.nt[m]; ++J)
             vp.push_back({wt_abs + ds.rel[m] + tri_index(J, I) * TE, ds.voff[m] + J * TS});
     }
@@ -394,6 +394,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
     off64 += off;
     mf.lt_base = off64;
     off64 += lt;
+    mf.ng_base = off64;
+    off64 += lt;
     int32_t nl = 0;
     for (int32_t t = 0; t < nf; ++t) nl = std::max(nl, mf.level[(size_t)t] + 1);
     mf.n_levels = nl;
@@ -414,17 +416,21 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
     auto A = [&](int32_t t, int64_t I, int64_t J) { return mf.a_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
     auto W = [&](int32_t t, int64_t I, int64_t J) { return mf.w_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
     auto Wt = [&](int32_t t, int64_t I, int64_t J) { return mf.wt_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
-    auto LT = [&](int32_t t, int64_t I, int64_t J) {  // I boundary tile (0-based), J own tile
+    // G = L21 W11 (boundary rows times the inverse of the own block) is stored
+    // negated, NG(I, J) with I a boundary tile and J an own tile, and as
+    // per-tile transposes NGT(I, J) = NG(I, J)^T.
+    auto NGT = [&](int32_t t, int64_t I, int64_t J) {
         return mf.lt_base + mf.ltrel[(size_t)t] + (I * mf.nt_d[(size_t)t] + J) * TE;
+    };
+    auto NG = [&](int32_t t, int64_t I, int64_t J) {
+        return mf.ng_base + mf.ltrel[(size_t)t] + (I * mf.nt_d[(size_t)t] + J) * TE;
     };
     mf.factor_prog.assign((size_t)nl, {});
     for (int s = 0; s < 2; ++s) mf.ext_rows[s].assign((size_t)nl, Range{});
     mf.vec_ext.assign((size_t)nl, Range{});
     mf.bwd_copy.assign((size_t)nl, Range{});
-    mf.fwd_W.assign((size_t)nl, Range{});
-    mf.fwd_L21.assign((size_t)nl, Range{});
-    mf.bwd_LT21.assign((size_t)nl, Range{});
-    mf.bwd_Wt.assign((size_t)nl, Range{});
+    mf.fwd.assign((size_t)nl, Range{});
+    mf.bwd.assign((size_t)nl, Range{});
     mf.va_ptr.push_back(0);
     for (int32_t l = 0; l < nl; ++l) {
         // factorisation of this level's fronts
@@ -441,11 +447,22 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         lv.w_base = mf.w_base;
         lv.wt_base = mf.wt_base;
         build_factor_program(lv, h.tl64, 2, &mf.factor_prog[(size_t)l], &ids);
+        // NG = -L21 W11, then its per-tile transposes
+        Launch g{LK_GEMM, (int64_t)h.tl64.gemm.size(), 0};
+        for (int32_t t : at[(size_t)l]) {
+            const int64_t nd = mf.nt_d[(size_t)t];
+            for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I)
+                for (int64_t J = 0; J < nd; ++J) {
+                    h.tl64.gemm.push_back({NG(t, I, J), -1, (int32_t)h.tl64.pairs.size(), (int32_t)(nd - J), GF_NEGATE, 0});
+                    for (int64_t K = J; K < nd; ++K) h.tl64.pairs.push_back({A(t, nd + I, K), W(t, K, J)});
+                }
+        }
+        g.count = (int64_t)h.tl64.gemm.size() - g.start;
+        if (g.count) mf.factor_prog[(size_t)l].push_back(g);
         Launch c{LK_TRANSPOSE, (int64_t)h.tl64.copy.size(), 0};
         for (int32_t t : at[(size_t)l])
             for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I)
-                for (int64_t J = 0; J < mf.nt_d[(size_t)t]; ++J)
-                    h.tl64.copy.push_back({A(t, mf.nt_d[(size_t)t] + I, J), LT(t, I, J)});
+                for (int64_t J = 0; J < mf.nt_d[(size_t)t]; ++J) h.tl64.copy.push_back({NG(t, I, J), NGT(t, I, J)});
         c.count = (int64_t)h.tl64.copy.size() - c.start;
         if (c.count) mf.factor_prog[(size_t)l].push_back(c);
         // extend-add of the children (level l+1) into this level's fronts
@@ -499,41 +516,35 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         // GEMV lists of the solve
         auto &vt = h.vtasks;
         auto &vp = h.vpairs;
-        mf.fwd_W[(size_t)l].start = (int64_t)vt.size();
-        for (int32_t t : at[(size_t)l])
-            for (int64_t I = 0; I < mf.nt_d[(size_t)t]; ++I) {
-                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)(I + 1)});
-                for (int64_t J = 0; J <= I; ++J) vp.push_back({W(t, I, J), mf.voff[(size_t)t] + J * TS});
-            }
-        mf.fwd_W[(size_t)l].count = (int64_t)vt.size() - mf.fwd_W[(size_t)l].start;
-        mf.fwd_L21[(size_t)l].start = (int64_t)vt.size();
+        // The front vectors live in one buffer: w (right-hand side, updated in
+        // place on the boundary) at 0, y at vec_len, x at 2 vec_len.
+        const int64_t vw = 0, vy = mf.vec_len, vx = 2 * mf.vec_len;
+        // forward: y_d = W11 w_d and w_u += NG w_d in one launch
+        mf.fwd[(size_t)l].start = (int64_t)vt.size();
         for (int32_t t : at[(size_t)l]) {
-            const int64_t nd = mf.nt_d[(size_t)t];
-            if (nd == 0) continue;
-            for (int64_t I = nd; I < nd + mf.nt_u[(size_t)t]; ++I) {
-                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)nd});
-                for (int64_t J = 0; J < nd; ++J) vp.push_back({A(t, I, J), mf.voff[(size_t)t] + J * TS});
-            }
-        }
-        mf.fwd_L21[(size_t)l].count = (int64_t)vt.size() - mf.fwd_L21[(size_t)l].start;
-        mf.bwd_LT21[(size_t)l].start = (int64_t)vt.size();
-        for (int32_t t : at[(size_t)l]) {
-            const int64_t nd = mf.nt_d[(size_t)t], nu = mf.nt_u[(size_t)t];
-            for (int64_t J = 0; J < nd; ++J) {
-                vt.push_back({mf.voff[(size_t)t] + J * TS, (int32_t)vp.size(), (int32_t)nu});
-                for (int64_t I = 0; I < nu; ++I) vp.push_back({LT(t, I, J), mf.voff[(size_t)t] + (nd + I) * TS});
-            }
-        }
-        mf.bwd_LT21[(size_t)l].count = (int64_t)vt.size() - mf.bwd_LT21[(size_t)l].start;
-        mf.bwd_Wt[(size_t)l].start = (int64_t)vt.size();
-        for (int32_t t : at[(size_t)l]) {
-            const int64_t nd = mf.nt_d[(size_t)t];
+            const int64_t nd = mf.nt_d[(size_t)t], o = mf.voff[(size_t)t];
             for (int64_t I = 0; I < nd; ++I) {
-                vt.push_back({mf.voff[(size_t)t] + I * TS, (int32_t)vp.size(), (int32_t)(nd - I)});
-                for (int64_t J = I; J < nd; ++J) vp.push_back({Wt(t, J, I), mf.voff[(size_t)t] + J * TS});
+                vt.push_back({vy + o + I * TS, (int32_t)vp.size(), (int32_t)(I + 1), -1});
+                for (int64_t J = 0; J <= I; ++J) vp.push_back({W(t, I, J), vw + o + J * TS});
+            }
+            if (nd == 0) continue;
+            for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I) {
+                vt.push_back({vw + o + (nd + I) * TS, (int32_t)vp.size(), (int32_t)nd, vw + o + (nd + I) * TS});
+                for (int64_t J = 0; J < nd; ++J) vp.push_back({NG(t, I, J), vw + o + J * TS});
             }
         }
-        mf.bwd_Wt[(size_t)l].count = (int64_t)vt.size() - mf.bwd_Wt[(size_t)l].start;
+        mf.fwd[(size_t)l].count = (int64_t)vt.size() - mf.fwd[(size_t)l].start;
+        // backward: x_d = W11^T y_d + NG^T x_u in one launch
+        mf.bwd[(size_t)l].start = (int64_t)vt.size();
+        for (int32_t t : at[(size_t)l]) {
+            const int64_t nd = mf.nt_d[(size_t)t], nu = mf.nt_u[(size_t)t], o = mf.voff[(size_t)t];
+            for (int64_t I = 0; I < nd; ++I) {
+                vt.push_back({vx + o + I * TS, (int32_t)vp.size(), (int32_t)(nd - I + nu), -1});
+                for (int64_t J = I; J < nd; ++J) vp.push_back({Wt(t, J, I), vy + o + J * TS});
+                for (int64_t K = 0; K < nu; ++K) vp.push_back({NGT(t, K, I), vx + o + (nd + K) * TS});
+            }
+        }
+        mf.bwd[(size_t)l].count = (int64_t)vt.size() - mf.bwd[(size_t)l].start;
     }
     // right-hand side in, solution out
     mf.init_map.assign((size_t)mf.vec_len, -1);
@@ -745,7 +756,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     // ---- layout ------------------------------------------------------------------
     layout_set(h.gset);
     layout_set(h.cset);
-    layout_set(h.sset);   // the coarse operator is factored by the multifrontal plan below
     int64_t off64 = 0, off32 = 0, offbf = 0;
     auto take64 = [&](int64_t k) { const int64_t o = off64; off64 += k; return o; };
     h.gset.a_base = take64(h.gset.region);
@@ -791,9 +801,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.wt_base = off32;
         off32 += h.cset.region;
     }
-    h.sset.a_base = take64(h.sset.region);
-    h.sset.w_base = take64(h.sset.region);
-    h.sset.wt_base = take64(h.sset.region);
     // reduced-precision smoother copies
     if (h.smoother_precision == 32) {
         h.gset.low_w_base = off32;
@@ -822,7 +829,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         build_factor_program(h.cset, h.tl64, 1);
     else
         build_factor_program(h.cset, h.tl32, 1);
-    build_factor_program(h.sset, h.tl64, 2);
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
     {
         auto &tl = h.tl64;
@@ -877,12 +883,11 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         const int64_t cw = h.smoother_precision == 16 ? h.cset.low_w_base : h.cset.w_base;
         const int64_t cwt = h.smoother_precision == 16 ? h.cset.low_wt_base : h.cset.wt_base;
         build_smoother_gemv(h.cset, h.vtasks, h.vpairs, cw, cwt);
-        build_smoother_gemv(h.sset, h.vtasks, h.vpairs, h.sset.w_base, h.sset.wt_base);
         // restriction t = X^T x, prolongation z = X u
         h.gemv_XT.start = (int64_t)h.vtasks.size();
         for (int64_t m = 0; m < nG; ++m)
             for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C) {
-                h.vtasks.push_back({h.gm_coff[(size_t)m] + C * TS, (int32_t)h.vpairs.size(), (int32_t)h.gset.nt[m]});
+                h.vtasks.push_back({h.gm_coff[(size_t)m] + C * TS, (int32_t)h.vpairs.size(), (int32_t)h.gset.nt[m], -1});
                 for (int64_t I = 0; I < h.gset.nt[m]; ++I)
                     h.vpairs.push_back({h.gm_xtoff[(size_t)m] + (I * h.gm_ntc[(size_t)m] + C) * TE, h.gset.voff[m] + I * TS});
             }
@@ -891,7 +896,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         for (int64_t m = 0; m < nG; ++m) {
             if (h.gm_ntc[(size_t)m] == 0) continue;
             for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
-                h.vtasks.push_back({h.gset.voff[m] + I * TS, (int32_t)h.vpairs.size(), (int32_t)h.gm_ntc[(size_t)m]});
+                h.vtasks.push_back({h.gset.voff[m] + I * TS, (int32_t)h.vpairs.size(), (int32_t)h.gm_ntc[(size_t)m], -1});
                 for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
                     h.vpairs.push_back({h.gm_roff[(size_t)m] + (C * h.gset.nt[m] + I) * TE, h.gm_coff[(size_t)m] + C * TS});
             }
@@ -900,7 +905,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     fill_flops(h.gset.factor_prog, h.tl64);
     fill_flops(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
-    fill_flops(h.sset.factor_prog, h.tl64);
     fill_flops(h.basis_prog, h.tl64);
     {
         const double ge = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
@@ -908,8 +912,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.gset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.gset.gemv_Wt, ge);
         h.cset.gemv_W.bytes = gemv_bytes(h.vtasks, h.cset.gemv_W, ge);
         h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
-        h.sset.gemv_W.bytes = gemv_bytes(h.vtasks, h.sset.gemv_W, 8.0);
-        h.sset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.sset.gemv_Wt, 8.0);
         h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
         h.gemv_X.bytes = gemv_bytes(h.vtasks, h.gemv_X, 8.0);
         // fine SpMV: 72 B of values + 4 B of index per stored block, x read and
@@ -918,13 +920,12 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         // one application of M^-1 (Eq. 16): the operators above once each, two
         // residual SpMVs (which also read r), and the vector gathers/combines
         h.apply_bytes = h.gset.gemv_W.bytes + h.gset.gemv_Wt.bytes + h.cset.gemv_W.bytes +
-                        h.cset.gemv_Wt.bytes + h.sset.gemv_W.bytes + h.sset.gemv_Wt.bytes +
+                        h.cset.gemv_Wt.bytes +
                         h.gemv_XT.bytes + h.gemv_X.bytes + 2.0 * (h.spmv_bytes + 24.0 * n) +
                         8.0 * (6.0 * h.N + 3.0 * (double)h.gset.vec_len + 2.0 * (double)h.cset.vec_len);
     }
     pad_ones(h.gset, h.pad_ones_g, h.gset.a_base);
     pad_ones(h.cset, h.pad_ones_c, lowp ? h.c_stage_base : h.cset.a_base);
-    pad_ones(h.sset, h.pad_ones_s, h.sset.a_base);
     // ---- index maps ------------------------------------------------------------------
     const int64_t s_pad = h.n_mortar;   // corrections follow the mortar dofs
     h.cvec_len = s_pad + h.n_corr;
@@ -1065,7 +1066,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.h_pairs = pairs;
     {
         // one application also runs the coarse forward and backward sweeps over
-        // the front factors (W11 and L21, then L21^T and W11^T) and their vectors
+        // the front factors (W11 and G, then W11^T and G^T) and their vectors
         h.apply_bytes += 2.0 * h.mf.factor_bytes + 8.0 * 8.0 * (double)h.mf.vec_len;
     }
     // ---- SELL-64 fine matrix ---------------------------------------------------------
@@ -1130,6 +1131,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             for (int64_t i = r.start; i < r.start + r.count; ++i) {
                 const GemvTask &t = h.vtasks[(size_t)i];
                 chk(in(t.y_off, TS, yl), what);
+                chk(t.base_off < 0 || in(t.base_off, TS, yl), what);
                 chk(t.pair_start >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)h.vpairs.size(), what);
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const GemvPair &pr = h.vpairs[(size_t)(t.pair_start + q)];
@@ -1141,8 +1143,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         chk_gemv(h.gset.gemv_Wt, low_n, h.gset.vec_len, h.gset.vec_len, "grain Wt gemv");
         chk_gemv(h.cset.gemv_W, c_n, h.cset.vec_len, h.cset.vec_len, "contact W gemv");
         chk_gemv(h.cset.gemv_Wt, c_n, h.cset.vec_len, h.cset.vec_len, "contact Wt gemv");
-        chk_gemv(h.sset.gemv_W, h.ar64_n, h.cvec_len, h.cvec_len, "coarse W gemv");
-        chk_gemv(h.sset.gemv_Wt, h.ar64_n, h.cvec_len, h.cvec_len, "coarse Wt gemv");
         chk_gemv(h.gemv_XT, h.ar64_n, h.gset.vec_len, h.gcol_len, "restriction gemv");
         chk_gemv(h.gemv_X, h.ar64_n, h.gcol_len, h.gset.vec_len, "prolongation gemv");
         for (auto v : g_slot_dof) chk(v >= -1 && v < h.N, "grain slot map");
@@ -1155,7 +1155,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         for (auto v : corr_koff) chk(in(v, 1, h.ar64_n), "correction pivot offset");
         for (auto v : h.pad_ones_g) chk(in(v, 1, h.ar64_n), "grain padding");
         for (auto v : h.pad_ones_c) chk(in(v, 1, h.ar64_n), "contact padding");
-        for (auto v : h.pad_ones_s) chk(in(v, 1, h.ar64_n), "coarse padding");
         for (auto v : scol) chk(v >= 0 && v < n, "SELL column");
         for (const auto &e : edges) chk(e.blk >= 0 && e.blk < h.nnzb, "coarse edge block");
         for (const auto &k : krefs) chk(in(k.koff, 1, h.ar64_n), "coarse K reference");
@@ -1165,7 +1164,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             chk(in(h.gm_koff[(size_t)m], tri_tiles(h.gm_ntc[(size_t)m]) * TE, h.ar64_n), "K region");
         }
         chk(in(h.gset.a_base, h.gset.region, h.ar64_n), "grain region");
-        chk(in(h.sset.a_base, h.sset.region, h.ar64_n), "coarse region");
         chk(h.n_coarse <= h.cvec_len, "coarse vector length");
         {
             const CoarseMF &mf = h.mf;
@@ -1177,7 +1175,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                 const int64_t nt = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
                 chk(in(mf.a_base + mf.rel[(size_t)t], tri_tiles(nt) * TE, h.ar64_n), "front tiles");
                 chk(in(mf.lt_base + mf.ltrel[(size_t)t], mf.nt_d[(size_t)t] * mf.nt_u[(size_t)t] * TE, h.ar64_n),
-                    "front L21^T tiles");
+                    "front NG^T tiles");
+                chk(in(mf.ng_base + mf.ltrel[(size_t)t], mf.nt_d[(size_t)t] * mf.nt_u[(size_t)t] * TE, h.ar64_n),
+                    "front NG tiles");
             }
             // every extend-add position lies inside the parent front
             std::unordered_map<int64_t, int64_t> front_nt;
@@ -1199,10 +1199,8 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             for (auto v : mf.out_src) chk(in(v, 1, mf.vec_len), "coarse solution source");
             for (auto v : mf.pad_ones) chk(in(v, 1, h.ar64_n), "front padding");
             for (int32_t l = 0; l < mf.n_levels; ++l) {
-                chk_gemv(mf.fwd_W[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front forward W");
-                chk_gemv(mf.fwd_L21[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front forward L21");
-                chk_gemv(mf.bwd_LT21[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front backward L21^T");
-                chk_gemv(mf.bwd_Wt[(size_t)l], h.ar64_n, mf.vec_len, mf.vec_len, "front backward W^T");
+                chk_gemv(mf.fwd[(size_t)l], h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front forward sweep");
+                chk_gemv(mf.bwd[(size_t)l], h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front backward sweep");
             }
             for (const auto &pr : pairs) {
                 chk(in(pr.f_off, 1, h.ar64_n), "coarse pair front");
@@ -1287,7 +1285,6 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.d_pairs = h.upload(pairs, s);
     h.d_edges = h.upload(edges, s);
     h.d_krefs = h.upload(krefs, s);
-    h.d_pad_s = h.upload(h.pad_ones_s, s);
     h.pair_vals = h.dalloc<double>(h.n_pair_vals);
     {
         CoarseMF &mf = h.mf;
@@ -1302,14 +1299,13 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         mf.d_out_dst = h.upload(mf.out_dst, s);
         mf.d_out_src = h.upload(mf.out_src, s);
         mf.d_pad = h.upload(mf.pad_ones, s);
-        mf.WV = h.dalloc<double>(mf.vec_len);
-        mf.YV = h.dalloc<double>(mf.vec_len);
-        mf.ZV = h.dalloc<double>(mf.vec_len);
-        mf.XV = h.dalloc<double>(mf.vec_len);
+        mf.V = h.dalloc<double>(3 * mf.vec_len);
+        mf.WV = mf.V;
+        mf.YV = mf.V + mf.vec_len;
+        mf.XV = mf.V + 2 * mf.vec_len;
         // padding slots of the front vectors are never written and must read as 0
-        for (double *v : {mf.WV, mf.YV, mf.ZV, mf.XV})
-            if (mf.vec_len > 0 && hipMemsetAsync(v, 0, sizeof(double) * (size_t)mf.vec_len, s) != hipSuccess)
-                fail(HPLMM_E_HIP, "hipMemsetAsync failed");
+        if (mf.vec_len > 0 && hipMemsetAsync(mf.V, 0, sizeof(double) * 3 * (size_t)mf.vec_len, s) != hipSuccess)
+            fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     }
     // task lists
     for (TaskLists *tl : {&h.tl64, &h.tl32}) {
