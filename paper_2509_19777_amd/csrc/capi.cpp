@@ -58,7 +58,7 @@ static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vec
             }
             case LK_GEMM: {
                 ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
-                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s);
+                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (T *)tl.d_part, tl.d_cnt);
                 break;
             }
             case LK_TRANSPOSE: launch_tile_transpose<T>(arena, arena, tl.d_copy + L.start, L.count, s); break;
@@ -189,10 +189,11 @@ static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, dou
         launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s);
 }
 
-// Front sweeps: long rows, few tasks per launch, so 16 wavefronts per task.
+// Front sweeps: few long rows per launch, split over many work-groups.
 static void gemv_front(Handle &h, Range r, hipStream_t s) {
     if (r.count == 0) return;
-    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, 16);
+    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, 4,
+                        h.d_gemv_part, h.d_gemv_cnt);
 }
 
 // u = S^-1 f for the mortar block of the coarse operator with the

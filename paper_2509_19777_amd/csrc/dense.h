@@ -30,6 +30,10 @@ enum GemmFlags : int32_t {
 };
 
 // One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p) [* P].
+// A long sum may be split into nchunk tasks over consecutive parts of its
+// pair list (same c_off, post_off and flags): each stores its partial sum in
+// part[part_off + 4096 chunk ..] and bumps counter grp; the work-group that
+// arrives last adds the partials in chunk order and applies the epilogue.
 struct GemmTask {
     int64_t c_off;
     int64_t post_off;
@@ -37,6 +41,10 @@ struct GemmTask {
     int32_t pair_count;
     int32_t flags;
     int32_t pad;
+    int64_t part_off = 0;
+    int32_t grp = -1;
+    int16_t chunk = 0;
+    int16_t nchunk = 1;
 };
 
 struct GemmPair {
@@ -55,12 +63,20 @@ struct DiagTask {
 };
 
 // Tiled matrix-vector product: y[y_off .. +64) = [base[base_off .. +64) +] sum_p T_p x[x_off_p .. +64)
-// (no base term when base_off < 0)
+// (no base term when base_off < 0).  A long row may be split into nchunk
+// tasks (one work-group each) that share y_off and base_off and cover
+// consecutive parts of its pair list: each writes its partial sum to
+// part[part_off + 64 chunk ..] and bumps counter grp; the work-group that
+// arrives last adds the partials in chunk order and writes y.
 struct GemvTask {
     int64_t y_off;
     int32_t pair_start;
     int32_t pair_count;
     int64_t base_off;
+    int64_t part_off = 0;
+    int32_t grp = -1;
+    int16_t chunk = 0;
+    int16_t nchunk = 1;
 };
 
 struct GemvPair {
@@ -75,9 +91,11 @@ struct CopyTask {  // dst tile = src tile^T
 
 // Launchers (stream-ordered, asynchronous).  `flag` points to a device int32
 // pair {status bits, first bad id}.
+// Split tasks need `part` (T) and the zeroed counters `cnt` (reset by the
+// last work-group of each group).
 template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
-                      hipStream_t s);
+                      hipStream_t s, T *part = nullptr, int32_t *cnt = nullptr);
 template <class T>
 void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int64_t ntasks,
                  int32_t *flag, hipStream_t s);
@@ -87,9 +105,12 @@ void launch_tile_transpose(T *arena_src, T *arena_dst, const CopyTask *tasks, in
 // One work-group per task with `waves` (4 or 16) wavefronts splitting the
 // pairs; base (needed only if some task has base_off >= 0) may alias y when
 // every task reads its base at its own output rows.
+// Split rows need the partial buffer `part` and the counters `cnt` (zero
+// before the launch; the last work-group of a group resets its counter, so
+// launches on one stream can reuse them).
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
                  const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
-                 int32_t waves = 4);
+                 int32_t waves = 4, double *part = nullptr, int32_t *cnt = nullptr);
 
 }  // namespace hplmm

@@ -102,9 +102,11 @@ __device__ __forceinline__ void mfma_tile(const T *As, const T *Bs, typename Mfm
 template <class T>
 __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
                                                         const GemmTask *__restrict__ tasks,
-                                                        const GemmPair *__restrict__ pairs) {
+                                                        const GemmPair *__restrict__ pairs, T *part,
+                                                        int32_t *cnt) {
     __shared__ T As[TS * LD];
     __shared__ T Bs[TS * LD];
+    __shared__ int32_t last;
     const GemmTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
@@ -129,6 +131,28 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
             fetch_tile(rb, arena + pr.b_off);
         }
         mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+    }
+    if (tk.nchunk > 1) {
+        // partial sums in accumulator order, reduced by the last arrival
+        T *pp = part + tk.part_off + (int64_t)tk.chunk * TE;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 4; ++r) pp[((i * 2 + j) * 4 + r) * 256 + threadIdx.x] = acc[i][j][r];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) last = atomicAdd(&cnt[tk.grp], 1) == tk.nchunk - 1;
+        __syncthreads();
+        if (!last) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        for (int c = 0; c < tk.nchunk; ++c) {
+            const T *pc = part + tk.part_off + (int64_t)c * TE;
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    for (int r = 0; r < 4; ++r) acc[i][j][r] += pc[((i * 2 + j) * 4 + r) * 256 + threadIdx.x];
+        }
+        if (threadIdx.x == 0) atomicExch(&cnt[tk.grp], 0);
     }
     const int lr = lane & 15, lq = lane >> 4;
     const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
@@ -341,7 +365,8 @@ struct Vec16<uint16_t> {   // bfloat16 storage
 template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
                                                        double *y, const GemvTask *__restrict__ tasks,
-                                                       const GemvPair *__restrict__ pairs, const double *base) {
+                                                       const GemvPair *__restrict__ pairs, const double *base,
+                                                       double *part, int32_t *cnt) {
     constexpr int R = Vec16<T>::R;          // rows per lane
     constexpr int LPC = TS / R;             // lanes per column
     __shared__ double red[NW * R * TS];
@@ -367,21 +392,34 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
 #pragma unroll
     for (int i = 0; i < R; ++i) red[(wave * R + phase) * TS + row0 + i] = acc[i];
     __syncthreads();
-    if (threadIdx.x < TS) {
-        double s = 0.0;
-        for (int q = 0; q < NW * R; ++q) s += red[q * TS + threadIdx.x];
-        if (tk.base_off >= 0) s += base[tk.base_off + threadIdx.x];
-        y[tk.y_off + threadIdx.x] = s;
+    if (threadIdx.x >= TS) return;   // wave 0 finishes the task
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int q = 0; q < NW * R; ++q) s += red[q * TS + t];
+    if (tk.nchunk > 1) {
+        part[tk.part_off + (int64_t)tk.chunk * TS + t] = s;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        int32_t old = 0;
+        if (t == 0) old = atomicAdd(&cnt[tk.grp], 1);
+        old = __shfl(old, 0, 64);
+        if (old != tk.nchunk - 1) return;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        s = 0.0;
+        for (int c = 0; c < tk.nchunk; ++c) s += part[tk.part_off + (int64_t)c * TS + t];
+        if (t == 0) atomicExch(&cnt[tk.grp], 0);
     }
+    if (tk.base_off >= 0) s += base[tk.base_off + t];
+    y[tk.y_off + t] = s;
 }
 
 // ---- launchers -----------------------------------------------------------
 static inline unsigned grid_of(int64_t n) { return (unsigned)n; }
 
 template <class T>
-void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s) {
+void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s,
+                      T *part, int32_t *cnt) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(tile_gemm_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, tasks, pairs);
+    hipLaunchKernelGGL(tile_gemm_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, tasks, pairs, part, cnt);
 }
 template <class T>
 void launch_diag(T *a, T *w, T *wt, const DiagTask *tasks, int64_t ntasks, int32_t *flag, hipStream_t s) {
@@ -395,27 +433,30 @@ void launch_tile_transpose(T *src, T *dst, const CopyTask *tasks, int64_t ntasks
 }
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const GemvPair *pairs,
-                 int64_t ntasks, hipStream_t s, const double *base, int32_t waves) {
+                 int64_t ntasks, hipStream_t s, const double *base, int32_t waves, double *part, int32_t *cnt) {
     if (ntasks <= 0) return;
     if (waves == 16)
         hipLaunchKernelGGL((gemv_kernel<T, 16>), dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y, tasks, pairs,
-                           base);
+                           base, part, cnt);
     else
         hipLaunchKernelGGL((gemv_kernel<T, 4>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
-                           base);
+                           base, part, cnt);
 }
 
-template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);
-template void launch_tile_gemm<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t);
+template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, double *,
+                                       int32_t *);
+template void launch_tile_gemm<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, float *,
+                                      int32_t *);
 template void launch_diag<double>(double *, double *, double *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_diag<float>(float *, float *, float *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);
 template void launch_tile_transpose<float>(float *, float *, const CopyTask *, int64_t, hipStream_t);
 template void launch_gemv<double>(const double *, const double *, double *, const GemvTask *, const GemvPair *,
-                                  int64_t, hipStream_t, const double *, int32_t);
+                                  int64_t, hipStream_t, const double *, int32_t, double *, int32_t *);
 template void launch_gemv<float>(const float *, const double *, double *, const GemvTask *, const GemvPair *,
-                                 int64_t, hipStream_t, const double *, int32_t);
+                                 int64_t, hipStream_t, const double *, int32_t, double *, int32_t *);
 template void launch_gemv<uint16_t>(const uint16_t *, const double *, double *, const GemvTask *,
-                                    const GemvPair *, int64_t, hipStream_t, const double *, int32_t);
+                                    const GemvPair *, int64_t, hipStream_t, const double *, int32_t, double *,
+                                    int32_t *);
 
 }  // namespace hplmm

@@ -54,6 +54,10 @@ struct TaskLists {
     GemmPair *d_pairs = nullptr;
     DiagTask *d_diag = nullptr;
     CopyTask *d_copy = nullptr;
+    int64_t part_len = 0;        // split-task partial tiles (elements of the list's type)
+    int32_t cnt_len = 0;         // split-task arrival counters
+    void *d_part = nullptr;
+    int32_t *d_cnt = nullptr;
 };
 
 struct Range {
@@ -180,6 +184,10 @@ struct Handle {
     int64_t arbf_n = 0;
     TaskLists tl64, tl32;
     GemvTask *d_vtasks = nullptr;
+    int64_t gemv_part_len = 0;          // split-row partial sums (doubles)
+    int32_t gemv_cnt_len = 0;           // split-row arrival counters
+    double *d_gemv_part = nullptr;
+    int32_t *d_gemv_cnt = nullptr;
     GemvPair *d_vpairs = nullptr;
     std::vector<GemvTask> vtasks;
     std::vector<GemvPair> vpairs;

@@ -164,6 +164,97 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
+// Split the long rows of one GEMV launch so that it spreads over at least
+// about 512 work-groups (a work-group streams tiles at a small fraction of the
+// device bandwidth): chunks of at least 4 pairs, partial sums of each split
+// row reduced in chunk order by the last work-group to finish.  The launch's
+// tasks are re-emitted at the end of vt and r is pointed at them; part_len
+// and cnt_len grow to what the launch needs.
+void split_rows(std::vector<GemvTask> &vt, Range &r, int64_t &part_len, int32_t &cnt_len) {
+    int64_t total = 0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i) total += vt[(size_t)i].pair_count;
+    const int64_t chunk = std::max<int64_t>(4, (total + 511) / 512);
+    const int64_t start = (int64_t)vt.size();
+    int64_t part = 0;
+    int32_t grp = 0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i) {
+        const GemvTask t = vt[(size_t)i];
+        const int64_t nc = (t.pair_count + chunk - 1) / chunk;
+        if (nc <= 1) {
+            vt.push_back(t);
+            continue;
+        }
+        if (nc > 32767) fail(HPLMM_E_ARG, "internal: GEMV row too long to split");
+        const int64_t per = (t.pair_count + nc - 1) / nc;
+        for (int64_t c = 0; c < nc; ++c) {
+            GemvTask u = t;
+            u.pair_start = (int32_t)(t.pair_start + c * per);
+            u.pair_count = (int32_t)std::min<int64_t>(per, t.pair_count - c * per);
+            u.part_off = part;
+            u.grp = grp;
+            u.chunk = (int16_t)c;
+            u.nchunk = (int16_t)nc;
+            vt.push_back(u);
+        }
+        part += nc * TS;
+        ++grp;
+    }
+    r.start = start;
+    r.count = (int64_t)vt.size() - start;
+    part_len = std::max(part_len, part);
+    cnt_len = std::max(cnt_len, grp);
+}
+
+// Split the long sums of a GEMM launch that has too few tasks to fill the
+// device: a work-group loads its tile pairs at a small fraction of the device
+// bandwidth, so a chain of k products is cut into about sqrt(k/2)-pair
+// chunks that run on different compute units (the last one to finish adds the
+// partials in order, a cost that grows with the number of chunks).
+void split_program(std::vector<Launch> &prog, TaskLists &tl) {
+    for (Launch &L : prog) {
+        if (L.kind != LK_GEMM || L.count >= 256) continue;
+        int64_t total = 0;
+        for (int64_t i = L.start; i < L.start + L.count; ++i) total += tl.gemm[(size_t)i].pair_count;
+        const int64_t floor_per = std::max<int64_t>(2, (total + 511) / 512);   // at most ~512 work-groups
+        const int64_t start = (int64_t)tl.gemm.size();
+        int64_t part = 0;
+        int32_t grp = 0;
+        bool any = false;
+        for (int64_t i = L.start; i < L.start + L.count; ++i) {
+            const GemmTask t = tl.gemm[(size_t)i];
+            const int64_t k = t.pair_count;
+            const int64_t per = std::max<int64_t>(floor_per, (int64_t)std::lround(std::sqrt((double)k / 2.0)));
+            const int64_t nc = k >= 4 ? (k + per - 1) / per : 1;
+            if (nc <= 1) {
+                tl.gemm.push_back(t);
+                continue;
+            }
+            any = true;
+            const int64_t each = (k + nc - 1) / nc;
+            for (int64_t c = 0; c < nc; ++c) {
+                GemmTask u = t;
+                u.pair_start = (int32_t)(t.pair_start + c * each);
+                u.pair_count = (int32_t)std::min<int64_t>(each, k - c * each);
+                u.part_off = part;
+                u.grp = grp;
+                u.chunk = (int16_t)c;
+                u.nchunk = (int16_t)nc;
+                tl.gemm.push_back(u);
+            }
+            part += nc * TE;
+            ++grp;
+        }
+        if (!any) {
+            tl.gemm.resize((size_t)start);
+            continue;
+        }
+        L.start = start;
+        L.count = (int64_t)tl.gemm.size() - start;
+        tl.part_len = std::max(tl.part_len, part);
+        tl.cnt_len = std::max(tl.cnt_len, grp);
+    }
+}
+
 // Algorithmic flops of every GEMM launch: 2*64^3 per tile product.
 void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
     for (Launch &L : prog) {
@@ -171,7 +262,7 @@ void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
         double f = 0.0;
         for (int64_t i = L.start; i < L.start + L.count; ++i) {
             const GemmTask &t = tl.gemm[(size_t)i];
-            f += (double)t.pair_count + ((t.flags & (GF_POST | GF_POST_RIGHT)) ? 1.0 : 0.0);
+            f += (double)t.pair_count + ((t.flags & (GF_POST | GF_POST_RIGHT)) && t.chunk == 0 ? 1.0 : 0.0);
         }
         L.flops = f * 2.0 * TS * TS * TS;
     }
@@ -545,6 +636,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
             }
         }
         mf.bwd[(size_t)l].count = (int64_t)vt.size() - mf.bwd[(size_t)l].start;
+        split_rows(vt, mf.fwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
+        split_rows(vt, mf.bwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
     }
     // right-hand side in, solution out
     mf.init_map.assign((size_t)mf.vec_len, -1);
@@ -579,6 +672,7 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         voffp += 9 * (int64_t)iface_nu[(size_t)pr.c] * iface_nu[(size_t)pr.c2];
     }
     h.n_pair_vals = voffp;
+    for (int32_t l = 0; l < nl; ++l) split_program(mf.factor_prog[(size_t)l], h.tl64);
     for (int32_t l = 0; l < nl; ++l) fill_flops(mf.factor_prog[(size_t)l], h.tl64);
     for (int32_t l = 0; l < nl; ++l)
         for (const Launch &L : mf.factor_prog[(size_t)l]) mf.flops += L.flops;
@@ -903,6 +997,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         }
         h.gemv_X.count = (int64_t)h.vtasks.size() - h.gemv_X.start;
     }
+    split_program(h.gset.factor_prog, h.tl64);
+    split_program(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
+    split_program(h.basis_prog, h.tl64);
     fill_flops(h.gset.factor_prog, h.tl64);
     fill_flops(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
@@ -1120,6 +1217,12 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                 if (t.flags & (GF_POST | GF_POST_RIGHT)) chk(in(t.post_off, TE, an), "gemm post tile");
                 chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
                     "gemm pair range");
+                if (t.nchunk > 1)
+                    chk(t.grp >= 0 && t.grp < tl.cnt_len && t.chunk >= 0 && t.chunk < t.nchunk && t.part_off >= 0 &&
+                            t.part_off + (int64_t)t.nchunk * TE <= tl.part_len,
+                        "gemm split task");
+                else
+                    chk(t.nchunk == 1 && t.chunk == 0, "gemm task");
             }
             for (const auto &pr : tl.pairs) chk(in(pr.a_off, TE, an) && in(pr.b_off, TE, an), "gemm operand tile");
             for (const auto &d : tl.diag) chk(in(d.a_off, TE, an) && in(d.w_off, TE, an) && in(d.wt_off, TE, an), "diag tile");
@@ -1132,6 +1235,12 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                 const GemvTask &t = h.vtasks[(size_t)i];
                 chk(in(t.y_off, TS, yl), what);
                 chk(t.base_off < 0 || in(t.base_off, TS, yl), what);
+                if (t.nchunk > 1)
+                    chk(t.grp >= 0 && t.grp < h.gemv_cnt_len && t.chunk >= 0 && t.chunk < t.nchunk &&
+                            t.part_off >= 0 && t.part_off + (int64_t)t.nchunk * TS <= h.gemv_part_len,
+                        what);
+                else
+                    chk(t.nchunk == 1 && t.chunk == 0, what);
                 chk(t.pair_start >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)h.vpairs.size(), what);
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const GemvPair &pr = h.vpairs[(size_t)(t.pair_start + q)];
@@ -1313,9 +1422,18 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         tl->d_pairs = h.upload(tl->pairs, s);
         tl->d_diag = h.upload(tl->diag, s);
         tl->d_copy = h.upload(tl->copy, s);
+        tl->d_cnt = h.dalloc<int32_t>(std::max<int32_t>(1, tl->cnt_len));
+        if (hipMemsetAsync(tl->d_cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, tl->cnt_len), s) != hipSuccess)
+            fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     }
+    h.tl64.d_part = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
+    h.tl32.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tl32.part_len));
     h.d_vtasks = h.upload(h.vtasks, s);
     h.d_vpairs = h.upload(h.vpairs, s);
+    h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
+    h.d_gemv_cnt = h.dalloc<int32_t>(std::max<int32_t>(1, h.gemv_cnt_len));
+    if (hipMemsetAsync(h.d_gemv_cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.gemv_cnt_len), s) != hipSuccess)
+        fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     // arenas and vectors
     h.ar64 = h.dalloc<double>(h.ar64_n);
     if (h.ar32_n) h.ar32 = h.dalloc<float>(h.ar32_n);
