@@ -114,7 +114,17 @@ def main():
                  "units_per_launch": d["units"] / d["launches"], "traffic": traffic_for(dom)})
     spmv_gbs = prof["spmv"]["units"] / (prof["spmv"]["ms"] * 1e-3) / 1e9 if prof["spmv"]["ms"] else None
     apply_gbs = prof["apply"]["units"] / (prof["apply"]["ms"] * 1e-3) / 1e9 if prof["apply"]["ms"] else None
-    breakdown = {k: {"ms_per_step": round(v["ms"] / a.steps, 3), "launches_per_step": v["launches"] // a.steps}
+    def _rate(k, v):
+        # tile_gemm units are flops, every other class counts algorithmic bytes
+        if not v["ms"]:
+            return None
+        r = v["units"] / (v["ms"] * 1e-3)
+        if k == "diag":
+            return None
+        return {"tflops": round(r / 1e12, 2)} if k == "tile_gemm" else {"gbs": round(r / 1e9, 1)}
+
+    breakdown = {k: {"ms_per_step": round(v["ms"] / a.steps, 3), "launches_per_step": v["launches"] // a.steps,
+                     **(_rate(k, v) or {})}
                  for k, v in prof.items() if v["launches"]}
     out = {
         "metric": METRIC, "value": round(ms, 3), "unit": "ms", "n_gpus": 1, "steps": a.steps,

@@ -213,6 +213,9 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *   6 device bytes held: int64[1]
  *   7 profiler totals (see hplmm_profile)
  *   8 algorithmic bytes: double[2] = {one application of M^-1, one SpMV}
+ *   9 coarse solve structure: double[5 * levels], per front level (0 = root)
+ *            {fronts, forward work-groups, forward bytes, backward
+ *            work-groups, backward bytes}
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);

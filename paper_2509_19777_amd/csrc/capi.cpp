@@ -580,6 +580,17 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 break;
             }
             case 6: put(&h.dev_bytes, sizeof(int64_t)); break;
+            case 9: {
+                std::vector<double> v;
+                for (int32_t l = 0; l < h.mf.n_levels; ++l) {
+                    int64_t nf = 0;
+                    for (int32_t t = 0; t < h.mf.n_fronts; ++t) nf += h.mf.level[(size_t)t] == l;
+                    const Range &f = h.mf.fwd[(size_t)l], &b = h.mf.bwd[(size_t)l];
+                    for (double x : {(double)nf, (double)f.count, f.bytes, (double)b.count, b.bytes}) v.push_back(x);
+                }
+                put(v.data(), sizeof(double) * v.size());
+                break;
+            }
             default: fail(HPLMM_E_ARG, "unknown query");
         }
         if (needed) *needed = (int64_t)buf.size();

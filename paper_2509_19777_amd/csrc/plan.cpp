@@ -164,16 +164,19 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
-// Split the long rows of one GEMV launch so that it spreads over at least
-// about 512 work-groups (a work-group streams tiles at a small fraction of the
-// device bandwidth): chunks of at least 4 pairs, partial sums of each split
-// row reduced in chunk order by the last work-group to finish.  The launch's
-// tasks are re-emitted at the end of vt and r is pointed at them; part_len
-// and cnt_len grow to what the launch needs.
+// Split the long rows of a GEMV launch with fewer than 128 tasks so that it
+// spreads over about 256 work-groups (a work-group streams tiles at a small
+// fraction of the device bandwidth): chunks of at least 4 pairs, partial sums
+// of each split row reduced in chunk order by the last work-group to finish.
+// Launches with more tasks are left alone: the release/acquire fences of a
+// split work-group cost more than they save there.  The launch's tasks are
+// re-emitted at the end of vt and r is pointed at them; part_len and cnt_len
+// grow to what the launch needs.
 void split_rows(std::vector<GemvTask> &vt, Range &r, int64_t &part_len, int32_t &cnt_len) {
+    if (r.count >= 128) return;
     int64_t total = 0;
     for (int64_t i = r.start; i < r.start + r.count; ++i) total += vt[(size_t)i].pair_count;
-    const int64_t chunk = std::max<int64_t>(4, (total + 511) / 512);
+    const int64_t chunk = std::max<int64_t>(4, (total + 255) / 256);
     const int64_t start = (int64_t)vt.size();
     int64_t part = 0;
     int32_t grp = 0;
@@ -638,6 +641,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         mf.bwd[(size_t)l].count = (int64_t)vt.size() - mf.bwd[(size_t)l].start;
         split_rows(vt, mf.fwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
         split_rows(vt, mf.bwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
+        mf.fwd[(size_t)l].bytes = gemv_bytes(vt, mf.fwd[(size_t)l], 8.0);
+        mf.bwd[(size_t)l].bytes = gemv_bytes(vt, mf.bwd[(size_t)l], 8.0);
     }
     // right-hand side in, solution out
     mf.init_map.assign((size_t)mf.vec_len, -1);

@@ -89,9 +89,12 @@ void launch_combine(int64_t n, const double *base, const int64_t *gslot, const d
 }
 
 // ---- restriction / prolongation ------------------------------------------------
-__global__ void coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r, const double *__restrict__ t,
-                                  double *__restrict__ f) {
-    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per coarse dof: the lanes share the interface's node sum and
+// the per-grain restriction terms, then a fixed butterfly adds them up.
+__global__ void __launch_bounds__(256) coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r,
+                                                         const double *__restrict__ t, double *__restrict__ f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     if (q >= m.n_coarse) return;
     double s = 0.0;
     if (q < m.n_mortar) {
@@ -101,15 +104,16 @@ __global__ void coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r, co
         const int32_t a = lq / 3, d = lq % 3;
         const double *H = m.H + m.iface_hoff[c];
         const int64_t p0 = m.iface_ptr[c], p1 = m.iface_ptr[c + 1];
-        for (int64_t p = p0; p < p1; ++p) s += H[(p - p0) * nu + a] * r[3 * (int64_t)m.iface_nodes[p] + d];
+        for (int64_t p = p0 + lane; p < p1; p += 64) s += H[(p - p0) * nu + a] * r[3 * (int64_t)m.iface_nodes[p] + d];
     }
-    double g = 0.0;
-    for (int64_t p = m.tptr[q]; p < m.tptr[q + 1]; ++p) g += t[m.tslot[p]];
-    f[m.fpos[q]] = s + g;
+    for (int64_t p = m.tptr[q] + lane; p < m.tptr[q + 1]; p += 64) s += t[m.tslot[p]];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    if (lane == 0) f[m.fpos[q]] = s;
 }
 void launch_coarse_rhs(const CoarseMaps &m, const double *r, const double *t, double *f, hipStream_t s) {
     if (m.n_coarse <= 0) return;
-    hipLaunchKernelGGL(coarse_rhs_kernel, dim3(blocks_for(m.n_coarse, 256)), dim3(256), 0, s, m, r, t, f);
+    hipLaunchKernelGGL(coarse_rhs_kernel, dim3(blocks_for(m.n_coarse, 4)), dim3(256), 0, s, m, r, t, f);
 }
 
 __global__ void corr_solve_kernel(CoarseMaps m, const double *__restrict__ f, double *__restrict__ u) {

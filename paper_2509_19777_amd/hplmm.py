@@ -264,9 +264,10 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "h", None)
-        if h is not None and h.value:
-            lib().hplmm_destroy(h)
-            self.h = None
+        if h is None or not h.value or lib is None:   # lib is None once the interpreter tears the module down
+            return
+        lib().hplmm_destroy(h)
+        self.h = None
 
     def setup(self):
         _check(lib().hplmm_setup(self.h, _stream()))
