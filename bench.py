@@ -47,7 +47,8 @@ def parse():
                     help="mortar nodes per interface (4 minimises set-up + solve time on this workload)")
     ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--quick", action="store_true", help="skip the SpMV/apply bandwidth loops")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
 
 
@@ -67,6 +68,16 @@ def main():
     t_plan = time.perf_counter() - t0
     sizes = S.sizes()
     print(f"# plan done in {t_plan:.1f} s: {sizes}", file=sys.stderr, flush=True)
+
+    if a.copy_calibration_mib > 0:
+        # a plain copy of known size: reads and writes exactly this many bytes,
+        # so hardware fetch/write counters of this kernel give their scale
+        src = torch.ones(a.copy_calibration_mib * (1 << 20) // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def step():
         S.setup()
