@@ -26,6 +26,7 @@ METRIC = "GMRES time-to-1e-8 residual (setup+solve) & SpMV/apply HBM GB/s, 64^3 
 HBM_PEAK_GBS = 8000.0           # MI355X HBM3E
 FP64_MFMA_TFLOPS = 78.6         # MI355X dense FP64 matrix peak
 FP32_MFMA_TFLOPS = 157.3
+CPU_SAMPLE_N = 32               # voxels per side of the oracle's sample of the workload
 KERNEL_NAMES = {
     "tile_gemm": "tile_gemm_kernel<double>",
     "gemv_smoother": "gemv_kernel (grain + contact smoother)",
@@ -185,8 +186,8 @@ def _source_hash():
 
 def cpu_baseline(a, gpu_iters, gpu_dofs):
     """The oracle, untuned, on a bounded sample of the same workload: the lower
-    24^3 corner of the same 64^3 fields with the same 8^3 boxes, solved to
-    1e-8 (assembly excluded, as on the GPU).  Its set-up time is scaled by the
+    32^3 corner of the same 64^3 fields with the same 8^3 boxes, solved to
+    1e-8 (assembly excluded, as on the GPU; about 10-20 s of CPU work).  Its set-up time is scaled by the
     subdomain-count ratio and its solve time by (dof ratio) x (GPU iteration
     count / oracle iteration count)."""
     try:
@@ -197,7 +198,7 @@ def cpu_baseline(a, gpu_iters, gpu_dofs):
     from oracle import fem, gmres, hplmm as oh
     from paper_2509_19777_amd import synth
     full = synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar)
-    sub = synth.crop(full, 24, box=a.box)
+    sub = synth.crop(full, CPU_SAMPLE_N, box=a.box)
     A, b, mesh = fem.assemble(sub)
     t0 = time.perf_counter()
     H = oh.HPLMM(sub, A=A, b=b, mesh=mesh, n=a.mortar)
@@ -209,7 +210,7 @@ def cpu_baseline(a, gpu_iters, gpu_dofs):
     setup_ms = (t1 - t0) * 1e3 * full_grains / n_sub
     solve_ms = (t2 - t1) * 1e3 * (gpu_dofs / A.shape[0]) * (gpu_iters / max(r.iters, 1))
     return {"value": round(setup_ms + solve_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on the 24^3 corner crop of the same fields "
+            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on the {CPU_SAMPLE_N}^3 corner crop of the same fields "
                        f"({A.shape[0]} dofs, {n_sub} subdomains, {r.iters} iterations, set-up "
                        f"{(t1 - t0):.2f} s, solve {(t2 - t1):.2f} s); set-up scaled x{full_grains / n_sub:.1f} "
                        f"(subdomains), solve scaled x{gpu_dofs / A.shape[0]:.1f} (dofs) "
