@@ -1,0 +1,68 @@
+/* Learned basis surrogate of libhplmm: a small 3D convolutional network that
+ * predicts grain basis columns (Eq. 23: the grain-interior response
+ * A_gi^-1 Abar_gi,m e_k to one mortar mode) from the assembled operator,
+ * trained on the columns the method itself computes, with the exact local
+ * solve as fallback.
+ *
+ * Network.  Input: 4 channels on the 9 x 9 x 9 node lattice of an 8^3-voxel
+ * box grain (interior indicator; log trace of the node's diagonal 3x3 block
+ * of A minus its grain mean; stored blocks of the node row / 27; the Gaussian
+ * weight H_c[., a] of Eq. 8 on the nodes of interface c).  Output: 9 channels
+ * = the three basis columns 3a + x, 3a + y, 3a + z as (u_x, u_y, u_z) each.
+ * Layers: channels c0 -> c1 -> c2 -> c3 -> c4 (normally 4, 32, 32, 32, 9;
+ * every c <= 32), 3x3x3 'same' convolutions with zero padding and bias, ReLU
+ * after the first three.  Tensors are float32 device arrays, channel-last:
+ * t[s][p][c], p = (z * 9 + y) * 9 + x.  Parameters: per layer w[d][ci][co]
+ * (d = (dz+1) * 9 + (dy+1) * 3 + (dx+1)) then b[co], layers concatenated.
+ *
+ * Errors follow hplmm.h (status codes, hplmm_last_error()).
+ */
+#ifndef HPLMM_SURROGATE_H
+#define HPLMM_SURROGATE_H
+
+#include "hplmm.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hplmm_sg_net hplmm_sg_net;
+
+/* Create a network with channels[0..4] and room for batches of up to
+ * max_batch samples (activations, gradients and partial sums are allocated
+ * here, about 1.1 MB per sample).  Parameters start at zero.
+ * E_ARG on bad channel counts or max_batch < 1; E_OOM / E_HIP. */
+hplmm_status hplmm_sg_create(const int32_t channels[5], int32_t max_batch, hplmm_sg_net **out);
+
+/* Number of float32 parameters. */
+hplmm_status hplmm_sg_param_count(const hplmm_sg_net *net, int64_t *count);
+
+/* Copy parameters from / to host memory (count must equal the parameter
+ * count).  set_params also resets the Adam state. */
+hplmm_status hplmm_sg_set_params(hplmm_sg_net *net, const float *host, int64_t count);
+hplmm_status hplmm_sg_get_params(const hplmm_sg_net *net, float *host, int64_t count);
+
+/* y_dev[n][729][c4] = network(x_dev[n][729][c0]); 1 <= n <= max_batch.
+ * Asynchronous on stream. */
+hplmm_status hplmm_sg_forward(hplmm_sg_net *net, const float *x_dev, int32_t n, float *y_dev, void *stream);
+
+/* Forward pass, loss and gradients of the loss w.r.t. every parameter for
+ * the batch (x_dev as above, y_dev the targets [n][729][c4]).  Loss = mean
+ * over samples of |m (net(x) - y)|^2 / (|m y|^2 + 1e-30), m = interior
+ * indicator x[s][p][0] > 0.5.  The gradients stay in the network (see
+ * get_grads / adam); *loss receives the mean (synchronises the stream). */
+hplmm_status hplmm_sg_gradient(hplmm_sg_net *net, const float *x_dev, const float *y_dev, int32_t n, double *loss,
+                               void *stream);
+
+/* Copy the last gradients to host memory (count = parameter count). */
+hplmm_status hplmm_sg_get_grads(const hplmm_sg_net *net, float *host, int64_t count, void *stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the last gradients. */
+hplmm_status hplmm_sg_adam(hplmm_sg_net *net, float lr, void *stream);
+
+void hplmm_sg_destroy(hplmm_sg_net *net);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HPLMM_SURROGATE_H */

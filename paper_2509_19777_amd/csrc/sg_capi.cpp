@@ -1,0 +1,205 @@
+// C ABI of the learned basis surrogate network (training and inference).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/hplmm_surrogate.h"
+#include "common.h"
+#include "surrogate.h"
+
+namespace hplmm {
+namespace {
+
+void sg_check(hipError_t e, const char *what) {
+    if (e != hipSuccess) fail(HPLMM_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+template <class T>
+T *sg_alloc(std::vector<void *> &owned, int64_t n) {
+    void *p = nullptr;
+    if (n > 0 && hipMalloc(&p, sizeof(T) * (size_t)n) != hipSuccess) fail(HPLMM_E_OOM, "hipMalloc failed");
+    owned.push_back(p);
+    return (T *)p;
+}
+
+hipStream_t to_stream(void *s) { return (hipStream_t)s; }
+
+}  // namespace
+}  // namespace hplmm
+
+using namespace hplmm;
+
+struct hplmm_sg_net {
+    int32_t ch[5] = {0, 0, 0, 0, 0};
+    int32_t max_batch = 0;
+    int64_t nparam = 0;
+    int64_t w_off[4] = {0, 0, 0, 0}, b_off[4] = {0, 0, 0, 0};
+    float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
+    int32_t t = 0;
+    float *act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // act[0] unused (caller's x)
+    float *gbuf[2] = {nullptr, nullptr};
+    float *part = nullptr;
+    int32_t chunks = 0;
+    double *loss_s = nullptr;
+    std::vector<void *> owned;
+    ~hplmm_sg_net() {
+        for (void *p : owned)
+            if (p) (void)hipFree(p);
+    }
+};
+
+static void forward_all(hplmm_sg_net &nt, const float *x, int32_t n, float *y, hipStream_t s) {
+    const float *in = x;
+    for (int l = 0; l < 4; ++l) {
+        float *out = (l == 3 && y) ? y : nt.act[l + 1];
+        sg::launch_conv_fwd(in, nt.ch[l], nt.params + nt.w_off[l], nt.params + nt.b_off[l], out, nt.ch[l + 1], n,
+                            l < 3 ? 1 : 0, s);
+        in = out;
+    }
+}
+
+extern "C" hplmm_status hplmm_sg_create(const int32_t channels[5], int32_t max_batch, hplmm_sg_net **out) {
+    return guarded([&]() -> hplmm_status {
+        if (!channels || !out || max_batch < 1) fail(HPLMM_E_ARG, "NULL argument or max_batch < 1");
+        for (int i = 0; i < 5; ++i)
+            if (channels[i] < 1 || channels[i] > 32) fail(HPLMM_E_ARG, "every channel count must be in [1, 32]");
+        auto *nt = new hplmm_sg_net();
+        try {
+            std::memcpy(nt->ch, channels, sizeof(nt->ch));
+            nt->max_batch = max_batch;
+            int64_t off = 0;
+            int64_t maxc = 0;
+            for (int l = 0; l < 4; ++l) {
+                nt->w_off[l] = off;
+                off += (int64_t)sg::NOFF * channels[l] * channels[l + 1];
+                nt->b_off[l] = off;
+                off += channels[l + 1];
+                maxc = std::max<int64_t>(maxc, std::max(channels[l], channels[l + 1]));
+            }
+            nt->nparam = off;
+            nt->params = sg_alloc<float>(nt->owned, off);
+            nt->grads = sg_alloc<float>(nt->owned, off);
+            nt->adam_m = sg_alloc<float>(nt->owned, off);
+            nt->adam_v = sg_alloc<float>(nt->owned, off);
+            for (float *p : {nt->params, nt->grads, nt->adam_m, nt->adam_v})
+                sg_check(hipMemset(p, 0, sizeof(float) * (size_t)off), "hipMemset");
+            for (int l = 1; l < 5; ++l) nt->act[l] = sg_alloc<float>(nt->owned, (int64_t)max_batch * sg::P * channels[l]);
+            for (auto &g : nt->gbuf) g = sg_alloc<float>(nt->owned, (int64_t)max_batch * sg::P * maxc);
+            nt->chunks = std::max<int32_t>(1, std::min<int32_t>(64, max_batch));
+            int64_t plen = 0;
+            for (int l = 0; l < 4; ++l)
+                plen = std::max<int64_t>(plen, (int64_t)sg::NOFF * channels[l] * channels[l + 1] + channels[l + 1]);
+            nt->part = sg_alloc<float>(nt->owned, plen * nt->chunks);
+            nt->loss_s = sg_alloc<double>(nt->owned, max_batch);
+        } catch (...) {
+            delete nt;
+            throw;
+        }
+        *out = nt;
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_param_count(const hplmm_sg_net *net, int64_t *count) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !count) fail(HPLMM_E_ARG, "NULL argument");
+        *count = net->nparam;
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_set_params(hplmm_sg_net *net, const float *host, int64_t count) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !host) fail(HPLMM_E_ARG, "NULL argument");
+        if (count != net->nparam) fail(HPLMM_E_ARG, "count differs from the parameter count");
+        sg_check(hipMemcpy(net->params, host, sizeof(float) * (size_t)count, hipMemcpyHostToDevice), "copy");
+        for (float *p : {net->adam_m, net->adam_v}) sg_check(hipMemset(p, 0, sizeof(float) * (size_t)count), "hipMemset");
+        net->t = 0;
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_get_params(const hplmm_sg_net *net, float *host, int64_t count) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !host) fail(HPLMM_E_ARG, "NULL argument");
+        if (count != net->nparam) fail(HPLMM_E_ARG, "count differs from the parameter count");
+        sg_check(hipMemcpy(host, net->params, sizeof(float) * (size_t)count, hipMemcpyDeviceToHost), "copy");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_forward(hplmm_sg_net *net, const float *x, int32_t n, float *y, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !x || !y) fail(HPLMM_E_ARG, "NULL argument");
+        if (n < 1 || n > net->max_batch) fail(HPLMM_E_ARG, "n must be in [1, max_batch]");
+        forward_all(*net, x, n, y, to_stream(stream));
+        sg_check(hipGetLastError(), "kernel launch");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_gradient(hplmm_sg_net *net, const float *x, const float *y, int32_t n, double *loss,
+                                          void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !x || !y) fail(HPLMM_E_ARG, "NULL argument");
+        if (n < 1 || n > net->max_batch) fail(HPLMM_E_ARG, "n must be in [1, max_batch]");
+        hplmm_sg_net &nt = *net;
+        const hipStream_t s = to_stream(stream);
+        forward_all(nt, x, n, nullptr, s);
+        // d loss / d output, then back through the layers: layer l's output
+        // gradient g (ReLU already applied for l < 3) gives its parameter
+        // gradients, and its data gradient masked by act[l] > 0 is layer
+        // (l - 1)'s output gradient
+        float *g = nt.gbuf[0];
+        sg::launch_loss(nt.act[4], y, nt.ch[4], x, nt.ch[0], n, g, nt.loss_s, s);
+        int cur = 0;
+        for (int l = 3; l >= 0; --l) {
+            const float *in = l == 0 ? x : nt.act[l];
+            sg::launch_conv_bwd_weight(in, nt.ch[l], nt.gbuf[cur], nt.ch[l + 1], n, nt.part, nt.chunks,
+                                       nt.grads + nt.w_off[l], s);
+            if (l > 0) {
+                sg::launch_conv_bwd_data(nt.gbuf[cur], nt.ch[l + 1], nt.params + nt.w_off[l], nt.gbuf[1 - cur], nt.ch[l],
+                                         nt.act[l], n, s);
+                cur = 1 - cur;
+            }
+        }
+        sg_check(hipGetLastError(), "kernel launch");
+        if (loss) {
+            std::vector<double> ls((size_t)n);
+            sg_check(hipMemcpyAsync(ls.data(), nt.loss_s, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s), "copy");
+            sg_check(hipStreamSynchronize(s), "sync");
+            double t = 0.0;
+            for (double v : ls) t += v;
+            *loss = t / n;
+        }
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_get_grads(const hplmm_sg_net *net, float *host, int64_t count, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!net || !host) fail(HPLMM_E_ARG, "NULL argument");
+        if (count != net->nparam) fail(HPLMM_E_ARG, "count differs from the parameter count");
+        const hipStream_t s = to_stream(stream);
+        sg_check(hipMemcpyAsync(host, net->grads, sizeof(float) * (size_t)count, hipMemcpyDeviceToHost, s), "copy");
+        sg_check(hipStreamSynchronize(s), "sync");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_adam(hplmm_sg_net *net, float lr, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!net) fail(HPLMM_E_ARG, "NULL argument");
+        if (!(lr > 0.f)) fail(HPLMM_E_ARG, "lr must be > 0");
+        net->t += 1;
+        sg::launch_adam(net->params, net->grads, net->adam_m, net->adam_v, net->nparam, lr, 0.9f, 0.999f, 1e-8f,
+                        net->t, to_stream(stream));
+        sg_check(hipGetLastError(), "kernel launch");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" void hplmm_sg_destroy(hplmm_sg_net *net) { delete net; }

@@ -1,0 +1,42 @@
+// Kernels of the learned basis surrogate: a 3D convolutional network on the
+// 9 x 9 x 9 node lattice of a box subdomain (four 3x3x3 'same' convolutions
+// with bias, ReLU after the first three), its training (loss, gradients, Adam)
+// and its inference.  Activations are float32, channel-last:
+// act[s][p][c] with p = (z * 9 + y) * 9 + x.  Weights w[d][ci][co] with
+// d = (dz + 1) * 9 + (dy + 1) * 3 + (dx + 1), then the biases b[co].
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace hplmm {
+namespace sg {
+
+constexpr int G = 9;
+constexpr int P = G * G * G;
+constexpr int NOFF = 27;
+
+// out[s][p][co] = bias[co] + sum_{d, ci} w[d][ci][co] in[s][p + o(d)][ci]
+// (zero outside the lattice), then ReLU when relu != 0.  cin <= 32, cout <= 32.
+void launch_conv_fwd(const float *in, int cin, const float *w, const float *bias, float *out, int cout, int n,
+                     int relu, hipStream_t s);
+// gin[s][p][ci] = [act[s][p][ci] > 0] sum_{d, co} w[d][ci][co] g[s][p - o(d)][co]
+// (act may be null: no mask).  g has cout channels, gin cin.
+void launch_conv_bwd_data(const float *g, int cout, const float *w, float *gin, int cin, const float *act, int n,
+                          hipStream_t s);
+// gw[d][ci][co] = sum_{s, p} in[s][p + o(d)][ci] g[s][p][co] and gb[co] = sum_{s, p} g[s][p][co]:
+// per-chunk partials in part (chunks * (27 cin cout + cout) floats), then a
+// fixed-order reduction into gw (27 cin cout floats) followed by gb.
+void launch_conv_bwd_weight(const float *in, int cin, const float *g, int cout, int n, float *part, int chunks,
+                            float *gwb, hipStream_t s);
+// Per-sample loss |m (pred - y)|^2 / (|m y|^2 + 1e-30) over the first c
+// channels, m = [x[s][p][0] > 0.5] (x has cx channels); gpred = d mean / d pred;
+// loss_s[s] receives each sample's term.
+void launch_loss(const float *pred, const float *y, int c, const float *x, int cx, int n, float *gpred,
+                 double *loss_s, hipStream_t s);
+// Adam with bias correction at step t (>= 1).
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int t, hipStream_t s);
+
+}  // namespace sg
+}  // namespace hplmm

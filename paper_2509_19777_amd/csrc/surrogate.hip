@@ -1,0 +1,293 @@
+// Convolution kernels of the learned basis surrogate on the matrix cores.
+//
+// A 3x3x3 'same' convolution on the 9^3 lattice is an implicit GEMM: rows =
+// lattice positions, columns = output channels, and the contraction runs over
+// the 27 kernel offsets times the input channels.  A work-group owns 64
+// positions of one sample; for each offset it gathers the 64 shifted input
+// rows and that offset's weight slice into LDS and multiplies them with
+// v_mfma_f32_16x16x4f32 (four wavefronts, 16 positions each).  The data
+// gradient is the same product with reversed offsets and transposed weight
+// slices; the weight gradient contracts over positions instead.
+#include <hip/hip_runtime.h>
+
+#include "surrogate.h"
+
+namespace hplmm {
+namespace sg {
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4f mfma(float a, float b, v4f c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// lattice neighbour of position p at offset index d, or -1 outside
+__device__ __forceinline__ int neighbour(int p, int d) {
+    const int x = p % G, y = (p / G) % G, z = p / (G * G);
+    const int xx = x + d % 3 - 1, yy = y + (d / 3) % 3 - 1, zz = z + d / 9 - 1;
+    if (xx < 0 || yy < 0 || zz < 0 || xx >= G || yy >= G || zz >= G) return -1;
+    return (zz * G + yy) * G + xx;
+}
+
+// KIN: input channels padded to a multiple of 4; NOUT: output channels padded
+// to a multiple of 16.  BWD: data gradient (offsets reversed, weights read as
+// w[26 - d][n][k]).
+template <int KIN, int NOUT, bool BWD>
+__global__ void __launch_bounds__(256) conv_kernel(const float *__restrict__ in, int cin, const float *__restrict__ w,
+                                                   int wc0, int wc1, const float *__restrict__ bias,
+                                                   const float *__restrict__ mask, float *__restrict__ out, int cout,
+                                                   int relu) {
+    __shared__ float Xs[64][KIN + 1];
+    __shared__ float Ws[KIN][NOUT + 1];
+    const int s = blockIdx.y;
+    const int p0 = blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    v4f acc[NOUT / 16];
+#pragma unroll
+    for (int nb = 0; nb < NOUT / 16; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float *ins = in + (int64_t)s * P * cin;
+    for (int d = 0; d < NOFF; ++d) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * KIN; e += 256) {
+            const int pl = e / KIN, k = e % KIN;
+            const int p = p0 + pl;
+            float v = 0.f;
+            if (p < P && k < cin) {
+                const int q = neighbour(p, d);
+                if (q >= 0) v = ins[q * cin + k];
+            }
+            Xs[pl][k] = v;
+        }
+        for (int e = threadIdx.x; e < KIN * NOUT; e += 256) {
+            const int k = e / NOUT, n = e % NOUT;
+            float v = 0.f;
+            if (!BWD) {
+                if (k < wc0 && n < wc1) v = w[((int64_t)d * wc0 + k) * wc1 + n];
+            } else {
+                if (n < wc0 && k < wc1) v = w[((int64_t)(NOFF - 1 - d) * wc0 + n) * wc1 + k];
+            }
+            Ws[k][n] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kk = 0; kk < KIN / 4; ++kk) {
+            const float a = Xs[16 * wave + lr][4 * kk + lk];
+#pragma unroll
+            for (int nb = 0; nb < NOUT / 16; ++nb) acc[nb] = mfma(a, Ws[4 * kk + lk][16 * nb + lr], acc[nb]);
+        }
+    }
+    float *outs = out + (int64_t)s * P * cout;
+#pragma unroll
+    for (int nb = 0; nb < NOUT / 16; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = p0 + 16 * wave + 4 * lk + r;
+            const int n = 16 * nb + lr;
+            if (p >= P || n >= cout) continue;
+            float v = acc[nb][r];
+            if (bias) v += bias[n];
+            if (relu) v = v > 0.f ? v : 0.f;
+            if (mask && !(mask[((int64_t)s * P + p) * cout + n] > 0.f)) v = 0.f;
+            outs[p * cout + n] = v;
+        }
+}
+
+template <bool BWD>
+static void conv_dispatch(const float *in, int cin, const float *w, int wc0, int wc1, const float *bias,
+                          const float *mask, float *out, int cout, int n, int relu, hipStream_t s) {
+    if (n <= 0) return;
+    const dim3 grid((P + 63) / 64, n);
+    const int kin = cin <= 4 ? 4 : (cin <= 16 ? 16 : 32);
+    const int nout = cout <= 16 ? 16 : 32;
+#define SG_CONV(K, N)                                                                                              \
+    hipLaunchKernelGGL((conv_kernel<K, N, BWD>), grid, dim3(256), 0, s, in, cin, w, wc0, wc1, bias, mask, out, cout, \
+                       relu)
+    if (kin == 4 && nout == 16) SG_CONV(4, 16);
+    else if (kin == 4) SG_CONV(4, 32);
+    else if (kin == 16 && nout == 16) SG_CONV(16, 16);
+    else if (kin == 16) SG_CONV(16, 32);
+    else if (nout == 16) SG_CONV(32, 16);
+    else SG_CONV(32, 32);
+#undef SG_CONV
+}
+
+void launch_conv_fwd(const float *in, int cin, const float *w, const float *bias, float *out, int cout, int n,
+                     int relu, hipStream_t s) {
+    conv_dispatch<false>(in, cin, w, cin, cout, bias, nullptr, out, cout, n, relu, s);
+}
+
+void launch_conv_bwd_data(const float *g, int cout, const float *w, float *gin, int cin, const float *act, int n,
+                          hipStream_t s) {
+    // the "input" is g (cout channels), the "output" gin (cin channels); the
+    // weight is still stored as w[d][ci][co] = (wc0 = cin, wc1 = cout)
+    conv_dispatch<true>(g, cout, w, cin, cout, nullptr, act, gin, cin, n, 0, s);
+}
+
+// Weight gradient: work-group (offset d, chunk c) contracts over the positions
+// of samples c, c + chunks, ...; wave (mb, nb) owns a 16x16 block of (ci, co).
+template <int KIN, int NOUT>
+__global__ void __launch_bounds__(256) conv_wgrad_kernel(const float *__restrict__ in, int cin,
+                                                         const float *__restrict__ g, int cout, int n, int chunks,
+                                                         float *__restrict__ part) {
+    __shared__ float Xs[64][KIN + 1];
+    __shared__ float Gs[64][NOUT + 1];
+    const int d = blockIdx.x, c = blockIdx.y;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    constexpr int MB = (KIN + 15) / 16, NB = NOUT / 16;
+    const int mb = wave % MB, nb = wave / MB;
+    const bool active = wave < MB * NB;
+    v4f acc = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int s = c; s < n; s += chunks) {
+        const float *ins = in + (int64_t)s * P * cin;
+        const float *gs = g + (int64_t)s * P * cout;
+        for (int p0 = 0; p0 < P; p0 += 64) {
+            __syncthreads();
+            for (int e = threadIdx.x; e < 64 * KIN; e += 256) {
+                const int pl = e / KIN, k = e % KIN;
+                const int p = p0 + pl;
+                float v = 0.f;
+                if (p < P && k < cin) {
+                    const int q = neighbour(p, d);
+                    if (q >= 0) v = ins[q * cin + k];
+                }
+                Xs[pl][k] = v;
+            }
+            for (int e = threadIdx.x; e < 64 * NOUT; e += 256) {
+                const int pl = e / NOUT, k = e % NOUT;
+                const int p = p0 + pl;
+                Gs[pl][k] = (p < P && k < cout) ? gs[p * cout + k] : 0.f;
+            }
+            __syncthreads();
+            if (active) {
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int m = 16 * mb + lr;
+                    const float a = m < KIN ? Xs[4 * kk + lk][m] : 0.f;
+                    acc = mfma(a, Gs[4 * kk + lk][16 * nb + lr], acc);
+                }
+            }
+        }
+    }
+    if (!active) return;
+    float *pc = part + (int64_t)c * (NOFF * cin * cout + cout) + (int64_t)d * cin * cout;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int m = 16 * mb + 4 * lk + r, nn = 16 * nb + lr;
+        if (m < cin && nn < cout) pc[m * cout + nn] = acc[r];
+    }
+}
+
+// bias partials: part[c][27 cin cout + co] = sum over the chunk's samples and positions
+__global__ void __launch_bounds__(256) conv_bgrad_kernel(const float *__restrict__ g, int cin, int cout, int n,
+                                                         int chunks, float *__restrict__ part) {
+    __shared__ float red[256];
+    const int c = blockIdx.x;
+    for (int co = 0; co < cout; ++co) {
+        float t = 0.f;
+        for (int s = c; s < n; s += chunks)
+            for (int p = threadIdx.x; p < P; p += 256) t += g[((int64_t)s * P + p) * cout + co];
+        red[threadIdx.x] = t;
+        __syncthreads();
+        for (int w = 128; w > 0; w >>= 1) {
+            if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) part[(int64_t)c * (NOFF * cin * cout + cout) + NOFF * cin * cout + co] = red[0];
+        __syncthreads();
+    }
+}
+
+__global__ void reduce_chunks_kernel(const float *__restrict__ part, int chunks, int64_t len,
+                                     float *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= len) return;
+    float t = 0.f;
+    for (int c = 0; c < chunks; ++c) t += part[(int64_t)c * len + i];
+    out[i] = t;
+}
+
+void launch_conv_bwd_weight(const float *in, int cin, const float *g, int cout, int n, float *part, int chunks,
+                            float *gwb, hipStream_t s) {
+    if (n <= 0) return;
+    const int kin = cin <= 4 ? 4 : (cin <= 16 ? 16 : 32);
+    const int nout = cout <= 16 ? 16 : 32;
+    const dim3 grid(NOFF, chunks);
+#define SG_WG(K, N) hipLaunchKernelGGL((conv_wgrad_kernel<K, N>), grid, dim3(256), 0, s, in, cin, g, cout, n, chunks, part)
+    if (kin == 4 && nout == 16) SG_WG(4, 16);
+    else if (kin == 4) SG_WG(4, 32);
+    else if (kin == 16 && nout == 16) SG_WG(16, 16);
+    else if (kin == 16) SG_WG(16, 32);
+    else if (nout == 16) SG_WG(32, 16);
+    else SG_WG(32, 32);
+#undef SG_WG
+    hipLaunchKernelGGL(conv_bgrad_kernel, dim3(chunks), dim3(256), 0, s, g, cin, cout, n, chunks, part);
+    const int64_t len = (int64_t)NOFF * cin * cout + cout;
+    hipLaunchKernelGGL(reduce_chunks_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, part, chunks, len,
+                       gwb);
+}
+
+// One work-group per sample: the masked norms by a fixed-order tree, then the gradient.
+__global__ void __launch_bounds__(256) loss_kernel(const float *__restrict__ pred, const float *__restrict__ y,
+                                                   int c, const float *__restrict__ x, int cx, int n,
+                                                   float *__restrict__ gpred, double *__restrict__ loss_s) {
+    __shared__ double rn[256], rd[256];
+    const int s = blockIdx.x;
+    double num = 0.0, den = 0.0;
+    for (int e = threadIdx.x; e < P * c; e += 256) {
+        const int p = e / c;
+        if (!(x[((int64_t)s * P + p) * cx] > 0.5f)) continue;
+        const double yv = y[(int64_t)s * P * c + e], dv = (double)pred[(int64_t)s * P * c + e] - yv;
+        num += dv * dv;
+        den += yv * yv;
+    }
+    rn[threadIdx.x] = num;
+    rd[threadIdx.x] = den;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            rn[threadIdx.x] += rn[threadIdx.x + w];
+            rd[threadIdx.x] += rd[threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    const double dd = rd[0] + 1e-30;
+    if (threadIdx.x == 0) loss_s[s] = rn[0] / dd;
+    const double scale = 2.0 / (dd * n);
+    for (int e = threadIdx.x; e < P * c; e += 256) {
+        const int p = e / c;
+        const int64_t i = (int64_t)s * P * c + e;
+        gpred[i] = (x[((int64_t)s * P + p) * cx] > 0.5f) ? (float)(scale * ((double)pred[i] - (double)y[i])) : 0.f;
+    }
+}
+
+void launch_loss(const float *pred, const float *y, int c, const float *x, int cx, int n, float *gpred,
+                 double *loss_s, hipStream_t s) {
+    if (n <= 0) return;
+    hipLaunchKernelGGL(loss_kernel, dim3(n), dim3(256), 0, s, pred, y, c, x, cx, n, gpred, loss_s);
+}
+
+__global__ void adam_kernel(float *__restrict__ p, const float *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, int64_t n, float lr, float b1, float b2, float eps, float c1,
+                            float c2) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
+                 float eps, int t, hipStream_t s) {
+    if (n <= 0) return;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, g, m, v, n, lr, beta1,
+                       beta2, eps, c1, c2);
+}
+
+}  // namespace sg
+}  // namespace hplmm

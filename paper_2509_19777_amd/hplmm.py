@@ -70,6 +70,15 @@ EXPORTS = {
     "hplmm_debug_read_arena": (i32, [C.c_void_p, i32, i64, i64, C.c_void_p]),
     "hplmm_debug_grain_layout": (i32, [C.c_void_p, P(i64), i64]),
     "hplmm_last_error": (C.c_char_p, []),
+    "hplmm_sg_create": (i32, [P(i32), i32, P(C.c_void_p)]),
+    "hplmm_sg_param_count": (i32, [C.c_void_p, P(i64)]),
+    "hplmm_sg_set_params": (i32, [C.c_void_p, P(C.c_float), i64]),
+    "hplmm_sg_get_params": (i32, [C.c_void_p, P(C.c_float), i64]),
+    "hplmm_sg_forward": (i32, [C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p]),
+    "hplmm_sg_gradient": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, i32, P(f64), C.c_void_p]),
+    "hplmm_sg_get_grads": (i32, [C.c_void_p, P(C.c_float), i64, C.c_void_p]),
+    "hplmm_sg_adam": (i32, [C.c_void_p, C.c_float, C.c_void_p]),
+    "hplmm_sg_destroy": (None, [C.c_void_p]),
 }
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_PARTITION", -3: "E_NOT_SPD",
@@ -378,3 +387,73 @@ def debug_grain_layout(solver):
 def build_problem(problem, w_zeta=None):
     """Assemble and partition a synth.Problem with the library (host only)."""
     return assemble_voxels(problem), partition_from_voxels(problem, w_zeta)
+
+
+# ---- learned basis surrogate network ------------------------------------------------
+class SurrogateNet:
+    """The 3D convolutional basis surrogate (see include/hplmm_surrogate.h).
+
+    Parameters are exchanged as one float32 vector in the library's order:
+    per layer w[d][ci][co] then b[co].  Inputs and targets are CUDA float32
+    tensors shaped (n, 9, 9, 9, c) (channel-last)."""
+
+    def __init__(self, channels=(4, 32, 32, 32, 9), max_batch=256):
+        self.channels = tuple(int(c) for c in channels)
+        self.max_batch = int(max_batch)
+        ch = (i32 * 5)(*self.channels)
+        h = C.c_void_p()
+        _check(lib().hplmm_sg_create(ch, self.max_batch, C.byref(h)))
+        self.h = h
+        n = i64(0)
+        _check(lib().hplmm_sg_param_count(self.h, C.byref(n)))
+        self.n_params = int(n.value)
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h is None or not h.value or lib is None:   # lib is None once the interpreter tears the module down
+            return
+        lib().hplmm_sg_destroy(h)
+        self.h = None
+
+    def set_params(self, flat):
+        a = np.ascontiguousarray(flat, dtype=np.float32)
+        _check(lib().hplmm_sg_set_params(self.h, a.ctypes.data_as(P(C.c_float)), a.size))
+
+    def get_params(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().hplmm_sg_get_params(self.h, a.ctypes.data_as(P(C.c_float)), a.size))
+        return a
+
+    def forward(self, x, out=None):
+        n = x.shape[0]
+        y = torch.empty((n, 9, 9, 9, self.channels[-1]), dtype=torch.float32, device=x.device) if out is None else out
+        _check(lib().hplmm_sg_forward(self.h, _vp(x), int(n), _vp(y), _stream()))
+        return y
+
+    def gradient(self, x, y):
+        loss = f64(0.0)
+        _check(lib().hplmm_sg_gradient(self.h, _vp(x), _vp(y), int(x.shape[0]), C.byref(loss), _stream()))
+        return float(loss.value)
+
+    def get_grads(self):
+        a = np.zeros(self.n_params, dtype=np.float32)
+        _check(lib().hplmm_sg_get_grads(self.h, a.ctypes.data_as(P(C.c_float)), a.size, _stream()))
+        return a
+
+    def adam(self, lr):
+        _check(lib().hplmm_sg_adam(self.h, C.c_float(lr), _stream()))
+
+
+def flatten_params(params):
+    """[(w (3,3,3,ci,co), b (co,)), ...] -> one float32 vector in the library's order."""
+    return np.concatenate([np.concatenate([w.reshape(-1), b.reshape(-1)]) for w, b in params]).astype(np.float32)
+
+
+def unflatten_params(flat, channels):
+    out, o = [], 0
+    for ci, co in zip(channels[:-1], channels[1:]):
+        nw = 27 * ci * co
+        out.append((np.asarray(flat[o:o + nw], dtype=np.float64).reshape(3, 3, 3, ci, co),
+                    np.asarray(flat[o + nw:o + nw + co], dtype=np.float64)))
+        o += nw + co
+    return out

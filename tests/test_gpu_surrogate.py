@@ -1,0 +1,102 @@
+"""GPU surrogate network (HIP kernels through the C ABI) against the float64
+oracle: forward outputs, loss, every parameter gradient and one Adam step.
+
+Tolerances: float32 arithmetic with float32 accumulation over at most
+27 x 32 = 864 products per output (forward) and 729 x n x 27 products per
+weight gradient; normwise relative error bounds 2e-5 (forward, loss) and
+2e-4 (gradients) leave a wide margin over the ~1e-6 expected."""
+import numpy as np
+import pytest
+
+from oracle import surrogate as osg
+
+pytestmark = pytest.mark.gpu
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _case(channels, n, seed):
+    rng = np.random.default_rng(seed)
+    params = osg.init_params(rng, channels)
+    params = [(w, 0.1 * rng.standard_normal(b.shape)) for w, b in params]
+    x = rng.standard_normal((n, 9, 9, 9, channels[0]))
+    x[..., 0] = (rng.random((n, 9, 9, 9)) < 0.6).astype(float)
+    y = rng.standard_normal((n, 9, 9, 9, channels[-1]))
+    return params, x, y
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b))
+
+
+@pytest.mark.parametrize("channels,n", [((4, 8, 8, 8, 9), 3), ((4, 32, 32, 32, 9), 2), ((4, 5, 17, 3, 9), 1)])
+def test_forward_matches_oracle(channels, n):
+    torch = _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    params, x, y = _case(channels, n, 1)
+    net = hp.SurrogateNet(channels, max_batch=4)
+    net.set_params(hp.flatten_params(params))
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    out = net.forward(xt).cpu().numpy().astype(np.float64)
+    ref = osg.forward(params, x)[-1]
+    assert _rel(out, ref) <= 2e-5
+
+
+@pytest.mark.parametrize("channels,n", [((4, 8, 8, 8, 9), 3), ((4, 32, 32, 32, 9), 2)])
+def test_gradients_match_oracle(channels, n):
+    torch = _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    params, x, y = _case(channels, n, 2)
+    net = hp.SurrogateNet(channels, max_batch=n)
+    net.set_params(hp.flatten_params(params))
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    yt = torch.from_numpy(y.astype(np.float32)).cuda()
+    loss = net.gradient(xt, yt)
+    acts = osg.forward(params, x)
+    mask = (x[..., 0] > 0.5).astype(float)
+    ref_loss = osg.loss(acts[-1], y, mask)
+    assert abs(loss - ref_loss) <= 2e-5 * ref_loss
+    ref = osg.backward(params, acts, osg.loss_grad(acts[-1], y, mask))
+    got = hp.unflatten_params(net.get_grads(), channels)
+    for l, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref)):
+        assert _rel(gw, rw) <= 2e-4, (l, _rel(gw, rw))
+        assert _rel(gb, rb) <= 2e-4, (l, _rel(gb, rb))
+
+
+def test_adam_step_matches_oracle():
+    torch = _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    channels = (4, 8, 8, 8, 9)
+    params, x, y = _case(channels, 2, 3)
+    net = hp.SurrogateNet(channels, max_batch=2)
+    net.set_params(hp.flatten_params(params))
+    net.gradient(torch.from_numpy(x.astype(np.float32)).cuda(), torch.from_numpy(y.astype(np.float32)).cuda())
+    lr = 1e-3
+    net.adam(lr)
+    got = net.get_params()
+    acts = osg.forward(params, x)
+    mask = (x[..., 0] > 0.5).astype(float)
+    grads = osg.backward(params, acts, osg.loss_grad(acts[-1], y, mask))
+    st = {"t": 0, "m": [0.0] * 8, "v": [0.0] * 8}
+    ref = hp.flatten_params(osg.adam_step(params, grads, st, lr)).astype(np.float64)
+    g = hp.flatten_params(grads).astype(np.float64)
+    p0 = hp.flatten_params(params).astype(np.float64)
+    # the first step is -lr g / (|g| + eps): compare where the gradient is not tiny (sign-stable)
+    big = np.abs(g) > 1e-3 * np.abs(g).max()
+    assert np.all(np.abs(got[big] - ref[big]) <= 1e-3 * lr + 1e-6 * np.abs(p0[big]))
+    assert np.all(np.abs(got - p0) <= 1.01 * lr + 1e-6 * np.abs(p0))
+
+
+def test_bad_arguments_raise():
+    _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    with pytest.raises(hp.HplmmError):
+        hp.SurrogateNet((4, 33, 8, 8, 9))
+    net = hp.SurrogateNet((4, 8, 8, 8, 9), max_batch=2)
+    with pytest.raises(hp.HplmmError):
+        net.set_params(np.zeros(net.n_params + 1, dtype=np.float32))
