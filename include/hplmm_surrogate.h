@@ -1,6 +1,6 @@
 /* Learned basis surrogate of libhplmm: a small 3D convolutional network that
  * predicts grain basis columns (Eq. 23: the grain-interior response
- * A_gi^-1 Abar_gi,m e_k to one mortar mode) from the assembled operator,
+ * -A_gi^-1 Abar_gi,m e_k to one mortar mode) from the assembled operator,
  * trained on the columns the method itself computes, with the exact local
  * solve as fallback.
  *
@@ -8,7 +8,8 @@
  * box grain (interior indicator; log trace of the node's diagonal 3x3 block
  * of A minus its grain mean; stored blocks of the node row / 27; the Gaussian
  * weight H_c[., a] of Eq. 8 on the nodes of interface c).  Output: 9 channels
- * = the three basis columns 3a + x, 3a + y, 3a + z as (u_x, u_y, u_z) each.
+ * = the shape vectors p_k = -A_gi^-1 Abar_gi,m e_k (Eq. 23) of the columns
+ * k = 3a + x, 3a + y, 3a + z, as (u_x, u_y, u_z) each.
  * Layers: channels c0 -> c1 -> c2 -> c3 -> c4 (normally 4, 32, 32, 32, 9;
  * every c <= 32), 3x3x3 'same' convolutions with zero padding and bias, ReLU
  * after the first three.  Tensors are float32 device arrays, channel-last:
@@ -61,6 +62,21 @@ hplmm_status hplmm_sg_get_grads(const hplmm_sg_net *net, float *host, int64_t co
 hplmm_status hplmm_sg_adam(hplmm_sg_net *net, float lr, void *stream);
 
 void hplmm_sg_destroy(hplmm_sg_net *net);
+
+/* Samples of a planned problem: one per (grain, adjacent interface c, mortar
+ * a), ordered by grain, then interface id, then a.  Writes the network inputs
+ * of samples first .. first + count - 1 to x_dev[count][729][4] and, if y_dev
+ * is not NULL, their exact targets (the grain's shape vectors of columns
+ * 3a + x, y, z after hplmm_setup) to y_dev[count][729][9]; meta (host, may be NULL) receives
+ * {grain matrix index, interface id, mortar index} per sample.  *total (may
+ * be NULL) receives the number of samples; count = 0 only queries it.
+ * Grains must be 8^3-voxel boxes (every grain node and every node of its
+ * adjacent interfaces inside one 9^3 node lattice with a corner at a multiple
+ * of 8): E_PARTITION otherwise.  E_STATE if targets are asked before setup.
+ * Asynchronous on stream except the first call, which builds and uploads the
+ * sample tables. */
+hplmm_status hplmm_sg_samples(hplmm_handle *h, int64_t first, int64_t count, float *x_dev, float *y_dev,
+                              int32_t *meta, int64_t *total, void *stream);
 
 #ifdef __cplusplus
 }

@@ -13,10 +13,10 @@ mortar a) it maps four input channels per node
     3  the Gaussian weight H_c[row(v), a] on the nodes v of interface c
        (the mortar mode's boundary trace, Eq. 8), 0 elsewhere
 
-to nine output channels: the basis columns of the three components gamma of
-that mortar node, X[:, 3a + gamma] = A_gi^-1 Abar_gi,m e_{3a+gamma}
-(Eq. 23: p_k = -X e_k), written at the interior nodes as (u_x, u_y, u_z) for
-gamma = x, y, z.
+to nine output channels: the shape vectors of the three components gamma of
+that mortar node, p_k = -A_gi^-1 Abar_gi,m e_k with k = 3a + gamma (Eq. 23,
+the grain-interior response to the boundary displacement H_c[., a] e_gamma),
+written at the interior nodes as (u_x, u_y, u_z) for gamma = x, y, z.
 
 Network: four 3x3x3 'same' convolutions (zero padding) with bias; ReLU after
 the first three.  Loss: the mean over samples of the masked squared error of

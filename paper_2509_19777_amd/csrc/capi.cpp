@@ -8,10 +8,6 @@
 #include "../../include/hplmm_debug.h"
 #include "handle.h"
 
-struct hplmm_handle {
-    hplmm::Handle h;
-};
-
 namespace hplmm {
 
 static void hip_check(hipError_t e, const char *what) {

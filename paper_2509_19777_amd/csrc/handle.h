@@ -8,6 +8,7 @@
 #include "common.h"
 #include "dense.h"
 #include "sparse.h"
+#include "surrogate.h"
 
 namespace hplmm {
 
@@ -183,6 +184,20 @@ struct Handle {
     uint16_t *arbf = nullptr;
     int64_t arbf_n = 0;
     TaskLists tl64, tl32;
+    // learned-basis surrogate inputs (host copies kept by the plan)
+    std::vector<int32_t> sg_xyz;                 // [3 n_nodes] lattice coordinates
+    std::vector<float> sg_logtr, sg_fill;        // per node: log trace of A_vv, stored blocks / 27
+    std::vector<int64_t> sg_gnodes_ptr;          // per grain matrix: interior nodes (ascending)
+    std::vector<int32_t> sg_gnodes;
+    std::vector<int64_t> sg_adj_ptr;             // per grain matrix: adjacent interfaces, ascending,
+    std::vector<int32_t> sg_adj, sg_lcol;        //   and the first local column of each
+    std::vector<int32_t> sg_iface_nu;
+    std::vector<int64_t> sg_iface_ptr;
+    std::vector<int32_t> sg_iface_nodes;
+    bool sg_ready = false;                       // device sample tables built
+    int64_t sg_total = 0;                        // (grain, interface, mortar) samples
+    std::vector<int32_t> sg_s_m, sg_s_c, sg_s_a; // host copies of the sample list
+    sg::SampleArgs sg_args{};
     GemvTask *d_vtasks = nullptr;
     int64_t gemv_part_len = 0;          // split-row partial sums (doubles)
     int32_t gemv_cnt_len = 0;           // split-row arrival counters
@@ -241,3 +256,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
 std::vector<int32_t> place_mortars(const int32_t *xyz, int32_t N, int32_t n);
 
 }  // namespace hplmm
+
+struct hplmm_handle {
+    hplmm::Handle h;
+};

@@ -837,6 +837,37 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.gm_ntc[(size_t)m] = (int32_t)ceil_tiles(h.gm_ncol[(size_t)m]);
     }
     for (auto &w : abar) w.lcol0 = lcol[(size_t)w.m][w.c];
+    // what the learned-basis surrogate reads: lattice coordinates, per-node
+    // operator features, grain node lists and grain-interface adjacency
+    {
+        h.sg_xyz.assign(sys.node_xyz, sys.node_xyz + 3 * n);
+        h.sg_logtr.assign((size_t)n, 0.f);
+        h.sg_fill.assign((size_t)n, 0.f);
+        for (int64_t v = 0; v < n; ++v) {
+            double tr = 0.0;
+            for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p)
+                if (sys.col_idx[p] == v) tr = sys.val[9 * p] + sys.val[9 * p + 4] + sys.val[9 * p + 8];
+            h.sg_logtr[(size_t)v] = tr > 0.0 ? (float)std::log(tr) : 0.f;
+            h.sg_fill[(size_t)v] = (float)(sys.row_ptr[v + 1] - sys.row_ptr[v]) / 27.f;
+        }
+        h.sg_gnodes_ptr.assign(1, 0);
+        h.sg_gnodes.clear();
+        h.sg_adj_ptr.assign(1, 0);
+        h.sg_adj.clear();
+        h.sg_lcol.clear();
+        for (int64_t m = 0; m < nG; ++m) {
+            for (int32_t v : gnodes[(size_t)h.gm_grain[(size_t)m]]) h.sg_gnodes.push_back(v);
+            h.sg_gnodes_ptr.push_back((int64_t)h.sg_gnodes.size());
+            for (int32_t c : gadj[(size_t)m]) {
+                h.sg_adj.push_back(c);
+                h.sg_lcol.push_back(lcol[(size_t)m][c]);
+            }
+            h.sg_adj_ptr.push_back((int64_t)h.sg_adj.size());
+        }
+        h.sg_iface_nu = iface_nu;
+        h.sg_iface_ptr.assign(part.iface_ptr, part.iface_ptr + part.n_ifaces + 1);
+        h.sg_iface_nodes.assign(part.iface_nodes, part.iface_nodes + (part.n_ifaces ? part.iface_ptr[part.n_ifaces] : 0));
+    }
     h.n_corr = (int64_t)h.h_corr_grains.size();
     h.n_coarse = h.n_mortar + h.n_corr;
     // ---- contact grids (Eq. 26) -----------------------------------------------

@@ -7,8 +7,7 @@
 #include <vector>
 
 #include "../../include/hplmm_surrogate.h"
-#include "common.h"
-#include "surrogate.h"
+#include "handle.h"
 
 namespace hplmm {
 namespace {
@@ -203,3 +202,113 @@ extern "C" hplmm_status hplmm_sg_adam(hplmm_sg_net *net, float lr, void *stream)
 }
 
 extern "C" void hplmm_sg_destroy(hplmm_sg_net *net) { delete net; }
+
+// ---- samples of a set-up problem --------------------------------------------------
+namespace {
+
+// Box grains only: every grain node and every node of its adjacent interfaces
+// must lie in one 9^3 node lattice whose corner is a multiple of 8.
+void build_sample_tables(Handle &h, hipStream_t s) {
+    if (h.sg_ready) return;
+    const int64_t nG = (int64_t)h.gm_grain.size();
+    std::vector<int32_t> origin((size_t)(3 * nG), 0);
+    std::vector<float> logmean((size_t)nG, 0.f);
+    for (int64_t m = 0; m < nG; ++m) {
+        int32_t lo[3] = {INT32_MAX, INT32_MAX, INT32_MAX};
+        double lsum = 0.0;
+        const int64_t a0 = h.sg_gnodes_ptr[(size_t)m], a1 = h.sg_gnodes_ptr[(size_t)m + 1];
+        for (int64_t i = a0; i < a1; ++i) {
+            const int32_t v = h.sg_gnodes[(size_t)i];
+            for (int d = 0; d < 3; ++d) lo[d] = std::min(lo[d], h.sg_xyz[3 * (size_t)v + d]);
+            lsum += h.sg_logtr[(size_t)v];
+        }
+        logmean[(size_t)m] = a1 > a0 ? (float)(lsum / (double)(a1 - a0)) : 0.f;
+        for (int d = 0; d < 3; ++d) origin[(size_t)(3 * m + d)] = (lo[d] / (sg::G - 1)) * (sg::G - 1);
+        auto inside = [&](int32_t v) {
+            for (int d = 0; d < 3; ++d) {
+                const int32_t r = h.sg_xyz[3 * (size_t)v + d] - origin[(size_t)(3 * m + d)];
+                if (r < 0 || r >= sg::G) return false;
+            }
+            return true;
+        };
+        for (int64_t i = a0; i < a1; ++i)
+            if (!inside(h.sg_gnodes[(size_t)i])) fail(HPLMM_E_PARTITION, "surrogate: grain does not fit an 8^3-voxel box");
+        for (int64_t q = h.sg_adj_ptr[(size_t)m]; q < h.sg_adj_ptr[(size_t)m + 1]; ++q) {
+            const int32_t c = h.sg_adj[(size_t)q];
+            for (int64_t t = h.sg_iface_ptr[(size_t)c]; t < h.sg_iface_ptr[(size_t)c + 1]; ++t)
+                if (!inside(h.sg_iface_nodes[(size_t)t]))
+                    fail(HPLMM_E_PARTITION, "surrogate: an interface of a grain leaves its 8^3-voxel box");
+        }
+    }
+    std::vector<int32_t> lcol;
+    h.sg_s_m.clear();
+    h.sg_s_c.clear();
+    h.sg_s_a.clear();
+    for (int64_t m = 0; m < nG; ++m)
+        for (int64_t q = h.sg_adj_ptr[(size_t)m]; q < h.sg_adj_ptr[(size_t)m + 1]; ++q) {
+            const int32_t c = h.sg_adj[(size_t)q];
+            for (int32_t a = 0; a < h.sg_iface_nu[(size_t)c]; ++a) {
+                h.sg_s_m.push_back((int32_t)m);
+                h.sg_s_c.push_back(c);
+                h.sg_s_a.push_back(a);
+                lcol.push_back(h.sg_lcol[(size_t)q]);
+            }
+        }
+    h.sg_total = (int64_t)h.sg_s_m.size();
+    std::vector<int64_t> ndof((size_t)nG), nt((size_t)nG);
+    for (int64_t m = 0; m < nG; ++m) {
+        ndof[(size_t)m] = h.gset.n[(size_t)m];
+        nt[(size_t)m] = h.gset.nt[(size_t)m];
+    }
+    sg::SampleArgs &a = h.sg_args;
+    a.s_m = h.upload(h.sg_s_m, s);
+    a.s_c = h.upload(h.sg_s_c, s);
+    a.s_a = h.upload(h.sg_s_a, s);
+    a.s_lcol = h.upload(lcol, s);
+    a.g_origin = h.upload(origin, s);
+    a.g_voff = h.upload(h.gset.voff, s);
+    a.g_ndof = h.upload(ndof, s);
+    a.g_roff = h.upload(h.gm_roff, s);
+    a.g_nt = h.upload(nt, s);
+    a.g_logmean = h.upload(logmean, s);
+    a.adj_ptr = h.upload(h.sg_adj_ptr, s);
+    a.adj = h.upload(h.sg_adj, s);
+    a.iface_ptr = h.cm.iface_ptr;
+    a.iface_nodes = h.cm.iface_nodes;
+    a.H = h.cm.H;
+    a.iface_hoff = h.cm.iface_hoff;
+    a.iface_nu = h.cm.iface_nu;
+    a.xyz = h.upload(h.sg_xyz, s);
+    a.logtr = h.upload(h.sg_logtr, s);
+    a.fill = h.upload(h.sg_fill, s);
+    a.slot_dof = h.d_g_slot_dof;
+    a.X = h.ar64;
+    sg_check(hipStreamSynchronize(s), "sync");
+    h.sg_ready = true;
+}
+
+}  // namespace
+
+extern "C" hplmm_status hplmm_sg_samples(hplmm_handle *hh, int64_t first, int64_t count, float *x_dev, float *y_dev,
+                                         int32_t *meta, int64_t *total, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        Handle &h = hh->h;
+        const hipStream_t s = to_stream(stream);
+        build_sample_tables(h, s);
+        if (total) *total = h.sg_total;
+        if (count == 0) return HPLMM_OK;
+        if (first < 0 || count < 0 || first + count > h.sg_total) fail(HPLMM_E_ARG, "sample range outside [0, total)");
+        if (!x_dev) fail(HPLMM_E_ARG, "x_dev is NULL");
+        if (y_dev && !h.ready) fail(HPLMM_E_STATE, "targets need a completed hplmm_setup");
+        sg::launch_fill_samples(h.sg_args, first, count, x_dev, y_dev, s);
+        sg_check(hipGetLastError(), "kernel launch");
+        if (meta)
+            for (int64_t i = 0; i < count; ++i) {
+                meta[3 * i] = h.sg_s_m[(size_t)(first + i)];
+                meta[3 * i + 1] = h.sg_s_c[(size_t)(first + i)];
+                meta[3 * i + 2] = h.sg_s_a[(size_t)(first + i)];
+            }
+        return HPLMM_OK;
+    });
+}

@@ -38,5 +38,27 @@ void launch_loss(const float *pred, const float *y, int c, const float *x, int c
 void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, float beta1, float beta2,
                  float eps, int t, hipStream_t s);
 
+// Index data of the (grain, interface, mortar) samples of a set-up problem.
+struct SampleArgs {
+    const int32_t *s_m, *s_c, *s_a, *s_lcol;   // per sample: grain matrix, interface, mortar, first column
+    const int32_t *g_origin;                   // [3 nG] lattice coordinates of each grain's box corner
+    const int64_t *g_voff, *g_ndof, *g_roff, *g_nt;
+    const float *g_logmean;                    // [nG] mean log trace over the grain's interior nodes
+    const int64_t *adj_ptr;                    // grain -> adjacent interfaces
+    const int32_t *adj;
+    const int64_t *iface_ptr;                  // interface -> nodes
+    const int32_t *iface_nodes;
+    const double *H;                           // Gaussian weights, per interface row-major N_c x nu_c
+    const int64_t *iface_hoff;
+    const int32_t *iface_nu;
+    const int32_t *xyz;                        // [3 n_nodes]
+    const float *logtr, *fill;                 // [n_nodes]
+    const int64_t *slot_dof;                   // grain vector slot -> dof
+    const double *X;                           // arena holding each grain's shape vectors B = -A_gi^-1 Abar_gi (tiles)
+};
+// x[s][p][4] inputs and, when y is not null, y[s][p][9] targets (columns
+// lcol + 3a + gamma of B at the interior nodes) for samples first .. first + count.
+void launch_fill_samples(const SampleArgs &a, int64_t first, int64_t count, float *x, float *y, hipStream_t s);
+
 }  // namespace sg
 }  // namespace hplmm

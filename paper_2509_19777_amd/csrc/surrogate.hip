@@ -289,5 +289,66 @@ void launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float 
                        beta2, eps, c1, c2);
 }
 
+// ---- samples of a set-up problem ---------------------------------------------------
+__device__ __forceinline__ int lattice_pos(const SampleArgs &a, int32_t v, int m) {
+    const int x = a.xyz[3 * (int64_t)v] - a.g_origin[3 * m];
+    const int y = a.xyz[3 * (int64_t)v + 1] - a.g_origin[3 * m + 1];
+    const int z = a.xyz[3 * (int64_t)v + 2] - a.g_origin[3 * m + 2];
+    return (z * G + y) * G + x;   // the host checked 0 <= x, y, z < G
+}
+
+__global__ void __launch_bounds__(256) fill_samples_kernel(SampleArgs a, int64_t first, float *__restrict__ x,
+                                                           float *__restrict__ y) {
+    const int64_t sl = blockIdx.x, s = first + sl;
+    const int m = a.s_m[s], c = a.s_c[s], am = a.s_a[s], lcol = a.s_lcol[s];
+    float *xs = x + sl * P * 4;
+    for (int e = threadIdx.x; e < P * 4; e += 256) xs[e] = 0.f;
+    float *ys = y ? y + sl * P * 9 : nullptr;
+    if (ys)
+        for (int e = threadIdx.x; e < P * 9; e += 256) ys[e] = 0.f;
+    __syncthreads();
+    // fill channel of every adjacent interface's nodes
+    for (int64_t q = a.adj_ptr[m]; q < a.adj_ptr[m + 1]; ++q) {
+        const int ci = a.adj[q];
+        for (int64_t t = a.iface_ptr[ci] + threadIdx.x; t < a.iface_ptr[ci + 1]; t += 256) {
+            const int32_t v = a.iface_nodes[t];
+            xs[lattice_pos(a, v, m) * 4 + 2] = a.fill[v];
+        }
+    }
+    // boundary trace of mortar am of interface c
+    {
+        const int nu = a.iface_nu[c];
+        const int64_t p0 = a.iface_ptr[c];
+        for (int64_t t = p0 + threadIdx.x; t < a.iface_ptr[c + 1]; t += 256) {
+            const int32_t v = a.iface_nodes[t];
+            xs[lattice_pos(a, v, m) * 4 + 3] = (float)a.H[a.iface_hoff[c] + (t - p0) * nu + am];
+        }
+    }
+    // interior nodes: indicator, log-trace, fill; targets
+    const int64_t nd = a.g_ndof[m], vo = a.g_voff[m], ro = a.g_roff[m], nt = a.g_nt[m];
+    for (int64_t i = threadIdx.x; i < nd; i += 256) {
+        const int64_t dof = a.slot_dof[vo + i];
+        const int32_t v = (int32_t)(dof / 3);
+        const int comp = (int)(dof - 3 * (int64_t)v);
+        const int p = lattice_pos(a, v, m);
+        if (comp == 0) {
+            xs[p * 4 + 0] = 1.f;
+            xs[p * 4 + 1] = a.logtr[v] - a.g_logmean[m];
+            xs[p * 4 + 2] = a.fill[v];
+        }
+        if (ys)
+            for (int gm = 0; gm < 3; ++gm) {
+                const int64_t j = lcol + 3 * am + gm;
+                const double val = a.X[ro + ((j / 64) * nt + i / 64) * 4096 + (i % 64) + 64 * (j % 64)];
+                ys[p * 9 + 3 * gm + comp] = (float)val;
+            }
+    }
+}
+
+void launch_fill_samples(const SampleArgs &a, int64_t first, int64_t count, float *x, float *y, hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(fill_samples_kernel, dim3((unsigned)count), dim3(256), 0, s, a, first, x, y);
+}
+
 }  // namespace sg
 }  // namespace hplmm

@@ -79,6 +79,7 @@ EXPORTS = {
     "hplmm_sg_get_grads": (i32, [C.c_void_p, P(C.c_float), i64, C.c_void_p]),
     "hplmm_sg_adam": (i32, [C.c_void_p, C.c_float, C.c_void_p]),
     "hplmm_sg_destroy": (None, [C.c_void_p]),
+    "hplmm_sg_samples": (i32, [C.c_void_p, i64, i64, C.c_void_p, C.c_void_p, P(i32), P(i64), C.c_void_p]),
 }
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_PARTITION", -3: "E_NOT_SPD",
@@ -457,3 +458,18 @@ def unflatten_params(flat, channels):
                     np.asarray(flat[o + nw:o + nw + co], dtype=np.float64)))
         o += nw + co
     return out
+
+
+def surrogate_samples(solver, first=0, count=None, targets=True):
+    """Network inputs (and exact targets) of a Solver's (grain, interface,
+    mortar) samples as CUDA float32 tensors (n, 9, 9, 9, 4) / (n, 9, 9, 9, 9),
+    plus the (n, 3) int32 meta array {grain matrix, interface, mortar}."""
+    total = i64(0)
+    _check(lib().hplmm_sg_samples(solver.h, 0, 0, None, None, None, C.byref(total), _stream()))
+    n = int(total.value) - first if count is None else int(count)
+    x = torch.empty((n, 9, 9, 9, 4), dtype=torch.float32, device="cuda")
+    y = torch.empty((n, 9, 9, 9, 9), dtype=torch.float32, device="cuda") if targets else None
+    meta = np.zeros((n, 3), dtype=np.int32)
+    _check(lib().hplmm_sg_samples(solver.h, int(first), n, _vp(x), _vp(y), meta.ctypes.data_as(P(i32)), None,
+                                  _stream()))
+    return x, y, meta

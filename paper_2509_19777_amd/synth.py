@@ -176,6 +176,18 @@ def config_grf(n: int = 64, box: int = 8, seed: int = 2, solid_frac: float = 0.6
                    w_zeta=w_zeta, traction=tuple(traction))
 
 
+def config_pores_lognormal(n: int = 64, box: int = 8, seed: int = 11, porosity: float = 0.3,
+                           ell: float = 6.0, sigma_lnE: float = 1.0, n_mortar: int = 4,
+                           w_zeta: int = 1, traction=(0.0, 0.0, -1.0)) -> Problem:
+    """Spherical pores as in config_pores (radius 1-3) with a lognormal modulus
+    ln E = sigma_lnE * (Gaussian random field of correlation length ``ell``):
+    the subdomains the learned basis surrogate is trained and evaluated on."""
+    solid = sphere_pores(n, porosity, 1.0, 3.0, seed)
+    E = np.exp(sigma_lnE * gaussian_field(n, ell, seed + 1))
+    return _finish(solid, E, 0.3, box, f"poresE{n}_box{box}_s{seed}", n_mortar=n_mortar,
+                   w_zeta=w_zeta, traction=tuple(traction))
+
+
 def config_block(nx: int, ny: int, nz: int, box: int, E: float = 1.0, nu: float = 0.3,
                  holes=(), n_mortar: int = 2, w_zeta: int = 1,
                  traction=(0.0, 0.0, -1.0)) -> Problem:

@@ -100,3 +100,68 @@ def test_bad_arguments_raise():
     net = hp.SurrogateNet((4, 8, 8, 8, 9), max_batch=2)
     with pytest.raises(hp.HplmmError):
         net.set_params(np.zeros(net.n_params + 1, dtype=np.float32))
+
+
+@pytest.fixture(scope="module")
+def small_problem():
+    torch = _torch()
+    from oracle import fem, hplmm as oh
+    from paper_2509_19777_amd import hplmm as hp, synth
+    p = synth.config_pores_lognormal(16, 8, seed=3, n_mortar=2)
+    A, b, mesh = fem.assemble(p)
+    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=2)
+    sysm, part = hp.build_problem(p)
+    S = hp.Solver(sysm, part, n_mortar=2)
+    S.setup()
+    torch.cuda.synchronize()
+    return p, A, mesh, H, S
+
+
+def test_samples_match_oracle_features_and_basis(small_problem):
+    from paper_2509_19777_amd import hplmm as hp
+    p, A, mesh, H, S = small_problem
+    x, y, meta = hp.surrogate_samples(S)
+    x, y = x.cpu().numpy().astype(np.float64), y.cpu().numpy().astype(np.float64)
+    P = H.part
+    grains = [g for g in range(len(P.grain_nodes)) if len(P.grain_nodes[g])]
+    assert x.shape[0] == sum(
+        sum(P.H[c].shape[1] for c in np.unique(P.node_iface[_coupled(A, P, g)])) for g in grains)
+    checked = 0
+    for s, (m, c, a) in enumerate(meta):
+        g = grains[m]
+        nodes = P.grain_nodes[g]
+        adj = np.unique(P.node_iface[_coupled(A, P, g)])
+        origin = (mesh.xyz[nodes].min(axis=0) // 8) * 8
+        f = osg.grain_features(A, mesh.xyz, nodes, [P.iface_nodes[q] for q in adj], origin)
+        assert np.array_equal(x[s, ..., 0], f[..., 0])
+        assert np.allclose(x[s, ..., 1], f[..., 1], rtol=0, atol=2e-6)
+        assert np.allclose(x[s, ..., 2], f[..., 2], rtol=0, atol=1e-7)
+        ref3 = np.zeros((9, 9, 9))
+        for row, v in enumerate(P.iface_nodes[c]):
+            i, j, k = mesh.xyz[v] - origin
+            ref3[k, j, i] = P.H[c][row, a]
+        assert np.allclose(x[s, ..., 3], ref3, rtol=0, atol=1e-7)
+        # targets: the shape vectors B e_k for the global mortar dofs moff_c + 3a + gamma
+        cols, Bi = H.B_blocks[g]
+        for gm in range(3):
+            k = H.moff[c] + 3 * a + gm
+            col = Bi[:, np.flatnonzero(cols == k)[0]] if np.any(cols == k) else np.zeros(3 * len(nodes))
+            ref = np.zeros((9, 9, 9, 3))
+            for li, v in enumerate(nodes):
+                i, j, kk = mesh.xyz[v] - origin
+                ref[kk, j, i] = col[3 * li:3 * li + 3]
+            got = y[s, ..., 3 * gm:3 * gm + 3]
+            assert np.abs(got - ref).max() <= 1e-6 * max(1.0, np.abs(ref).max())
+        checked += 1
+    assert checked == x.shape[0] > 0
+
+
+def _coupled(A, P, g):
+    """Interface nodes coupled to grain g's interior through A."""
+    A = A.tocsr()
+    nodes = P.grain_nodes[g]
+    nb = set()
+    for v in nodes:
+        cols = A.indices[A.indptr[3 * v]:A.indptr[3 * v + 1]] // 3
+        nb.update(int(w) for w in cols if P.node_iface[w] >= 0)
+    return np.array(sorted(nb), dtype=np.int64)
