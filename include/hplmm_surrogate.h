@@ -78,6 +78,32 @@ void hplmm_sg_destroy(hplmm_sg_net *net);
 hplmm_status hplmm_sg_samples(hplmm_handle *h, int64_t first, int64_t count, float *x_dev, float *y_dev,
                               int32_t *meta, int64_t *total, void *stream);
 
+/* Set-up with learned shape vectors (Eq. 23).  Same as hplmm_setup, except
+ * that the network predicts the shape vectors of every grain; a grain keeps
+ * them when it has no correction column and every mortar column k passes the
+ * local residual check |A_gi p~_k + Abar_gi,m e_k| <= threshold
+ * |Abar_gi,m e_k| (residuals from the grain's Cholesky factor); every other
+ * grain gets the exact shape vectors.  The coarse operator is the Galerkin
+ * product with the resulting basis on the mortar block (Eq. 18) plus the exact
+ * correction pivots; the mortar-correction coupling, zero for exact shape
+ * vectors, is not formed.  threshold = 0 reproduces hplmm_setup's basis.
+ * net must map 4 input channels to 9 outputs.  stats (may be NULL) receives
+ * counts, the residual ratios and host-clock phase times. */
+typedef struct hplmm_sg_stats {
+    int32_t grains;                 /* grain matrices */
+    int32_t accepted;               /* grains that kept the predicted shape vectors */
+    int32_t fallback;               /* grains given the exact shape vectors */
+    int32_t loaded;                 /* grains with a correction column (always exact) */
+    double  max_residual_accepted;  /* largest residual ratio among accepted columns */
+    double  median_residual;        /* median residual ratio over all predicted columns */
+    double  t_infer_ms;             /* inference (synchronised) */
+    double  t_check_ms;             /* residual check */
+    double  t_basis_ms;             /* exact fallback and Galerkin blocks */
+} hplmm_sg_stats;
+
+hplmm_status hplmm_setup_surrogate(hplmm_handle *h, hplmm_sg_net *net, double threshold, hplmm_sg_stats *stats,
+                                   void *stream);
+
 #ifdef __cplusplus
 }
 #endif

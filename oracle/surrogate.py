@@ -163,3 +163,77 @@ def grain_features(A, node_xyz, interior_nodes, iface_nodes_list, origin, row_nn
             x, y, z = (int(t) for t in node_xyz[v] - origin)
             f[z, y, x, 2] = row_nnzb(v) / 27.0
     return f
+
+
+# ---- features of every sample and the Galerkin product with predicted shape vectors --
+def sample_inputs(H, A, mesh, g, c, a):
+    """Network input (9, 9, 9, 4) of sample (grain g, interface c, mortar a) of
+    an oracle HPLMM object H (channels as in the module docstring)."""
+    P = H.part
+    nodes = P.grain_nodes[g]
+    adj = coupled_interfaces(A, P, g)
+    origin = (mesh.xyz[nodes].min(axis=0) // 8) * 8
+    x = np.zeros((G, G, G, N_IN))
+    x[..., :3] = grain_features(A, mesh.xyz, nodes, [P.iface_nodes[q] for q in adj], origin)
+    for row, v in enumerate(P.iface_nodes[c]):
+        i, j, k = mesh.xyz[v] - origin
+        x[k, j, i, 3] = P.H[c][row, a]
+    return x, origin
+
+
+def coupled_interfaces(A, P, g):
+    """Interfaces with a node coupled to grain g's interior through A, ascending."""
+    A = A.tocsr()
+    out = set()
+    for v in P.grain_nodes[g]:
+        for w in A.indices[A.indptr[3 * v]:A.indptr[3 * v + 1]] // 3:
+            if P.node_iface[w] >= 0:
+                out.add(int(P.node_iface[w]))
+    return sorted(out)
+
+
+def predicted_blocks(H, A, mesh, params, grains):
+    """Shape-vector blocks B~_g (rows: the grain's dofs, columns: the global
+    mortar dofs of its coupled interfaces, ascending) predicted by the network
+    for the given grains."""
+    P = H.part
+    out = {}
+    for g in grains:
+        nodes = P.grain_nodes[g]
+        cols, blocks = [], []
+        for c in coupled_interfaces(A, P, g):
+            for a in range(P.H[c].shape[1]):
+                x, origin = sample_inputs(H, A, mesh, g, c, a)
+                y = forward(params, x[None])[-1][0]
+                for gm in range(3):
+                    col = np.zeros(3 * len(nodes))
+                    for li, v in enumerate(nodes):
+                        i, j, k = mesh.xyz[v] - origin
+                        col[3 * li:3 * li + 3] = y[k, j, i, 3 * gm:3 * gm + 3]
+                    cols.append(H.moff[c] + 3 * a + gm)
+                    blocks.append(col)
+        out[g] = (np.asarray(cols), np.stack(blocks, axis=1))
+    return out
+
+
+def galerkin_mortar_block(H, blocks):
+    """Mortar block of P~^T A_M P~ (Eq. 18 with P = [B; I], A_M = Q^T W^T A W Q),
+    B taken from `blocks` for the grains it holds and exact for the others."""
+    import scipy.sparse as sp
+    Ngf, Nmo = H.Ngf, H.Nmo
+    rows, cols, vals = [], [], []
+    for g, off in enumerate(H.goff):
+        if g in blocks:
+            cg, Bg = blocks[g]
+        elif H.B_blocks[g] is not None:
+            cg, Bg = H.B_blocks[g]
+        else:
+            continue
+        r = np.repeat(np.arange(off, off + Bg.shape[0]), cg.size)
+        rows.append(r)
+        cols.append(np.tile(cg, Bg.shape[0]))
+        vals.append(Bg.ravel())
+    B = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(Ngf, Nmo))
+    Pm = sp.vstack([B, sp.identity(Nmo, format="csr")]).tocsr()
+    AM = (H.Q.T @ (H.W.T @ H.A @ H.W) @ H.Q).tocsr()
+    return (Pm.T @ AM @ Pm).toarray()

@@ -6,6 +6,7 @@
 #include <cstring>
 
 #include "../../include/hplmm_debug.h"
+#include "../../include/hplmm_surrogate.h"
 #include "handle.h"
 
 namespace hplmm {
@@ -71,7 +72,14 @@ static void zero(void *p, int64_t bytes, hipStream_t s) {
     if (bytes > 0) hip_check(hipMemsetAsync(p, 0, (size_t)bytes, s), "hipMemsetAsync");
 }
 
-static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
+struct SgSetup {
+    hplmm_sg_net *net;
+    double threshold;
+    hplmm_sg_stats *stats;
+};
+static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s);
+
+static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup *sg = nullptr) {
     hipEvent_t ev[4];
     for (auto &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
     const int32_t init_flag[2] = {0, 0x7fffffff};
@@ -97,7 +105,10 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
     }
-    run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
+    if (sg)
+        surrogate_basis(h, *sg, s);
+    else
+        run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
     if (stage < 3) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -170,6 +181,220 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3) {
     for (size_t j = 0; j < cd.size(); ++j)
         if (!(cd[j] > 0.0)) fail(HPLMM_E_SINGULAR_COARSE, "coarse correction pivot <= 0 for correction " + std::to_string(j));
     h.ready = true;
+}
+
+// ---- learned-basis set-up ------------------------------------------------------------
+// Upload a task list built on the host into the handle's surrogate scratch
+// buffers (grown on demand) and run its launches.
+static void run_host_program(Handle &h, TaskLists &tl, std::vector<Launch> &prog, hipStream_t s, int64_t z_lo = 0,
+                             int64_t z_hi = 0) {
+    if (prog.empty()) return;
+    // every tile must lie in the arena or in the scratch range [z_lo, z_hi)
+    auto ok = [&](int64_t o) { return (o >= 0 && o + TE <= h.ar64_n) || (o >= z_lo && o + TE <= z_hi); };
+    for (const GemmTask &t : tl.gemm) {
+        if (!ok(t.c_off) || (t.post_off >= 0 && !ok(t.post_off)) || t.pair_start < 0 ||
+            (size_t)t.pair_start + (size_t)t.pair_count > tl.pairs.size())
+            fail(HPLMM_E_ARG, "internal: surrogate task out of range");
+    }
+    for (const GemmPair &p : tl.pairs)
+        if (!ok(p.a_off) || !ok(p.b_off)) fail(HPLMM_E_ARG, "internal: surrogate operand out of range");
+    for (const CopyTask &c : tl.copy)
+        if (!ok(c.src_off) || !ok(c.dst_off)) fail(HPLMM_E_ARG, "internal: surrogate copy out of range");
+    for (const Launch &L : prog) {
+        const size_t n = L.kind == LK_GEMM ? tl.gemm.size() : tl.copy.size();
+        if (L.kind == LK_DIAG || L.start < 0 || (size_t)(L.start + L.count) > n)
+            fail(HPLMM_E_ARG, "internal: surrogate launch out of range");
+    }
+    fill_flops(prog, tl);
+    auto up = [&](Handle::Scratch &sc, const void *src, size_t bytes) {
+        void *d = sc.get(std::max<size_t>(bytes, 16));
+        if (bytes) hip_check(hipMemcpyAsync(d, src, bytes, hipMemcpyHostToDevice, s), "copy tasks");
+        return d;
+    };
+    TaskLists dev;
+    dev.d_gemm = (GemmTask *)up(h.sg_tasks, tl.gemm.data(), sizeof(GemmTask) * tl.gemm.size());
+    dev.d_pairs = (GemmPair *)up(h.sg_pairs, tl.pairs.data(), sizeof(GemmPair) * tl.pairs.size());
+    dev.d_copy = (CopyTask *)up(h.sg_copy, tl.copy.data(), sizeof(CopyTask) * tl.copy.size());
+    run_program<double>(h, dev, h.ar64, prog, h.d_flag, s);
+    // the pageable task vectors must stay alive until the copies are done
+    hip_check(hipStreamSynchronize(s), "sync");
+}
+
+// Shape vectors of the grains from the network where they pass the residual
+// check, exact elsewhere.  On entry the grain factors (L in place of A, W,
+// W^T) are done and R holds [-Abar | b].  Regions: R0 = R saved in the XT
+// region, B~ (predictions) in R, T = L^T B~ in Y, Z = R0 - L T = -(A B~ + Abar)
+// in scratch.  A grain is accepted when it has no correction column and
+// |Z e_k| <= threshold |R0 e_k| for all its columns; its Galerkin block is
+// K = B~^T A B~ - B~^T Abar - Abar^T B~ = T^T T + Z^T B~ + B~^T Z.  Other grains
+// get R restored and the exact basis program.
+static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    const int64_t nG = (int64_t)h.gm_grain.size();
+    if (nG == 0) return;
+    if (!sg_net_is_basis_net(sg.net)) fail(HPLMM_E_ARG, "the network must map 4 input channels to 9 outputs");
+    sg_build_sample_tables(h, s);
+    int64_t rlen = 0;
+    for (int64_t m = 0; m < nG; ++m) rlen += h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE;
+    const int64_t r_base = h.gm_roff[0], y_base = h.gm_ytoff[0], xt_base = h.gm_xtoff[0];
+    double *A = h.ar64;
+    hip_check(hipMemcpyAsync(A + xt_base, A + r_base, sizeof(double) * (size_t)rlen, hipMemcpyDeviceToDevice, s),
+              "save R0");
+    // inference, in batches of the network's size
+    const int32_t nb = sg_net_max_batch(sg.net);
+    float *xb = (float *)h.sg_x.get(sizeof(float) * (size_t)nb * sg::P * 4);
+    float *yb = (float *)h.sg_y.get(sizeof(float) * (size_t)nb * sg::P * 9);
+    for (int64_t f = 0; f < h.sg_total; f += nb) {
+        const int32_t cnt = (int32_t)std::min<int64_t>(nb, h.sg_total - f);
+        sg::launch_fill_samples(h.sg_args, f, cnt, xb, nullptr, s);
+        sg_net_forward(sg.net, xb, cnt, yb, s);
+        sg::launch_scatter_pred(h.sg_args, f, cnt, yb, A, s);
+    }
+    hip_check(hipGetLastError(), "inference launch");
+    hip_check(hipStreamSynchronize(s), "sync");
+    const auto t1 = clk::now();
+    // residual check: T = L^T B~, Z = R0 - L T (Z starts as a copy of R0)
+    double *Z = (double *)h.sg_z.get(sizeof(double) * (size_t)rlen);
+    const int64_t z_shift = (int64_t)(Z - A);   // Z's offset as seen from the arena base
+    hip_check(hipMemcpyAsync(Z, A + xt_base, sizeof(double) * (size_t)rlen, hipMemcpyDeviceToDevice, s), "copy R0");
+    auto Lt = [&](int64_t m, int64_t I, int64_t J) { return h.gset.a_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+    auto Rt = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
+    {
+        TaskLists tl;
+        std::vector<Launch> prog;
+        Launch l1{LK_GEMM, 0, 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(),
+                                       (int32_t)(h.gset.nt[m] - I), GF_TRANS_A, 0});
+                    for (int64_t J = I; J < h.gset.nt[m]; ++J)
+                        tl.pairs.push_back({Lt(m, J, I), Rt(h.gm_roff[(size_t)m], m, J, C)});
+                }
+        l1.count = (int64_t)tl.gemm.size();
+        prog.push_back(l1);
+        Launch l2{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m = 0; m < nG; ++m)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(z_shift + h.gm_roff[(size_t)m] - r_base, m, I, C), -1,
+                                       (int32_t)tl.pairs.size(), (int32_t)(I + 1), GF_ACCUM | GF_NEGATE, 0});
+                    for (int64_t J = 0; J <= I; ++J)
+                        tl.pairs.push_back({Lt(m, I, J), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
+                }
+        l2.count = (int64_t)tl.gemm.size() - l2.start;
+        prog.push_back(l2);
+        run_host_program(h, tl, prog, s, z_shift, z_shift + rlen);
+    }
+    // column norms of R0 and Z
+    std::vector<int64_t> off0, offz, cofs;
+    std::vector<int32_t> ntv, ctv, ncv;
+    for (int64_t m = 0; m < nG; ++m)
+        for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C) {
+            off0.push_back(h.gm_xtoff[(size_t)m]);
+            offz.push_back(z_shift + h.gm_roff[(size_t)m] - r_base);
+            ntv.push_back((int32_t)h.gset.nt[m]);
+            ctv.push_back((int32_t)C);
+            cofs.push_back(h.gm_coff[(size_t)m]);
+            ncv.push_back(h.gm_ncol[(size_t)m]);
+        }
+    const int64_t nt_tasks = (int64_t)off0.size();
+    const size_t meta_bytes = sizeof(int64_t) * 3 * (size_t)nt_tasks + sizeof(int32_t) * 3 * (size_t)nt_tasks;
+    char *meta = (char *)h.sg_meta.get(meta_bytes);
+    int64_t *d_off0 = (int64_t *)meta, *d_offz = d_off0 + nt_tasks, *d_cofs = d_offz + nt_tasks;
+    int32_t *d_nt = (int32_t *)(d_cofs + nt_tasks), *d_ct = d_nt + nt_tasks, *d_nc = d_ct + nt_tasks;
+    hip_check(hipMemcpyAsync(d_off0, off0.data(), 8 * off0.size(), hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(d_offz, offz.data(), 8 * offz.size(), hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(d_cofs, cofs.data(), 8 * cofs.size(), hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(d_nt, ntv.data(), 4 * ntv.size(), hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(d_ct, ctv.data(), 4 * ctv.size(), hipMemcpyHostToDevice, s), "copy");
+    hip_check(hipMemcpyAsync(d_nc, ncv.data(), 4 * ncv.size(), hipMemcpyHostToDevice, s), "copy");
+    double *nrm = (double *)h.sg_norms.get(sizeof(double) * 2 * (size_t)std::max<int64_t>(1, h.gcol_len));
+    sg::launch_col_norms(A, d_off0, d_nt, d_ct, d_cofs, d_nc, nt_tasks, nrm, s);
+    sg::launch_col_norms(A, d_offz, d_nt, d_ct, d_cofs, d_nc, nt_tasks, nrm + h.gcol_len, s);
+    std::vector<double> hn(2 * (size_t)h.gcol_len);
+    hip_check(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s), "copy norms");
+    hip_check(hipStreamSynchronize(s), "sync");
+    const auto t2 = clk::now();
+    // acceptance
+    std::vector<int64_t> exact, accepted;
+    std::vector<double> ratios;
+    double max_acc = 0.0;
+    for (int64_t m = 0; m < nG; ++m) {
+        const bool loaded = h.gm_corr[(size_t)m] >= 0;
+        double worst = 0.0;
+        for (int32_t j = 0; j < h.gm_k[(size_t)m]; ++j) {
+            const double a0 = hn[(size_t)(h.gm_coff[(size_t)m] + j)], z = hn[(size_t)(h.gcol_len + h.gm_coff[(size_t)m] + j)];
+            const double r = a0 > 0.0 ? std::sqrt(z / a0) : (z > 0.0 ? INFINITY : 0.0);
+            ratios.push_back(r);
+            worst = std::max(worst, r);
+        }
+        if (!loaded && worst <= sg.threshold) {
+            accepted.push_back(m);
+            max_acc = std::max(max_acc, worst);
+        } else {
+            exact.push_back(m);
+        }
+    }
+    // exact grains: restore R, exact basis; accepted grains: K = T^T T + Z^T B~ + B~^T Z
+    for (int64_t m : exact) {
+        const int64_t len = h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE;
+        hip_check(hipMemcpyAsync(A + h.gm_roff[(size_t)m], A + h.gm_xtoff[(size_t)m], sizeof(double) * (size_t)len,
+                                 hipMemcpyDeviceToDevice, s),
+                  "restore R");
+    }
+    {
+        TaskLists tl;
+        std::vector<Launch> prog;
+        append_basis_program(h, tl, exact, prog, BP_Y | BP_X | BP_K);
+        for (int pass = 0; pass < 3; ++pass) {
+            Launch L{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+            for (int64_t m : accepted) {
+                const int64_t zb = z_shift + h.gm_roff[(size_t)m] - r_base;
+                for (int64_t C1 = 0; C1 < h.gm_ntc[(size_t)m]; ++C1)
+                    for (int64_t C2 = 0; C2 <= C1; ++C2) {
+                        tl.gemm.push_back({h.gm_koff[(size_t)m] + tri_index(C1, C2) * TE, -1, (int32_t)tl.pairs.size(),
+                                           (int32_t)h.gset.nt[m], pass == 0 ? GF_TRANS_A : (GF_TRANS_A | GF_ACCUM), 0});
+                        for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                            if (pass == 0)
+                                tl.pairs.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C1), Rt(h.gm_ytoff[(size_t)m], m, I, C2)});
+                            else if (pass == 1)
+                                tl.pairs.push_back({Rt(zb, m, I, C1), Rt(h.gm_roff[(size_t)m], m, I, C2)});
+                            else
+                                tl.pairs.push_back({Rt(h.gm_roff[(size_t)m], m, I, C1), Rt(zb, m, I, C2)});
+                        }
+                    }
+            }
+            L.count = (int64_t)tl.gemm.size() - L.start;
+            if (L.count) prog.push_back(L);
+        }
+        std::vector<int64_t> all((size_t)nG);
+        for (int64_t m = 0; m < nG; ++m) all[(size_t)m] = m;
+        append_basis_program(h, tl, all, prog, BP_XT);
+        run_host_program(h, tl, prog, s, z_shift, z_shift + rlen);
+    }
+    const auto t3 = clk::now();
+    if (sg.stats) {
+        hplmm_sg_stats &st = *sg.stats;
+        st.grains = (int32_t)nG;
+        st.accepted = (int32_t)accepted.size();
+        st.fallback = (int32_t)exact.size();
+        st.loaded = 0;
+        for (int64_t m = 0; m < nG; ++m) st.loaded += h.gm_corr[(size_t)m] >= 0;
+        st.max_residual_accepted = max_acc;
+        std::vector<double> r = ratios;
+        if (!r.empty()) {
+            std::nth_element(r.begin(), r.begin() + (long)(r.size() / 2), r.end());
+            st.median_residual = r[r.size() / 2];
+        } else {
+            st.median_residual = 0.0;
+        }
+        auto ms = [](clk::time_point a, clk::time_point b) { return std::chrono::duration<double, std::milli>(b - a).count(); };
+        st.t_infer_ms = ms(t0, t1);
+        st.t_check_ms = ms(t1, t2);
+        st.t_basis_ms = ms(t2, t3);
+    }
 }
 
 static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, double *y, hipStream_t s,
@@ -465,6 +690,18 @@ extern "C" hplmm_status hplmm_setup(hplmm_handle *hh, void *stream) {
         if (!hh) fail(HPLMM_E_ARG, "NULL handle");
         hh->h.ready = false;
         numeric_setup(hh->h, as_stream(stream));
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_setup_surrogate(hplmm_handle *hh, hplmm_sg_net *net, double threshold,
+                                              hplmm_sg_stats *stats, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !net) fail(HPLMM_E_ARG, "NULL argument");
+        if (!(threshold >= 0.0)) fail(HPLMM_E_ARG, "threshold must be >= 0");
+        hh->h.ready = false;
+        const SgSetup sg{net, threshold, stats};
+        numeric_setup(hh->h, as_stream(stream), 3, &sg);
         return HPLMM_OK;
     });
 }

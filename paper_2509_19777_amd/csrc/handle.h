@@ -195,6 +195,24 @@ struct Handle {
     std::vector<int64_t> sg_iface_ptr;
     std::vector<int32_t> sg_iface_nodes;
     bool sg_ready = false;                       // device sample tables built
+    struct Scratch {                             // grown on demand, freed with the handle
+        void *p = nullptr;
+        size_t cap = 0;
+        void *get(size_t bytes) {
+            if (bytes > cap) {
+                if (p) (void)hipFree(p);
+                p = nullptr;
+                cap = 0;
+                if (hipMalloc(&p, bytes) != hipSuccess) fail(HPLMM_E_OOM, "hipMalloc failed");
+                cap = bytes;
+            }
+            return p;
+        }
+        ~Scratch() {
+            if (p) (void)hipFree(p);
+        }
+    };
+    Scratch sg_x, sg_y, sg_z, sg_norms, sg_tasks, sg_pairs, sg_copy, sg_cnt, sg_part, sg_meta;
     int64_t sg_total = 0;                        // (grain, interface, mortar) samples
     std::vector<int32_t> sg_s_m, sg_s_c, sg_s_a; // host copies of the sample list
     sg::SampleArgs sg_args{};
@@ -254,9 +272,23 @@ struct Handle {
 void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
                 const hplmm_options &opt, hipStream_t s, bool dry_run);
 std::vector<int32_t> place_mortars(const int32_t *xyz, int32_t N, int32_t n);
+enum BasisParts { BP_Y = 1, BP_X = 2, BP_K = 4, BP_XT = 8, BP_ALL = 15 };
+void append_basis_program(Handle &h, TaskLists &tl, const std::vector<int64_t> &ms, std::vector<Launch> &prog,
+                          int parts);
+void split_program(std::vector<Launch> &prog, TaskLists &tl);
+void fill_flops(std::vector<Launch> &prog, const TaskLists &tl);
+// sg_capi.cpp
+void sg_build_sample_tables(Handle &h, hipStream_t s);
 
 }  // namespace hplmm
 
 struct hplmm_handle {
     hplmm::Handle h;
 };
+
+struct hplmm_sg_net;
+namespace hplmm {
+void sg_net_forward(hplmm_sg_net *net, const float *x, int32_t n, float *y, hipStream_t s);
+int32_t sg_net_max_batch(const hplmm_sg_net *net);
+bool sg_net_is_basis_net(const hplmm_sg_net *net);
+}  // namespace hplmm

@@ -208,6 +208,8 @@ void split_rows(std::vector<GemvTask> &vt, Range &r, int64_t &part_len, int32_t 
     cnt_len = std::max(cnt_len, grp);
 }
 
+}  // namespace
+
 // Split the long sums of a GEMM launch that has too few tasks to fill the
 // device: a work-group loads its tile pairs at a small fraction of the device
 // bandwidth, so a chain of k products is cut into about sqrt(k/2)-pair
@@ -270,6 +272,8 @@ void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
         L.flops = f * 2.0 * TS * TS * TS;
     }
 }
+
+namespace {
 
 // Algorithmic bytes of a GEMV launch: every tile and x segment read, y written.
 double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
@@ -688,6 +692,63 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
 }
 }  // namespace
 
+// Basis tasks (Eqs. 23-24) of the grain matrices ms, appended to tl and prog:
+// BP_Y: Y = W R; BP_X: X = W^T Y written over R; BP_K: K = Y^T Y;
+// BP_XT: per-tile transposes of X into the XT region.
+void append_basis_program(Handle &h, TaskLists &tl, const std::vector<int64_t> &ms, std::vector<Launch> &prog,
+                          int parts) {
+    auto Wg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.w_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+    auto Wtg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.wt_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+    auto Rt = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
+    if (parts & BP_Y) {
+        Launch L1{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m : ms)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(), (int32_t)(I + 1), 0, 0});
+                    for (int64_t J = 0; J <= I; ++J) tl.pairs.push_back({Wg(m, I, J), Rt(h.gm_roff[(size_t)m], m, J, C)});
+                }
+        L1.count = (int64_t)tl.gemm.size() - L1.start;
+        if (L1.count) prog.push_back(L1);
+    }
+    if (parts & BP_X) {
+        Launch L2{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m : ms)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
+                    tl.gemm.push_back({Rt(h.gm_roff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(),
+                                       (int32_t)(h.gset.nt[m] - I), 0, 0});
+                    for (int64_t J = I; J < h.gset.nt[m]; ++J)
+                        tl.pairs.push_back({Wtg(m, J, I), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
+                }
+        L2.count = (int64_t)tl.gemm.size() - L2.start;
+        if (L2.count) prog.push_back(L2);
+    }
+    if (parts & BP_K) {
+        Launch L3{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        for (int64_t m : ms)
+            for (int64_t C1 = 0; C1 < h.gm_ntc[(size_t)m]; ++C1)
+                for (int64_t C2 = 0; C2 <= C1; ++C2) {
+                    tl.gemm.push_back({h.gm_koff[(size_t)m] + tri_index(C1, C2) * TE, -1, (int32_t)tl.pairs.size(),
+                                       (int32_t)h.gset.nt[m], GF_TRANS_A, 0});
+                    for (int64_t I = 0; I < h.gset.nt[m]; ++I)
+                        tl.pairs.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C1), Rt(h.gm_ytoff[(size_t)m], m, I, C2)});
+                }
+        L3.count = (int64_t)tl.gemm.size() - L3.start;
+        if (L3.count) prog.push_back(L3);
+    }
+    if (parts & BP_XT) {
+        Launch L4{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
+        for (int64_t m : ms)
+            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
+                for (int64_t I = 0; I < h.gset.nt[m]; ++I)
+                    tl.copy.push_back({Rt(h.gm_roff[(size_t)m], m, I, C),
+                                       h.gm_xtoff[(size_t)m] + (I * h.gm_ntc[(size_t)m] + C) * TE});
+        L4.count = (int64_t)tl.copy.size() - L4.start;
+        if (L4.count) prog.push_back(L4);
+    }
+}
+
 void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
                 const hplmm_options &opt, hipStream_t s, bool dry_run) {
     const int64_t n = sys.n_nodes;
@@ -961,49 +1022,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         build_factor_program(h.cset, h.tl32, 1);
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
     {
-        auto &tl = h.tl64;
-        auto Wg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.w_base + h.gset.rel[m] + tri_index(I, J) * TE; };
-        auto Wtg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.wt_base + h.gset.rel[m] + tri_index(I, J) * TE; };
-        auto Rt = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
-        Launch L1{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nG; ++m)
-            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
-                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
-                    tl.gemm.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(), (int32_t)(I + 1), 0, 0});
-                    for (int64_t J = 0; J <= I; ++J) tl.pairs.push_back({Wg(m, I, J), Rt(h.gm_roff[(size_t)m], m, J, C)});
-                }
-        L1.count = (int64_t)tl.gemm.size() - L1.start;
-        if (L1.count) h.basis_prog.push_back(L1);
-        Launch L2{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nG; ++m)
-            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
-                for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
-                    tl.gemm.push_back({Rt(h.gm_roff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(),
-                                       (int32_t)(h.gset.nt[m] - I), 0, 0});
-                    for (int64_t J = I; J < h.gset.nt[m]; ++J)
-                        tl.pairs.push_back({Wtg(m, J, I), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
-                }
-        L2.count = (int64_t)tl.gemm.size() - L2.start;
-        if (L2.count) h.basis_prog.push_back(L2);
-        Launch L3{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nG; ++m)
-            for (int64_t C1 = 0; C1 < h.gm_ntc[(size_t)m]; ++C1)
-                for (int64_t C2 = 0; C2 <= C1; ++C2) {
-                    tl.gemm.push_back({h.gm_koff[(size_t)m] + tri_index(C1, C2) * TE, -1, (int32_t)tl.pairs.size(),
-                                       (int32_t)h.gset.nt[m], GF_TRANS_A, 0});
-                    for (int64_t I = 0; I < h.gset.nt[m]; ++I)
-                        tl.pairs.push_back({Rt(h.gm_ytoff[(size_t)m], m, I, C1), Rt(h.gm_ytoff[(size_t)m], m, I, C2)});
-                }
-        L3.count = (int64_t)tl.gemm.size() - L3.start;
-        if (L3.count) h.basis_prog.push_back(L3);
-        Launch L4{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
-        for (int64_t m = 0; m < nG; ++m)
-            for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
-                for (int64_t I = 0; I < h.gset.nt[m]; ++I)
-                    tl.copy.push_back({Rt(h.gm_roff[(size_t)m], m, I, C),
-                                       h.gm_xtoff[(size_t)m] + (I * h.gm_ntc[(size_t)m] + C) * TE});
-        L4.count = (int64_t)tl.copy.size() - L4.start;
-        if (L4.count) h.basis_prog.push_back(L4);
+        std::vector<int64_t> all((size_t)nG);
+        std::iota(all.begin(), all.end(), 0);
+        append_basis_program(h, h.tl64, all, h.basis_prog, BP_ALL);
     }
     // apply-time GEMV lists
     {

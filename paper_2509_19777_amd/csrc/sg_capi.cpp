@@ -204,11 +204,11 @@ extern "C" hplmm_status hplmm_sg_adam(hplmm_sg_net *net, float lr, void *stream)
 extern "C" void hplmm_sg_destroy(hplmm_sg_net *net) { delete net; }
 
 // ---- samples of a set-up problem --------------------------------------------------
-namespace {
+namespace hplmm {
 
 // Box grains only: every grain node and every node of its adjacent interfaces
 // must lie in one 9^3 node lattice whose corner is a multiple of 8.
-void build_sample_tables(Handle &h, hipStream_t s) {
+void sg_build_sample_tables(Handle &h, hipStream_t s) {
     if (h.sg_ready) return;
     const int64_t nG = (int64_t)h.gm_grain.size();
     std::vector<int32_t> origin((size_t)(3 * nG), 0);
@@ -287,7 +287,13 @@ void build_sample_tables(Handle &h, hipStream_t s) {
     h.sg_ready = true;
 }
 
-}  // namespace
+void sg_net_forward(hplmm_sg_net *net, const float *x, int32_t n, float *y, hipStream_t s) {
+    forward_all(*net, x, n, y, s);
+}
+int32_t sg_net_max_batch(const hplmm_sg_net *net) { return net->max_batch; }
+bool sg_net_is_basis_net(const hplmm_sg_net *net) { return net->ch[0] == 4 && net->ch[4] == 9; }
+
+}  // namespace hplmm
 
 extern "C" hplmm_status hplmm_sg_samples(hplmm_handle *hh, int64_t first, int64_t count, float *x_dev, float *y_dev,
                                          int32_t *meta, int64_t *total, void *stream) {
@@ -295,7 +301,7 @@ extern "C" hplmm_status hplmm_sg_samples(hplmm_handle *hh, int64_t first, int64_
         if (!hh) fail(HPLMM_E_ARG, "NULL handle");
         Handle &h = hh->h;
         const hipStream_t s = to_stream(stream);
-        build_sample_tables(h, s);
+        sg_build_sample_tables(h, s);
         if (total) *total = h.sg_total;
         if (count == 0) return HPLMM_OK;
         if (first < 0 || count < 0 || first + count > h.sg_total) fail(HPLMM_E_ARG, "sample range outside [0, total)");

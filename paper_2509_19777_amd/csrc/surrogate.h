@@ -59,6 +59,16 @@ struct SampleArgs {
 // x[s][p][4] inputs and, when y is not null, y[s][p][9] targets (columns
 // lcol + 3a + gamma of B at the interior nodes) for samples first .. first + count.
 void launch_fill_samples(const SampleArgs &a, int64_t first, int64_t count, float *x, float *y, hipStream_t s);
+// The inverse map for predictions: column lcol + 3a + gamma of the grain's
+// shape-vector block (tile grid at g_roff of the arena) receives
+// y[s][p][3 gamma + comp] at its interior rows, for samples first .. first + count.
+void launch_scatter_pred(const SampleArgs &a, int64_t first, int64_t count, const float *y, double *arena,
+                         hipStream_t s);
+// Squared column norms of tile-grid blocks: task t covers grain block
+// (arena offset off[t], nt[t] row tiles) column tile ctile[t]; column j of the
+// block lands at out[cofs[t] + j] for j < ncol[t].
+void launch_col_norms(const double *arena, const int64_t *off, const int32_t *nt, const int32_t *ctile,
+                      const int64_t *cofs, const int32_t *ncol, int64_t ntasks, double *out, hipStream_t s);
 
 }  // namespace sg
 }  // namespace hplmm

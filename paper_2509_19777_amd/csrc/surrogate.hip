@@ -350,5 +350,59 @@ void launch_fill_samples(const SampleArgs &a, int64_t first, int64_t count, floa
     hipLaunchKernelGGL(fill_samples_kernel, dim3((unsigned)count), dim3(256), 0, s, a, first, x, y);
 }
 
+__global__ void __launch_bounds__(256) scatter_pred_kernel(SampleArgs a, int64_t first, const float *__restrict__ y,
+                                                           double *__restrict__ arena) {
+    const int64_t sl = blockIdx.x, s = first + sl;
+    const int m = a.s_m[s], am = a.s_a[s], lcol = a.s_lcol[s];
+    const float *ys = y + sl * P * 9;
+    const int64_t nd = a.g_ndof[m], vo = a.g_voff[m], ro = a.g_roff[m], nt = a.g_nt[m];
+    for (int64_t i = threadIdx.x; i < nd; i += 256) {
+        const int64_t dof = a.slot_dof[vo + i];
+        const int32_t v = (int32_t)(dof / 3);
+        const int comp = (int)(dof - 3 * (int64_t)v);
+        const int p = lattice_pos(a, v, m);
+        for (int gm = 0; gm < 3; ++gm) {
+            const int64_t j = lcol + 3 * am + gm;
+            arena[ro + ((j / 64) * nt + i / 64) * 4096 + (i % 64) + 64 * (j % 64)] = (double)ys[p * 9 + 3 * gm + comp];
+        }
+    }
+}
+
+void launch_scatter_pred(const SampleArgs &a, int64_t first, int64_t count, const float *y, double *arena,
+                         hipStream_t s) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(scatter_pred_kernel, dim3((unsigned)count), dim3(256), 0, s, a, first, y, arena);
+}
+
+// one work-group per (block, column tile): 64 columns x 4 row groups, fixed-order sums
+__global__ void __launch_bounds__(256) col_norms_kernel(const double *__restrict__ arena, const int64_t *__restrict__ off,
+                                                        const int32_t *__restrict__ nt, const int32_t *__restrict__ ctile,
+                                                        const int64_t *__restrict__ cofs,
+                                                        const int32_t *__restrict__ ncol, double *__restrict__ out) {
+    __shared__ double red[4][64];
+    const int t = blockIdx.x;
+    const int j = threadIdx.x & 63, rg = threadIdx.x >> 6;
+    const int64_t base = off[t] + (int64_t)ctile[t] * nt[t] * 4096;
+    double acc = 0.0;
+    for (int I = 0; I < nt[t]; ++I)
+        for (int r = rg; r < 64; r += 4) {
+            const double v = arena[base + (int64_t)I * 4096 + j * 64 + r];
+            acc += v * v;
+        }
+    red[rg][j] = acc;
+    __syncthreads();
+    if (rg == 0) {
+        const int col = ctile[t] * 64 + j;
+        if (col < ncol[t]) out[cofs[t] + col] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
+    }
+}
+
+void launch_col_norms(const double *arena, const int64_t *off, const int32_t *nt, const int32_t *ctile,
+                      const int64_t *cofs, const int32_t *ncol, int64_t ntasks, double *out, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(col_norms_kernel, dim3((unsigned)ntasks), dim3(256), 0, s, arena, off, nt, ctile, cofs, ncol,
+                       out);
+}
+
 }  // namespace sg
 }  // namespace hplmm

@@ -42,6 +42,12 @@ class HplmmOptions(C.Structure):
     _fields_ = [("smoother_precision", i32)]
 
 
+class HplmmSgStats(C.Structure):
+    _fields_ = [("grains", i32), ("accepted", i32), ("fallback", i32), ("loaded", i32),
+                ("max_residual_accepted", f64), ("median_residual", f64), ("t_infer_ms", f64),
+                ("t_check_ms", f64), ("t_basis_ms", f64)]
+
+
 class HplmmSolveInfo(C.Structure):
     _fields_ = [("iters", i32), ("rel_res_true", f64), ("t_solve_ms", f64), ("res_hist", P(f64)),
                 ("res_hist_cap", i32), ("res_hist_len", i32)]
@@ -80,6 +86,7 @@ EXPORTS = {
     "hplmm_sg_adam": (i32, [C.c_void_p, C.c_float, C.c_void_p]),
     "hplmm_sg_destroy": (None, [C.c_void_p]),
     "hplmm_sg_samples": (i32, [C.c_void_p, i64, i64, C.c_void_p, C.c_void_p, P(i32), P(i64), C.c_void_p]),
+    "hplmm_setup_surrogate": (i32, [C.c_void_p, C.c_void_p, f64, C.c_void_p, C.c_void_p]),
 }
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_PARTITION", -3: "E_NOT_SPD",
@@ -281,6 +288,13 @@ class Solver:
 
     def setup(self):
         _check(lib().hplmm_setup(self.h, _stream()))
+
+    def setup_surrogate(self, net, threshold):
+        """Set-up with the network's shape vectors where they pass the local
+        residual check (see include/hplmm_surrogate.h); returns the stats."""
+        st = HplmmSgStats()
+        _check(lib().hplmm_setup_surrogate(self.h, net.h, float(threshold), C.byref(st), _stream()))
+        return {k: getattr(st, k) for k, _ in HplmmSgStats._fields_}
 
     def apply(self, r, which=0, out=None):
         z = torch.empty_like(r) if out is None else out

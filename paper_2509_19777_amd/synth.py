@@ -96,27 +96,40 @@ def sphere_pores(n: int, porosity: float, rmin: float, rmax: float, seed: int,
     sphere overlapping an accepted one is rejected.  Voxels whose centre lies
     inside a sphere are void.  Spheres are added until the void fraction of
     voxel centres reaches ``porosity`` (or the attempt budget runs out).
+    Each accepted sphere only touches the voxels of its bounding box, and the
+    void count is kept incrementally.
     """
     rng = np.random.default_rng(seed)
-    c = (np.arange(n) + 0.5)
-    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
     void = np.zeros((n, n, n), dtype=bool)
-    centres, radii = [], []
+    n_void, total = 0, n ** 3
+    cap = 1024
+    cen = np.zeros((cap, 3))
+    rad = np.zeros(cap)
+    k = 0
     tries = 0
-    while void.mean() < porosity and tries < max_tries:
+    while n_void < porosity * total and tries < max_tries:
         tries += 1
         p = rng.uniform(0.0, n, size=3)
         r = rng.uniform(rmin, rmax)
-        ok = True
-        for q, s in zip(centres, radii):
-            if np.sum((p - q) ** 2) < (r + s) ** 2:
-                ok = False
-                break
-        if not ok:
+        if k and np.any(np.sum((cen[:k] - p) ** 2, axis=1) < (r + rad[:k]) ** 2):
             continue
-        centres.append(p)
-        radii.append(r)
-        void |= (X - p[0]) ** 2 + (Y - p[1]) ** 2 + (Z - p[2]) ** 2 < r * r
+        if k == cap:
+            cap *= 2
+            cen = np.resize(cen, (cap, 3))
+            rad = np.resize(rad, cap)
+        cen[k] = p
+        rad[k] = r
+        k += 1
+        lo = np.maximum(np.floor(p - r - 0.5).astype(int), 0)
+        hi = np.minimum(np.ceil(p + r + 0.5).astype(int), n)
+        cz = np.arange(lo[2], hi[2]) + 0.5
+        cy = np.arange(lo[1], hi[1]) + 0.5
+        cx = np.arange(lo[0], hi[0]) + 0.5
+        inside = ((cx[None, None, :] - p[0]) ** 2 + (cy[None, :, None] - p[1]) ** 2
+                  + (cz[:, None, None] - p[2]) ** 2) < r * r
+        sub = void[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]]
+        n_void += int(np.count_nonzero(inside & ~sub))
+        sub |= inside
     return (~void).astype(np.uint8)
 
 

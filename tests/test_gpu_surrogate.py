@@ -165,3 +165,53 @@ def _coupled(A, P, g):
         cols = A.indices[A.indptr[3 * v]:A.indptr[3 * v + 1]] // 3
         nb.update(int(w) for w in cols if P.node_iface[w] >= 0)
     return np.array(sorted(nb), dtype=np.int64)
+
+
+def _random_net(channels=(4, 8, 8, 8, 9), scale=0.3, seed=12):
+    """A network with seeded random weights (drawn here, in the test)."""
+    from paper_2509_19777_amd import hplmm as hp
+    rng = np.random.default_rng(seed)
+    params = []
+    for ci, co in zip(channels[:-1], channels[1:]):
+        params.append((rng.standard_normal((3, 3, 3, ci, co)) * scale / np.sqrt(27 * ci),
+                       0.01 * rng.standard_normal(co)))
+    net = hp.SurrogateNet(channels, max_batch=64)
+    net.set_params(hp.flatten_params(params))
+    return net, params
+
+
+def test_surrogate_setup_with_zero_threshold_is_the_exact_setup(small_problem):
+    p, A, mesh, H, S = small_problem
+    ref = S.coarse_matrix().copy()
+    net, _ = _random_net()
+    st = S.setup_surrogate(net, 0.0)
+    assert st["accepted"] == 0 and st["fallback"] == st["grains"] > 0
+    got = S.coarse_matrix()
+    assert np.abs(got - ref).max() <= 1e-12 * np.abs(ref).max()
+    S.setup()   # leave the fixture's solver in its exact state
+
+
+def test_surrogate_galerkin_block_matches_oracle(small_problem):
+    p, A, mesh, H, S = small_problem
+    net, params = _random_net()
+    st = S.setup_surrogate(net, 1e300)
+    loaded = {g for g in H.corr_grains}
+    grains = [g for g in range(len(H.B_blocks)) if H.B_blocks[g] is not None and g not in loaded]
+    assert st["accepted"] == len(grains) and st["fallback"] == st["loaded"]
+    blocks = osg.predicted_blocks(H, A, mesh, params, grains)
+    ref = osg.galerkin_mortar_block(H, blocks)
+    got = S.coarse_matrix()[:H.Nmo, :H.Nmo]
+    assert np.abs(got - ref).max() <= 1e-4 * np.abs(ref).max(), np.abs(got - ref).max() / np.abs(ref).max()
+    # the correction pivots stay exact
+    nc = len(H.corr_grains)
+    if nc:
+        assert np.allclose(np.diag(S.coarse_matrix())[H.Nmo:], np.diag(H.Acoarse)[H.Nmo:], rtol=1e-12, atol=0)
+    # the preconditioner stays SPD: FGMRES still reaches the FP64 tolerance
+    x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
+    assert info["status"] == "OK"
+    assert np.linalg.norm(p_rhs(S) - A @ x.cpu().numpy()) <= 1e-8 * np.linalg.norm(p_rhs(S))
+    S.setup()
+
+
+def p_rhs(S):
+    return S.b.cpu().numpy()

@@ -117,3 +117,45 @@ def test_loss_is_zero_at_target_and_scale_invariant():
     assert sg.loss(y, y, mask) == 0.0
     p = y + 0.1 * rng.standard_normal(y.shape)
     assert np.isclose(sg.loss(p, y, mask), sg.loss(5 * p, 5 * y, mask), rtol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    from oracle import fem, hplmm as oh
+    from paper_2509_19777_amd import synth
+    p = synth.config_pores_lognormal(16, 8, seed=3, n_mortar=2)
+    A, b, mesh = fem.assemble(p)
+    return A, mesh, oh.HPLMM(p, A=A, b=b, mesh=mesh, n=2)
+
+
+def test_galerkin_with_exact_blocks_is_the_coarse_operator(small_oracle):
+    A, mesh, H = small_oracle
+    S = sg.galerkin_mortar_block(H, {})
+    ref = H.Acoarse[:H.Nmo, :H.Nmo]
+    assert np.abs(S - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_exact_shape_vectors_minimise_the_coarse_energy(small_oracle):
+    # the harmonic extension minimises the energy of P for fixed interface
+    # values, so any other grain block raises P^T A P by a PSD matrix
+    A, mesh, H = small_oracle
+    rng = _rng(8)
+    pert = {}
+    for g, blk in enumerate(H.B_blocks):
+        if blk is not None:
+            cols, B = blk
+            pert[g] = (cols, B + 0.05 * rng.standard_normal(B.shape))
+    d = sg.galerkin_mortar_block(H, pert) - sg.galerkin_mortar_block(H, {})
+    ev = np.linalg.eigvalsh(0.5 * (d + d.T))
+    assert ev.min() >= -1e-10 * abs(ev).max()
+    assert ev.max() > 0
+
+
+def test_predicted_blocks_cover_every_mortar_column(small_oracle):
+    A, mesh, H = small_oracle
+    params = sg.init_params(_rng(9), (4, 4, 4, 4, 9))
+    g = next(i for i, b in enumerate(H.B_blocks) if b is not None)
+    blocks = sg.predicted_blocks(H, A, mesh, params, [g])
+    cols, B = blocks[g]
+    ecols, EB = H.B_blocks[g]
+    assert np.array_equal(np.sort(cols), np.sort(ecols)) and B.shape == EB.shape
