@@ -9,6 +9,7 @@ only holds the device tensors and draws the mini-batches.
 
     python -m paper_2509_19777_amd.surrogate train --domains 40 --per-grain 4 --epochs 32 --out w.npz
     python -m paper_2509_19777_amd.surrogate eval --weights w.npz
+    python -m paper_2509_19777_amd.surrogate compare   (exact vs surrogate set-up on a fresh 64^3 domain)
 """
 from __future__ import annotations
 
@@ -25,6 +26,7 @@ from . import synth
 
 CHANNELS = (4, 32, 32, 32, 9)
 TRAIN_SEED0, EVAL_SEED = 1000, 7
+DEFAULT_WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "data", "basis_surrogate_poresE64_n4.npz")
 
 
 def conv_macs(channels=CHANNELS):
@@ -163,9 +165,46 @@ def per_sample_error(net, X, Y, batch):
     return np.concatenate(errs)
 
 
+def compare(net, prob, thresholds, reps=3, log=None):
+    """Exact set-up versus the surrogate set-up at each threshold on one
+    problem: FGMRES(50) iterations to 1e-8 and the set-up / solve times (best
+    of reps, host clock around synchronised calls)."""
+    import torch
+    sysm, part = hp.build_problem(prob)
+    S = hp.Solver(sysm, part, n_mortar=prob.n_mortar)
+    rows = []
+
+    def timed(fn):
+        best, out = None, None
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn()
+            torch.cuda.synchronize()
+            t = (time.perf_counter() - t0) * 1e3
+            best = t if best is None else min(best, t)
+        return best, out
+
+    for thr in [None] + list(thresholds):
+        if thr is None:
+            t_set, st = timed(lambda: S.setup())
+        else:
+            t_set, st = timed(lambda: S.setup_surrogate(net, thr))
+        t_sol, (x, info) = timed(lambda: S.solve(rtol=1e-8, restart=50, maxit=300))
+        rec = {"basis": "exact" if thr is None else f"surrogate, threshold {thr:g}",
+               "setup_ms": round(t_set, 2), "solve_ms": round(t_sol, 2), "iters": info["iters"],
+               "status": info["status"], "rel_res": info["rel_res"]}
+        if thr is not None:
+            rec.update({k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()})
+        rows.append(rec)
+        if log:
+            log(json.dumps(rec))
+    return rows
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "compare"])
     ap.add_argument("--domains", type=int, default=40)
     ap.add_argument("--per-grain", type=int, default=4)
     ap.add_argument("--epochs", type=int, default=96)
@@ -181,6 +220,13 @@ def main(argv=None):
         train_probs, val_probs = probs[:-1], probs[-1:]
     else:
         eval_probs = problems([EVAL_SEED], workers=1)
+        if a.cmd == "compare":
+            import torch
+            torch.cuda.set_device(0)
+            net = hp.SurrogateNet(CHANNELS, max_batch=a.batch)
+            net.set_params(np.load(a.weights or DEFAULT_WEIGHTS)["params"])
+            compare(net, eval_probs[0], [1e-3, 1e-2, 1e-1, 1.0, 1e300], log=log)
+            return 0
     log("problems generated")
     import torch
     torch.cuda.set_device(0)
