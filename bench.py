@@ -42,8 +42,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["grf", "uneven"], default="grf",
+                    help="grf: Gaussian-random-field solid, lognormal E, box subdomains (the headline case); "
+                         "uneven: pores + disc fractures, two-phase E, irregular Voronoi subdomains")
     ap.add_argument("--n", type=int, default=64, help="voxels per side")
     ap.add_argument("--box", type=int, default=8)
+    ap.add_argument("--dofs-per-cell", type=float, default=1000.0, help="uneven workload: target dofs per subdomain")
     ap.add_argument("--mortar", type=int, default=4,
                     help="mortar nodes per interface (4 minimises set-up + solve time on this workload)")
     ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
@@ -63,7 +67,7 @@ def main():
 
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    prob = synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar)
+    prob = make_problem(a, a.n)
     sysm, part = hp.build_problem(prob)
     S = hp.Solver(sysm, part, n_mortar=a.mortar, smoother_precision=a.precision)
     t_plan = time.perf_counter() - t0
@@ -143,7 +147,7 @@ def main():
         "warmup": a.warmup, "ms_per_step": round(ms, 3), "higher_is_better": False, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if a.precision == 64 else f"f64+{'f32' if a.precision == 32 else 'bf16'}-smoother",
         "data": "synthetic",
-        "config": {"workload": f"grf{a.n}^3 solid 0.6, lognormal E, {a.box}^3-voxel boxes, n={a.mortar}, FGMRES(50) to 1e-8",
+        "config": {"workload": workload_name(a),
                    "dofs": 3 * sizes["n_nodes"], "subdomains": sizes["grain_mats"], "coarse_dofs": sizes["n_coarse"]},
         "iters": infos[-1]["iters"], "rel_res_true": infos[-1]["rel_res"],
         "setup_ms": {k: round(float(v), 3) for k, v in setup_ms.items()},
@@ -155,7 +159,7 @@ def main():
         "spmv_algorithmic_bytes": S.algorithmic_bytes()["spmv"],
         "kernel_breakdown": breakdown,
         "roofline": roof,
-        "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"]),
+        "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"], sizes["grain_mats"]),
     }
     print(json.dumps(out), flush=True)
 
@@ -184,7 +188,21 @@ def _source_hash():
     return h.hexdigest()
 
 
-def cpu_baseline(a, gpu_iters, gpu_dofs):
+def make_problem(a, n):
+    from paper_2509_19777_amd import synth
+    if a.workload == "uneven":
+        return synth.config_uneven(n, seed=31, n_mortar=a.mortar, dofs_per_cell=a.dofs_per_cell)
+    return synth.config_grf(n, a.box, seed=2, n_mortar=a.mortar)
+
+
+def workload_name(a):
+    if a.workload == "uneven":
+        return (f"uneven{a.n}^3 pores + 5 disc fractures, E in {{1, 10}}, Voronoi subdomains of ~{a.dofs_per_cell:g} "
+                f"dofs, n={a.mortar}, FGMRES(50) to 1e-8")
+    return f"grf{a.n}^3 solid 0.6, lognormal E, {a.box}^3-voxel boxes, n={a.mortar}, FGMRES(50) to 1e-8"
+
+
+def cpu_baseline(a, gpu_iters, gpu_dofs, full_grains):
     """The oracle, untuned, on a bounded sample of the same workload: the lower
     32^3 corner of the same 64^3 fields with the same 8^3 boxes, solved to
     1e-8 (assembly excluded, as on the GPU; about 10-20 s of CPU work).  Its set-up time is scaled by the
@@ -197,8 +215,13 @@ def cpu_baseline(a, gpu_iters, gpu_dofs):
         threads = None
     from oracle import fem, gmres, hplmm as oh
     from paper_2509_19777_amd import synth
-    full = synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar)
-    sub = synth.crop(full, CPU_SAMPLE_N, box=a.box)
+    if a.workload == "uneven":
+        # a smaller realisation of the same generator (cropping would re-partition)
+        sub = make_problem(a, CPU_SAMPLE_N)
+        what = f"a {CPU_SAMPLE_N}^3 realisation of the same generator"
+    else:
+        sub = synth.crop(synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar), CPU_SAMPLE_N, box=a.box)
+        what = f"the {CPU_SAMPLE_N}^3 corner crop of the same fields"
     A, b, mesh = fem.assemble(sub)
     t0 = time.perf_counter()
     H = oh.HPLMM(sub, A=A, b=b, mesh=mesh, n=a.mortar)
@@ -206,11 +229,10 @@ def cpu_baseline(a, gpu_iters, gpu_dofs):
     r = gmres.gmres(A, b, H.apply, tol=1e-8, restart=50, maxit=300, flexible=True)
     t2 = time.perf_counter()
     n_sub = sum(1 for g in H.part.grain_nodes if len(g))
-    full_grains = len(np.unique(full.labels[full.solid > 0]))
     setup_ms = (t1 - t0) * 1e3 * full_grains / n_sub
     solve_ms = (t2 - t1) * 1e3 * (gpu_dofs / A.shape[0]) * (gpu_iters / max(r.iters, 1))
     return {"value": round(setup_ms + solve_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on the {CPU_SAMPLE_N}^3 corner crop of the same fields "
+            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on {what} "
                        f"({A.shape[0]} dofs, {n_sub} subdomains, {r.iters} iterations, set-up "
                        f"{(t1 - t0):.2f} s, solve {(t2 - t1):.2f} s); set-up scaled x{full_grains / n_sub:.1f} "
                        f"(subdomains), solve scaled x{gpu_dofs / A.shape[0]:.1f} (dofs) "

@@ -102,24 +102,34 @@ def sphere_pores(n: int, porosity: float, rmin: float, rmax: float, seed: int,
     rng = np.random.default_rng(seed)
     void = np.zeros((n, n, n), dtype=bool)
     n_void, total = 0, n ** 3
-    cap = 1024
-    cen = np.zeros((cap, 3))
-    rad = np.zeros(cap)
-    k = 0
+    # accepted spheres bucketed on a grid of cell 2 rmax: two spheres can
+    # overlap only if their buckets are neighbours (the test itself is exact)
+    cell = 2.0 * rmax
+    nb = max(1, int(np.ceil(n / cell)))
+    buckets = {}
     tries = 0
     while n_void < porosity * total and tries < max_tries:
         tries += 1
         p = rng.uniform(0.0, n, size=3)
         r = rng.uniform(rmin, rmax)
-        if k and np.any(np.sum((cen[:k] - p) ** 2, axis=1) < (r + rad[:k]) ** 2):
+        b = tuple(min(nb - 1, int(p[d] // cell)) for d in range(3))
+        hit = False
+        for dz in (-1, 0, 1):
+            for dy in (-1, 0, 1):
+                for dx in (-1, 0, 1):
+                    for q, s in buckets.get((b[0] + dx, b[1] + dy, b[2] + dz), ()):
+                        if (p[0] - q[0]) ** 2 + (p[1] - q[1]) ** 2 + (p[2] - q[2]) ** 2 < (r + s) ** 2:
+                            hit = True
+                            break
+                    if hit:
+                        break
+                if hit:
+                    break
+            if hit:
+                break
+        if hit:
             continue
-        if k == cap:
-            cap *= 2
-            cen = np.resize(cen, (cap, 3))
-            rad = np.resize(rad, cap)
-        cen[k] = p
-        rad[k] = r
-        k += 1
+        buckets.setdefault(b, []).append((p, r))
         lo = np.maximum(np.floor(p - r - 0.5).astype(int), 0)
         hi = np.minimum(np.ceil(p + r + 0.5).astype(int), n)
         cz = np.arange(lo[2], hi[2]) + 0.5
@@ -199,6 +209,60 @@ def config_pores_lognormal(n: int = 64, box: int = 8, seed: int = 11, porosity: 
     E = np.exp(sigma_lnE * gaussian_field(n, ell, seed + 1))
     return _finish(solid, E, 0.3, box, f"poresE{n}_box{box}_s{seed}", n_mortar=n_mortar,
                    w_zeta=w_zeta, traction=tuple(traction))
+
+
+def voronoi_labels(shape, n_cells: int, seed: int) -> np.ndarray:
+    """Irregular partition: every voxel takes the id of the nearest of n_cells
+    seed points drawn uniformly in the cube (ties to the lower id)."""
+    from scipy.spatial import cKDTree
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    pts = rng.uniform(0.0, 1.0, size=(n_cells, 3)) * np.array([nx, ny, nz], dtype=float)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    cen = np.stack([i.ravel() + 0.5, j.ravel() + 0.5, k.ravel() + 0.5], axis=1)
+    _, idx = cKDTree(pts).query(cen, k=1)
+    return idx.reshape(shape).astype(np.int32)
+
+
+def disc_fractures(shape, n_fractures: int, seed: int, rmin: float, rmax: float) -> np.ndarray:
+    """Mask of n_fractures planar discs one voxel thick: voxel centres within
+    half a voxel of a random plane through a random centre and within a random
+    radius of that centre."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    k, j, i = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    X = np.stack([i + 0.5, j + 0.5, k + 0.5], axis=-1)
+    out = np.zeros(shape, dtype=bool)
+    for _ in range(n_fractures):
+        c = rng.uniform(0.0, 1.0, size=3) * np.array([nx, ny, nz], dtype=float)
+        nrm = rng.standard_normal(3)
+        nrm /= np.linalg.norm(nrm)
+        r = rng.uniform(rmin, rmax)
+        d = X - c
+        h = d @ nrm
+        rad = np.linalg.norm(d - h[..., None] * nrm, axis=-1)
+        out |= (np.abs(h) < 0.5) & (rad < r)
+    return out
+
+
+def config_uneven(n: int = 128, seed: int = 31, porosity: float = 0.45, n_fractures: int = 5,
+                  dofs_per_cell: float = 1000.0, n_mortar: int = 2, w_zeta: int = 1,
+                  traction=(0.0, 0.0, -1.0), max_tries: int = 400000) -> Problem:
+    """Uneven batching workload: spherical pores (radius 1-3, up to the given
+    porosity or the attempt budget), n_fractures planar disc fractures as
+    zero-stiffness (void) one-voxel layers, a two-phase modulus E in {1, 10}
+    (thresholded Gaussian random field, correlation length 6), and an
+    irregular Voronoi partition sized for about dofs_per_cell dofs per cell."""
+    solid = sphere_pores(n, porosity, 1.0, 3.0, seed, max_tries=max_tries)
+    solid[disc_fractures(solid.shape, n_fractures, seed + 1, n / 6.0, n / 3.0)] = 0
+    solid = keep_clamped_components(solid)
+    E = np.where(gaussian_field(n, 6.0, seed + 2) > 0.0, 10.0, 1.0)
+    n_cells = max(2, int(round(3.3 * int(solid.sum()) / dofs_per_cell)))
+    lab = voronoi_labels(solid.shape, n_cells, seed + 3)
+    lab = np.where(solid > 0, lab, -1).astype(np.int32)
+    E = np.where(solid > 0, E, 0.0).astype(np.float64)
+    return Problem(solid=solid, E=E, nu=0.3, labels=lab, n_grains=n_cells, name=f"uneven{n}_s{seed}",
+                   n_mortar=n_mortar, w_zeta=w_zeta, traction=tuple(traction))
 
 
 def config_block(nx: int, ny: int, nz: int, box: int, E: float = 1.0, nu: float = 0.3,
