@@ -220,6 +220,16 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);
 
+/* HIP graphs for the solver (on by default): hplmm_solve captures each
+ * Arnoldi step j of the restart cycle (M^-1 application, SpMV, the two
+ * Gram-Schmidt passes, normalisation: kernel launches only) into a graph the
+ * first time it runs and replays it afterwards on an internal stream ordered
+ * after and before the caller's stream.  Graphs are rebuilt when the Krylov
+ * buffers are reallocated and are not used while the profiler is on.  The
+ * results are identical with graphs on and off.  on = 0 turns them off and
+ * frees them. */
+hplmm_status hplmm_use_graphs(hplmm_handle *h, int32_t on);
+
 /* Built-in kernel profiler: when bit c of mask is set, HIP events are
  * recorded on the launch stream around every launch of kernel class c:
  *   0 set-up tile contractions, 1 diagonal-tile factorisations, 2 smoother

@@ -538,10 +538,44 @@ static double device_dot(Handle &h, const double *a, const double *b, double *ds
     return v;
 }
 
+// One Arnoldi step j of FGMRES: z_j = M^-1 v_j, w = A z_j, classical
+// Gram-Schmidt twice (h = V^T w; w -= V h and h2 = V^T w in one pass; w -= V h2
+// into v_{j+1} with |w|^2 in one pass; h += h2), v_{j+1} normalised.  Kernel
+// launches only, so the step can be captured into a graph.
+static void arnoldi_step(Handle &h, int32_t j, hipStream_t s) {
+    const int64_t N = h.N;
+    double *vj = h.V + (int64_t)j * N, *zj = h.Z + (int64_t)j * N;
+    apply_op(h, 0, vj, zj, s);
+    spmv(h, zj, nullptr, h.w, s);
+    const int32_t k = j + 1;
+    double *vn = h.V + (int64_t)(j + 1) * N;
+    launch_kr_pass(nullptr, 0, 0, nullptr, h.w, nullptr, N, h.V, N, k, h.part, s);
+    launch_kr_reduce(h.part, h.kr_blocks, k, h.hbuf, nullptr, s);
+    launch_kr_pass(h.V, N, k, h.hbuf, h.w, h.w, N, h.V, N, k, h.part, s);
+    launch_kr_reduce(h.part, h.kr_blocks, k, h.h2, h.hbuf, s);
+    launch_kr_pass(h.V, N, k, h.h2, h.w, vn, N, nullptr, 0, 1, h.part, s);
+    launch_kr_reduce(h.part, h.kr_blocks, 1, h.hbuf + j + 1, nullptr, s);
+    launch_normalize(vn, h.hbuf + j + 1, vn, N, s);
+}
+
 static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, int32_t m, int32_t maxit,
                           int32_t fixed, hplmm_solve_info *info, hipStream_t s) {
     ensure_krylov(h, m);
     const int64_t N = h.N;
+    // graphs of the Arnoldi steps: only with the profiler off (its events are
+    // recorded per launch on the caller's stream)
+    const bool graphs = h.use_graphs && h.prof.mask == 0;
+    if (graphs) {
+        if (!h.gstream) {
+            hip_check(hipStreamCreateWithFlags(&h.gstream, hipStreamNonBlocking), "stream");
+            for (auto &e : h.gev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+        }
+        if (h.graph_key_V != h.V || (int32_t)h.arnoldi_graphs.size() < m) {
+            h.drop_graphs();
+            h.arnoldi_graphs.assign((size_t)h.kr_restart, nullptr);
+            h.graph_key_V = h.V;
+        }
+    }
     const double bnorm = std::sqrt(device_dot(h, b, b, h.hbuf, s));
     std::vector<double> hist;
     int32_t it = 0;
@@ -568,20 +602,31 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
         g[0] = beta;
         int32_t j = 0;
         for (; j < m && it < limit; ++j) {
-            double *vj = h.V + (int64_t)j * N, *zj = h.Z + (int64_t)j * N;
-            apply_op(h, 0, vj, zj, s);
-            spmv(h, zj, nullptr, h.w, s);
-            // classical Gram-Schmidt, twice: h = V^T w; w -= V h and h2 = V^T w in
-            // one pass; w -= V h2 into v_{j+1} with |w|^2 in one pass; h += h2
-            const int32_t k = j + 1;
-            double *vn = h.V + (int64_t)(j + 1) * N;
-            launch_kr_pass(nullptr, 0, 0, nullptr, h.w, nullptr, N, h.V, N, k, h.part, s);
-            launch_kr_reduce(h.part, h.kr_blocks, k, h.hbuf, nullptr, s);
-            launch_kr_pass(h.V, N, k, h.hbuf, h.w, h.w, N, h.V, N, k, h.part, s);
-            launch_kr_reduce(h.part, h.kr_blocks, k, h.h2, h.hbuf, s);
-            launch_kr_pass(h.V, N, k, h.h2, h.w, vn, N, nullptr, 0, 1, h.part, s);
-            launch_kr_reduce(h.part, h.kr_blocks, 1, h.hbuf + j + 1, nullptr, s);
-            launch_normalize(vn, h.hbuf + j + 1, vn, N, s);
+            if (graphs) {
+                hipGraphExec_t &ge = h.arnoldi_graphs[(size_t)j];
+                if (!ge) {
+                    hipGraph_t g = nullptr;
+                    hip_check(hipStreamBeginCapture(h.gstream, hipStreamCaptureModeThreadLocal), "begin capture");
+                    try {
+                        arnoldi_step(h, j, h.gstream);
+                    } catch (...) {
+                        // leave the stream out of capture mode before reporting
+                        if (hipStreamEndCapture(h.gstream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+                        throw;
+                    }
+                    hip_check(hipStreamEndCapture(h.gstream, &g), "end capture");
+                    const hipError_t e = hipGraphInstantiateWithFlags(&ge, g, 0);
+                    (void)hipGraphDestroy(g);
+                    hip_check(e, "graph instantiate");
+                }
+                hip_check(hipEventRecord(h.gev[0], s), "event");
+                hip_check(hipStreamWaitEvent(h.gstream, h.gev[0], 0), "wait");
+                hip_check(hipGraphLaunch(ge, h.gstream), "graph launch");
+                hip_check(hipEventRecord(h.gev[1], h.gstream), "event");
+                hip_check(hipStreamWaitEvent(s, h.gev[1], 0), "wait");
+            } else {
+                arnoldi_step(h, j, s);
+            }
             hip_check(hipMemcpyAsync(hv.data(), h.hbuf, sizeof(double) * (size_t)(j + 2), hipMemcpyDeviceToHost, s), "copy h");
             hip_check(hipStreamSynchronize(s), "step");
             hv[(size_t)j + 1] = std::sqrt(hv[(size_t)j + 1]);
@@ -702,6 +747,15 @@ extern "C" hplmm_status hplmm_setup_surrogate(hplmm_handle *hh, hplmm_sg_net *ne
         hh->h.ready = false;
         const SgSetup sg{net, threshold, stats};
         numeric_setup(hh->h, as_stream(stream), 3, &sg);
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_use_graphs(hplmm_handle *hh, int32_t on) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        hh->h.use_graphs = on != 0;
+        if (!on) hh->h.drop_graphs();
         return HPLMM_OK;
     });
 }

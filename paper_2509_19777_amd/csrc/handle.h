@@ -238,6 +238,19 @@ struct Handle {
     // Krylov workspace
     int32_t kr_restart = 0;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *hbuf = nullptr, *h2 = nullptr;
+    // HIP graphs of the Arnoldi steps (one per step index j of the restart
+    // cycle), replayed on an internal stream; rebuilt when the Krylov buffers change
+    bool use_graphs = true;
+    hipStream_t gstream = nullptr;
+    hipEvent_t gev[2] = {nullptr, nullptr};
+    std::vector<hipGraphExec_t> arnoldi_graphs;
+    const double *graph_key_V = nullptr;
+    void drop_graphs() {
+        for (hipGraphExec_t g : arnoldi_graphs)
+            if (g) (void)hipGraphExecDestroy(g);
+        arnoldi_graphs.clear();
+        graph_key_V = nullptr;
+    }
     double *ydev = nullptr;
     int32_t kr_blocks = 0;
 
@@ -263,6 +276,10 @@ struct Handle {
         return p;
     }
     ~Handle() {
+        drop_graphs();
+        for (hipEvent_t e : gev)
+            if (e) (void)hipEventDestroy(e);
+        if (gstream) (void)hipStreamDestroy(gstream);
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }

@@ -70,6 +70,7 @@ EXPORTS = {
     "hplmm_query": (i32, [C.c_void_p, i32, C.c_void_p, i64, P(i64)]),
     "hplmm_destroy": (None, [C.c_void_p]),
     "hplmm_profile": (i32, [C.c_void_p, i32]),
+    "hplmm_use_graphs": (i32, [C.c_void_p, i32]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
@@ -288,6 +289,10 @@ class Solver:
 
     def setup(self):
         _check(lib().hplmm_setup(self.h, _stream()))
+
+    def use_graphs(self, on=True):
+        """Replay the Arnoldi steps of the solver as HIP graphs (default on)."""
+        _check(lib().hplmm_use_graphs(self.h, 1 if on else 0))
 
     def setup_surrogate(self, net, threshold):
         """Set-up with the network's shape vectors where they pass the local

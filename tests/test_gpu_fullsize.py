@@ -80,6 +80,11 @@ def test_solve_full(big):
     assert np.linalg.norm(b - A @ xg) / np.linalg.norm(b) < 1e-8
     x2, _ = S.solve(rtol=1e-8, restart=50, maxit=300)
     assert np.array_equal(xg, x2.cpu().numpy())
+    # graph replay and eager launches give the same bits
+    S.use_graphs(False)
+    x3, _ = S.solve(rtol=1e-8, restart=50, maxit=300)
+    S.use_graphs(True)
+    assert np.array_equal(xg, x3.cpu().numpy())
 
 
 def test_solve_full_bf16_smoother(big):

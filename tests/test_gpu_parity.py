@@ -108,3 +108,24 @@ def test_solve_parity(case16):
     # at the oracle's iteration count the iterates agree to 1e-8
     xf, inf2 = S.solve(rtol=1e-8, restart=50, maxit=300, fixed_iters=ro.iters)
     assert _rel(xf.cpu().numpy(), ro.x) <= 1e-8
+
+
+def test_solve_with_graphs_matches_eager(case16):
+    # the captured Arnoldi steps replay to the same bits as eager launches,
+    # on every replay (three solves with graphs, one without)
+    p, A, b, mesh, H, S = case16
+    S.use_graphs(False)
+    x0, i0 = S.solve(rtol=1e-8, restart=50, maxit=300)
+    ref = x0.cpu().numpy()
+    S.use_graphs(True)
+    for _ in range(3):
+        x1, i1 = S.solve(rtol=1e-8, restart=50, maxit=300)
+        assert i1["iters"] == i0["iters"]
+        assert np.array_equal(x1.cpu().numpy(), ref)
+    # a shorter restart cycle reuses the buffers, a longer one rebuilds the graphs
+    for m in (20, 60):
+        S.use_graphs(False)
+        e, ie = S.solve(rtol=1e-8, restart=m, maxit=300)
+        S.use_graphs(True)
+        g, ig = S.solve(rtol=1e-8, restart=m, maxit=300)
+        assert ig["iters"] == ie["iters"] and np.array_equal(g.cpu().numpy(), e.cpu().numpy())
