@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--mortar", type=int, default=4,
                     help="mortar nodes per interface (4 minimises set-up + solve time on this workload)")
     ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
+    ap.add_argument("--autotune-reps", type=int, default=3,
+                    help="launch-shape autotuning after the warm-up steps, untimed (0: default shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
@@ -90,6 +92,18 @@ def main():
         return x, info
 
     for _ in range(a.warmup):
+        step()
+    tune = None
+    if a.autotune_reps > 0:
+        # launch shapes depend on the problem's structure only: chosen once,
+        # like the plan, before the timed region
+        t_t = time.perf_counter()
+        recs = S.autotune(a.autotune_reps)
+        t_t = time.perf_counter() - t_t
+        changed = [r for r in recs if r["variant"] != 0 or r["waves"] != 4]
+        tune = {"launches": len(recs), "changed": len(changed), "tuning_s": round(t_t, 3),
+                "saved_us_per_apply": round(sum(r["t_default_us"] - r["t_best_us"] for r in changed), 1)}
+        print(f"# autotune: {tune}", file=sys.stderr, flush=True)
         step()
     # timed region: every kernel class timed live with HIP events on its stream
     S.profile(S.PROF_CLASSES)
@@ -158,6 +172,7 @@ def main():
         "apply_algorithmic_bytes": S.algorithmic_bytes()["apply"],
         "spmv_algorithmic_bytes": S.algorithmic_bytes()["spmv"],
         "kernel_breakdown": breakdown,
+        "autotune": tune,
         "roofline": roof,
         "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"], sizes["grain_mats"]),
     }

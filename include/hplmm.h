@@ -215,16 +215,43 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *   8 algorithmic bytes: double[2] = {one application of M^-1, one SpMV}
  *   9 coarse solve structure: double[5 * levels], per front level (0 = root)
  *            {fronts, forward work-groups, forward bytes, backward
- *            work-groups, backward bytes}
+ *            work-groups, backward bytes} (with the current launch shapes)
+ *  10 tuning records: double[7 * k], one per tuned launch {kind, index,
+ *            variant, target work-groups, waves, default us, chosen us}
+ *            (see hplmm_autotune; empty with the default shapes)
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);
 
+/* Launch-shape autotuning of the solve phase (after hplmm_setup).  The
+ * GEMV launches of M^-1 are timed on this problem's own operators (reps
+ * back-to-back launches, best of three, events on stream; the call
+ * synchronises) and each keeps its fastest shape:
+ *   kind 0 / 1, index l: the forward / backward coarse sweep at front level l,
+ *     variants = its rows as planned (variant 0: split over about 256
+ *     work-groups when the level has fewer than 128 rows, else unsplit),
+ *     unsplit, or split over about 256, 512, 1024, 2048 work-groups;
+ *   kind 2, index 0..5: grain W, grain W^T, contact W, contact W^T, X^T, X
+ *     products (variant 0 only);
+ * each at 4 or 16 wavefronts per work-group.  A different shape changes the
+ * order in which partial sums are added (results agree to rounding; a fixed
+ * set of shapes always gives the same bits).  The coarse front vectors are
+ * zeroed.  Query 10 returns the choices with the timings; E_STATE before
+ * set-up; reps in 1..1000. */
+hplmm_status hplmm_autotune(hplmm_handle *h, int32_t reps, void *stream);
+
+/* Pin launch shapes without timing: rec holds n records {kind, index,
+ * variant, waves} (int32, as in query 10); launches not named keep their
+ * default shape, n = 0 restores every default.  E_ARG on a kind, index,
+ * variant or waves (4 or 16) out of range, in which case the defaults are
+ * restored.  Synchronises the device. */
+hplmm_status hplmm_set_tuning(hplmm_handle *h, const int32_t *rec, int64_t n);
+
 /* HIP graphs for the solver (on by default): hplmm_solve captures each
  * Arnoldi step j of the restart cycle (M^-1 application, SpMV, the two
  * Gram-Schmidt passes, normalisation: kernel launches only) into a graph the
- * first time it runs and replays it afterwards on an internal stream ordered
- * after and before the caller's stream.  Graphs are rebuilt when the Krylov
+ * first time it runs (capture happens on an internal stream) and launches
+ * the graph on the caller's stream from then on.  Graphs are rebuilt when the Krylov
  * buffers are reallocated and are not used while the profiler is on.  The
  * results are identical with graphs on and off.  on = 0 turns them off and
  * frees them. */

@@ -397,23 +397,27 @@ static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
     }
 }
 
-static void gemv_set(Handle &h, Range r, bool smoother_low, const double *x, double *y, hipStream_t s,
+static void launch_set(Handle &h, const Range &r, bool smoother_low, const double *x, double *y, hipStream_t s) {
+    const GemvTask *t = h.d_vtasks + r.start;
+    if (!smoother_low || h.smoother_precision == 64)
+        launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
+    else if (h.smoother_precision == 32)
+        launch_gemv<float>(h.ar32, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
+    else
+        launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
+}
+
+static void gemv_set(Handle &h, const Range &r, bool smoother_low, const double *x, double *y, hipStream_t s,
                      int32_t cls = PC_GEMV_SMOOTH) {
     if (r.count == 0) return;
     ProfScope ps(h, cls, r.bytes, s);
-    const GemvTask *t = h.d_vtasks + r.start;
-    if (!smoother_low || h.smoother_precision == 64)
-        launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s);
-    else if (h.smoother_precision == 32)
-        launch_gemv<float>(h.ar32, x, y, t, h.d_vpairs, r.count, s);
-    else
-        launch_gemv<uint16_t>(h.arbf, x, y, t, h.d_vpairs, r.count, s);
+    launch_set(h, r, smoother_low, x, y, s);
 }
 
 // Front sweeps: few long rows per launch, split over many work-groups.
-static void gemv_front(Handle &h, Range r, hipStream_t s) {
+static void gemv_front(Handle &h, const Range &r, hipStream_t s) {
     if (r.count == 0) return;
-    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, 4,
+    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, r.waves,
                         h.d_gemv_part, h.d_gemv_cnt);
 }
 
@@ -443,17 +447,8 @@ static void coarse_solve(Handle &h, const double *f, double *u, hipStream_t s) {
 static void contact_solve(Handle &h, const double *rr, hipStream_t s) {
     launch_gather(h.d_c_slot_dof, rr, h.cx, h.cset.vec_len, s);
     const bool low = h.smoother_precision != 64;
-    if (h.smoother_precision == 32) {
-        {
-            ProfScope ps(h, PC_GEMV_SMOOTH, h.cset.gemv_W.bytes, s);
-            launch_gemv<float>(h.ar32, h.cx, h.ct, h.d_vtasks + h.cset.gemv_W.start, h.d_vpairs, h.cset.gemv_W.count, s);
-        }
-        ProfScope ps(h, PC_GEMV_SMOOTH, h.cset.gemv_Wt.bytes, s);
-        launch_gemv<float>(h.ar32, h.ct, h.cy, h.d_vtasks + h.cset.gemv_Wt.start, h.d_vpairs, h.cset.gemv_Wt.count, s);
-    } else {
-        gemv_set(h, h.cset.gemv_W, low, h.cx, h.ct, s);
-        gemv_set(h, h.cset.gemv_Wt, low, h.ct, h.cy, s);
-    }
+    gemv_set(h, h.cset.gemv_W, low, h.cx, h.ct, s);
+    gemv_set(h, h.cset.gemv_Wt, low, h.ct, h.cy, s);
 }
 
 static void grain_solve(Handle &h, const double *rr, hipStream_t s) {
@@ -562,13 +557,13 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
                           int32_t fixed, hplmm_solve_info *info, hipStream_t s) {
     ensure_krylov(h, m);
     const int64_t N = h.N;
-    // graphs of the Arnoldi steps: only with the profiler off (its events are
-    // recorded per launch on the caller's stream)
+    // graphs of the Arnoldi steps, captured on an internal stream (the caller's
+    // may be the null stream, which cannot be captured) and launched on the
+    // caller's; only with the profiler off (its events are recorded per launch)
     const bool graphs = h.use_graphs && h.prof.mask == 0;
     if (graphs) {
         if (!h.gstream) {
             hip_check(hipStreamCreateWithFlags(&h.gstream, hipStreamNonBlocking), "stream");
-            for (auto &e : h.gev) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
         }
         if (h.graph_key_V != h.V || (int32_t)h.arnoldi_graphs.size() < m) {
             h.drop_graphs();
@@ -619,11 +614,7 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
                     (void)hipGraphDestroy(g);
                     hip_check(e, "graph instantiate");
                 }
-                hip_check(hipEventRecord(h.gev[0], s), "event");
-                hip_check(hipStreamWaitEvent(h.gstream, h.gev[0], 0), "wait");
-                hip_check(hipGraphLaunch(ge, h.gstream), "graph launch");
-                hip_check(hipEventRecord(h.gev[1], h.gstream), "event");
-                hip_check(hipStreamWaitEvent(s, h.gev[1], 0), "wait");
+                hip_check(hipGraphLaunch(ge, s), "graph launch");
             } else {
                 arnoldi_step(h, j, s);
             }
@@ -747,6 +738,185 @@ extern "C" hplmm_status hplmm_setup_surrogate(hplmm_handle *hh, hplmm_sg_net *ne
         hh->h.ready = false;
         const SgSetup sg{net, threshold, stats};
         numeric_setup(hh->h, as_stream(stream), 3, &sg);
+        return HPLMM_OK;
+    });
+}
+
+// ---- autotuning of the solve-phase GEMV launches ------------------------------
+// The smoother / basis GEMV launches of M^-1 in a fixed order (the index of
+// their tuning records), with the vectors they read and write.
+struct SetLaunch {
+    Range *r;
+    bool low;
+    const double *x;
+    double *y;
+};
+static std::vector<SetLaunch> set_launches(Handle &h) {
+    const bool low = h.smoother_precision != 64;
+    return {{&h.gset.gemv_W, low, h.gx, h.gt},   {&h.gset.gemv_Wt, low, h.gt, h.gy},
+            {&h.cset.gemv_W, low, h.cx, h.ct},   {&h.cset.gemv_Wt, low, h.ct, h.cy},
+            {&h.gemv_XT, false, h.gx, h.gc_t},   {&h.gemv_X, false, h.gc_u, h.gy}};
+}
+
+// Mean duration of fn in us: one warm-up call, then the best of three
+// intervals of reps back-to-back calls timed with events on s.
+template <class F>
+static double time_us(hipStream_t s, int32_t reps, hipEvent_t e0, hipEvent_t e1, F fn) {
+    fn();
+    float best = 0.f;
+    for (int trial = 0; trial < 3; ++trial) {
+        hip_check(hipEventRecord(e0, s), "event");
+        for (int32_t r = 0; r < reps; ++r) fn();
+        hip_check(hipEventRecord(e1, s), "event");
+        hip_check(hipEventSynchronize(e1), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        if (trial == 0 || ms < best) best = ms;
+    }
+    return 1e3 * best / reps;
+}
+
+// Put the chosen shapes in place: coarse levels from their variant lists,
+// smoother / basis launches by their waves.
+static void apply_tuning(Handle &h, const std::vector<TuneRecord> &log) {
+    CoarseMF &mf = h.mf;
+    const auto sets = set_launches(h);
+    for (const TuneRecord &t : log) {
+        if (t.kind == 0 || t.kind == 1) {
+            if (t.index < 0 || t.index >= mf.n_levels) fail(HPLMM_E_ARG, "tuning: level out of range");
+            const GemvShapes &g = (t.kind == 0 ? mf.fwd_shapes : mf.bwd_shapes)[(size_t)t.index];
+            if (t.variant < 0 || t.variant >= (int32_t)g.var.size()) fail(HPLMM_E_ARG, "tuning: variant out of range");
+            Range r = g.var[(size_t)t.variant];
+            r.waves = t.waves;
+            (t.kind == 0 ? mf.fwd : mf.bwd)[(size_t)t.index] = r;
+        } else if (t.kind == 2) {
+            if (t.index < 0 || t.index >= (int32_t)sets.size()) fail(HPLMM_E_ARG, "tuning: launch out of range");
+            sets[(size_t)t.index].r->waves = t.waves;
+        } else {
+            fail(HPLMM_E_ARG, "tuning: unknown launch kind");
+        }
+        if (t.waves != 4 && t.waves != 16) fail(HPLMM_E_ARG, "tuning: waves must be 4 or 16");
+    }
+}
+
+static void default_tuning(Handle &h) {
+    CoarseMF &mf = h.mf;
+    for (int32_t l = 0; l < mf.n_levels; ++l) {
+        mf.fwd[(size_t)l] = mf.fwd_shapes[(size_t)l].var[0];
+        mf.bwd[(size_t)l] = mf.bwd_shapes[(size_t)l].var[0];
+    }
+    for (auto &sl : set_launches(h)) sl.r->waves = 4;
+    h.tune_log.clear();
+}
+
+static void autotune(Handle &h, int32_t reps, hipStream_t s) {
+    CoarseMF &mf = h.mf;
+    default_tuning(h);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hip_check(hipEventCreate(&e0), "event");
+    const hipError_t ec = hipEventCreate(&e1);
+    if (ec != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        hip_check(ec, "event");
+    }
+    std::vector<TuneRecord> log;
+    try {
+        // the sweeps run on zeroed front vectors: their in-place updates stay zero
+        if (mf.n_fronts) zero(mf.V, sizeof(double) * 3 * (size_t)mf.vec_len, s);
+        for (int32_t kind = 0; kind < 2; ++kind)
+            for (int32_t l = 0; l < mf.n_levels; ++l) {
+                const GemvShapes &g = (kind == 0 ? mf.fwd_shapes : mf.bwd_shapes)[(size_t)l];
+                if (g.var.empty() || g.var[0].count == 0) continue;
+                TuneRecord best{kind, l, 0, g.target[0], 4, 0.0, 0.0};
+                for (int32_t v = 0; v < (int32_t)g.var.size(); ++v)
+                    for (int32_t w : {4, 16}) {
+                        Range r = g.var[(size_t)v];
+                        r.waves = w;
+                        const double t = time_us(s, reps, e0, e1, [&] { gemv_front(h, r, s); });
+                        if (v == 0 && w == 4) best.t_default_us = best.t_best_us = t;
+                        else if (t < best.t_best_us) {
+                            best.variant = v;
+                            best.target = g.target[(size_t)v];
+                            best.waves = w;
+                            best.t_best_us = t;
+                        }
+                    }
+                log.push_back(best);
+            }
+        const auto sets = set_launches(h);
+        for (int32_t i = 0; i < (int32_t)sets.size(); ++i) {
+            const SetLaunch &sl = sets[(size_t)i];
+            if (sl.r->count == 0) continue;
+            TuneRecord best{2, i, 0, 0, 4, 0.0, 0.0};
+            for (int32_t w : {4, 16}) {
+                Range r = *sl.r;
+                r.waves = w;
+                const double t = time_us(s, reps, e0, e1, [&] { launch_set(h, r, sl.low, sl.x, sl.y, s); });
+                if (w == 4) best.t_default_us = best.t_best_us = t;
+                else if (t < best.t_best_us) {
+                    best.waves = w;
+                    best.t_best_us = t;
+                }
+            }
+            log.push_back(best);
+        }
+    } catch (...) {
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        throw;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    apply_tuning(h, log);
+    h.tune_log = log;
+}
+
+extern "C" hplmm_status hplmm_autotune(hplmm_handle *hh, int32_t reps, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        Handle &h = hh->h;
+        if (!h.ready) fail(HPLMM_E_STATE, "hplmm_setup has not completed");
+        if (reps < 1 || reps > 1000) fail(HPLMM_E_ARG, "reps must be 1..1000");
+        const int32_t mask = h.prof.mask;
+        h.prof.mask = 0;
+        h.drop_graphs();   // captured steps hold the old launch shapes
+        try {
+            autotune(h, reps, (hipStream_t)stream);
+        } catch (...) {
+            h.prof.mask = mask;
+            default_tuning(h);
+            throw;
+        }
+        h.prof.mask = mask;
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_set_tuning(hplmm_handle *hh, const int32_t *rec, int64_t n) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        Handle &h = hh->h;
+        if (n < 0 || (n > 0 && !rec)) fail(HPLMM_E_ARG, "bad tuning records");
+        hip_check(hipDeviceSynchronize(), "sync");
+        h.drop_graphs();
+        default_tuning(h);
+        std::vector<TuneRecord> log;
+        for (int64_t i = 0; i < n; ++i) {
+            const int32_t *q = rec + 4 * i;
+            TuneRecord t{q[0], q[1], q[2], 0, q[3], 0.0, 0.0};
+            if ((t.kind == 0 || t.kind == 1) && t.index >= 0 && t.index < h.mf.n_levels) {
+                const GemvShapes &g = (t.kind == 0 ? h.mf.fwd_shapes : h.mf.bwd_shapes)[(size_t)t.index];
+                if (t.variant >= 0 && t.variant < (int32_t)g.target.size()) t.target = g.target[(size_t)t.variant];
+            }
+            log.push_back(t);
+        }
+        try {
+            apply_tuning(h, log);
+        } catch (...) {
+            default_tuning(h);
+            throw;
+        }
+        h.tune_log = log;
         return HPLMM_OK;
     });
 }
@@ -875,6 +1045,15 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                     const Range &f = h.mf.fwd[(size_t)l], &b = h.mf.bwd[(size_t)l];
                     for (double x : {(double)nf, (double)f.count, f.bytes, (double)b.count, b.bytes}) v.push_back(x);
                 }
+                put(v.data(), sizeof(double) * v.size());
+                break;
+            }
+            case 10: {
+                std::vector<double> v;
+                for (const TuneRecord &t : h.tune_log)
+                    for (double x : {(double)t.kind, (double)t.index, (double)t.variant, (double)t.target,
+                                     (double)t.waves, t.t_default_us, t.t_best_us})
+                        v.push_back(x);
                 put(v.data(), sizeof(double) * v.size());
                 break;
             }

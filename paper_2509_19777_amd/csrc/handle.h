@@ -64,6 +64,23 @@ struct TaskLists {
 struct Range {
     int64_t start = 0, count = 0;
     double bytes = 0.0;   // algorithmic bytes read and written by the launch
+    int32_t waves = 4;    // GEMV launches: wavefronts per work-group (4 or 16)
+};
+
+// Launch shapes of one GEMV launch that the autotuner chooses from: the same
+// rows emitted for several work-group targets (split rows, target 0 = as
+// planned); var[0] is the default.
+struct GemvShapes {
+    std::vector<Range> var;
+    std::vector<int32_t> target;
+};
+
+// One autotuned launch: kind 0/1 = coarse forward/backward sweep at level
+// index, kind 2 = smoother / basis GEMV (index: grain W, grain W^T, contact
+// W, contact W^T, X^T, X); the chosen variant, waves and timings (us).
+struct TuneRecord {
+    int32_t kind, index, variant, target, waves;
+    double t_default_us, t_best_us;
 };
 
 // A batch of symmetric positive definite matrices stored as packed lower
@@ -98,7 +115,8 @@ struct CoarseMF {
     std::vector<std::vector<Launch>> factor_prog;   // per level
     std::vector<Range> ext_rows[2];                 // per level: extend-add rows (left / right children)
     std::vector<Range> vec_ext, bwd_copy;           // per level
-    std::vector<Range> fwd, bwd;                    // per level: one GEMV launch each way
+    std::vector<Range> fwd, bwd;                    // per level: one GEMV launch each way (the chosen shape)
+    std::vector<GemvShapes> fwd_shapes, bwd_shapes; // per level: the shapes the autotuner may pick
     std::vector<ExtendRow> rows;
     std::vector<int32_t> maps;
     std::vector<int64_t> va_dst, va_ptr, va_src, cp_dst, cp_src, init_map, out_dst, out_src;
@@ -239,10 +257,11 @@ struct Handle {
     int32_t kr_restart = 0;
     double *V = nullptr, *Z = nullptr, *w = nullptr, *part = nullptr, *hbuf = nullptr, *h2 = nullptr;
     // HIP graphs of the Arnoldi steps (one per step index j of the restart
-    // cycle), replayed on an internal stream; rebuilt when the Krylov buffers change
+    // cycle), captured on an internal stream and replayed on the caller's; rebuilt
+    // when the Krylov buffers change
+    std::vector<TuneRecord> tune_log;   // launches chosen by hplmm_autotune (empty: defaults)
     bool use_graphs = true;
     hipStream_t gstream = nullptr;
-    hipEvent_t gev[2] = {nullptr, nullptr};
     std::vector<hipGraphExec_t> arnoldi_graphs;
     const double *graph_key_V = nullptr;
     void drop_graphs() {
@@ -277,8 +296,6 @@ struct Handle {
     }
     ~Handle() {
         drop_graphs();
-        for (hipEvent_t e : gev)
-            if (e) (void)hipEventDestroy(e);
         if (gstream) (void)hipStreamDestroy(gstream);
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);

@@ -164,19 +164,25 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
-// Split the long rows of a GEMV launch with fewer than 128 tasks so that it
-// spreads over about 256 work-groups (a work-group streams tiles at a small
-// fraction of the device bandwidth): chunks of at least 4 pairs, partial sums
-// of each split row reduced in chunk order by the last work-group to finish.
-// Launches with more tasks are left alone: the release/acquire fences of a
-// split work-group cost more than they save there.  The launch's tasks are
-// re-emitted at the end of vt and r is pointed at them; part_len and cnt_len
-// grow to what the launch needs.
-void split_rows(std::vector<GemvTask> &vt, Range &r, int64_t &part_len, int32_t &cnt_len) {
-    if (r.count >= 128) return;
+// Algorithmic bytes of a GEMV launch: every tile and x segment read, y written.
+double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
+    double b = 0.0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i)
+        b += (double)vt[(size_t)i].pair_count * (TE * elem + TS * 8.0) + TS * 8.0;
+    return b;
+}
+
+// Re-emit the rows of GEMV launch r at the end of vt so that the launch
+// spreads over about target work-groups (a work-group streams tiles at a small
+// fraction of the device bandwidth): rows longer than the chunk length (at
+// least 4 pairs) are cut into chunks whose partial sums the last work-group of
+// the row reduces in chunk order.  target 0 returns r unchanged.  part_len and
+// cnt_len grow to what the launch needs.
+Range split_rows(std::vector<GemvTask> &vt, Range r, int64_t target, int64_t &part_len, int32_t &cnt_len) {
+    if (target <= 0) return r;
     int64_t total = 0;
     for (int64_t i = r.start; i < r.start + r.count; ++i) total += vt[(size_t)i].pair_count;
-    const int64_t chunk = std::max<int64_t>(4, (total + 255) / 256);
+    const int64_t chunk = std::max<int64_t>(4, (total + target - 1) / target);
     const int64_t start = (int64_t)vt.size();
     int64_t part = 0;
     int32_t grp = 0;
@@ -202,10 +208,30 @@ void split_rows(std::vector<GemvTask> &vt, Range &r, int64_t &part_len, int32_t 
         part += nc * TS;
         ++grp;
     }
-    r.start = start;
-    r.count = (int64_t)vt.size() - start;
+    Range out = r;
+    out.start = start;
+    out.count = (int64_t)vt.size() - start;
     part_len = std::max(part_len, part);
     cnt_len = std::max(cnt_len, grp);
+    return out;
+}
+
+// The shapes of one coarse-sweep launch: by default a launch with fewer than
+// 128 rows is split over about 256 work-groups and a larger one is left alone
+// (the release/acquire fences of split work-groups cost more than they save
+// there); the autotuner may also pick the unsplit rows or 256 to 2048
+// work-groups.
+GemvShapes sweep_shapes(std::vector<GemvTask> &vt, Range base, int64_t &part_len, int32_t &cnt_len) {
+    GemvShapes g;
+    const int32_t def = base.count < 128 ? 256 : 0;
+    const double bytes = gemv_bytes(vt, base, 8.0);   // the same rows whatever the shape
+    for (int32_t t : {def, 0, 256, 512, 1024, 2048}) {
+        if (!g.target.empty() && t == def) continue;
+        g.target.push_back(t);
+        g.var.push_back(split_rows(vt, base, t, part_len, cnt_len));
+        g.var.back().bytes = bytes;
+    }
+    return g;
 }
 
 }  // namespace
@@ -274,14 +300,6 @@ void fill_flops(std::vector<Launch> &prog, const TaskLists &tl) {
 }
 
 namespace {
-
-// Algorithmic bytes of a GEMV launch: every tile and x segment read, y written.
-double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
-    double b = 0.0;
-    for (int64_t i = r.start; i < r.start + r.count; ++i)
-        b += (double)vt[(size_t)i].pair_count * (TE * elem + TS * 8.0) + TS * 8.0;
-    return b;
-}
 
 void layout_set(DenseSet &ds) {
     ds.rel.resize(ds.n.size());
@@ -529,6 +547,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
     mf.bwd_copy.assign((size_t)nl, Range{});
     mf.fwd.assign((size_t)nl, Range{});
     mf.bwd.assign((size_t)nl, Range{});
+    mf.fwd_shapes.assign((size_t)nl, GemvShapes{});
+    mf.bwd_shapes.assign((size_t)nl, GemvShapes{});
     mf.va_ptr.push_back(0);
     for (int32_t l = 0; l < nl; ++l) {
         // factorisation of this level's fronts
@@ -643,10 +663,10 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
             }
         }
         mf.bwd[(size_t)l].count = (int64_t)vt.size() - mf.bwd[(size_t)l].start;
-        split_rows(vt, mf.fwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
-        split_rows(vt, mf.bwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
-        mf.fwd[(size_t)l].bytes = gemv_bytes(vt, mf.fwd[(size_t)l], 8.0);
-        mf.bwd[(size_t)l].bytes = gemv_bytes(vt, mf.bwd[(size_t)l], 8.0);
+        mf.fwd_shapes[(size_t)l] = sweep_shapes(vt, mf.fwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
+        mf.bwd_shapes[(size_t)l] = sweep_shapes(vt, mf.bwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
+        mf.fwd[(size_t)l] = mf.fwd_shapes[(size_t)l].var[0];
+        mf.bwd[(size_t)l] = mf.bwd_shapes[(size_t)l].var[0];
     }
     // right-hand side in, solution out
     mf.init_map.assign((size_t)mf.vec_len, -1);

@@ -71,6 +71,8 @@ EXPORTS = {
     "hplmm_destroy": (None, [C.c_void_p]),
     "hplmm_profile": (i32, [C.c_void_p, i32]),
     "hplmm_use_graphs": (i32, [C.c_void_p, i32]),
+    "hplmm_autotune": (i32, [C.c_void_p, i32, C.c_void_p]),
+    "hplmm_set_tuning": (i32, [C.c_void_p, C.c_void_p, i64]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
@@ -293,6 +295,25 @@ class Solver:
     def use_graphs(self, on=True):
         """Replay the Arnoldi steps of the solver as HIP graphs (default on)."""
         _check(lib().hplmm_use_graphs(self.h, 1 if on else 0))
+
+    TUNE_KEYS = ["kind", "index", "variant", "target", "waves", "t_default_us", "t_best_us"]
+
+    def autotune(self, reps=5):
+        """Time the solve-phase GEMV launch shapes on this problem and keep the
+        fastest; returns the tuning records (dicts)."""
+        _check(lib().hplmm_autotune(self.h, int(reps), _stream()))
+        return self.tuning()
+
+    def tuning(self):
+        v = self.query(10, np.float64).reshape(-1, 7)
+        return [{k: (float(x) if k.startswith("t_") else int(x)) for k, x in zip(self.TUNE_KEYS, row)} for row in v]
+
+    def set_tuning(self, records):
+        """Pin launch shapes: records as returned by autotune() / tuning()
+        (kind, index, variant, waves are used); [] restores the defaults."""
+        a = np.array([[r["kind"], r["index"], r["variant"], r["waves"]] for r in records], dtype=np.int32).reshape(-1, 4)
+        a = np.ascontiguousarray(a)
+        _check(lib().hplmm_set_tuning(self.h, a.ctypes.data_as(C.c_void_p) if a.size else None, a.shape[0]))
 
     def setup_surrogate(self, net, threshold):
         """Set-up with the network's shape vectors where they pass the local

@@ -95,3 +95,20 @@ def test_solve_full_bf16_smoother(big):
     x, info = S16.solve(rtol=1e-8, restart=50, maxit=300)
     assert info["status"] == "OK"
     assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+
+
+def test_autotuned_solve_full(big):
+    # the shapes the autotuner picks at full size solve to the same bar, and
+    # M^-1 agrees with the default shapes to rounding
+    p, A, b, mesh, part, S = big
+    r = _cu(synth.random_vector(A.shape[0], 25))
+    z0 = S.apply(r, 0).cpu().numpy()
+    recs = S.autotune(reps=3)
+    print("autotune:", [(rc["kind"], rc["index"], rc["target"], rc["waves"], round(rc["t_default_us"], 1),
+                         round(rc["t_best_us"], 1)) for rc in recs])
+    z1 = S.apply(r, 0).cpu().numpy()
+    assert np.linalg.norm(z1 - z0) <= 1e-12 * np.linalg.norm(z0)
+    x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
+    assert info["status"] == "OK"
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+    S.set_tuning([])
