@@ -19,8 +19,8 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libhplmm.so")
 ARCH = "gfx950"
 
-DEVICE_SOURCES = ["dense.hip", "sparse.hip", "surrogate.hip"]
-HOST_SOURCES = ["host_problem.cpp", "plan.cpp", "capi.cpp", "sg_capi.cpp"]
+DEVICE_SOURCES = ["dense.hip", "sparse.hip", "surrogate.hip", "post.hip"]
+HOST_SOURCES = ["host_problem.cpp", "plan.cpp", "capi.cpp", "sg_capi.cpp", "post_capi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]
 # Packed FP32 VALU ops are disabled for all device code (hipcc's host pass

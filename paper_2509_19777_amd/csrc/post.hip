@@ -1,0 +1,87 @@
+// Stress recovery at voxel centroids (Hooke's law, Eqs. 1 and 3) and the
+// maximum shear stress (the Mohr-circle radius used by the error metric of
+// Eq. 28).  One thread per voxel: the eight corner displacements give the
+// displacement gradient at the centroid of the unit Q1 cube, where every
+// shape-function derivative is +-1/4.
+#include "post.h"
+
+namespace hplmm {
+namespace {
+
+// Smallest and largest eigenvalue of a symmetric 3x3 matrix by cyclic Jacobi
+// rotations (the two-sided symmetric Schur rotation of Golub and Van Loan,
+// Matrix Computations, Sec. 8.5): each rotation zeroes a[p][q]; six sweeps
+// take a 3x3 matrix to a diagonal within rounding.
+__device__ void sym3_eig_range(double a[3][3], double &lo, double &hi) {
+    for (int sweep = 0; sweep < 6; ++sweep) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int p = k == 2 ? 1 : 0, q = k == 0 ? 1 : 2, r = 3 - p - q;
+            const double apq = a[p][q];
+            if (apq == 0.0) continue;
+            const double tau = (a[q][q] - a[p][p]) / (2.0 * apq);
+            const double t = fabs(tau) > 1e150 ? 0.5 / tau : copysign(1.0, tau) / (fabs(tau) + sqrt(1.0 + tau * tau));
+            const double c = 1.0 / sqrt(1.0 + t * t), s = t * c;
+            const double arp = a[r][p], arq = a[r][q];
+            a[p][p] -= t * apq;
+            a[q][q] += t * apq;
+            a[p][q] = a[q][p] = 0.0;
+            a[r][p] = a[p][r] = c * arp - s * arq;
+            a[r][q] = a[q][r] = s * arp + c * arq;
+        }
+    }
+    lo = fmin(a[0][0], fmin(a[1][1], a[2][2]));
+    hi = fmax(a[0][0], fmax(a[1][1], a[2][2]));
+}
+
+__global__ void __launch_bounds__(256) voxel_fields_kernel(VoxelGrid g, const double *__restrict__ x,
+                                                           double *__restrict__ st, double *__restrict__ uc) {
+    const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= nvox) return;
+    if (!g.solid[v]) {
+        st[v] = 0.0;
+        if (uc)
+            for (int c = 0; c < 3; ++c) uc[3 * v + c] = 0.0;
+        return;
+    }
+    const int64_t i = v % g.nx, j = (v / g.nx) % g.ny, k = v / ((int64_t)g.nx * g.ny);
+    const int64_t NX = g.nx + 1, NY = g.ny + 1;
+    double grad[3][3] = {{0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}, {0.0, 0.0, 0.0}};   // grad[c][d] = du_c / dx_d
+    double us[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int cx = a & 1, cy = (a >> 1) & 1, cz = (a >> 2) & 1;
+        const int32_t node = g.lat2node[(i + cx) + NX * ((j + cy) + NY * (k + cz))];
+        if (node < 0 || node >= g.n_nodes) continue;   // clamped or unused: zero displacement
+        const double sx = cx ? 0.25 : -0.25, sy = cy ? 0.25 : -0.25, sz = cz ? 0.25 : -0.25;
+        for (int c = 0; c < 3; ++c) {
+            const double u = x[3 * (int64_t)node + c];
+            us[c] += u;
+            grad[c][0] += sx * u;
+            grad[c][1] += sy * u;
+            grad[c][2] += sz * u;
+        }
+    }
+    const double E = g.E[v];
+    const double lam = E * g.nu / ((1.0 + g.nu) * (1.0 - 2.0 * g.nu)), mu = E / (2.0 * (1.0 + g.nu));
+    const double tr = grad[0][0] + grad[1][1] + grad[2][2];
+    double s[3][3];
+    for (int c = 0; c < 3; ++c)
+        for (int d = 0; d < 3; ++d) s[c][d] = mu * (grad[c][d] + grad[d][c]) + (c == d ? lam * tr : 0.0);
+    double lo, hi;
+    sym3_eig_range(s, lo, hi);
+    st[v] = 0.5 * (hi - lo);
+    if (uc)
+        for (int c = 0; c < 3; ++c) uc[3 * v + c] = 0.125 * us[c];
+}
+
+}  // namespace
+
+void launch_voxel_fields(const VoxelGrid &g, const double *x, double *sigma_t, double *uc, hipStream_t s) {
+    const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;
+    if (nvox <= 0) return;
+    hipLaunchKernelGGL(voxel_fields_kernel, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, s, g, x, sigma_t, uc);
+}
+
+}  // namespace hplmm

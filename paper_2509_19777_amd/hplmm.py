@@ -90,6 +90,8 @@ EXPORTS = {
     "hplmm_sg_destroy": (None, [C.c_void_p]),
     "hplmm_sg_samples": (i32, [C.c_void_p, i64, i64, C.c_void_p, C.c_void_p, P(i32), P(i64), C.c_void_p]),
     "hplmm_setup_surrogate": (i32, [C.c_void_p, C.c_void_p, f64, C.c_void_p, C.c_void_p]),
+    "hplmm_voxel_fields": (i32, [i32, i32, i32, C.c_void_p, C.c_void_p, f64, C.c_void_p, i64, C.c_void_p,
+                                 C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", -1: "E_ARG", -2: "E_PARTITION", -3: "E_NOT_SPD",
@@ -423,6 +425,34 @@ def debug_grain_layout(solver):
     out = np.zeros(11 * nm, dtype=np.int64)
     _check(lib().hplmm_debug_grain_layout(solver.h, _ptr(out, i64), out.size))
     return out.reshape(nm, 11)
+
+
+class VoxelGrid:
+    """A problem's voxel grid on the device with the library's node numbering
+    (lattice point -> free node from System.node_xyz), for hplmm_voxel_fields."""
+
+    def __init__(self, problem, system):
+        nz, ny, nx = problem.solid.shape
+        self.dims = (nx, ny, nz)
+        self.nu = float(problem.nu)
+        self.n_nodes = system.n_nodes
+        xyz = system.node_xyz.reshape(-1, 3).astype(np.int64)
+        lat = -np.ones((nx + 1) * (ny + 1) * (nz + 1), dtype=np.int32)
+        lat[xyz[:, 0] + (nx + 1) * (xyz[:, 1] + (ny + 1) * xyz[:, 2])] = np.arange(system.n_nodes, dtype=np.int32)
+        self.solid = torch.from_numpy(np.ascontiguousarray(problem.solid, dtype=np.uint8).ravel()).cuda()
+        self.E = torch.from_numpy(np.ascontiguousarray(problem.E, dtype=np.float64).ravel()).cuda()
+        self.lat2node = torch.from_numpy(lat).cuda()
+        self.mask = self.solid.bool()
+
+    def fields(self, x):
+        """(sigma_t [n_vox], u_centroid [n_vox, 3]) of the displacement x (device)."""
+        nx, ny, nz = self.dims
+        nv = nx * ny * nz
+        st = torch.empty(nv, dtype=torch.float64, device=x.device)
+        uc = torch.empty(3 * nv, dtype=torch.float64, device=x.device)
+        _check(lib().hplmm_voxel_fields(nx, ny, nz, _vp(self.solid), _vp(self.E), self.nu, _vp(self.lat2node),
+                                        self.n_nodes, _vp(x), _vp(st), _vp(uc), _stream()))
+        return st, uc.view(nv, 3)
 
 
 def build_problem(problem, w_zeta=None):

@@ -129,3 +129,24 @@ def test_solve_with_graphs_matches_eager(case16):
         S.use_graphs(True)
         g, ig = S.solve(rtol=1e-8, restart=m, maxit=300)
         assert ig["iters"] == ie["iters"] and np.array_equal(g.cpu().numpy(), e.cpu().numpy())
+
+
+@pytest.mark.parametrize("w_zeta", [2])
+def test_wider_contact_grids_parity(w_zeta):
+    # contact grids dilated further (Sec. 3.1): the smoother and the whole
+    # preconditioner against the oracle, and FGMRES iteration counts
+    _torch()
+    from oracle import fem, gmres, hplmm as oh
+    from paper_2509_19777_amd import hplmm as hp
+    p = synth.config_pores(16, 4, seed=1)
+    A, b, mesh = fem.assemble(p)
+    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=4, w_zeta=w_zeta)
+    sysm, part = hp.build_problem(p, w_zeta)
+    S = hp.Solver(sysm, part, n_mortar=4)
+    S.setup()
+    for which, op in ((3, H.apply_Mzeta), (0, H.apply)):
+        r = synth.random_vector(A.shape[0], 40 + which)
+        assert _rel(S.apply(_cu(r), which).cpu().numpy(), op(r)) <= 1e-12
+    ro = gmres.gmres(A, b, H.apply, tol=1e-8, restart=50, flexible=True)
+    x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
+    assert info["status"] == "OK" and abs(info["iters"] - ro.iters) <= 1
