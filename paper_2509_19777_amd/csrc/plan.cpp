@@ -542,7 +542,7 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         return mf.ng_base + mf.ltrel[(size_t)t] + (I * mf.nt_d[(size_t)t] + J) * TE;
     };
     mf.factor_prog.assign((size_t)nl, {});
-    for (int s = 0; s < 2; ++s) mf.ext_rows[s].assign((size_t)nl, Range{});
+    for (int s = 0; s < 2; ++s) mf.ext_tiles[s].assign((size_t)nl, Range{});
     mf.vec_ext.assign((size_t)nl, Range{});
     mf.bwd_copy.assign((size_t)nl, Range{});
     mf.fwd.assign((size_t)nl, Range{});
@@ -585,16 +585,18 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         if (c.count) mf.factor_prog[(size_t)l].push_back(c);
         // extend-add of the children (level l+1) into this level's fronts
         for (int s = 0; s < 2; ++s) {
-            Range r{(int64_t)mf.rows.size(), 0};
+            Range r{(int64_t)mf.ext.size(), 0};
             for (int32_t t : at[(size_t)l]) {
                 const int32_t ch = child[(size_t)t][s];
                 if (ch < 0) continue;
-                for (int64_t rr = 0; rr < mf.u[(size_t)ch]; ++rr)
-                    mf.rows.push_back({mf.a_base + mf.rel[(size_t)ch], mf.a_base + mf.rel[(size_t)t],
-                                       map_off[(size_t)ch], (int32_t)mf.nt_d[(size_t)ch], (int32_t)rr});
+                for (int64_t I = 0; I < mf.nt_u[(size_t)ch]; ++I)
+                    for (int64_t J = 0; J <= I; ++J)
+                        mf.ext.push_back({mf.a_base + mf.rel[(size_t)ch], mf.a_base + mf.rel[(size_t)t],
+                                          map_off[(size_t)ch], (int32_t)mf.nt_d[(size_t)ch], (int32_t)mf.u[(size_t)ch],
+                                          (int32_t)I, (int32_t)J, 0});
             }
-            r.count = (int64_t)mf.rows.size() - r.start;
-            mf.ext_rows[s][(size_t)l] = r;
+            r.count = (int64_t)mf.ext.size() - r.start;
+            mf.ext_tiles[s][(size_t)l] = r;
         }
         // forward vector extend-add: parent slot <- sum of child boundary slots
         {
@@ -1353,9 +1355,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         chk(h.n_coarse <= h.cvec_len, "coarse vector length");
         {
             const CoarseMF &mf = h.mf;
-            for (const auto &r : mf.rows) {
+            for (const auto &r : mf.ext) {
                 chk(in(r.child_off, 1, h.ar64_n) && in(r.parent_off, 1, h.ar64_n), "extend-add fronts");
-                chk(r.map_off >= 0 && r.map_off + r.r < (int64_t)mf.maps.size(), "extend-add map");
+                chk(r.u > 0 && r.map_off >= 0 && r.map_off + r.u <= (int64_t)mf.maps.size(), "extend-add map");
+                chk(r.I >= r.J && r.J >= 0 && (int64_t)r.I * TS < r.u, "extend-add tile");
             }
             for (int32_t t = 0; t < mf.n_fronts; ++t) {
                 const int64_t nt = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
@@ -1369,11 +1372,13 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             std::unordered_map<int64_t, int64_t> front_nt;
             for (int32_t t = 0; t < mf.n_fronts; ++t)
                 front_nt[mf.a_base + mf.rel[(size_t)t]] = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
-            for (const auto &r : mf.rows) {
+            for (const auto &r : mf.ext) {
                 auto it = front_nt.find(r.parent_off), ic = front_nt.find(r.child_off);
                 chk(it != front_nt.end() && ic != front_nt.end(), "extend-add front offsets");
-                chk(r.nt_d * TS + r.r < ic->second * TS, "extend-add child row");
-                chk(mf.maps[(size_t)(r.map_off + r.r)] < it->second * TS, "extend-add parent position");
+                chk((int64_t)r.nt_d * TS + r.u <= ic->second * TS, "extend-add child rows");
+                if (r.J == 0)
+                    for (int64_t q = (int64_t)r.I * TS; q < std::min<int64_t>(r.u, (int64_t)(r.I + 1) * TS); ++q)
+                        chk(mf.maps[(size_t)(r.map_off + q)] < it->second * TS, "extend-add parent position");
             }
             for (auto v : mf.maps) chk(v >= 0, "extend-add position");
             for (auto v : mf.va_dst) chk(in(v, 1, mf.vec_len), "front vector extend-add");
@@ -1474,7 +1479,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.pair_vals = h.dalloc<double>(h.n_pair_vals);
     {
         CoarseMF &mf = h.mf;
-        mf.d_rows = h.upload(mf.rows, s);
+        mf.d_ext = h.upload(mf.ext, s);
         mf.d_maps = h.upload(mf.maps, s);
         mf.d_va_dst = h.upload(mf.va_dst, s);
         mf.d_va_ptr = h.upload(mf.va_ptr, s);

@@ -134,18 +134,19 @@ void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const Coars
                             const CoarseKRef *krefs, const CoarseMaps &cm, const double *bsr_val,
                             const double *karena, double *farena, double *vals, hipStream_t s);
 
-// Multifrontal extend-add of update matrices: work item = (child front tile
-// offset, child own tiles nt_d, parent front tile offset, boundary row r, map
-// offset); the child's boundary block row r (columns 0..r) is added into the
-// parent at positions map[r], map[s].
-struct ExtendRow {
-    int64_t child_off;
-    int64_t parent_off;
-    int64_t map_off;
-    int32_t nt_d;
-    int32_t r;
+// Multifrontal extend-add of update matrices: one work-group per 64x64 tile of
+// a child's boundary block; its lower-triangle elements (r, s), r >= s,
+// r, s < u, are added into the parent at positions (map[r], map[s]).
+struct ExtendTile {
+    int64_t child_off;    // child front (packed lower tiles)
+    int64_t parent_off;   // parent front
+    int64_t map_off;      // child boundary row -> parent position (maps[map_off + r])
+    int32_t nt_d;         // tiles of the child's own block (its boundary block starts there)
+    int32_t u;            // boundary dofs of the child
+    int32_t I, J;         // tile of the child's boundary block, I >= J
+    int32_t pad;
 };
-void launch_extend_add(const ExtendRow *rows, int64_t nrows, const int32_t *maps, double *arena, hipStream_t s);
+void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *maps, double *arena, hipStream_t s);
 // dst[dst_idx[i]] += sum_{q in [ptr[i], ptr[i+1])} src[src_idx[q]], i < n
 void launch_gather_add(const int64_t *dst_idx, const int64_t *ptr, const int64_t *src_idx, int64_t n,
                        const double *src, double *dst, hipStream_t s);

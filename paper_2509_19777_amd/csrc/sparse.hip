@@ -336,24 +336,28 @@ void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const Coars
 }
 
 // ---- multifrontal extend-add ---------------------------------------------------------
-__global__ void __launch_bounds__(64) extend_add_kernel(const ExtendRow *__restrict__ rows,
-                                                        const int32_t *__restrict__ maps, double *arena) {
-    const ExtendRow w = rows[blockIdx.x];
-    const int64_t base = (int64_t)w.nt_d * TS;
-    const double *C = arena + w.child_off;
+// One work-group per child tile: consecutive threads read consecutive rows
+// of a tile column (the stored order), and a column's parent positions are
+// mostly contiguous too.  Every child element is added exactly once.
+__global__ void __launch_bounds__(256) extend_add_kernel(const ExtendTile *__restrict__ tiles,
+                                                         const int32_t *__restrict__ maps, double *arena) {
+    const ExtendTile w = tiles[blockIdx.x];
+    const double *C = arena + w.child_off + tri_index(w.nt_d + w.I, w.nt_d + w.J) * TE;
     double *P = arena + w.parent_off;
     const int32_t *map = maps + w.map_off;
-    const int64_t pr = map[w.r];
-    for (int s = threadIdx.x; s <= w.r; s += 64) {
-        const double v = C[tile_elem(base + w.r, base + s)];
-        // (r, s) with r >= s of the child; same-tile mirror of the parent is
-        // written explicitly unless r == s
-        sym_put(P, pr, map[s], v, true, true);
+#pragma unroll 4
+    for (int q = 0; q < TE / 256; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int64_t r = (int64_t)w.I * TS + (e & (TS - 1)), c = (int64_t)w.J * TS + (e >> 6);
+        if (r >= w.u || c >= w.u || r < c) continue;
+        // (r, c) with r >= c of the child; same-tile mirror of the parent is
+        // written explicitly unless the positions coincide
+        sym_put(P, map[r], map[c], C[e], true, true);
     }
 }
-void launch_extend_add(const ExtendRow *rows, int64_t nrows, const int32_t *maps, double *arena, hipStream_t s) {
-    if (nrows <= 0) return;
-    hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)nrows), dim3(64), 0, s, rows, maps, arena);
+void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *maps, double *arena, hipStream_t s) {
+    if (ntiles <= 0) return;
+    hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, maps, arena);
 }
 
 __global__ void gather_add_kernel(const int64_t *__restrict__ dst_idx, const int64_t *__restrict__ ptr,
