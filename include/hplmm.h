@@ -164,8 +164,10 @@ hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_partition *pa
  * contact and coupling blocks; batched Cholesky and triangular inversion of
  * grain blocks A_gi and contact blocks; basis X_i = A_gi^-1 [-Abar_gi | b_gi]
  * (Eqs. 23-24); Galerkin coarse operator P^T A P^ (Eq. 18) and its
- * factorisation.  Asynchronous on `stream` except for one final check of the
- * pivot flags (reported as HPLMM_E_NOT_SPD / HPLMM_E_SINGULAR_COARSE). */
+ * factorisation.  The contact-grid blocks are factored on an internal stream
+ * that is forked from `stream` and joined back into it.  Returns after one
+ * final synchronising check of the pivot flags (reported as HPLMM_E_NOT_SPD /
+ * HPLMM_E_SINGULAR_COARSE). */
 hplmm_status hplmm_setup(hplmm_handle *h, void *stream);
 
 /* z = Op r for r, z device vectors of 3*n_nodes float64 (must not alias).
@@ -209,7 +211,10 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *   3 correction grains: int32[n_corr] grain ids, ascending
  *   4 coarse matrix: float64 n_coarse x n_coarse row-major (after setup):
  *            mortar block then the correction diagonal
- *   5 setup phase times in ms: double[4] = {grains, contacts, coarse, total}
+ *   5 setup phase times in ms: double[4] = {grains, contacts, coarse, total};
+ *            the contact grids are set up on an internal stream beside the
+ *            grains and the coarse operator, so total (the wall time of the
+ *            set-up) is less than the sum
  *   6 device bytes held: int64[1]
  *   7 profiler totals (see hplmm_profile)
  *   8 algorithmic bytes: double[2] = {one application of M^-1, one SpMV}

@@ -43,9 +43,12 @@ struct ProfScope {
     }
 };
 
+// part / cnt: split-task scratch (default: the task lists' own)
 template <class T>
 static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vector<Launch> &prog, int32_t *flag,
-                        hipStream_t s) {
+                        hipStream_t s, void *part = nullptr, int32_t *cnt = nullptr) {
+    if (!part) part = tl.d_part;
+    if (!cnt) cnt = tl.d_cnt;
     for (const Launch &L : prog) {
         switch (L.kind) {
             case LK_DIAG: {
@@ -55,7 +58,7 @@ static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vec
             }
             case LK_GEMM: {
                 ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
-                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (T *)tl.d_part, tl.d_cnt);
+                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (T *)part, cnt);
                 break;
             }
             case LK_TRANSPOSE: launch_tile_transpose<T>(arena, arena, tl.d_copy + L.start, L.count, s); break;
@@ -79,12 +82,54 @@ struct SgSetup {
 };
 static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s);
 
+// Contact grids (Eq. 26): blocks, factor and inverse, on stream s.
+static void contact_setup(Handle &h, hipStream_t s) {
+    if (h.smoother_precision == 64) {
+        zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
+        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
+        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
+        run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+    } else {
+        zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
+        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
+        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
+        launch_convert_f64_f32(h.ar64 + h.c_stage_base, h.ar32 + h.cset.a_base, h.cset.region, s);
+        run_program<float>(h, h.tl32, h.ar32, h.cset.factor_prog, h.d_flag, s);
+        if (h.smoother_precision == 16) {
+            launch_convert_f32_bf16(h.ar32 + h.cset.w_base, h.arbf + h.cset.low_w_base, h.cset.region, s);
+            launch_convert_f32_bf16(h.ar32 + h.cset.wt_base, h.arbf + h.cset.low_wt_base, h.cset.region, s);
+        }
+    }
+}
+
+// The numeric set-up.  A full set-up (stage 3) runs the contact grids on the
+// side stream, forked after the pivot flag is reset and joined at the end,
+// beside the grains and the coarse operator on s (disjoint arena regions and
+// split-task scratch).
 static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup *sg = nullptr) {
-    hipEvent_t ev[4];
-    for (auto &e : ev) hip_check(hipEventCreate(&e), "hipEventCreate");
+    struct Events {
+        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        ~Events() {
+            for (hipEvent_t x : e)
+                if (x) (void)hipEventDestroy(x);
+        }
+    } evs;
+    hipEvent_t *ev = evs.e;
+    for (int i = 0; i < 4; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
     const int32_t init_flag[2] = {0, 0x7fffffff};
     hip_check(hipMemcpyAsync(h.d_flag, init_flag, sizeof(init_flag), hipMemcpyHostToDevice, s), "flag init");
     hip_check(hipEventRecord(ev[0], s), "event");
+    const bool fork = stage >= 3;
+    if (fork) {
+        if (!h.side) {
+            hip_check(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking), "stream");
+            for (auto &e : h.side_ev) hip_check(hipEventCreate(&e), "event");
+        }
+        hip_check(hipStreamWaitEvent(h.side, ev[0], 0), "fork");
+        hip_check(hipEventRecord(h.side_ev[0], h.side), "event");
+        contact_setup(h, h.side);
+        hip_check(hipEventRecord(h.side_ev[1], h.side), "event");
+    }
     // ---- grains: blocks, factor, inverse, basis (Eqs. 23-24) ----
     zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
     if (!h.gm_roff.empty()) {
@@ -122,24 +167,6 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         launch_convert_f64_bf16(h.ar64 + h.gset.wt_base, h.arbf + h.gset.low_wt_base, h.gset.region, s);
     }
     hip_check(hipEventRecord(ev[1], s), "event");
-    // ---- contact grids (Eq. 26) ----
-    if (h.smoother_precision == 64) {
-        zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
-        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
-        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
-        run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s);
-    } else {
-        zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
-        launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
-        launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
-        launch_convert_f64_f32(h.ar64 + h.c_stage_base, h.ar32 + h.cset.a_base, h.cset.region, s);
-        run_program<float>(h, h.tl32, h.ar32, h.cset.factor_prog, h.d_flag, s);
-        if (h.smoother_precision == 16) {
-            launch_convert_f32_bf16(h.ar32 + h.cset.w_base, h.arbf + h.cset.low_w_base, h.cset.region, s);
-            launch_convert_f32_bf16(h.ar32 + h.cset.wt_base, h.arbf + h.cset.low_wt_base, h.cset.region, s);
-        }
-    }
-    hip_check(hipEventRecord(ev[2], s), "event");
     // ---- coarse operator P^T A P (Eq. 18) and its factorisation ----
     if (h.n_mortar > 0) {
         // assemble every front, then factor level by level from the leaves,
@@ -157,6 +184,8 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
             run_program<double>(h, h.tl64, h.ar64, mf.factor_prog[(size_t)l], h.d_flag, s);
         }
     }
+    hip_check(hipEventRecord(ev[2], s), "event");
+    hip_check(hipStreamWaitEvent(s, h.side_ev[1], 0), "join");
     hip_check(hipEventRecord(ev[3], s), "event");
     hip_check(hipGetLastError(), "kernel launch");
     int32_t flag[2];
@@ -165,13 +194,14 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
     if (h.n_corr)
         hip_check(hipMemcpyAsync(cd.data(), h.corr_d, sizeof(double) * cd.size(), hipMemcpyDeviceToHost, s), "corr copy");
     hip_check(hipStreamSynchronize(s), "set-up");
-    float ms[3];
-    for (int i = 0; i < 3; ++i) hip_check(hipEventElapsedTime(&ms[i], ev[i], ev[i + 1]), "elapsed");
-    h.t_setup_ms[0] = ms[0];
-    h.t_setup_ms[1] = ms[1];
-    h.t_setup_ms[2] = ms[2];
-    h.t_setup_ms[3] = (double)ms[0] + ms[1] + ms[2];
-    for (auto &e : ev) (void)hipEventDestroy(e);
+    // phases: grains [0, 1], contact grids on the side stream, coarse [1, 2];
+    // the total is the wall time [0, 3]
+    float ms[4];
+    hip_check(hipEventElapsedTime(&ms[0], ev[0], ev[1]), "elapsed");
+    hip_check(hipEventElapsedTime(&ms[1], h.side_ev[0], h.side_ev[1]), "elapsed");
+    hip_check(hipEventElapsedTime(&ms[2], ev[1], ev[2]), "elapsed");
+    hip_check(hipEventElapsedTime(&ms[3], ev[0], ev[3]), "elapsed");
+    for (int i = 0; i < 4; ++i) h.t_setup_ms[i] = ms[i];
     if (flag[0]) {
         const int set = flag[1] >> 26, m = flag[1] & ((1 << 26) - 1);
         const char *names[3] = {"grain", "contact-grid", "coarse"};

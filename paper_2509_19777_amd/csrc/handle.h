@@ -260,6 +260,12 @@ struct Handle {
     // cycle), captured on an internal stream and replayed on the caller's; rebuilt
     // when the Krylov buffers change
     std::vector<TuneRecord> tune_log;   // launches chosen by hplmm_autotune (empty: defaults)
+    // the contact-grid factorisation runs beside the grain and coarse stages on
+    // its own stream, with its own split-task scratch when it shares tl64
+    hipStream_t side = nullptr;
+    hipEvent_t side_ev[3] = {nullptr, nullptr, nullptr};
+    void *d_part_side = nullptr;
+    int32_t *d_cnt_side = nullptr;
     bool use_graphs = true;
     hipStream_t gstream = nullptr;
     std::vector<hipGraphExec_t> arnoldi_graphs;
@@ -297,6 +303,9 @@ struct Handle {
     ~Handle() {
         drop_graphs();
         if (gstream) (void)hipStreamDestroy(gstream);
+        for (hipEvent_t e : side_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (side) (void)hipStreamDestroy(side);
         for (hipEvent_t e : prof.pool) (void)hipEventDestroy(e);
         for (void *p : allocs) (void)hipFree(p);
     }

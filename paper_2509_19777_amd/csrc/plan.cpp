@@ -1510,6 +1510,15 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     h.tl64.d_part = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
     h.tl32.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tl32.part_len));
+    if (h.smoother_precision == 64) {
+        // the FP64 contact-grid program runs on the side stream next to the
+        // grain and coarse programs, which use tl64's scratch
+        h.d_part_side = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
+        h.d_cnt_side = h.dalloc<int32_t>(std::max<int32_t>(1, h.tl64.cnt_len));
+        if (hipMemsetAsync(h.d_cnt_side, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.tl64.cnt_len), s) !=
+            hipSuccess)
+            fail(HPLMM_E_HIP, "hipMemsetAsync failed");
+    }
     h.d_vtasks = h.upload(h.vtasks, s);
     h.d_vpairs = h.upload(h.vpairs, s);
     h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
