@@ -58,7 +58,7 @@ class HPLMM:
     """
 
     def __init__(self, problem, A=None, b=None, mesh=None, n=None, beta=None, w_zeta=None,
-                 use_rhs=True, smoother_precision="f64", tile=64):
+                 use_rhs=True, smoother_precision="f64", tile=64, mortar_kind="gaussian"):
         if A is None:
             A, b_asm, mesh = fem.assemble(problem)
             if b is None:
@@ -73,7 +73,7 @@ class HPLMM:
         self.N = self.A.shape[0]
         P = part_mod.classify(problem, mesh)
         part_mod.contact_grids(P, mesh, self.w_zeta)
-        mortar_mod.build_mortars(P, mesh, self.n, self.beta)
+        mortar_mod.build_mortars(P, mesh, self.n, self.beta, kind=mortar_kind, A=self.A)
         self.part = P
         self.smoother_precision = smoother_precision
         self.tile = tile
@@ -94,24 +94,20 @@ class HPLMM:
         self.Ncf = int(sum(d.size for d in iface_dofs))
         # x^ = W x : W[orig, permuted] = 1
         self.W = sp.csr_matrix((np.ones(self.N), (perm, np.arange(self.N))), shape=(self.N, self.N))
-        # Q^o = blockdiag_c (H_c (x) I_3): rows 3*v+gamma of the interface block,
-        # columns moff_c + 3*i + delta
+        # Q^o = blockdiag_c M^c (Eq. 21): rows 3*v+g of the interface block,
+        # columns moff_c + 3*i + gamma; M^c = H_c (x) I_3 for Gaussian mortars
         rows, cols, vals = [], [], []
         roff, coff = 0, 0
         self.moff = []
-        for c, H in enumerate(P.H):
-            Nc, nu = H.shape
+        for c, M in enumerate(P.M):
+            N3, n3 = M.shape
             self.moff.append(coff)
-            for v in range(Nc):
-                for i in range(nu):
-                    if H[v, i] == 0.0:
-                        continue
-                    for g in range(3):
-                        rows.append(roff + 3 * v + g)
-                        cols.append(coff + 3 * i + g)
-                        vals.append(H[v, i])
-            roff += 3 * Nc
-            coff += 3 * nu
+            r, q = np.nonzero(M)
+            rows.extend((roff + r).tolist())
+            cols.extend((coff + q).tolist())
+            vals.extend(M[r, q].tolist())
+            roff += N3
+            coff += n3
         self.Nmo = coff
         Qo = sp.csr_matrix((vals, (rows, cols)), shape=(self.Ncf, self.Nmo))
         self.Qo = Qo

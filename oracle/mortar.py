@@ -112,12 +112,50 @@ def gaussian_weights(pos, mortar_idx, beta=4.0):
     return alpha / alpha.sum(axis=1, keepdims=True)
 
 
-def build_mortars(P, mesh, n, beta=4.0):
-    """Mortar node indices and weight blocks H_c for every interface."""
-    P.mortar_idx, P.H = [], []
+def algebraic_block(Acc, mortar_idx):
+    """Algebraic mortar block M^{c} (3 N_c x 3 nu) of one interface, built as
+    the Remark after Eq. 22 describes: column (i, gamma) holds 1 at dof gamma
+    of mortar node i, 0 at every other mortar-node dof, and on the remaining
+    (free) interface dofs F the values -(A_FF)^-1 A_F,(i,gamma), i.e. the
+    interface-restricted operator's response to that unit constraint.
+
+    Acc: the interface-interface block of A (3 N_c x 3 N_c, dofs 3 v + g in
+    the interface's node order).  Rows of the result are 3 v + g, columns
+    3 i + gamma (mortar order)."""
+    Acc = np.asarray(Acc.todense() if hasattr(Acc, "todense") else Acc, dtype=float)
+    N3 = Acc.shape[0]
+    nu = len(mortar_idx)
+    K = np.array([3 * m + g for m in mortar_idx for g in range(3)], dtype=np.int64)   # column order 3 i + gamma
+    F = np.setdiff1d(np.arange(N3), K)
+    M = np.zeros((N3, 3 * nu))
+    M[K, np.arange(3 * nu)] = 1.0
+    if F.size:
+        # steps 1-3: drop the constrained rows, take the constrained columns as
+        # right-hand sides and the free columns as the matrix; step 4: solve
+        M[F, :] = -np.linalg.solve(Acc[np.ix_(F, F)], Acc[np.ix_(F, K)])
+    return M
+
+
+def build_mortars(P, mesh, n, beta=4.0, kind="gaussian", A=None):
+    """Mortar node indices and the blocks of Q^o for every interface:
+    P.H[c] (N_c x nu) for Gaussian mortars (Eq. 8), and P.M[c]
+    (3 N_c x 3 nu, rows 3 v + g, columns 3 i + gamma) for both kinds
+    (Gaussian: H_c (x) I_3; algebraic: algebraic_block of the interface block
+    of A, which must then be given)."""
+    P.mortar_idx, P.H, P.M = [], [], []
+    P.mortar_kind = kind
     for nodes in P.iface_nodes:
         nu = min(n, len(nodes))
         idx = place_mortars(mesh.xyz[nodes], nu)
         P.mortar_idx.append(idx)
-        P.H.append(gaussian_weights(mesh.xyz[nodes], idx, beta))
+        if kind == "gaussian":
+            H = gaussian_weights(mesh.xyz[nodes], idx, beta)
+            P.H.append(H)
+            P.M.append(np.kron(H, np.eye(3)))
+        elif kind == "algebraic":
+            d = (3 * np.asarray(nodes, dtype=np.int64)[:, None] + np.arange(3)).ravel()
+            P.H.append(None)
+            P.M.append(algebraic_block(A[d][:, d], idx))
+        else:
+            raise ValueError(kind)
     return P
