@@ -116,10 +116,23 @@ hplmm_status hplmm_partition_from_voxels(int32_t nx, int32_t ny, int32_t nz,
 void hplmm_partition_free(hplmm_partition *part);
 
 /* Mortar space (Sec. 3.3): n = mortar nodes per interface (n = 1 is PLMM),
- * beta = Gaussian spread (Eq. 8; the paper uses 4). */
+ * beta = Gaussian spread (Eq. 8; the paper uses 4), kind = the mortar
+ * functions:
+ *   HPLMM_MORTAR_GAUSSIAN   Gaussian weights normalised to a partition of
+ *                           unity, acting alike on x, y, z (Eq. 8);
+ *   HPLMM_MORTAR_ALGEBRAIC  algebraic mortars (Eq. 9 in the algebraic form
+ *                           that follows Eq. 22): column (node i, component g)
+ *                           is 1 at that dof, 0 at the other mortar-node dofs
+ *                           and -(A_FF)^-1 A_F,(i,g) on the remaining dofs F
+ *                           of the interface, from the interface block of the
+ *                           system matrix (computed by hplmm_plan; beta unused;
+ *                           the learned surrogate needs Gaussian mortars). */
+#define HPLMM_MORTAR_GAUSSIAN   0
+#define HPLMM_MORTAR_ALGEBRAIC  1
 typedef struct hplmm_mortar {
     int32_t n;
     double  beta;
+    int32_t kind;
 } hplmm_mortar;
 
 /* Smoother precision: 64 = float64; 32 = float32 contact factorisation and
@@ -207,7 +220,9 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *            coarse_levels, max_front_dofs}
  *   1 mortar node ids: int32 per interface, concatenated in interface order
  *            (nu_c entries each, local indices into the interface's nodes)
- *   2 Gaussian weights: float64, per interface row-major N_c x nu_c
+ *   2 mortar blocks: float64 per interface, row-major; Gaussian: H_c
+ *            (N_c x nu_c), algebraic: the 3 N_c x 3 nu_c block of Q^o (rows
+ *            3 v + g, columns 3 i + g')
  *   3 correction grains: int32[n_corr] grain ids, ascending
  *   4 coarse matrix: float64 n_coarse x n_coarse row-major (after setup):
  *            mortar block then the correction diagonal

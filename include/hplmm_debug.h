@@ -48,6 +48,12 @@ hplmm_status hplmm_debug_read_arena(hplmm_handle *h, int32_t arena, int64_t off,
  * offset, R offset, Y offset, K offset) -- 11 values per matrix. */
 hplmm_status hplmm_debug_grain_layout(hplmm_handle *h, int64_t *out, int64_t cap);
 
+/* Host only: the per-interface mortar blocks that hplmm_plan would build (the
+ * layout of query 2), concatenated in interface order, without touching the
+ * device.  out receives at most cap doubles; *needed gets the total. */
+hplmm_status hplmm_debug_mortar_blocks(const hplmm_system *sys, const hplmm_partition *part,
+                                       const hplmm_mortar *mortar, double *out, int64_t cap, int64_t *needed);
+
 #ifdef __cplusplus
 }
 #endif

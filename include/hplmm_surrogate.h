@@ -72,7 +72,7 @@ void hplmm_sg_destroy(hplmm_sg_net *net);
  * be NULL) receives the number of samples; count = 0 only queries it.
  * Grains must be 8^3-voxel boxes (every grain node and every node of its
  * adjacent interfaces inside one 9^3 node lattice with a corner at a multiple
- * of 8): E_PARTITION otherwise.  E_STATE if targets are asked before setup.
+ * of 8): E_PARTITION otherwise; the mortars must be Gaussian: E_ARG otherwise.  E_STATE if targets are asked before setup.
  * Asynchronous on stream except the first call, which builds and uploads the
  * sample tables. */
 hplmm_status hplmm_sg_samples(hplmm_handle *h, int64_t first, int64_t count, float *x_dev, float *y_dev,

@@ -751,6 +751,21 @@ extern "C" hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_pa
     });
 }
 
+extern "C" hplmm_status hplmm_debug_mortar_blocks(const hplmm_system *sys, const hplmm_partition *part,
+                                                  const hplmm_mortar *mortar, double *out, int64_t cap,
+                                                  int64_t *needed) {
+    return guarded([&]() -> hplmm_status {
+        if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
+        if (cap < 0 || (cap > 0 && !out)) fail(HPLMM_E_ARG, "bad output buffer");
+        Handle h;
+        hplmm_options o{64};
+        build_plan(h, *sys, *part, *mortar, o, nullptr, true);
+        if (needed) *needed = (int64_t)h.h_H.size();
+        if (out) std::memcpy(out, h.h_H.data(), sizeof(double) * (size_t)std::min<int64_t>(cap, (int64_t)h.h_H.size()));
+        return HPLMM_OK;
+    });
+}
+
 extern "C" hplmm_status hplmm_setup(hplmm_handle *hh, void *stream) {
     return guarded([&]() -> hplmm_status {
         if (!hh) fail(HPLMM_E_ARG, "NULL handle");

@@ -139,6 +139,7 @@ struct Handle {
     int32_t n_grains = 0, n_ifaces = 0, n_contacts = 0;
     int64_t n_mortar = 0, n_corr = 0, n_coarse = 0;
     int32_t smoother_precision = 64;
+    int32_t mortar_kind = HPLMM_MORTAR_GAUSSIAN;
     bool ready = false;
 
     // fine matrix

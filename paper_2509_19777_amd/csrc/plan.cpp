@@ -57,6 +57,85 @@ std::vector<double> gaussian_weights(const std::vector<int32_t> &xyz, int32_t N,
 // factorisation leaves the Schur complement in the trailing block), then the
 // triangular inverse W = L^-1 of the factored block by diagonals, then its
 // transposed tiles Wt = W^T.
+// Algebraic mortar block of interface c (Eq. 9 in the algebraic form that
+// follows Eq. 22): 3 Nc x 3 nu, row-major, rows 3 v + g (interface order),
+// columns 3 i + g (mortar order).  Column (i, g) is 1 at dof g of mortar node
+// i, 0 at the other mortar-node dofs, and -(A_FF)^-1 A_F,(i,g) on the free
+// dofs F.  A_FF is factored by a banded Cholesky: interface nodes in
+// ascending id order couple only to nearby positions.
+std::vector<double> algebraic_block(const hplmm_system &sys, const int32_t *nodes, int32_t Nc, int32_t c,
+                                    const std::vector<int32_t> &node_iface, const std::vector<int32_t> &node_irow,
+                                    const std::vector<int32_t> &idx) {
+    const int32_t n3 = 3 * Nc, k3 = 3 * (int32_t)idx.size();
+    std::vector<int32_t> col((size_t)n3, -1), fpos((size_t)n3, -1), F;
+    for (size_t i = 0; i < idx.size(); ++i)
+        for (int g = 0; g < 3; ++g) col[(size_t)(3 * idx[i] + g)] = (int32_t)(3 * i + g);
+    for (int32_t d = 0; d < n3; ++d)
+        if (col[(size_t)d] < 0) {
+            fpos[(size_t)d] = (int32_t)F.size();
+            F.push_back(d);
+        }
+    const int64_t nf = (int64_t)F.size();
+    std::vector<double> M((size_t)n3 * k3, 0.0);
+    for (int32_t d = 0; d < n3; ++d)
+        if (col[(size_t)d] >= 0) M[(size_t)d * k3 + col[(size_t)d]] = 1.0;
+    if (nf == 0) return M;
+    std::vector<double> L((size_t)(nf * nf), 0.0), B((size_t)(nf * k3), 0.0);
+    int64_t bw = 0;
+    for (int32_t v = 0; v < Nc; ++v) {
+        const int32_t gv = nodes[v];
+        for (int64_t p = sys.row_ptr[gv]; p < sys.row_ptr[gv + 1]; ++p) {
+            const int32_t w = sys.col_idx[p];
+            if (node_iface[(size_t)w] != c) continue;
+            const int32_t lw = node_irow[(size_t)w];
+            for (int gi = 0; gi < 3; ++gi) {
+                const int64_t fr = fpos[(size_t)(3 * v + gi)];
+                if (fr < 0) continue;   // constrained rows are dropped
+                for (int di = 0; di < 3; ++di) {
+                    const int32_t cd = 3 * lw + di;
+                    const double a = sys.val[9 * p + 3 * gi + di];
+                    if (fpos[(size_t)cd] >= 0) {
+                        const int64_t fc = fpos[(size_t)cd];
+                        L[(size_t)(fr * nf + fc)] = a;
+                        bw = std::max<int64_t>(bw, fr > fc ? fr - fc : fc - fr);
+                    } else {
+                        B[(size_t)(fr * k3 + col[(size_t)cd])] = a;
+                    }
+                }
+            }
+        }
+    }
+    // A_FF = L L^T within the band (lower triangle of L, row-major)
+    for (int64_t k = 0; k < nf; ++k) {
+        double d = L[(size_t)(k * nf + k)];
+        for (int64_t q = std::max<int64_t>(0, k - bw); q < k; ++q) d -= L[(size_t)(k * nf + q)] * L[(size_t)(k * nf + q)];
+        if (!(d > 0.0)) fail(HPLMM_E_NOT_SPD, "algebraic mortars: interface block " + std::to_string(c) + " is not positive definite");
+        const double lkk = std::sqrt(d);
+        L[(size_t)(k * nf + k)] = lkk;
+        for (int64_t i = k + 1; i <= std::min<int64_t>(nf - 1, k + bw); ++i) {
+            double t = L[(size_t)(i * nf + k)];
+            for (int64_t q = std::max<int64_t>(0, i - bw); q < k; ++q) t -= L[(size_t)(i * nf + q)] * L[(size_t)(k * nf + q)];
+            L[(size_t)(i * nf + k)] = t / lkk;
+        }
+    }
+    // A_FF X = A_FK by the two banded triangular solves; M_F = -X
+    std::vector<double> x((size_t)nf);
+    for (int32_t j = 0; j < k3; ++j) {
+        for (int64_t i = 0; i < nf; ++i) {
+            double t = B[(size_t)(i * k3 + j)];
+            for (int64_t q = std::max<int64_t>(0, i - bw); q < i; ++q) t -= L[(size_t)(i * nf + q)] * x[(size_t)q];
+            x[(size_t)i] = t / L[(size_t)(i * nf + i)];
+        }
+        for (int64_t i = nf - 1; i >= 0; --i) {
+            double t = x[(size_t)i];
+            for (int64_t q = i + 1; q <= std::min<int64_t>(nf - 1, i + bw); ++q) t -= L[(size_t)(q * nf + i)] * x[(size_t)q];
+            x[(size_t)i] = t / L[(size_t)(i * nf + i)];
+        }
+        for (int64_t i = 0; i < nf; ++i) M[(size_t)F[(size_t)i] * k3 + j] = -x[(size_t)i];
+    }
+    return M;
+}
+
 void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vector<Launch> *out = nullptr,
                           const std::vector<int64_t> *ids = nullptr) {
     std::vector<Launch> &prog = out ? *out : ds.factor_prog;
@@ -782,6 +861,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     if (part.n_contacts < 0 || (part.n_contacts > 0 && (!part.contact_ptr || !part.contact_nodes)))
         fail(HPLMM_E_ARG, "contact arrays missing");
     if (mort.n <= 0 || !(mort.beta > 0)) fail(HPLMM_E_ARG, "mortar n must be > 0 and beta > 0");
+    if (mort.kind != HPLMM_MORTAR_GAUSSIAN && mort.kind != HPLMM_MORTAR_ALGEBRAIC)
+        fail(HPLMM_E_ARG, "unknown mortar kind");
+    h.mortar_kind = mort.kind;
     if (opt.smoother_precision != 64 && opt.smoother_precision != 32 && opt.smoother_precision != 16)
         fail(HPLMM_E_ARG, "smoother_precision must be 64, 32 or 16");
     h.smoother_precision = opt.smoother_precision;
@@ -839,7 +921,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         for (int32_t v = 0; v < Nc; ++v)
             for (int d = 0; d < 3; ++d) xyz[(size_t)3 * v + d] = sys.node_xyz[3 * (int64_t)part.iface_nodes[p0 + v] + d];
         auto idx = place_mortars(xyz.data(), Nc, mort.n);
-        auto H = gaussian_weights(xyz, Nc, idx, mort.beta);
+        auto H = mort.kind == HPLMM_MORTAR_GAUSSIAN
+                     ? gaussian_weights(xyz, Nc, idx, mort.beta)
+                     : algebraic_block(sys, part.iface_nodes + p0, Nc, c, node_iface, node_irow, idx);
         iface_nu[(size_t)c] = (int32_t)idx.size();
         iface_moff[(size_t)c] = moff;
         iface_hoff[(size_t)c] = (int64_t)h.h_H.size();
@@ -1429,6 +1513,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.cm.iface_nu = h.upload(iface_nu, s);
     h.cm.iface_moff = h.upload(iface_moff, s);
     h.cm.H = h.upload(h.h_H, s);
+    h.cm.general = h.mortar_kind == HPLMM_MORTAR_ALGEBRAIC ? 1 : 0;
     h.cm.tptr = h.upload(tptr, s);
     h.cm.tslot = h.upload(tslot, s);
     h.corr_d = h.dalloc<double>(h.n_corr);

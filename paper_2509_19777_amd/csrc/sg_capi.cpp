@@ -210,6 +210,8 @@ namespace hplmm {
 // must lie in one 9^3 node lattice whose corner is a multiple of 8.
 void sg_build_sample_tables(Handle &h, hipStream_t s) {
     if (h.sg_ready) return;
+    if (h.mortar_kind != HPLMM_MORTAR_GAUSSIAN)
+        fail(HPLMM_E_ARG, "the learned surrogate's inputs need Gaussian mortars");
     const int64_t nG = (int64_t)h.gm_grain.size();
     std::vector<int32_t> origin((size_t)(3 * nG), 0);
     std::vector<float> logmean((size_t)nG, 0.f);

@@ -44,10 +44,13 @@ struct CoarseMaps {
     const int32_t *q_local;      // [n_mortar] q - moff(iface)
     const int64_t *iface_ptr;    // [n_ifaces+1]
     const int32_t *iface_nodes;  // interface node lists
-    const int64_t *iface_hoff;   // [n_ifaces] offset of H_c (row-major N_c x nu_c)
+    const int64_t *iface_hoff;   // [n_ifaces] offset of the interface's block in H
     const int32_t *iface_nu;     // [n_ifaces]
     const int64_t *iface_moff;   // [n_ifaces] first mortar dof
-    const double *H;             // Gaussian weights
+    const double *H;             // mortar blocks: general == 0: Gaussian H_c (N_c x nu_c,
+                                 // Q^o block H_c (x) I_3); general == 1: the Q^o block
+                                 // itself (3 N_c x 3 nu_c, rows 3 v + g, columns 3 a + g')
+    int32_t general;
     const int64_t *tptr;         // [n_coarse+1]
     const int64_t *tslot;        // slots into the per-grain t arena
     const double *corr_d;        // [n_corr] coarse correction pivots b_i^T c_i
@@ -57,7 +60,7 @@ struct CoarseMaps {
 void launch_coarse_rhs(const CoarseMaps &m, const double *r, const double *t, double *f, hipStream_t s);
 // u[fpos[q]] = f[fpos[q]] / corr_d[q - n_mortar] for corrections
 void launch_corr_solve(const CoarseMaps &m, const double *f, double *u, hipStream_t s);
-// z[3v+g] = gslot[3v+g] >= 0 ? zl[gslot] : sum_a H[v,a] u[fpos[moff + 3a + g]]
+// z[3v+g] = gslot[3v+g] >= 0 ? zl[gslot] : (Q^o u)[3v+g], Q^o from the interface blocks
 void launch_prolong_nodes(const CoarseMaps &m, int64_t n_nodes, const int64_t *gslot, const double *zl,
                           const double *u, double *z, hipStream_t s);
 

@@ -104,7 +104,16 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(CoarseMaps m, const dou
         const int32_t a = lq / 3, d = lq % 3;
         const double *H = m.H + m.iface_hoff[c];
         const int64_t p0 = m.iface_ptr[c], p1 = m.iface_ptr[c + 1];
-        for (int64_t p = p0 + lane; p < p1; p += 64) s += H[(p - p0) * nu + a] * r[3 * (int64_t)m.iface_nodes[p] + d];
+        if (!m.general) {
+            for (int64_t p = p0 + lane; p < p1; p += 64) s += H[(p - p0) * nu + a] * r[3 * (int64_t)m.iface_nodes[p] + d];
+        } else {
+            const int64_t k3 = 3 * (int64_t)nu;
+            for (int64_t p = p0 + lane; p < p1; p += 64) {
+                const double *row = H + 3 * (p - p0) * k3 + lq;
+                const double *rv = r + 3 * (int64_t)m.iface_nodes[p];
+                s += row[0] * rv[0] + row[k3] * rv[1] + row[2 * k3] * rv[2];
+            }
+        }
     }
     for (int64_t p = m.tptr[q] + lane; p < m.tptr[q + 1]; p += 64) s += t[m.tslot[p]];
 #pragma unroll
@@ -144,9 +153,15 @@ __global__ void prolong_nodes_kernel(CoarseMaps m, int64_t n_nodes, const int64_
     double s = 0.0;
     if (c >= 0) {
         const int32_t nu = m.iface_nu[c];
-        const double *H = m.H + m.iface_hoff[c] + (int64_t)m.node_irow[v] * nu;
         const int64_t mo = m.iface_moff[c];
-        for (int a = 0; a < nu; ++a) s += H[a] * u[m.fpos[mo + 3 * a + g]];
+        if (!m.general) {
+            const double *H = m.H + m.iface_hoff[c] + (int64_t)m.node_irow[v] * nu;
+            for (int a = 0; a < nu; ++a) s += H[a] * u[m.fpos[mo + 3 * a + g]];
+        } else {
+            const int64_t k3 = 3 * (int64_t)nu;
+            const double *H = m.H + m.iface_hoff[c] + (3 * (int64_t)m.node_irow[v] + g) * k3;
+            for (int64_t k = 0; k < k3; ++k) s += H[k] * u[m.fpos[mo + k]];
+        }
     }
     z[d] = s;
 }
@@ -222,14 +237,25 @@ __global__ void gather_abar_kernel(FineCsr A, const AbarWork *__restrict__ work,
     const double *H = cm.H + cm.iface_hoff[wk.c];
     double *R = arena + g.mat_roff[wk.m];
     const int64_t nt = g.mat_nt[wk.m];
+    const int64_t k3 = 3 * (int64_t)nu;
     for (int a = 0; a < nu; ++a) {
-        double acc[9];
+        double acc[9];   // acc[3 gi + di]: row gi of the node, column 3 a + di
         for (int j = 0; j < 9; ++j) acc[j] = 0.0;
         for (int64_t p = A.row_ptr[wk.v]; p < A.row_ptr[wk.v + 1]; ++p) {
             const int32_t w = A.col[p];
             if (cm.node_iface[w] != wk.c) continue;
-            const double h = H[(int64_t)cm.node_irow[w] * nu + a];
-            for (int j = 0; j < 9; ++j) acc[j] += A.val[9 * p + j] * h;
+            if (!cm.general) {
+                const double h = H[(int64_t)cm.node_irow[w] * nu + a];
+                for (int j = 0; j < 9; ++j) acc[j] += A.val[9 * p + j] * h;
+            } else {
+                const double *Mw = H + 3 * (int64_t)cm.node_irow[w] * k3 + 3 * a;   // rows 3 w + d, columns 3 a + di
+                for (int gi = 0; gi < 3; ++gi)
+                    for (int di = 0; di < 3; ++di) {
+                        double t = 0.0;
+                        for (int d = 0; d < 3; ++d) t += A.val[9 * p + 3 * gi + d] * Mw[d * k3 + di];
+                        acc[3 * gi + di] += t;
+                    }
+            }
         }
         for (int gi = 0; gi < 3; ++gi)
             for (int di = 0; di < 3; ++di)
@@ -305,9 +331,24 @@ __global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *_
         const int i = e / n2, j = e - (e / n2) * n2;
         const int a = i / 3, gi = i % 3, bb = j / 3, di = j % 3;
         double acc = 0.0;
-        for (int32_t k = 0; k < pr.e_count; ++k) {
-            const CoarseEdge ed = edges[pr.e_start + k];
-            acc += H1[(int64_t)ed.rv * nu1 + a] * H2[(int64_t)ed.rw * nu2 + bb] * bval[9 * ed.blk + 3 * gi + di];
+        if (!cm.general) {
+            for (int32_t k = 0; k < pr.e_count; ++k) {
+                const CoarseEdge ed = edges[pr.e_start + k];
+                acc += H1[(int64_t)ed.rv * nu1 + a] * H2[(int64_t)ed.rw * nu2 + bb] * bval[9 * ed.blk + 3 * gi + di];
+            }
+        } else {
+            // sum over the edge's 3x3 block: M1[(rv, d1), i] A[d1][d2] M2[(rw, d2), j]
+            for (int32_t k = 0; k < pr.e_count; ++k) {
+                const CoarseEdge ed = edges[pr.e_start + k];
+                const double *m1 = H1 + 3 * (int64_t)ed.rv * n1 + i;
+                const double *m2 = H2 + 3 * (int64_t)ed.rw * n2 + j;
+                const double *blk = bval + 9 * ed.blk;
+                for (int d1 = 0; d1 < 3; ++d1) {
+                    double t = 0.0;
+                    for (int d2 = 0; d2 < 3; ++d2) t += blk[3 * d1 + d2] * m2[d2 * n2];
+                    acc += m1[d1 * n1] * t;
+                }
+            }
         }
         double kk = 0.0;
         for (int32_t k = 0; k < pr.k_count; ++k) {

@@ -35,7 +35,10 @@ class HplmmPartition(C.Structure):
 
 
 class HplmmMortar(C.Structure):
-    _fields_ = [("n", i32), ("beta", f64)]
+    _fields_ = [("n", i32), ("beta", f64), ("kind", i32)]
+
+
+MORTAR_KINDS = {"gaussian": 0, "algebraic": 1}
 
 
 class HplmmOptions(C.Structure):
@@ -71,6 +74,7 @@ EXPORTS = {
     "hplmm_destroy": (None, [C.c_void_p]),
     "hplmm_profile": (i32, [C.c_void_p, i32]),
     "hplmm_use_graphs": (i32, [C.c_void_p, i32]),
+    "hplmm_debug_mortar_blocks": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, P(f64), i64, P(i64)]),
     "hplmm_autotune": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_set_tuning": (i32, [C.c_void_p, C.c_void_p, i64]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
@@ -240,16 +244,37 @@ def place_mortars(xyz, n):
     return out.tolist()
 
 
-def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64):
+def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64, mortar_kind="gaussian"):
     """Host-only symbolic phase plus bounds check of every launch list."""
     s, p = system.c_struct(), part.c_struct()
-    m = HplmmMortar(int(n_mortar), float(beta))
+    m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
     o = HplmmOptions(int(smoother_precision))
     out = np.zeros(16, dtype=np.int64)
     _check(lib().hplmm_plan_check(C.byref(s), C.byref(p), C.byref(m), C.byref(o), _ptr(out, i64)))
     keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
             "grain_mats", "ar64", "ar32", "arbf", "tile_tasks", "coarse_fronts", "coarse_levels", "max_front_dofs"]
     return dict(zip(keys, (int(x) for x in out)))
+
+
+def mortar_blocks(system, part, n_mortar=2, beta=4.0, mortar_kind="gaussian"):
+    """Host only: the per-interface mortar blocks of the plan, one array per
+    interface (Gaussian: N_c x nu_c; algebraic: 3 N_c x 3 nu_c)."""
+    s, p = system.c_struct(), part.c_struct()
+    m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
+    need = i64(0)
+    _check(lib().hplmm_debug_mortar_blocks(C.byref(s), C.byref(p), C.byref(m), None, 0, C.byref(need)))
+    buf = np.zeros(max(int(need.value), 1))
+    _check(lib().hplmm_debug_mortar_blocks(C.byref(s), C.byref(p), C.byref(m), _ptr(buf, f64), buf.size,
+                                           C.byref(need)))
+    out, off = [], 0
+    for c in range(part.n_ifaces):
+        Nc = int(part.iface_ptr[c + 1] - part.iface_ptr[c])
+        nu = min(int(n_mortar), Nc)
+        r, k = (Nc, nu) if mortar_kind == "gaussian" else (3 * Nc, 3 * nu)
+        out.append(buf[off:off + r * k].reshape(r, k))
+        off += r * k
+    assert off == int(need.value)
+    return out
 
 
 # ---- device solver --------------------------------------------------------------------
@@ -270,13 +295,14 @@ class Solver:
     tensors of length 3*n_nodes.
     """
 
-    def __init__(self, system: System, part: Partition, n_mortar=2, beta=4.0, smoother_precision=64):
+    def __init__(self, system: System, part: Partition, n_mortar=2, beta=4.0, smoother_precision=64,
+                 mortar_kind="gaussian"):
         if not torch.cuda.is_available():
             raise RuntimeError("hplmm.Solver needs a GPU")
         self.system, self.part = system, part
         self._keep = (system.c_struct(), part.c_struct())
         h = C.c_void_p()
-        m = HplmmMortar(int(n_mortar), float(beta))
+        m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
         o = HplmmOptions(int(smoother_precision))
         _check(lib().hplmm_plan(C.byref(self._keep[0]), C.byref(self._keep[1]), C.byref(m), C.byref(o), _stream(),
                                 C.byref(h)))

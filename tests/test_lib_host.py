@@ -133,3 +133,35 @@ def test_plan_rejects_coupled_grains(hp):
     with pytest.raises(hp.HplmmError) as e:
         hp.plan_check(sysm, bad)
     assert e.value.code == -2
+
+
+@pytest.mark.parametrize("kind", ["gaussian", "algebraic"])
+@pytest.mark.parametrize("n", [1, 2, 4])
+def test_mortar_blocks_match_oracle(hp, kind, n):
+    # the plan's interface blocks of Q^o against the oracle's (Gaussian: H_c;
+    # algebraic: the elimination of the interface block, here a banded
+    # Cholesky against the oracle's dense solve)
+    from oracle import fem, mortar, partition
+    p = synth.config_pores(16, 4, seed=1)
+    A, b, mesh = fem.assemble(p)
+    sysm, part = hp.build_problem(p)
+    got = hp.mortar_blocks(sysm, part, n_mortar=n, mortar_kind=kind)
+    P = partition.classify(p, mesh)
+    mortar.build_mortars(P, mesh, n, kind=kind, A=A.tocsr())
+    assert len(got) == len(P.M)
+    for c, G in enumerate(got):
+        want = P.H[c] if kind == "gaussian" else P.M[c]
+        assert G.shape == want.shape
+        assert np.abs(G - want).max() <= 1e-12 * max(1.0, np.abs(want).max()), (c, np.abs(G - want).max())
+
+
+def test_plan_check_algebraic_mortars(hp):
+    p = synth.config_pores(16, 4, seed=1)
+    sysm, part = hp.build_problem(p)
+    a = hp.plan_check(sysm, part, n_mortar=4, mortar_kind="algebraic")
+    g = hp.plan_check(sysm, part, n_mortar=4)
+    assert a["n_coarse"] == g["n_coarse"] and a["ar64"] == g["ar64"]
+    with pytest.raises(hp.HplmmError):
+        s, q = sysm.c_struct(), part.c_struct()
+        m = hp.HplmmMortar(4, 4.0, 7)
+        hp._check(hp.lib().hplmm_plan_check(hp.C.byref(s), hp.C.byref(q), hp.C.byref(m), None, None))
