@@ -98,6 +98,8 @@ def main():
         # launch shapes depend on the problem's structure only: chosen once,
         # like the plan, before the timed region
         t_t = time.perf_counter()
+        if a.warmup == 0:
+            S.setup()   # the tuner times the set-up's operators
         recs = S.autotune(a.autotune_reps)
         t_t = time.perf_counter() - t_t
         changed = [r for r in recs if r["variant"] != 0 or r["waves"] != 4]
