@@ -190,18 +190,19 @@ def traffic_for(dom):
     try:
         t = json.load(open(path))
         rec = t.get(dom)
-        if not rec or rec.get("source_sha256") != _source_hash():
+        if not rec or rec.get("source_sha256") != _source_hash(rec.get("source_files", [])):
             return None
         return rec.get("bytes_per_launch")
     except Exception:
         return None
 
 
-def _source_hash():
+def _source_hash(files):
+    """SHA-256 over the sources of the counted kernel (paths relative to the repository)."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("dense.hip", "sparse.hip"):
-        h.update(open(os.path.join(ROOT, "paper_2509_19777_amd", "csrc", f), "rb").read())
+    for f in files:
+        h.update(open(os.path.join(ROOT, f), "rb").read())
     return h.hexdigest()
 
 

@@ -486,12 +486,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 // One pass over the block's rows of a Krylov basis:
 //   x = w - sum_{j < k_sub} hsub[j] V_j      (k_sub may be 0; x written to wout if given)
 //   part[b * k_dot + j] = sum_rows x . D_j   (D_j = D + j * ld_d), or x . x when D is null
+// The subtraction streams four basis vectors at a time; the dot products go
+// in chunks of eight vectors: every thread accumulates its rows for the
+// chunk, one LDS transpose hands each vector to 32 lanes, and a 32-lane
+// butterfly finishes it (one reduction per chunk instead of one per vector).
 __global__ void __launch_bounds__(256) kr_pass_kernel(const double *__restrict__ V, int64_t ld, int32_t k_sub,
                                                       const double *__restrict__ hsub, const double *w,
                                                       double *wout, int64_t n, const double *__restrict__ D,
                                                       int64_t ld_d, int32_t k_dot, double *__restrict__ part) {
     __shared__ double hs[KR_MAXK];
-    __shared__ double red[4][KR_MAXK];
+    __shared__ double red[8][256];
     for (int j = threadIdx.x; j < k_sub; j += 256) hs[j] = hsub[j];
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * (256 * KR_ROWS) + threadIdx.x;
@@ -502,15 +506,27 @@ __global__ void __launch_bounds__(256) kr_pass_kernel(const double *__restrict__
         x[r] = i < n ? w[i] : 0.0;
     }
     if (k_sub > 0) {
-        for (int32_t j = 0; j < k_sub; ++j) {
-            const double hj = hs[j];
-            const double *v = V + j * ld;
+        int32_t j = 0;
+        for (; j + 4 <= k_sub; j += 4) {
 #pragma unroll
             for (int r = 0; r < KR_ROWS; ++r) {
                 const int64_t i = base + 256 * r;
-                if (i < n) x[r] -= hj * v[i];
+                if (i < n) {
+                    const double a0 = V[(j + 0) * ld + i], a1 = V[(j + 1) * ld + i];
+                    const double a2 = V[(j + 2) * ld + i], a3 = V[(j + 3) * ld + i];
+                    x[r] -= hs[j] * a0;
+                    x[r] -= hs[j + 1] * a1;
+                    x[r] -= hs[j + 2] * a2;
+                    x[r] -= hs[j + 3] * a3;
+                }
             }
         }
+        for (; j < k_sub; ++j)
+#pragma unroll
+            for (int r = 0; r < KR_ROWS; ++r) {
+                const int64_t i = base + 256 * r;
+                if (i < n) x[r] -= hs[j] * V[j * ld + i];
+            }
         if (wout) {
 #pragma unroll
             for (int r = 0; r < KR_ROWS; ++r) {
@@ -519,26 +535,39 @@ __global__ void __launch_bounds__(256) kr_pass_kernel(const double *__restrict__
             }
         }
     }
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    for (int32_t j = 0; j < k_dot; ++j) {
-        double sj = 0.0;
-        if (D) {
-            const double *d = D + j * ld_d;
+    const int t = threadIdx.x;
+    for (int32_t c = 0; c < k_dot; c += 8) {
+        const int m = k_dot - c < 8 ? k_dot - c : 8;
+        double acc[8];
 #pragma unroll
-            for (int r = 0; r < KR_ROWS; ++r) {
-                const int64_t i = base + 256 * r;
-                if (i < n) sj += x[r] * d[i];
+        for (int q = 0; q < 8; ++q) {
+            acc[q] = 0.0;
+            if (q < m) {
+                if (D) {
+                    const double *d = D + (c + q) * ld_d;
+#pragma unroll
+                    for (int r = 0; r < KR_ROWS; ++r) {
+                        const int64_t i = base + 256 * r;
+                        if (i < n) acc[q] += x[r] * d[i];
+                    }
+                } else {
+#pragma unroll
+                    for (int r = 0; r < KR_ROWS; ++r) acc[q] += x[r] * x[r];
+                }
             }
-        } else {
-#pragma unroll
-            for (int r = 0; r < KR_ROWS; ++r) sj += x[r] * x[r];
         }
-        sj = wave_sum(sj);
-        if (lane == 0) red[wv][j] = sj;
+        __syncthreads();   // the previous chunk's reads of red are done
+#pragma unroll
+        for (int q = 0; q < 8; ++q) red[q][t] = acc[q];
+        __syncthreads();
+        const int q = t >> 5, l = t & 31;
+        double sq = 0.0;
+#pragma unroll
+        for (int z = 0; z < 8; ++z) sq += red[q][l + 32 * z];
+#pragma unroll
+        for (int o = 16; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+        if (l == 0 && q < m) part[(int64_t)blockIdx.x * k_dot + c + q] = sq;
     }
-    __syncthreads();
-    for (int j = threadIdx.x; j < k_dot; j += 256)
-        part[(int64_t)blockIdx.x * k_dot + j] = ((red[0][j] + red[1][j]) + red[2][j]) + red[3][j];
 }
 void launch_kr_pass(const double *V, int64_t ld, int32_t k_sub, const double *hsub, const double *w, double *wout,
                     int64_t n, const double *D, int64_t ld_d, int32_t k_dot, double *part, hipStream_t s) {
