@@ -138,9 +138,14 @@ typedef struct hplmm_mortar {
 /* Smoother precision: 64 = float64; 32 = float32 contact factorisation and
  * float32 smoother operators; 16 = float32 contact factorisation and
  * bfloat16 smoother operators.  The coarse space (basis, coarse operator,
- * coarse solve) and the Krylov solver are float64 in every mode. */
+ * coarse solve) and the Krylov solver are float64 in every mode.
+ * coarse_leaf_dofs: the nested dissection of the coarse operator stops at
+ * subsets of at most this many dofs (0 = the default, 192); larger leaves
+ * give fewer front levels (fewer launches per coarse solve) and larger dense
+ * leaf fronts. */
 typedef struct hplmm_options {
     int32_t smoother_precision;
+    int32_t coarse_leaf_dofs;
 } hplmm_options;
 
 /* Place the mortar nodes of one interface (Sec. 3.3, Eq. 7): xyz[3*N] lattice

@@ -713,7 +713,7 @@ extern "C" hplmm_status hplmm_plan(const hplmm_system *sys, const hplmm_partitio
         if (!out) fail(HPLMM_E_ARG, "out is NULL");
         *out = nullptr;
         if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
-        hplmm_options o{64};
+        hplmm_options o{64, 0};
         if (opt) o = *opt;
         int dev = 0;
         hip_check(hipGetDevice(&dev), "hipGetDevice");
@@ -734,7 +734,7 @@ extern "C" hplmm_status hplmm_plan_check(const hplmm_system *sys, const hplmm_pa
                                          const hplmm_mortar *mortar, const hplmm_options *opt, int64_t *sizes) {
     return guarded([&]() -> hplmm_status {
         if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
-        hplmm_options o{64};
+        hplmm_options o{64, 0};
         if (opt) o = *opt;
         Handle h;
         build_plan(h, *sys, *part, *mortar, o, nullptr, true);
@@ -758,7 +758,7 @@ extern "C" hplmm_status hplmm_debug_mortar_blocks(const hplmm_system *sys, const
         if (!sys || !part || !mortar) fail(HPLMM_E_ARG, "NULL argument");
         if (cap < 0 || (cap > 0 && !out)) fail(HPLMM_E_ARG, "bad output buffer");
         Handle h;
-        hplmm_options o{64};
+        hplmm_options o{64, 0};
         build_plan(h, *sys, *part, *mortar, o, nullptr, true);
         if (needed) *needed = (int64_t)h.h_H.size();
         if (out) std::memcpy(out, h.h_H.data(), sizeof(double) * (size_t)std::min<int64_t>(cap, (int64_t)h.h_H.size()));

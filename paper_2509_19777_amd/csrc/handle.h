@@ -140,6 +140,7 @@ struct Handle {
     int64_t n_mortar = 0, n_corr = 0, n_coarse = 0;
     int32_t smoother_precision = 64;
     int32_t mortar_kind = HPLMM_MORTAR_GAUSSIAN;
+    int64_t coarse_leaf_dofs = 192;
     bool ready = false;
 
     // fine matrix

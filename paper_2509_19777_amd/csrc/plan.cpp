@@ -407,15 +407,14 @@ void pad_ones(const DenseSet &ds, std::vector<int64_t> &out, int64_t a_base) {
 // Nested dissection of the interface graph (two interfaces are adjacent when
 // the coarse operator couples them) by recursive coordinate bisection of the
 // interface centroids; each bisection's separator is the boundary layer of
-// the side with fewer dofs.  Subsets of at most kLeafDofs dofs become leaves.
-constexpr int64_t kLeafDofs = 192;
-
+// the side with fewer dofs.  Subsets of at most leaf_dofs dofs become leaves.
 struct NDCtx {
     const std::vector<std::vector<int32_t>> &adj;
     const std::vector<std::array<double, 3>> &cen;
     const std::vector<int32_t> &dofs;
     CoarseMF &mf;
     std::vector<int32_t> mark;
+    int64_t leaf_dofs;
 };
 
 int32_t nd_build(NDCtx &x, std::vector<int32_t> I, int32_t par, int32_t side, int32_t depth) {
@@ -428,7 +427,7 @@ int32_t nd_build(NDCtx &x, std::vector<int32_t> I, int32_t par, int32_t side, in
     mf.bnd.emplace_back();
     int64_t tot = 0;
     for (int32_t c : I) tot += x.dofs[(size_t)c];
-    if (tot <= kLeafDofs || I.size() <= 2) {
+    if (tot <= x.leaf_dofs || I.size() <= 2) {
         std::sort(I.begin(), I.end());
         mf.own[(size_t)t] = I;
         return t;
@@ -506,7 +505,7 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         for (int d = 0; d < 3; ++d) cen[(size_t)c][d] = s[d] / (double)(p1 - p0);
         dofs[(size_t)c] = 3 * iface_nu[(size_t)c];
     }
-    NDCtx x{adj, cen, dofs, mf, std::vector<int32_t>((size_t)nI, 0)};
+    NDCtx x{adj, cen, dofs, mf, std::vector<int32_t>((size_t)nI, 0), h.coarse_leaf_dofs};
     std::vector<int32_t> all((size_t)nI);
     std::iota(all.begin(), all.end(), 0);
     nd_build(x, all, -1, 0, 0);
@@ -867,6 +866,8 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     if (opt.smoother_precision != 64 && opt.smoother_precision != 32 && opt.smoother_precision != 16)
         fail(HPLMM_E_ARG, "smoother_precision must be 64, 32 or 16");
     h.smoother_precision = opt.smoother_precision;
+    if (opt.coarse_leaf_dofs < 0) fail(HPLMM_E_ARG, "coarse_leaf_dofs must be >= 0");
+    h.coarse_leaf_dofs = opt.coarse_leaf_dofs > 0 ? opt.coarse_leaf_dofs : 192;
     h.n_nodes = n;
     h.N = 3 * n;
     h.nnzb = sys.row_ptr[n];

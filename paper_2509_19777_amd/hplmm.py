@@ -42,7 +42,7 @@ MORTAR_KINDS = {"gaussian": 0, "algebraic": 1}
 
 
 class HplmmOptions(C.Structure):
-    _fields_ = [("smoother_precision", i32)]
+    _fields_ = [("smoother_precision", i32), ("coarse_leaf_dofs", i32)]
 
 
 class HplmmSgStats(C.Structure):
@@ -244,11 +244,12 @@ def place_mortars(xyz, n):
     return out.tolist()
 
 
-def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64, mortar_kind="gaussian"):
+def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64, mortar_kind="gaussian",
+               coarse_leaf_dofs=0):
     """Host-only symbolic phase plus bounds check of every launch list."""
     s, p = system.c_struct(), part.c_struct()
     m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
-    o = HplmmOptions(int(smoother_precision))
+    o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs))
     out = np.zeros(16, dtype=np.int64)
     _check(lib().hplmm_plan_check(C.byref(s), C.byref(p), C.byref(m), C.byref(o), _ptr(out, i64)))
     keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
@@ -296,14 +297,14 @@ class Solver:
     """
 
     def __init__(self, system: System, part: Partition, n_mortar=2, beta=4.0, smoother_precision=64,
-                 mortar_kind="gaussian"):
+                 mortar_kind="gaussian", coarse_leaf_dofs=0):
         if not torch.cuda.is_available():
             raise RuntimeError("hplmm.Solver needs a GPU")
         self.system, self.part = system, part
         self._keep = (system.c_struct(), part.c_struct())
         h = C.c_void_p()
         m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
-        o = HplmmOptions(int(smoother_precision))
+        o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs))
         _check(lib().hplmm_plan(C.byref(self._keep[0]), C.byref(self._keep[1]), C.byref(m), C.byref(o), _stream(),
                                 C.byref(h)))
         self.h = h

@@ -150,3 +150,21 @@ def test_wider_contact_grids_parity(w_zeta):
     ro = gmres.gmres(A, b, H.apply, tol=1e-8, restart=50, flexible=True)
     x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
     assert info["status"] == "OK" and abs(info["iters"] - ro.iters) <= 1
+
+
+@pytest.mark.parametrize("leaf", [48, 1000])
+def test_coarse_leaf_size_parity(leaf):
+    # other nested-dissection leaf sizes give other front trees but the same
+    # coarse solve: M_G^-1 and M^-1 against the oracle
+    _torch()
+    from oracle import fem, hplmm as oh
+    from paper_2509_19777_amd import hplmm as hp
+    p = synth.config_pores(16, 4, seed=1)
+    A, b, mesh = fem.assemble(p)
+    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=4)
+    sysm, part = hp.build_problem(p)
+    S = hp.Solver(sysm, part, n_mortar=4, coarse_leaf_dofs=leaf)
+    S.setup()
+    r = synth.random_vector(A.shape[0], 17)
+    assert _rel(S.apply(_cu(r), 1).cpu().numpy(), H.apply_MG(r)) <= 1e-12
+    assert _rel(S.apply(_cu(r), 0).cpu().numpy(), H.apply(r)) <= 1e-12

@@ -165,3 +165,15 @@ def test_plan_check_algebraic_mortars(hp):
         s, q = sysm.c_struct(), part.c_struct()
         m = hp.HplmmMortar(4, 4.0, 7)
         hp._check(hp.lib().hplmm_plan_check(hp.C.byref(s), hp.C.byref(q), hp.C.byref(m), None, None))
+
+
+def test_coarse_leaf_option(hp):
+    p = synth.config_pores(16, 4, seed=1)
+    sysm, part = hp.build_problem(p)
+    small = hp.plan_check(sysm, part, n_mortar=4, coarse_leaf_dofs=48)
+    big = hp.plan_check(sysm, part, n_mortar=4, coarse_leaf_dofs=100000)
+    default = hp.plan_check(sysm, part, n_mortar=4)
+    assert small["coarse_levels"] >= default["coarse_levels"] >= big["coarse_levels"] == 1
+    assert small["n_coarse"] == big["n_coarse"] == default["n_coarse"]
+    with pytest.raises(hp.HplmmError):
+        hp.plan_check(sysm, part, n_mortar=4, coarse_leaf_dofs=-1)
