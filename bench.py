@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--mortar", type=int, default=4,
                     help="mortar nodes per interface (4 minimises set-up + solve time on this workload)")
     ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
+    ap.add_argument("--assembled", action="store_true",
+                    help="products with A from the assembled blocks (default: matrix-free from the voxel grid)")
     ap.add_argument("--autotune-reps", type=int, default=3,
                     help="launch-shape autotuning after the warm-up steps, untimed (0: default shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -72,6 +74,8 @@ def main():
     prob = make_problem(a, a.n)
     sysm, part = hp.build_problem(prob)
     S = hp.Solver(sysm, part, n_mortar=a.mortar, smoother_precision=a.precision)
+    if not a.assembled:
+        S.set_voxel_operator(prob)
     t_plan = time.perf_counter() - t0
     sizes = S.sizes()
     print(f"# plan done in {t_plan:.1f} s: {sizes}", file=sys.stderr, flush=True)
@@ -169,7 +173,8 @@ def main():
         "vs_baseline": None, "dtype": "f64" if a.precision == 64 else f"f64+{'f32' if a.precision == 32 else 'bf16'}-smoother",
         "data": "synthetic",
         "config": {"workload": workload_name(a),
-                   "dofs": 3 * sizes["n_nodes"], "subdomains": sizes["grain_mats"], "coarse_dofs": sizes["n_coarse"]},
+                   "dofs": 3 * sizes["n_nodes"], "subdomains": sizes["grain_mats"], "coarse_dofs": sizes["n_coarse"],
+                   "fine_operator": "assembled SELL-64" if a.assembled else "matrix-free Q1"},
         "iters": infos[-1]["iters"], "rel_res_true": infos[-1]["rel_res"],
         "setup_ms": {k: round(float(v), 3) for k, v in setup_ms.items()},
         "solve_ms": round(float(np.mean([i["t_solve_ms"] for i in infos])), 3),

@@ -272,6 +272,21 @@ hplmm_status hplmm_autotune(hplmm_handle *h, int32_t reps, void *stream);
  * restored.  Synchronises the device. */
 hplmm_status hplmm_set_tuning(hplmm_handle *h, const int32_t *rec, int64_t n);
 
+/* Matrix-free fine operator for problems assembled from a voxel grid (the
+ * grid, E and nu that hplmm_assemble_voxels was given): every later product
+ * with A (hplmm_spmv, the preconditioner's residuals, the solver) sums
+ * E_e Khat(nu) x over each free node's solid voxels instead of streaming the
+ * assembled 3x3 blocks (Eq. 4).  The set-up still uses the assembled matrix.
+ * solid[nx*ny*nz] (uint8) and E[nx*ny*nz] are host arrays (copied).  The
+ * call compares both operators on a seeded vector and fails with E_ARG,
+ * leaving the assembled operator in use, if they differ by more than 1e-12
+ * of max |A x| (a different grid, modulus or nu).  nx = ny = nz = 0 returns
+ * to the assembled operator.  Synchronises stream; each call that turns the
+ * operator on allocates its own device copies (held until hplmm_destroy);
+ * captured solver graphs are dropped. */
+hplmm_status hplmm_set_voxel_operator(hplmm_handle *h, int32_t nx, int32_t ny, int32_t nz,
+                                      const uint8_t *solid, const double *E, double nu, void *stream);
+
 /* HIP graphs for the solver (on by default): hplmm_solve captures each
  * Arnoldi step j of the restart cycle (M^-1 application, SpMV, the two
  * Gram-Schmidt passes, normalisation: kernel launches only) into a graph the

@@ -68,7 +68,10 @@ static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vec
 
 static void spmv(Handle &h, const double *x, const double *r, double *y, hipStream_t s) {
     ProfScope ps(h, PC_SPMV, h.spmv_bytes + (r ? 24.0 * h.n_nodes : 0.0), s);
-    launch_spmv(h.sell, x, r, y, s);
+    if (h.vop_on)
+        launch_spmv_voxel(h.vop, h.vop_xyz, h.vop_K, x, r, y, s);
+    else
+        launch_spmv(h.sell, x, r, y, s);
 }
 
 static void zero(void *p, int64_t bytes, hipStream_t s) {
@@ -962,6 +965,84 @@ extern "C" hplmm_status hplmm_set_tuning(hplmm_handle *hh, const int32_t *rec, i
             throw;
         }
         h.tune_log = log;
+        return HPLMM_OK;
+    });
+}
+
+// ---- matrix-free fine operator --------------------------------------------------
+extern "C" hplmm_status hplmm_set_voxel_operator(hplmm_handle *hh, int32_t nx, int32_t ny, int32_t nz,
+                                                 const uint8_t *solid, const double *E, double nu, void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh) fail(HPLMM_E_ARG, "NULL handle");
+        Handle &h = hh->h;
+        const hipStream_t s = (hipStream_t)stream;
+        hip_check(hipStreamSynchronize(s), "sync");
+        h.drop_graphs();   // captured steps hold the old operator
+        if (h.spmv_bytes_assembled < 0.0) {
+            h.spmv_bytes_assembled = h.spmv_bytes;
+            h.apply_bytes_assembled = h.apply_bytes;
+        }
+        if (nx == 0 && ny == 0 && nz == 0) {
+            h.vop_on = false;
+            h.spmv_bytes = h.spmv_bytes_assembled;
+            h.apply_bytes = h.apply_bytes_assembled;
+            return HPLMM_OK;
+        }
+        if (nx < 1 || ny < 1 || nz < 1) fail(HPLMM_E_ARG, "grid dimensions must be positive (all zero: assembled operator)");
+        const int64_t nvox = (int64_t)nx * ny * nz;
+        if (nvox > ((int64_t)1 << 31)) fail(HPLMM_E_ARG, "more than 2^31 voxels");
+        if (!solid || !E) fail(HPLMM_E_ARG, "NULL array");
+        if (!(nu > -1.0 && nu < 0.5)) fail(HPLMM_E_ARG, "nu must lie in (-1, 0.5)");
+        for (int64_t q = 0; q < nvox; ++q)
+            if (solid[q] && !(std::isfinite(E[q]) && E[q] >= 0.0)) fail(HPLMM_E_ARG, "E must be finite and >= 0 on solid voxels");
+        // lattice point -> free node, from the planned node coordinates
+        const int64_t NX = nx + 1, NY = ny + 1, NZ = nz + 1;
+        std::vector<int32_t> lat((size_t)(NX * NY * NZ), -1);
+        for (int64_t v = 0; v < h.n_nodes; ++v) {
+            const int32_t i = h.sg_xyz[(size_t)(3 * v)], j = h.sg_xyz[(size_t)(3 * v + 1)], k = h.sg_xyz[(size_t)(3 * v + 2)];
+            if (i < 0 || j < 0 || k < 0 || i > nx || j > ny || k > nz) fail(HPLMM_E_ARG, "a node lies outside the grid");
+            int32_t &slot = lat[(size_t)(i + NX * (j + NY * (int64_t)k))];
+            if (slot >= 0) fail(HPLMM_E_ARG, "two nodes share a lattice point");
+            slot = (int32_t)v;
+        }
+        double K[24][24];
+        q1_element_stiffness(nu, K);
+        const std::vector<uint8_t> vs(solid, solid + nvox);
+        const std::vector<double> ve(E, E + nvox), vk(&K[0][0], &K[0][0] + 24 * 24);
+        VoxelGrid g{nx, ny, nz, h.upload(vs, s), h.upload(ve, s), nu, h.upload(lat, s), h.n_nodes};
+        const int32_t *xyz = h.upload(h.sg_xyz, s);
+        const double *Kd = h.upload(vk, s);
+        // the two operators on one seeded vector must agree to rounding
+        const int64_t N = h.N;
+        std::vector<double> xr((size_t)N), y1((size_t)N), y2((size_t)N);
+        uint64_t st = 0x9e3779b97f4a7c15ull;
+        for (auto &v : xr) {
+            st = st * 6364136223846793005ull + 1442695040888963407ull;
+            v = (double)(st >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+        }
+        double *dx = h.upload(xr, s), *dy1 = h.dalloc<double>(N), *dy2 = h.dalloc<double>(N);
+        launch_spmv(h.sell, dx, nullptr, dy1, s);
+        launch_spmv_voxel(g, xyz, Kd, dx, nullptr, dy2, s);
+        hip_check(hipGetLastError(), "kernel launch");
+        hip_check(hipMemcpyAsync(y1.data(), dy1, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, s), "copy");
+        hip_check(hipMemcpyAsync(y2.data(), dy2, sizeof(double) * (size_t)N, hipMemcpyDeviceToHost, s), "copy");
+        hip_check(hipStreamSynchronize(s), "sync");
+        double mx = 0.0, md = 0.0;
+        for (int64_t q = 0; q < N; ++q) {
+            mx = std::max(mx, std::fabs(y1[(size_t)q]));
+            md = std::max(md, std::fabs(y1[(size_t)q] - y2[(size_t)q]));
+        }
+        if (!(md <= 1e-12 * mx))
+            fail(HPLMM_E_ARG, "the voxel operator differs from the assembled matrix (max |difference| " +
+                                  std::to_string(md) + " against max |A x| " + std::to_string(mx) + ")");
+        h.vop = g;
+        h.vop_xyz = xyz;
+        h.vop_K = Kd;
+        h.vop_on = true;
+        // algorithmic bytes: x read and y written per node, the voxel grid and the lattice map
+        const double mf = (double)h.n_nodes * 48.0 + (double)nvox * 9.0 + (double)lat.size() * 4.0;
+        h.spmv_bytes = mf;
+        h.apply_bytes = h.apply_bytes_assembled - 2.0 * h.spmv_bytes_assembled + 2.0 * mf;
         return HPLMM_OK;
     });
 }

@@ -8,6 +8,7 @@
 #include "common.h"
 #include "dense.h"
 #include "sparse.h"
+#include "post.h"
 #include "surrogate.h"
 
 namespace hplmm {
@@ -285,6 +286,13 @@ struct Handle {
     double t_setup_ms[4] = {0, 0, 0, 0};
     Profiler prof;
     double apply_bytes = 0.0, spmv_bytes = 0.0;
+    // matrix-free fine operator (hplmm_set_voxel_operator): used by every SpMV
+    // when on; the assembled figures are kept to switch back
+    bool vop_on = false;
+    VoxelGrid vop{};
+    const int32_t *vop_xyz = nullptr;
+    const double *vop_K = nullptr;
+    double spmv_bytes_assembled = -1.0, apply_bytes_assembled = -1.0;
 
     template <class T>
     T *dalloc(int64_t n) {

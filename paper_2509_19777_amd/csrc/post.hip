@@ -1,8 +1,11 @@
-// Stress recovery at voxel centroids (Hooke's law, Eqs. 1 and 3) and the
-// maximum shear stress (the Mohr-circle radius used by the error metric of
-// Eq. 28).  One thread per voxel: the eight corner displacements give the
-// displacement gradient at the centroid of the unit Q1 cube, where every
-// shape-function derivative is +-1/4.
+// Kernels on a problem's voxel grid.
+// * Stress recovery at voxel centroids (Hooke's law, Eqs. 1 and 3) and the
+//   maximum shear stress (the Mohr-circle radius used by the error metric of
+//   Eq. 28), one thread per voxel: the eight corner displacements give the
+//   displacement gradient at the centroid of the unit Q1 cube, where every
+//   shape-function derivative is +-1/4.
+// * The matrix-free Q1 operator (Eq. 4 without the assembled blocks), one
+//   thread per free node.
 #include "post.h"
 
 namespace hplmm {
@@ -76,7 +79,63 @@ __global__ void __launch_bounds__(256) voxel_fields_kernel(VoxelGrid g, const do
         for (int c = 0; c < 3; ++c) uc[3 * v + c] = 0.125 * us[c];
 }
 
+// One thread per free node: for each of its (up to) eight solid voxels, the
+// node's three rows of E_e Khat times the element's corner displacements
+// (clamped or unused corners are zero).  Khat is staged in LDS.
+__global__ void __launch_bounds__(256) spmv_voxel_kernel(VoxelGrid g, const int32_t *__restrict__ xyz,
+                                                         const double *__restrict__ Khat,
+                                                         const double *__restrict__ x,
+                                                         const double *__restrict__ r, double *__restrict__ y) {
+    __shared__ double K[24 * 24];
+    for (int e = threadIdx.x; e < 24 * 24; e += blockDim.x) K[e] = Khat[e];
+    __syncthreads();
+    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (v >= g.n_nodes) return;
+    const int32_t i = xyz[3 * v], j = xyz[3 * v + 1], k = xyz[3 * v + 2];
+    const int64_t NX = g.nx + 1, NY = g.ny + 1;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int e = 0; e < 8; ++e) {
+        // voxel (i - cx, j - cy, k - cz) has this node at its corner (cx, cy, cz)
+        const int cx = e & 1, cy = (e >> 1) & 1, cz = (e >> 2) & 1;
+        const int32_t ex = i - cx, ey = j - cy, ez = k - cz;
+        if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx || ey >= g.ny || ez >= g.nz) continue;
+        const int64_t vox = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
+        if (!g.solid[vox]) continue;
+        const double *Kr = K + 3 * e * 24;   // the node's rows: local index e = cx + 2 cy + 4 cz
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const int32_t w = g.lat2node[(ex + (b & 1)) + NX * ((ey + ((b >> 1) & 1)) + NY * (int64_t)(ez + ((b >> 2) & 1)))];
+            if (w < 0 || w >= g.n_nodes) continue;
+            const double x0 = x[3 * (int64_t)w], x1 = x[3 * (int64_t)w + 1], x2 = x[3 * (int64_t)w + 2];
+            s0 += Kr[3 * b] * x0 + Kr[3 * b + 1] * x1 + Kr[3 * b + 2] * x2;
+            s1 += Kr[24 + 3 * b] * x0 + Kr[24 + 3 * b + 1] * x1 + Kr[24 + 3 * b + 2] * x2;
+            s2 += Kr[48 + 3 * b] * x0 + Kr[48 + 3 * b + 1] * x1 + Kr[48 + 3 * b + 2] * x2;
+        }
+        const double E = g.E[vox];
+        a0 += E * s0;
+        a1 += E * s1;
+        a2 += E * s2;
+    }
+    if (r) {
+        y[3 * v] = r[3 * v] - a0;
+        y[3 * v + 1] = r[3 * v + 1] - a1;
+        y[3 * v + 2] = r[3 * v + 2] - a2;
+    } else {
+        y[3 * v] = a0;
+        y[3 * v + 1] = a1;
+        y[3 * v + 2] = a2;
+    }
+}
+
 }  // namespace
+
+void launch_spmv_voxel(const VoxelGrid &g, const int32_t *xyz, const double *Khat, const double *x, const double *r,
+                       double *y, hipStream_t s) {
+    if (g.n_nodes <= 0) return;
+    hipLaunchKernelGGL(spmv_voxel_kernel, dim3((unsigned)((g.n_nodes + 255) / 256)), dim3(256), 0, s, g, xyz, Khat, x,
+                       r, y);
+}
 
 void launch_voxel_fields(const VoxelGrid &g, const double *x, double *sigma_t, double *uc, hipStream_t s) {
     const int64_t nvox = (int64_t)g.nx * g.ny * g.nz;

@@ -74,6 +74,7 @@ EXPORTS = {
     "hplmm_destroy": (None, [C.c_void_p]),
     "hplmm_profile": (i32, [C.c_void_p, i32]),
     "hplmm_use_graphs": (i32, [C.c_void_p, i32]),
+    "hplmm_set_voxel_operator": (i32, [C.c_void_p, i32, i32, i32, P(u8), P(f64), f64, C.c_void_p]),
     "hplmm_debug_mortar_blocks": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, P(f64), i64, P(i64)]),
     "hplmm_autotune": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_set_tuning": (i32, [C.c_void_p, C.c_void_p, i64]),
@@ -320,6 +321,18 @@ class Solver:
 
     def setup(self):
         _check(lib().hplmm_setup(self.h, _stream()))
+
+    def set_voxel_operator(self, problem=None):
+        """Matrix-free products with A from the problem's voxel grid (checked
+        against the assembled matrix); None returns to the assembled operator."""
+        if problem is None:
+            _check(lib().hplmm_set_voxel_operator(self.h, 0, 0, 0, None, None, 0.3, _stream()))
+            return
+        nz, ny, nx = problem.solid.shape
+        solid = np.ascontiguousarray(problem.solid, dtype=np.uint8).ravel()
+        E = np.ascontiguousarray(problem.E, dtype=np.float64).ravel()
+        _check(lib().hplmm_set_voxel_operator(self.h, nx, ny, nz, _ptr(solid, u8), _ptr(E, f64), float(problem.nu),
+                                              _stream()))
 
     def use_graphs(self, on=True):
         """Replay the Arnoldi steps of the solver as HIP graphs (default on)."""
