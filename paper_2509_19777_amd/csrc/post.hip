@@ -79,9 +79,12 @@ __global__ void __launch_bounds__(256) voxel_fields_kernel(VoxelGrid g, const do
         for (int c = 0; c < 3; ++c) uc[3 * v + c] = 0.125 * us[c];
 }
 
-// One thread per free node: for each of its (up to) eight solid voxels, the
-// node's three rows of E_e Khat times the element's corner displacements
-// (clamped or unused corners are zero).  Khat is staged in LDS.
+// One thread per free node.  The moduli of its eight surrounding voxels are
+// read once (zero for void or outside voxels); then for each of the 27
+// neighbouring lattice nodes w the displacement x_w is read once and
+// multiplied by the sum over the voxels holding both nodes of E_e times the
+// 3x3 block of Khat that couples their corners.  Khat is staged in LDS; the
+// loops are unrolled so every corner index is a constant.
 __global__ void __launch_bounds__(256) spmv_voxel_kernel(VoxelGrid g, const int32_t *__restrict__ xyz,
                                                          const double *__restrict__ Khat,
                                                          const double *__restrict__ x,
@@ -93,29 +96,38 @@ __global__ void __launch_bounds__(256) spmv_voxel_kernel(VoxelGrid g, const int3
     if (v >= g.n_nodes) return;
     const int32_t i = xyz[3 * v], j = xyz[3 * v + 1], k = xyz[3 * v + 2];
     const int64_t NX = g.nx + 1, NY = g.ny + 1;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-    for (int e = 0; e < 8; ++e) {
-        // voxel (i - cx, j - cy, k - cz) has this node at its corner (cx, cy, cz)
-        const int cx = e & 1, cy = (e >> 1) & 1, cz = (e >> 2) & 1;
-        const int32_t ex = i - cx, ey = j - cy, ez = k - cz;
-        if (ex < 0 || ey < 0 || ez < 0 || ex >= g.nx || ey >= g.ny || ez >= g.nz) continue;
-        const int64_t vox = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
-        if (!g.solid[vox]) continue;
-        const double *Kr = K + 3 * e * 24;   // the node's rows: local index e = cx + 2 cy + 4 cz
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    double Ee[8];   // voxel (i - cx, j - cy, k - cz) holds this node at its corner e = cx + 2 cy + 4 cz
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const int32_t w = g.lat2node[(ex + (b & 1)) + NX * ((ey + ((b >> 1) & 1)) + NY * (int64_t)(ez + ((b >> 2) & 1)))];
-            if (w < 0 || w >= g.n_nodes) continue;
-            const double x0 = x[3 * (int64_t)w], x1 = x[3 * (int64_t)w + 1], x2 = x[3 * (int64_t)w + 2];
-            s0 += Kr[3 * b] * x0 + Kr[3 * b + 1] * x1 + Kr[3 * b + 2] * x2;
-            s1 += Kr[24 + 3 * b] * x0 + Kr[24 + 3 * b + 1] * x1 + Kr[24 + 3 * b + 2] * x2;
-            s2 += Kr[48 + 3 * b] * x0 + Kr[48 + 3 * b + 1] * x1 + Kr[48 + 3 * b + 2] * x2;
+    for (int e = 0; e < 8; ++e) {
+        const int32_t ex = i - (e & 1), ey = j - ((e >> 1) & 1), ez = k - ((e >> 2) & 1);
+        double val = 0.0;
+        if (ex >= 0 && ey >= 0 && ez >= 0 && ex < g.nx && ey < g.ny && ez < g.nz) {
+            const int64_t vox = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
+            if (g.solid[vox]) val = g.E[vox];
         }
-        const double E = g.E[vox];
-        a0 += E * s0;
-        a1 += E * s1;
-        a2 += E * s2;
+        Ee[e] = val;
+    }
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int o = 0; o < 27; ++o) {
+        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
+        const int32_t wi = i + ox, wj = j + oy, wk = k + oz;
+        if (wi < 0 || wj < 0 || wk < 0 || wi > g.nx || wj > g.ny || wk > g.nz) continue;
+        const int32_t w = g.lat2node[wi + NX * (wj + NY * (int64_t)wk)];
+        if (w < 0 || w >= g.n_nodes) continue;
+        const double x0 = x[3 * (int64_t)w], x1 = x[3 * (int64_t)w + 1], x2 = x[3 * (int64_t)w + 2];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int cx = e & 1, cy = (e >> 1) & 1, cz = (e >> 2) & 1;
+            const int bx = cx + ox, by = cy + oy, bz = cz + oz;
+            if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
+            const int b = bx + 2 * by + 4 * bz;
+            const double *Kr = K + 3 * e * 24 + 3 * b;
+            const double E = Ee[e];
+            a0 += E * (Kr[0] * x0 + Kr[1] * x1 + Kr[2] * x2);
+            a1 += E * (Kr[24] * x0 + Kr[25] * x1 + Kr[26] * x2);
+            a2 += E * (Kr[48] * x0 + Kr[49] * x1 + Kr[50] * x2);
+        }
     }
     if (r) {
         y[3 * v] = r[3 * v] - a0;
