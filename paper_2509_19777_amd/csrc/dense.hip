@@ -3,9 +3,10 @@
 // All batched dense linear algebra of the set-up (Cholesky, triangular
 // inversion, basis products, Galerkin products) is expressed as lists of
 // 64x64 tile tasks built on the host; one launch processes one list.  The
-// contraction kernel stages operand tiles through LDS and multiplies them on
-// the matrix cores (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32), four
-// wavefronts per 64x64 output tile, each owning a 32x32 quadrant.
+// contraction kernel stages operand tiles through LDS in 32-deep halves and
+// multiplies them on the matrix cores (v_mfma_f64_16x16x4f64 /
+// v_mfma_f32_16x16x4f32), four wavefronts per 64x64 output tile, each owning
+// a 32x32 quadrant.
 #include <hip/hip_runtime.h>
 
 #include "dense.h"
@@ -37,54 +38,62 @@ struct Mfma<float> {
 };
 
 constexpr int LD = TS + 1;  // padded LDS row length (elements)
+constexpr int KH = TS / 2;  // contraction depth of one staged half
 
-// One 64x64 tile held across the 256 threads of a work-group: thread t keeps
-// stored elements t, t + 256, ... (coalesced global loads).
+// One 64x64 operand tile held across the 256 threads of a work-group, 16
+// stored elements per thread, fetched so that elements 0-7 of every thread
+// hold contraction indices k < 32 and elements 8-15 hold k >= 32.  The
+// contraction then stages one 32-deep half at a time: 33 KB of LDS per
+// work-group instead of 66 KB, so three work-groups (the register limit)
+// share a CU instead of two.  With k along the stored columns (kr = false)
+// element q of thread t is stored element t + 256 q; with k along the stored
+// rows (kr = true) it is row (t & 31) + 32 (q >> 3), column (t >> 5) +
+// 8 (q & 7).  Both orders read whole 256-byte runs.
 template <class T>
 struct TileRegs {
     T v[TE / 256];
 };
 
-template <class T>
-__device__ __forceinline__ void fetch_tile(TileRegs<T> &r, const T *__restrict__ src) {
+// Where thread t's elements of one operand live: a per-thread base plus an
+// offset that depends only on q and kr (uniform over the work-group), both in
+// the stored tile (g) and in the LDS half (l).
+struct OpMap {
+    int g, l;
+    bool kr;
+    __device__ __forceinline__ OpMap(bool kr_, int t)
+        : g(kr_ ? (t & 31) + TS * (t >> 5) : t), l(kr_ ? (t & 31) * LD + (t >> 5) : (t >> 6) * LD + (t & 63)),
+          kr(kr_) {}
+    __device__ __forceinline__ int goff(int q) const { return kr ? 32 * (q >> 3) + 8 * TS * (q & 7) : 256 * q; }
+    // offset in half H (q in [8 H, 8 H + 8)) of the element's slot S[k - 32 H][j]
+    template <int H>
+    __device__ __forceinline__ int loff(int q) const { return kr ? 8 * (q & 7) : (4 * q - KH * H) * LD; }
+};
+
+template <int H, class T>
+__device__ __forceinline__ void fetch_half(TileRegs<T> &r, const T *__restrict__ src, const OpMap &om) {
+    const T *s = src + om.g;
 #pragma unroll
-    for (int q = 0; q < TE / 256; ++q) r.v[q] = src[threadIdx.x + 256 * q];
+    for (int q = 8 * H; q < 8 * H + 8; ++q) r.v[q] = s[om.goff(q)];
 }
 
-// Stage into LDS as S[k][m] = op(tile)[m][k]  (A operand).
-template <class T>
-__device__ __forceinline__ void stage_A(T *S, const TileRegs<T> &r, bool trans) {
+// Stage half H into LDS as S[k - 32 H][j], j the operand's other index (m for
+// the A operand, n for B).  Operand A enters as op(A)[m][k] and B as
+// op(B)[k][n], so kr is TRANS_A for A and !TRANS_B for B.  (Element q of
+// thread t has k = row (t & 31) + 32 (q >> 3) and j = column (t >> 5) +
+// 8 (q & 7) when kr, k = column (t >> 6) + 4 q and j = row t & 63 otherwise.)
+template <int H, class T>
+__device__ __forceinline__ void stage_half(T *S, const TileRegs<T> &r, const OpMap &om) {
+    T *d = S + om.l;
 #pragma unroll
-    for (int q = 0; q < TE / 256; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        const int rr = e & (TS - 1), c = e >> 6;   // stored element (row rr, col c)
-        if (!trans)
-            S[c * LD + rr] = r.v[q];
-        else
-            S[rr * LD + c] = r.v[q];
-    }
-}
-
-// Stage into LDS as S[k][n] = op(tile)[k][n]  (B operand).
-template <class T>
-__device__ __forceinline__ void stage_B(T *S, const TileRegs<T> &r, bool trans) {
-#pragma unroll
-    for (int q = 0; q < TE / 256; ++q) {
-        const int e = threadIdx.x + 256 * q;
-        const int rr = e & (TS - 1), c = e >> 6;
-        if (!trans)
-            S[rr * LD + c] = r.v[q];
-        else
-            S[c * LD + rr] = r.v[q];
-    }
+    for (int q = 8 * H; q < 8 * H + 8; ++q) d[om.template loff<H>(q)] = r.v[q];
 }
 
 template <class T>
-__device__ __forceinline__ void mfma_tile(const T *As, const T *Bs, typename Mfma<T>::acc_t acc[2][2],
-                                          int lane, int wm, int wn) {
+__device__ __forceinline__ void mfma_half(const T *As, const T *Bs, typename Mfma<T>::acc_t acc[2][2], int lane,
+                                          int wm, int wn) {
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll 4
-    for (int kk = 0; kk < TS; kk += 4) {
+    for (int kk = 0; kk < KH; kk += 4) {
         const int k = kk + lk;
         const T a0 = As[k * LD + wm + lr];
         const T a1 = As[k * LD + wm + 16 + lr];
@@ -97,15 +106,48 @@ __device__ __forceinline__ void mfma_tile(const T *As, const T *Bs, typename Mfm
     }
 }
 
-// Tile contraction task.  The operands of pair p+1 are fetched into registers
-// while the matrix cores work on pair p from LDS.
+// Second product of a GF_POST / GF_POST_RIGHT task, half H: the accumulated
+// sum leaves the registers 32 contraction indices at a time.  For C = alpha
+// P S the sum is the B operand (k = its row m), held by the waves of one row
+// of the 2x2 wave grid; for C = ([C +] alpha S) P the bracket is the A
+// operand (k = its column n), held by the waves of one column.
+template <int H, class T>
+__device__ __forceinline__ void post_half(T *As, T *Bs, const T *C, const TileRegs<T> &rp,
+                                          typename Mfma<T>::acc_t acc[2][2], typename Mfma<T>::acc_t res[2][2],
+                                          bool left, bool acc_c, T alpha, int lane, int wm, int wn) {
+    const int lr = lane & 15, lq = lane >> 4;
+    __syncthreads();
+    if ((left ? wm : wn) == KH * H) {
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j)
+                for (int r = 0; r < 4; ++r) {
+                    const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
+                    T v = alpha * acc[i][j][r];
+                    if (left) {
+                        Bs[(m - KH * H) * LD + n] = v;
+                    } else {
+                        if (acc_c) v += C[n * TS + m];
+                        As[(n - KH * H) * LD + m] = v;
+                    }
+                }
+    }
+    stage_half<H>(left ? As : Bs, rp, OpMap(!left, threadIdx.x));
+    __syncthreads();
+    mfma_half<T>(As, Bs, res, lane, wm, wn);
+}
+
+// Tile contraction task.  Each pair is contracted in two 32-deep halves; the
+// registers of a half are refilled with the next pair's operands as soon as
+// that half is in LDS, so the fetch overlaps the matrix-core work.
 template <class T>
 __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
                                                         const GemmTask *__restrict__ tasks,
                                                         const GemmPair *__restrict__ pairs, T *part,
                                                         int32_t *cnt) {
-    __shared__ T As[TS * LD];
-    __shared__ T Bs[TS * LD];
+    // the two operand halves; together they hold one padded 64x64 tile for
+    // the output staging
+    __shared__ T S[2 * KH * LD];
+    T *As = S, *Bs = S + KH * LD;
     __shared__ int32_t last;
     const GemmTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -113,24 +155,36 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     typename Mfma<T>::acc_t acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
+    const OpMap ka(tk.flags & GF_TRANS_A, threadIdx.x), kb(!(tk.flags & GF_TRANS_B), threadIdx.x);
     TileRegs<T> ra, rb;
     if (tk.pair_count > 0) {
         const GemmPair pr = pairs[tk.pair_start];
-        fetch_tile(ra, arena + pr.a_off);
-        fetch_tile(rb, arena + pr.b_off);
+        fetch_half<0>(ra, arena + pr.a_off, ka);
+        fetch_half<0>(rb, arena + pr.b_off, kb);
+        fetch_half<1>(ra, arena + pr.a_off, ka);
+        fetch_half<1>(rb, arena + pr.b_off, kb);
     }
     for (int p = 0; p < tk.pair_count; ++p) {
+        const bool more = p + 1 < tk.pair_count;
+        const GemmPair nx = pairs[tk.pair_start + (more ? p + 1 : p)];
         __syncthreads();
-        stage_A(As, ra, ta);
-        stage_B(Bs, rb, tb);
+        stage_half<0>(As, ra, ka);
+        stage_half<0>(Bs, rb, kb);
         __syncthreads();
-        if (p + 1 < tk.pair_count) {
-            const GemmPair pr = pairs[tk.pair_start + p + 1];
-            fetch_tile(ra, arena + pr.a_off);
-            fetch_tile(rb, arena + pr.b_off);
+        if (more) {
+            fetch_half<0>(ra, arena + nx.a_off, ka);
+            fetch_half<0>(rb, arena + nx.b_off, kb);
         }
-        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+        mfma_half<T>(As, Bs, acc, lane, wm, wn);
+        __syncthreads();
+        stage_half<1>(As, ra, ka);
+        stage_half<1>(Bs, rb, kb);
+        __syncthreads();
+        if (more) {
+            fetch_half<1>(ra, arena + nx.a_off, ka);
+            fetch_half<1>(rb, arena + nx.b_off, kb);
+        }
+        mfma_half<T>(As, Bs, acc, lane, wm, wn);
     }
     if (tk.nchunk > 1) {
         // partial sums in accumulator order, reduced by the last arrival
@@ -158,45 +212,30 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
     T *C = arena + tk.c_off;
     const bool post = tk.flags & (GF_POST | GF_POST_RIGHT);
-    if (tk.flags & GF_POST) {
-        // C = alpha P S with S the accumulated sum: S becomes the B operand.
-        __syncthreads();
+    if (post) {
+        // GF_POST: C = alpha P S, P the A operand (k along its columns);
+        // GF_POST_RIGHT: C = ([C +] alpha S) P, P the B operand (k along its rows)
+        const bool left = tk.flags & GF_POST;
+        const bool acc_c = !left && (tk.flags & GF_ACCUM);
+        TileRegs<T> rp;
+        const OpMap kp(!left, threadIdx.x);
+        fetch_half<0>(rp, arena + tk.post_off, kp);
+        fetch_half<1>(rp, arena + tk.post_off, kp);
+        typename Mfma<T>::acc_t res[2][2];
         for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                for (int r = 0; r < 4; ++r) {
-                    const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
-                    Bs[m * LD + n] = alpha * acc[i][j][r];
-                    acc[i][j][r] = 0;
-                }
-        fetch_tile(ra, arena + tk.post_off);
-        stage_A(As, ra, false);
-        __syncthreads();
-        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
-    } else if (tk.flags & GF_POST_RIGHT) {
-        // C = ([C +] alpha S) P: the bracket becomes the A operand.
-        const bool acc_c = tk.flags & GF_ACCUM;
-        __syncthreads();
+            for (int j = 0; j < 2; ++j) res[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        post_half<0, T>(As, Bs, C, rp, acc, res, left, acc_c, alpha, lane, wm, wn);
+        post_half<1, T>(As, Bs, C, rp, acc, res, left, acc_c, alpha, lane, wm, wn);
         for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                for (int r = 0; r < 4; ++r) {
-                    const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
-                    T v = alpha * acc[i][j][r];
-                    if (acc_c) v += C[n * TS + m];
-                    As[n * LD + m] = v;
-                    acc[i][j][r] = 0;
-                }
-        fetch_tile(rb, arena + tk.post_off);
-        stage_B(Bs, rb, false);
-        __syncthreads();
-        mfma_tile<T>(As, Bs, acc, lane, wm, wn);
+            for (int j = 0; j < 2; ++j) acc[i][j] = res[i][j];
     }
-    // stage the result column-major in LDS, then store coalesced
+    // stage the result column-major in LDS (both halves), then store coalesced
     __syncthreads();
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int r = 0; r < 4; ++r) {
                 const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
-                As[n * LD + m] = acc[i][j][r];
+                S[n * LD + m] = acc[i][j][r];
             }
     __syncthreads();
     const T a2 = post ? T(1) : alpha;
@@ -206,7 +245,7 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     for (int q = 0; q < TE / 256; ++q) {
         const int e = t + 256 * q;
         const int m = e & (TS - 1), n = e >> 6;
-        const T v = a2 * As[n * LD + m];
+        const T v = a2 * S[n * LD + m];
         C[e] = accum ? C[e] + v : v;
     }
 }
