@@ -142,10 +142,28 @@ typedef struct hplmm_mortar {
  * coarse_leaf_dofs: the nested dissection of the coarse operator stops at
  * subsets of at most this many dofs (0 = the default, 192); larger leaves
  * give fewer front levels (fewer launches per coarse solve) and larger dense
- * leaf fronts. */
+ * leaf fronts.
+ * smoother_form: how the smoother applies the local inverses A_g^-1 and
+ * A_zeta^-1 of Eqs. 25-26 (the same operator either way, up to rounding):
+ *   HPLMM_SMOOTHER_FACTORS  y = W^T (W x) with W = L^-1: two passes, each over
+ *                           the lower tiles of the block;
+ *   HPLMM_SMOOTHER_INVERSE  y = S x with S = W^T W formed in the set-up (one
+ *                           more batched tile product and one more arena
+ *                           region per set): one pass over the lower tiles of
+ *                           S, each off-diagonal tile serving S_ij x_j and
+ *                           S_ij^T x_i, then a short sum of the transposed
+ *                           products per tile row.  Half the smoother's HBM
+ *                           reads.  float64 smoother only (HPLMM_E_ARG
+ *                           otherwise);
+ *   HPLMM_SMOOTHER_AUTO (0) the inverse form at smoother_precision 64, the
+ *                           factor form otherwise. */
+#define HPLMM_SMOOTHER_AUTO     0
+#define HPLMM_SMOOTHER_FACTORS  1
+#define HPLMM_SMOOTHER_INVERSE  2
 typedef struct hplmm_options {
     int32_t smoother_precision;
     int32_t coarse_leaf_dofs;
+    int32_t smoother_form;
 } hplmm_options;
 
 /* Place the mortar nodes of one interface (Sec. 3.3, Eq. 7): xyz[3*N] lattice
@@ -234,7 +252,9 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *   5 setup phase times in ms: double[4] = {grains, contacts, coarse, total};
  *            the contact grids are set up on an internal stream beside the
  *            grains and the coarse operator, so total (the wall time of the
- *            set-up) is less than the sum
+ *            set-up) is less than the sum; in the inverse smoother form the
+ *            grain inverse S = W^T W follows the contact grids on that stream
+ *            and is counted in none of the first three
  *   6 device bytes held: int64[1]
  *   7 profiler totals (see hplmm_profile)
  *   8 algorithmic bytes: double[2] = {one application of M^-1, one SpMV}
@@ -243,7 +263,11 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *            work-groups, backward bytes} (with the current launch shapes)
  *  10 tuning records: double[7 * k], one per tuned launch {kind, index,
  *            variant, target work-groups, waves, default us, chosen us}
- *            (see hplmm_autotune; empty with the default shapes)
+ *            (see hplmm_autotune; empty with the default shapes); the
+ *            smoother launches are listed as grain W, grain W^T, contact W,
+ *            contact W^T, X^T, X in the factor form and grain S, contact S,
+ *            X^T, X in the inverse form
+ *  11 smoother form in use: int32[1] (HPLMM_SMOOTHER_FACTORS or _INVERSE)
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);
@@ -301,8 +325,9 @@ hplmm_status hplmm_use_graphs(hplmm_handle *h, int32_t on);
  * recorded on the launch stream around every launch of kernel class c:
  *   0 set-up tile contractions, 1 diagonal-tile factorisations, 2 smoother
  *   GEMVs, 3 coarse-solve GEMVs, 4 restriction/prolongation GEMVs, 5 fine
- *   SpMV, 6 whole applications of M^-1.
- * Query 7 returns double[3*7] = per class {launches, total ms, total
+ *   SpMV, 6 whole applications of M^-1, 7 sums of the transposed products
+ *   of the symmetric smoother (inverse form).
+ * Query 7 returns double[3*8] = per class {launches, total ms, total
  * algorithmic units} (flops for class 0, tiles for 1, bytes otherwise) over
  * all launches since the last hplmm_profile call, which clears them.  mask = 0 turns the
  * profiler off (no events are recorded). */

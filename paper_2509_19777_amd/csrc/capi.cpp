@@ -92,6 +92,7 @@ static void contact_setup(Handle &h, hipStream_t s) {
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
         run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+        run_program<double>(h, h.tl64, h.ar64, h.cset.inverse_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
     } else {
         zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
@@ -111,14 +112,14 @@ static void contact_setup(Handle &h, hipStream_t s) {
 // split-task scratch).
 static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup *sg = nullptr) {
     struct Events {
-        hipEvent_t e[4] = {nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
         ~Events() {
             for (hipEvent_t x : e)
                 if (x) (void)hipEventDestroy(x);
         }
     } evs;
     hipEvent_t *ev = evs.e;
-    for (int i = 0; i < 4; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
+    for (int i = 0; i < 5; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
     const int32_t init_flag[2] = {0, 0x7fffffff};
     hip_check(hipMemcpyAsync(h.d_flag, init_flag, sizeof(init_flag), hipMemcpyHostToDevice, s), "flag init");
     hip_check(hipEventRecord(ev[0], s), "event");
@@ -149,6 +150,17 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         return;
     }
     run_program<double>(h, h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
+    if (fork) {
+        // the grain inverse S = W^T W follows the contact grids on the side
+        // stream, beside the basis and the coarse operator on s
+        if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+            hip_check(hipEventRecord(ev[4], s), "event");
+            hip_check(hipStreamWaitEvent(h.side, ev[4], 0), "wait");
+            run_program<double>(h, h.tl64, h.ar64, h.gset.inverse_prog, h.d_flag, h.side, h.d_part_side,
+                                h.d_cnt_side);
+        }
+        hip_check(hipEventRecord(h.side_ev[2], h.side), "event");
+    }
     if (stage < 2) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -188,7 +200,7 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         }
     }
     hip_check(hipEventRecord(ev[2], s), "event");
-    hip_check(hipStreamWaitEvent(s, h.side_ev[1], 0), "join");
+    hip_check(hipStreamWaitEvent(s, h.side_ev[2], 0), "join");
     hip_check(hipEventRecord(ev[3], s), "event");
     hip_check(hipGetLastError(), "kernel launch");
     int32_t flag[2];
@@ -432,7 +444,9 @@ static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
 
 static void launch_set(Handle &h, const Range &r, bool smoother_low, const double *x, double *y, hipStream_t s) {
     const GemvTask *t = h.d_vtasks + r.start;
-    if (!smoother_low || h.smoother_precision == 64)
+    if (r.sym)
+        launch_sym_gemv(h.ar64, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
+    else if (!smoother_low || h.smoother_precision == 64)
         launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
     else if (h.smoother_precision == 32)
         launch_gemv<float>(h.ar32, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
@@ -476,19 +490,33 @@ static void coarse_solve(Handle &h, const double *f, double *u, hipStream_t s) {
     launch_copy_idx(mf.d_out_dst, mf.d_out_src, (int64_t)mf.out_dst.size(), mf.XV, u, s);
 }
 
-// Contact-grid smoother (reduced precision applies to the stored operators).
+// y = A^-1 x for every matrix of a dense set: y = W^T (W x) (factor form,
+// reduced precision applies to the stored operators) or y = S x, with the
+// transposed products of the tiles below the diagonal summed into y after the
+// pass (inverse form).
+static void set_solve(Handle &h, DenseSet &ds, const double *x, double *t, double *y, hipStream_t s) {
+    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        gemv_set(h, ds.gemv_S, false, x, y, s);
+        if (ds.red_S.count) {
+            ProfScope ps(h, PC_SMOOTH_REDUCE, ds.red_S.bytes, s);
+            launch_sym_reduce(h.d_rtasks + ds.red_S.start, ds.red_S.count, h.d_sym_part, y, s);
+        }
+        return;
+    }
+    const bool low = h.smoother_precision != 64;
+    gemv_set(h, ds.gemv_W, low, x, t, s);
+    gemv_set(h, ds.gemv_Wt, low, t, y, s);
+}
+
+// Contact-grid smoother (Eq. 26).
 static void contact_solve(Handle &h, const double *rr, hipStream_t s) {
     launch_gather(h.d_c_slot_dof, rr, h.cx, h.cset.vec_len, s);
-    const bool low = h.smoother_precision != 64;
-    gemv_set(h, h.cset.gemv_W, low, h.cx, h.ct, s);
-    gemv_set(h, h.cset.gemv_Wt, low, h.ct, h.cy, s);
+    set_solve(h, h.cset, h.cx, h.ct, h.cy, s);
 }
 
 static void grain_solve(Handle &h, const double *rr, hipStream_t s) {
     launch_gather(h.d_g_slot_dof, rr, h.gx, h.gset.vec_len, s);
-    const bool low = h.smoother_precision != 64;
-    gemv_set(h, h.gset.gemv_W, low, h.gx, h.gt, s);
-    gemv_set(h, h.gset.gemv_Wt, low, h.gt, h.gy, s);
+    set_solve(h, h.gset, h.gx, h.gt, h.gy, s);
 }
 
 // z1 = M_G^-1 r = P^ (P^T A P^)^-1 P^T r   (Eq. 18)
@@ -801,6 +829,11 @@ struct SetLaunch {
 };
 static std::vector<SetLaunch> set_launches(Handle &h) {
     const bool low = h.smoother_precision != 64;
+    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE)
+        return {{&h.gset.gemv_S, false, h.gx, h.gy},
+                {&h.cset.gemv_S, false, h.cx, h.cy},
+                {&h.gemv_XT, false, h.gx, h.gc_t},
+                {&h.gemv_X, false, h.gc_u, h.gy}};
     return {{&h.gset.gemv_W, low, h.gx, h.gt},   {&h.gset.gemv_Wt, low, h.gt, h.gy},
             {&h.cset.gemv_W, low, h.cx, h.ct},   {&h.cset.gemv_Wt, low, h.ct, h.cy},
             {&h.gemv_XT, false, h.gx, h.gc_t},   {&h.gemv_X, false, h.gc_u, h.gy}};
@@ -1183,6 +1216,7 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 put(v.data(), sizeof(double) * v.size());
                 break;
             }
+            case 11: put(&h.smoother_form, sizeof(int32_t)); break;
             default: fail(HPLMM_E_ARG, "unknown query");
         }
         if (needed) *needed = (int64_t)buf.size();

@@ -89,6 +89,26 @@ struct CopyTask {  // dst tile = src tile^T
     int64_t dst_off;
 };
 
+// y = S x for a batch of symmetric matrices stored as their lower tiles, each
+// tile read once.  A task (a GemvTask) is one tile row i of one matrix; its
+// pairs are the tiles S_ij, j <= i.  Pair j adds S_ij x_j to y_i and, below
+// the diagonal (p_off >= 0), writes the 64 values of S_ij^T x_i, the part of
+// row j carried by this tile, to part[p_off ..).
+struct SymPair {
+    int64_t t_off;
+    int64_t x_off;
+    int64_t p_off;   // -1 on the diagonal
+};
+
+// Row j of the symmetric product: y[y_off + r] += sum_k part[p_off + 64 k + r]
+// for k < count, in ascending k (fixed order: reproducible sums).
+struct SymReduce {
+    int64_t y_off;
+    int64_t p_off;
+    int32_t count;
+    int32_t pad = 0;
+};
+
 // Launchers (stream-ordered, asynchronous).  `flag` points to a device int32
 // pair {status bits, first bad id}.
 // Split tasks need `part` (T) and the zeroed counters `cnt` (reset by the
@@ -112,5 +132,12 @@ template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
                  const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
                  int32_t waves = 4, double *part = nullptr, int32_t *cnt = nullptr);
+// Symmetric-operator GEMV (FP64): one work-group of `waves` (4 or 16)
+// wavefronts per tile row; y receives the rows' own parts, part the
+// transposed products of the tiles below the diagonal.  x and y must not
+// alias.  launch_sym_reduce then adds the transposed products into y.
+void launch_sym_gemv(const double *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
+                     int64_t ntasks, double *part, int32_t waves, hipStream_t s);
+void launch_sym_reduce(const SymReduce *tasks, int64_t ntasks, const double *part, double *y, hipStream_t s);
 
 }  // namespace hplmm

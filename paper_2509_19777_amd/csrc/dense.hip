@@ -451,6 +451,84 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
     y[tk.y_off + t] = s;
 }
 
+// ---- symmetric-operator GEMV ----------------------------------------------
+// Lane l of a wave reads rows 2 (l & 31) and 2 (l & 31) + 1 of the tile
+// columns c = (l >> 5) + 2 u, sixteen bytes per load, so each load
+// instruction covers two whole columns.  The row part S_ij x_j accumulates in
+// two registers over all tiles of the task.  The transposed part needs, per
+// column, the sum over the 32 lanes of a half-wave; it is formed per
+// 16-column chunk (8 columns per lane): a reduce-scatter over lane bits 4, 3
+// and 2 (8 -> 4 -> 2 -> 1 values per lane) and a butterfly over bits 1 and 0
+// leave lane l with the column u = 4 b4 + 2 b3 + b2 of its half.
+template <int NW>
+__global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const double *__restrict__ arena,
+                                                           const double *__restrict__ x, double *__restrict__ y,
+                                                           const GemvTask *__restrict__ tasks,
+                                                           const SymPair *__restrict__ pairs,
+                                                           double *__restrict__ part) {
+    __shared__ double red[NW * 2 * TS];
+    const GemvTask tk = tasks[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int phase = lane >> 5, row0 = 2 * (lane & 31);
+    const bool b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
+    const int uq = 4 * (int)b4 + 2 * (int)b3 + (int)b2;
+    const double xi0 = x[tk.y_off + row0], xi1 = x[tk.y_off + row0 + 1];
+    double acc0 = 0.0, acc1 = 0.0;
+    for (int p = wave; p < tk.pair_count; p += NW) {
+        const SymPair pr = pairs[tk.pair_start + p];
+        const double *tile = arena + pr.t_off;
+        const double *xs = x + pr.x_off;
+        const bool below = pr.p_off >= 0;
+#pragma unroll 1
+        for (int ch = 0; ch < 4; ++ch) {
+            double cs[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int c = 16 * ch + 2 * u + phase;
+                const double2 v = *reinterpret_cast<const double2 *>(tile + c * TS + row0);
+                const double xc = xs[c];
+                acc0 += v.x * xc;
+                acc1 += v.y * xc;
+                cs[u] = v.x * xi0 + v.y * xi1;
+            }
+            if (below) {
+                double t4[4], t3[2];
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    t4[k] = (b4 ? cs[k + 4] : cs[k]) + __shfl_xor(b4 ? cs[k] : cs[k + 4], 16);
+#pragma unroll
+                for (int k = 0; k < 2; ++k)
+                    t3[k] = (b3 ? t4[k + 2] : t4[k]) + __shfl_xor(b3 ? t4[k] : t4[k + 2], 8);
+                double t = (b2 ? t3[1] : t3[0]) + __shfl_xor(b2 ? t3[0] : t3[1], 4);
+                t += __shfl_xor(t, 2);
+                t += __shfl_xor(t, 1);
+                if ((lane & 3) == 0) part[pr.p_off + 16 * ch + 2 * uq + phase] = t;
+            }
+        }
+    }
+    red[(wave * 2 + phase) * TS + row0] = acc0;
+    red[(wave * 2 + phase) * TS + row0 + 1] = acc1;
+    __syncthreads();
+    if (threadIdx.x >= TS) return;   // wave 0 finishes the row
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int q = 0; q < NW * 2; ++q) s += red[q * TS + t];
+    y[tk.y_off + t] = s;
+}
+
+// One wavefront per row: lane r adds the row's transposed products in order.
+__global__ void __launch_bounds__(256) sym_reduce_kernel(const SymReduce *__restrict__ tasks, int64_t ntasks,
+                                                         const double *__restrict__ part, double *__restrict__ y) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= ntasks) return;
+    const SymReduce tk = tasks[i];
+    const int r = threadIdx.x & 63;
+    double s = y[tk.y_off + r];
+    const double *pp = part + tk.p_off + r;
+    for (int32_t k = 0; k < tk.count; ++k) s += pp[(int64_t)k * TS];
+    y[tk.y_off + r] = s;
+}
+
 // ---- launchers -----------------------------------------------------------
 static inline unsigned grid_of(int64_t n) { return (unsigned)n; }
 
@@ -480,6 +558,22 @@ void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tas
     else
         hipLaunchKernelGGL((gemv_kernel<T, 4>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
                            base, part, cnt);
+}
+
+void launch_sym_gemv(const double *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
+                     int64_t ntasks, double *part, int32_t waves, hipStream_t s) {
+    if (ntasks <= 0) return;
+    if (waves == 16)
+        hipLaunchKernelGGL(sym_gemv_kernel<16>, dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y, tasks, pairs,
+                           part);
+    else
+        hipLaunchKernelGGL(sym_gemv_kernel<4>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
+                           part);
+}
+void launch_sym_reduce(const SymReduce *tasks, int64_t ntasks, const double *part, double *y, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, tasks, ntasks, part,
+                       y);
 }
 
 template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, double *,

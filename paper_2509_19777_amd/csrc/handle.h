@@ -31,7 +31,8 @@ enum ProfClass : int32_t {
     PC_GEMV_BASIS = 4,    // restriction / prolongation GEMVs (units: bytes)
     PC_SPMV = 5,          // fine SpMV (units: bytes)
     PC_APPLY = 6,         // one whole preconditioner application (units: bytes)
-    PC_COUNT = 7
+    PC_SMOOTH_REDUCE = 7, // transposed-product sums of the symmetric smoother (units: bytes)
+    PC_COUNT = 8
 };
 
 struct Profiler {
@@ -66,6 +67,7 @@ struct Range {
     int64_t start = 0, count = 0;
     double bytes = 0.0;   // algorithmic bytes read and written by the launch
     int32_t waves = 4;    // GEMV launches: wavefronts per work-group (4 or 16)
+    bool sym = false;     // GEMV launches: symmetric-operator tasks (SymPair lists)
 };
 
 // Launch shapes of one GEMV launch that the autotuner chooses from: the same
@@ -86,13 +88,17 @@ struct TuneRecord {
 
 // A batch of symmetric positive definite matrices stored as packed lower
 // tiles; A (factored in place to L), W = L^-1 and Wt = L^-T share the same
-// relative layout in three regions of one arena.
+// relative layout in three regions of one arena, and so does the inverse
+// S = W^T W when the smoother applies it (s_base >= 0).
 struct DenseSet {
     std::vector<int64_t> n, nt, rel;   // size, tiles per side, relative offset
     int64_t region = 0;                // elements per region
     int64_t a_base = 0, w_base = 0, wt_base = 0;   // absolute arena offsets
+    int64_t s_base = -1;
     std::vector<Launch> factor_prog;   // potrf + trtri + transposes
-    Range gemv_W, gemv_Wt;             // apply-time task ranges
+    std::vector<Launch> inverse_prog;  // S = W^T W (lower tiles)
+    Range gemv_W, gemv_Wt;             // apply-time task ranges (factor form)
+    Range gemv_S, red_S;               // apply-time task ranges (inverse form)
     int64_t vec_len = 0;               // local vector length (sum nt*64)
     std::vector<int64_t> voff;         // local vector offset per matrix
     int64_t low_w_base = 0, low_wt_base = 0;   // offsets in the reduced-precision arena
@@ -245,6 +251,15 @@ struct Handle {
     GemvPair *d_vpairs = nullptr;
     std::vector<GemvTask> vtasks;
     std::vector<GemvPair> vpairs;
+    // symmetric smoother (inverse form): pairs of its row tasks (in vtasks),
+    // the row sums of the transposed products, and their partial buffer
+    int32_t smoother_form = HPLMM_SMOOTHER_FACTORS;
+    std::vector<SymPair> spairs;
+    std::vector<SymReduce> rtasks;
+    SymPair *d_spairs = nullptr;
+    SymReduce *d_rtasks = nullptr;
+    int64_t sym_part_len = 0;
+    double *d_sym_part = nullptr;
     int64_t grain_region_zero_n = 0;   // elements zeroed before each set-up
 
     // vectors

@@ -243,6 +243,66 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
+// S = W^T W for every matrix of a dense set (the inverse smoother form), lower
+// tiles S_ij = sum_{k >= i} W_ki^T W_kj, i >= j, one task per tile with the
+// stored transposes Wt_ki = W_ki^T as left operands.
+void build_inverse_program(DenseSet &ds, TaskLists &tl) {
+    auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
+    auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
+    auto S = [&](int64_t m, int64_t I, int64_t J) { return ds.s_base + ds.rel[m] + tri_index(I, J) * TE; };
+    Launch L{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+    for (int64_t m = 0; m < (int64_t)ds.n.size(); ++m)
+        for (int64_t i = 0; i < ds.nt[m]; ++i)
+            for (int64_t j = 0; j <= i; ++j) {
+                tl.gemm.push_back({S(m, i, j), -1, (int32_t)tl.pairs.size(), (int32_t)(ds.nt[m] - i), 0, 0});
+                for (int64_t k = i; k < ds.nt[m]; ++k) tl.pairs.push_back({Wt(m, k, i), W(m, k, j)});
+            }
+    L.count = (int64_t)tl.gemm.size() - L.start;
+    if (L.count) ds.inverse_prog.push_back(L);
+}
+
+// Apply-time lists of y = S x (inverse form): one task per tile row I, longest
+// rows first, with pairs S_IJ, J <= I; pair J < I also yields row J's part
+// S_IJ^T x_I, kept in a slot of the partial buffer.  The slots of row J (from
+// rows I = J+1 .. nt-1) lie contiguously, and one sum task per row adds them.
+void build_sym_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<SymPair> &sp, std::vector<SymReduce> &rt,
+                    int64_t &part_len) {
+    const int64_t nm = (int64_t)ds.n.size();
+    std::vector<int64_t> pbase((size_t)nm);
+    for (int64_t m = 0; m < nm; ++m) {
+        pbase[(size_t)m] = part_len;
+        part_len += ds.nt[m] * (ds.nt[m] - 1) / 2 * TS;
+    }
+    auto slot = [&](int64_t m, int64_t I, int64_t J) {   // row J's part from row I > J
+        const int64_t row = J * (ds.nt[m] - 1) - J * (J - 1) / 2;
+        return pbase[(size_t)m] + (row + I - J - 1) * TS;
+    };
+    std::vector<std::pair<int64_t, int64_t>> order;
+    for (int64_t m = 0; m < nm; ++m)
+        for (int64_t I = 0; I < ds.nt[m]; ++I) order.push_back({m, I});
+    std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) { return a.second > b.second; });
+    ds.gemv_S.start = (int64_t)vt.size();
+    for (auto [m, I] : order) {
+        vt.push_back({ds.voff[m] + I * TS, (int32_t)sp.size(), (int32_t)(I + 1), -1});
+        for (int64_t J = 0; J <= I; ++J)
+            sp.push_back({ds.s_base + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS, J < I ? slot(m, I, J) : -1});
+    }
+    ds.gemv_S.count = (int64_t)vt.size() - ds.gemv_S.start;
+    ds.gemv_S.sym = true;
+    ds.red_S.start = (int64_t)rt.size();
+    for (int64_t m = 0; m < nm; ++m)
+        for (int64_t J = 0; J + 1 < ds.nt[m]; ++J)
+            rt.push_back({ds.voff[m] + J * TS, slot(m, J + 1, J), (int32_t)(ds.nt[m] - 1 - J), 0});
+    ds.red_S.count = (int64_t)rt.size() - ds.red_S.start;
+}
+
+// Bytes of a sum launch: the slots read, y read and written.
+double sym_reduce_bytes(const std::vector<SymReduce> &rt, Range r) {
+    double b = 0.0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i) b += ((double)rt[(size_t)i].count + 2.0) * TS * 8.0;
+    return b;
+}
+
 // Algorithmic bytes of a GEMV launch: every tile and x segment read, y written.
 double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
     double b = 0.0;
@@ -866,6 +926,13 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     if (opt.smoother_precision != 64 && opt.smoother_precision != 32 && opt.smoother_precision != 16)
         fail(HPLMM_E_ARG, "smoother_precision must be 64, 32 or 16");
     h.smoother_precision = opt.smoother_precision;
+    if (opt.smoother_form < HPLMM_SMOOTHER_AUTO || opt.smoother_form > HPLMM_SMOOTHER_INVERSE)
+        fail(HPLMM_E_ARG, "smoother_form must be 0 (auto), 1 (factors) or 2 (inverse)");
+    if (opt.smoother_form == HPLMM_SMOOTHER_INVERSE && h.smoother_precision != 64)
+        fail(HPLMM_E_ARG, "the inverse smoother form needs smoother_precision 64");
+    h.smoother_form = opt.smoother_form == HPLMM_SMOOTHER_AUTO
+                          ? (h.smoother_precision == 64 ? HPLMM_SMOOTHER_INVERSE : HPLMM_SMOOTHER_FACTORS)
+                          : opt.smoother_form;
     if (opt.coarse_leaf_dofs < 0) fail(HPLMM_E_ARG, "coarse_leaf_dofs must be >= 0");
     h.coarse_leaf_dofs = opt.coarse_leaf_dofs > 0 ? opt.coarse_leaf_dofs : 192;
     h.n_nodes = n;
@@ -1117,6 +1184,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.low_wt_base = offbf;
         offbf += h.cset.region;
     }
+    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        h.gset.s_base = take64(h.gset.region);
+        h.cset.s_base = take64(h.cset.region);
+    }
     h.ar64_n = off64;
     h.ar32_n = off32;
     h.arbf_n = offbf;
@@ -1127,6 +1198,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         build_factor_program(h.cset, h.tl64, 1);
     else
         build_factor_program(h.cset, h.tl32, 1);
+    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        build_inverse_program(h.gset, h.tl64);
+        build_inverse_program(h.cset, h.tl64);
+    }
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
     {
         std::vector<int64_t> all((size_t)nG);
@@ -1135,12 +1210,17 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     // apply-time GEMV lists
     {
-        const int64_t gw = lowp ? h.gset.low_w_base : h.gset.w_base;
-        const int64_t gwt = lowp ? h.gset.low_wt_base : h.gset.wt_base;
-        build_smoother_gemv(h.gset, h.vtasks, h.vpairs, gw, gwt);
-        const int64_t cw = h.smoother_precision == 16 ? h.cset.low_w_base : h.cset.w_base;
-        const int64_t cwt = h.smoother_precision == 16 ? h.cset.low_wt_base : h.cset.wt_base;
-        build_smoother_gemv(h.cset, h.vtasks, h.vpairs, cw, cwt);
+        if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+            build_sym_gemv(h.gset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len);
+            build_sym_gemv(h.cset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len);
+        } else {
+            const int64_t gw = lowp ? h.gset.low_w_base : h.gset.w_base;
+            const int64_t gwt = lowp ? h.gset.low_wt_base : h.gset.wt_base;
+            build_smoother_gemv(h.gset, h.vtasks, h.vpairs, gw, gwt);
+            const int64_t cw = h.smoother_precision == 16 ? h.cset.low_w_base : h.cset.w_base;
+            const int64_t cwt = h.smoother_precision == 16 ? h.cset.low_wt_base : h.cset.wt_base;
+            build_smoother_gemv(h.cset, h.vtasks, h.vpairs, cw, cwt);
+        }
         // restriction t = X^T x, prolongation z = X u
         h.gemv_XT.start = (int64_t)h.vtasks.size();
         for (int64_t m = 0; m < nG; ++m)
@@ -1164,6 +1244,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     split_program(h.gset.factor_prog, h.tl64);
     split_program(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
     split_program(h.basis_prog, h.tl64);
+    split_program(h.gset.inverse_prog, h.tl64);
+    split_program(h.cset.inverse_prog, h.tl64);
+    fill_flops(h.gset.inverse_prog, h.tl64);
+    fill_flops(h.cset.inverse_prog, h.tl64);
     fill_flops(h.gset.factor_prog, h.tl64);
     fill_flops(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
@@ -1173,6 +1257,11 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.gset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.gset.gemv_Wt, ge);
         h.cset.gemv_W.bytes = gemv_bytes(h.vtasks, h.cset.gemv_W, ge);
         h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
+        for (DenseSet *ds : {&h.gset, &h.cset}) {
+            // the symmetric product reads its own x segment once more per row
+            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, 8.0) + (double)ds->gemv_S.count * TS * 8.0;
+            ds->red_S.bytes = sym_reduce_bytes(h.rtasks, ds->red_S);
+        }
         h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
         h.gemv_X.bytes = gemv_bytes(h.vtasks, h.gemv_X, 8.0);
         // fine SpMV: 72 B of values + 4 B of index per stored block, x read and
@@ -1181,7 +1270,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         // one application of M^-1 (Eq. 16): the operators above once each, two
         // residual SpMVs (which also read r), and the vector gathers/combines
         h.apply_bytes = h.gset.gemv_W.bytes + h.gset.gemv_Wt.bytes + h.cset.gemv_W.bytes +
-                        h.cset.gemv_Wt.bytes +
+                        h.cset.gemv_Wt.bytes + h.gset.gemv_S.bytes + h.cset.gemv_S.bytes +
                         h.gemv_XT.bytes + h.gemv_X.bytes + 2.0 * (h.spmv_bytes + 24.0 * n) +
                         8.0 * (6.0 * h.N + 3.0 * (double)h.gset.vec_len + 2.0 * (double)h.cset.vec_len);
     }
@@ -1416,6 +1505,32 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         chk_gemv(h.gset.gemv_Wt, low_n, h.gset.vec_len, h.gset.vec_len, "grain Wt gemv");
         chk_gemv(h.cset.gemv_W, c_n, h.cset.vec_len, h.cset.vec_len, "contact W gemv");
         chk_gemv(h.cset.gemv_Wt, c_n, h.cset.vec_len, h.cset.vec_len, "contact Wt gemv");
+        auto chk_sym = [&](const DenseSet &ds, const char *what) {
+            const Range r = ds.gemv_S;
+            for (int64_t i = r.start; i < r.start + r.count; ++i) {
+                const GemvTask &t = h.vtasks[(size_t)i];
+                chk(in(t.y_off, TS, ds.vec_len) && t.base_off < 0 && t.nchunk == 1 && t.chunk == 0, what);
+                chk(t.pair_start >= 0 && t.pair_count >= 1 && (int64_t)t.pair_start + t.pair_count <= (int64_t)h.spairs.size(),
+                    what);
+                for (int32_t q = 0; q < t.pair_count; ++q) {
+                    const SymPair &pr = h.spairs[(size_t)(t.pair_start + q)];
+                    chk(in(pr.t_off, TE, h.ar64_n) && in(pr.x_off, TS, ds.vec_len), what);
+                    // the diagonal tile, last in its row, carries no transposed product
+                    chk(q + 1 == t.pair_count ? pr.p_off == -1 : in(pr.p_off, TS, h.sym_part_len), what);
+                }
+            }
+            for (int64_t i = ds.red_S.start; i < ds.red_S.start + ds.red_S.count; ++i) {
+                const SymReduce &t = h.rtasks[(size_t)i];
+                chk(t.count >= 1 && in(t.y_off, TS, ds.vec_len) && in(t.p_off, (int64_t)t.count * TS, h.sym_part_len), what);
+            }
+        };
+        if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+            chk(h.gset.s_base >= 0 && h.cset.s_base >= 0, "inverse regions");
+            chk_sym(h.gset, "grain S gemv");
+            chk_sym(h.cset, "contact S gemv");
+        } else {
+            chk(h.gset.gemv_S.count == 0 && h.cset.gemv_S.count == 0, "symmetric lists in the factor form");
+        }
         chk_gemv(h.gemv_XT, h.ar64_n, h.gset.vec_len, h.gcol_len, "restriction gemv");
         chk_gemv(h.gemv_X, h.ar64_n, h.gcol_len, h.gset.vec_len, "prolongation gemv");
         for (auto v : g_slot_dof) chk(v >= -1 && v < h.N, "grain slot map");
@@ -1607,6 +1722,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     h.d_vtasks = h.upload(h.vtasks, s);
     h.d_vpairs = h.upload(h.vpairs, s);
+    h.d_spairs = h.upload(h.spairs, s);
+    h.d_rtasks = h.upload(h.rtasks, s);
+    h.d_sym_part = h.dalloc<double>(std::max<int64_t>(1, h.sym_part_len));
     h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
     h.d_gemv_cnt = h.dalloc<int32_t>(std::max<int32_t>(1, h.gemv_cnt_len));
     if (hipMemsetAsync(h.d_gemv_cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.gemv_cnt_len), s) != hipSuccess)

@@ -42,7 +42,7 @@ MORTAR_KINDS = {"gaussian": 0, "algebraic": 1}
 
 
 class HplmmOptions(C.Structure):
-    _fields_ = [("smoother_precision", i32), ("coarse_leaf_dofs", i32)]
+    _fields_ = [("smoother_precision", i32), ("coarse_leaf_dofs", i32), ("smoother_form", i32)]
 
 
 class HplmmSgStats(C.Structure):
@@ -245,12 +245,15 @@ def place_mortars(xyz, n):
     return out.tolist()
 
 
+SMOOTHER_FORMS = {"auto": 0, "factors": 1, "inverse": 2}
+
+
 def plan_check(system, part, n_mortar=2, beta=4.0, smoother_precision=64, mortar_kind="gaussian",
-               coarse_leaf_dofs=0):
+               coarse_leaf_dofs=0, smoother_form="auto"):
     """Host-only symbolic phase plus bounds check of every launch list."""
     s, p = system.c_struct(), part.c_struct()
     m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
-    o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs))
+    o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs), SMOOTHER_FORMS[smoother_form])
     out = np.zeros(16, dtype=np.int64)
     _check(lib().hplmm_plan_check(C.byref(s), C.byref(p), C.byref(m), C.byref(o), _ptr(out, i64)))
     keys = ["n_nodes", "nnzb", "n_grains", "n_ifaces", "n_contacts", "n_mortar", "n_corr", "n_coarse",
@@ -298,14 +301,14 @@ class Solver:
     """
 
     def __init__(self, system: System, part: Partition, n_mortar=2, beta=4.0, smoother_precision=64,
-                 mortar_kind="gaussian", coarse_leaf_dofs=0):
+                 mortar_kind="gaussian", coarse_leaf_dofs=0, smoother_form="auto"):
         if not torch.cuda.is_available():
             raise RuntimeError("hplmm.Solver needs a GPU")
         self.system, self.part = system, part
         self._keep = (system.c_struct(), part.c_struct())
         h = C.c_void_p()
         m = HplmmMortar(int(n_mortar), float(beta), MORTAR_KINDS[mortar_kind])
-        o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs))
+        o = HplmmOptions(int(smoother_precision), int(coarse_leaf_dofs), SMOOTHER_FORMS[smoother_form])
         _check(lib().hplmm_plan(C.byref(self._keep[0]), C.byref(self._keep[1]), C.byref(m), C.byref(o), _stream(),
                                 C.byref(h)))
         self.h = h
@@ -321,6 +324,10 @@ class Solver:
 
     def setup(self):
         _check(lib().hplmm_setup(self.h, _stream()))
+
+    def smoother_form(self):
+        """'factors' (y = W^T W x in two passes) or 'inverse' (y = S x, S = W^T W)."""
+        return {1: "factors", 2: "inverse"}[int(self.query(11, np.int32)[0])]
 
     def set_voxel_operator(self, problem=None):
         """Matrix-free products with A from the problem's voxel grid (checked
@@ -402,7 +409,8 @@ class Solver:
         n = self.sizes()["n_coarse"]
         return self.query(4, np.float64).reshape(n, n)
 
-    PROF_CLASSES = ["tile_gemm", "diag", "gemv_smoother", "gemv_coarse", "gemv_basis", "spmv", "apply"]
+    PROF_CLASSES = ["tile_gemm", "diag", "gemv_smoother", "gemv_coarse", "gemv_basis", "spmv", "apply",
+                    "smoother_reduce"]
 
     def profile(self, classes):
         """Enable event timing for the named kernel classes (empty: off)."""

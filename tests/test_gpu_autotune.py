@@ -29,6 +29,12 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
+def _set_launches(S):
+    # smoother and basis GEMV launches: grain W, W^T, contact W, W^T, X^T, X
+    # (factor form) or grain S, contact S, X^T, X (inverse form)
+    return 4 if S.smoother_form() == "inverse" else 6
+
+
 @pytest.fixture(scope="module")
 def case():
     _torch()
@@ -76,7 +82,7 @@ def test_every_shape_matches_oracle(case, variant, waves):
     p, A, b, H, S, _ = case
     levels = S.sizes()["coarse_levels"]
     recs = [{"kind": k, "index": l, "variant": variant, "waves": waves} for k in (0, 1) for l in range(levels)]
-    recs += [{"kind": 2, "index": i, "variant": 0, "waves": waves} for i in range(6)]
+    recs += [{"kind": 2, "index": i, "variant": 0, "waves": waves} for i in range(_set_launches(S))]
     S.set_tuning(recs)
     for seed in (10, 12):
         r = synth.random_vector(A.shape[0], seed)
@@ -134,7 +140,7 @@ def test_bad_records_restore_defaults(case):
     for bad in ({"kind": 0, "index": 0, "variant": 0, "waves": 8},
                 {"kind": 0, "index": 999, "variant": 0, "waves": 4},
                 {"kind": 1, "index": 0, "variant": 99, "waves": 4},
-                {"kind": 2, "index": 6, "variant": 0, "waves": 4},
+                {"kind": 2, "index": _set_launches(S), "variant": 0, "waves": 4},
                 {"kind": 5, "index": 0, "variant": 0, "waves": 4}):
         with pytest.raises(HplmmError):
             S.set_tuning([{"kind": 2, "index": 0, "variant": 0, "waves": 16}, bad])

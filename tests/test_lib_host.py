@@ -177,3 +177,27 @@ def test_coarse_leaf_option(hp):
     assert small["n_coarse"] == big["n_coarse"] == default["n_coarse"]
     with pytest.raises(hp.HplmmError):
         hp.plan_check(sysm, part, n_mortar=4, coarse_leaf_dofs=-1)
+
+
+def test_smoother_forms(hp):
+    """The inverse form adds one region per dense set (S = W^T W, the same
+    packed layout) and one tile product task per stored tile of S, at least;
+    auto picks it at float64 only; the inverse form refuses reduced precision."""
+    p = synth.config_pores(16, 4, seed=1)
+    sysm, part = hp.build_problem(p)
+    fac = hp.plan_check(sysm, part, n_mortar=4, smoother_form="factors")
+    inv = hp.plan_check(sysm, part, n_mortar=4, smoother_form="inverse")
+    auto = hp.plan_check(sysm, part, n_mortar=4)
+    assert auto == inv
+    s_tiles = (inv["ar64"] - fac["ar64"]) // 4096
+    assert s_tiles > 0 and (inv["ar64"] - fac["ar64"]) % 4096 == 0
+    assert inv["tile_tasks"] - fac["tile_tasks"] >= s_tiles
+    assert hp.plan_check(sysm, part, n_mortar=4, smoother_precision=32) == \
+        hp.plan_check(sysm, part, n_mortar=4, smoother_precision=32, smoother_form="factors")
+    with pytest.raises(hp.HplmmError):
+        hp.plan_check(sysm, part, n_mortar=4, smoother_precision=32, smoother_form="inverse")
+    s, q = sysm.c_struct(), part.c_struct()
+    m = hp.HplmmMortar(4, 4.0, 0)
+    o = hp.HplmmOptions(64, 0, 3)
+    with pytest.raises(hp.HplmmError):
+        hp._check(hp.lib().hplmm_plan_check(hp.C.byref(s), hp.C.byref(q), hp.C.byref(m), hp.C.byref(o), None))
