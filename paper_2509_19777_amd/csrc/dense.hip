@@ -112,10 +112,13 @@ __device__ __forceinline__ void mfma_half(const T *As, const T *Bs, typename Mfm
 // of the 2x2 wave grid; for C = ([C +] alpha S) P the bracket is the A
 // operand (k = its column n), held by the waves of one column.
 template <int H, class T>
-__device__ __forceinline__ void post_half(T *As, T *Bs, const T *C, const TileRegs<T> &rp,
-                                          typename Mfma<T>::acc_t acc[2][2], typename Mfma<T>::acc_t res[2][2],
-                                          bool left, bool acc_c, T alpha, int lane, int wm, int wn) {
+__device__ __forceinline__ void post_half(T *As, T *Bs, const T *C, const T *P, typename Mfma<T>::acc_t acc[2][2],
+                                          typename Mfma<T>::acc_t res[2][2], bool left, bool acc_c, T alpha,
+                                          int lane, int wm, int wn) {
     const int lr = lane & 15, lq = lane >> 4;
+    const OpMap kp(!left, threadIdx.x);
+    TileRegs<T> rp;
+    fetch_half<H>(rp, P, kp);
     __syncthreads();
     if ((left ? wm : wn) == KH * H) {
         for (int i = 0; i < 2; ++i)
@@ -131,14 +134,51 @@ __device__ __forceinline__ void post_half(T *As, T *Bs, const T *C, const TileRe
                     }
                 }
     }
-    stage_half<H>(left ? As : Bs, rp, OpMap(!left, threadIdx.x));
+    stage_half<H>(left ? As : Bs, rp, kp);
     __syncthreads();
     mfma_half<T>(As, Bs, res, lane, wm, wn);
 }
 
-// Tile contraction task.  Each pair is contracted in two 32-deep halves; the
-// registers of a half are refilled with the next pair's operands as soon as
-// that half is in LDS, so the fetch overlaps the matrix-core work.
+// The pairs of one task, accumulated into acc.  One half of each operand is
+// held in registers at a time; its fetch overlaps the matrix-core work on the
+// other half, already in LDS.  KA / KB: the operands' contraction index runs
+// along the stored rows (compile-time, so every offset is a constant).
+template <class T, bool KA, bool KB>
+__device__ __forceinline__ void gemm_pairs(const T *__restrict__ arena, const GemmPair *__restrict__ pairs,
+                                           const GemmTask &tk, T *As, T *Bs, typename Mfma<T>::acc_t acc[2][2],
+                                           int lane, int wm, int wn) {
+    const OpMap ka(KA, threadIdx.x), kb(KB, threadIdx.x);
+    TileRegs<T> ra, rb;
+    if (tk.pair_count > 0) {
+        const GemmPair pr = pairs[tk.pair_start];
+        fetch_half<0>(ra, arena + pr.a_off, ka);
+        fetch_half<0>(rb, arena + pr.b_off, kb);
+    }
+    for (int p = 0; p < tk.pair_count; ++p) {
+        const GemmPair cur = pairs[tk.pair_start + p];
+        const bool more = p + 1 < tk.pair_count;
+        const GemmPair nx = pairs[tk.pair_start + (more ? p + 1 : p)];
+        __syncthreads();
+        stage_half<0>(As, ra, ka);
+        stage_half<0>(Bs, rb, kb);
+        __syncthreads();
+        fetch_half<1>(ra, arena + cur.a_off, ka);
+        fetch_half<1>(rb, arena + cur.b_off, kb);
+        mfma_half<T>(As, Bs, acc, lane, wm, wn);
+        __syncthreads();
+        stage_half<1>(As, ra, ka);
+        stage_half<1>(Bs, rb, kb);
+        __syncthreads();
+        if (more) {
+            fetch_half<0>(ra, arena + nx.a_off, ka);
+            fetch_half<0>(rb, arena + nx.b_off, kb);
+        }
+        mfma_half<T>(As, Bs, acc, lane, wm, wn);
+    }
+}
+
+// Tile contraction task: the pairs in 32-deep halves, then the optional
+// second product and the output.
 template <class T>
 __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
                                                         const GemmTask *__restrict__ tasks,
@@ -155,36 +195,18 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     typename Mfma<T>::acc_t acc[2][2];
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    const OpMap ka(tk.flags & GF_TRANS_A, threadIdx.x), kb(!(tk.flags & GF_TRANS_B), threadIdx.x);
-    TileRegs<T> ra, rb;
-    if (tk.pair_count > 0) {
-        const GemmPair pr = pairs[tk.pair_start];
-        fetch_half<0>(ra, arena + pr.a_off, ka);
-        fetch_half<0>(rb, arena + pr.b_off, kb);
-        fetch_half<1>(ra, arena + pr.a_off, ka);
-        fetch_half<1>(rb, arena + pr.b_off, kb);
-    }
-    for (int p = 0; p < tk.pair_count; ++p) {
-        const bool more = p + 1 < tk.pair_count;
-        const GemmPair nx = pairs[tk.pair_start + (more ? p + 1 : p)];
-        __syncthreads();
-        stage_half<0>(As, ra, ka);
-        stage_half<0>(Bs, rb, kb);
-        __syncthreads();
-        if (more) {
-            fetch_half<0>(ra, arena + nx.a_off, ka);
-            fetch_half<0>(rb, arena + nx.b_off, kb);
-        }
-        mfma_half<T>(As, Bs, acc, lane, wm, wn);
-        __syncthreads();
-        stage_half<1>(As, ra, ka);
-        stage_half<1>(Bs, rb, kb);
-        __syncthreads();
-        if (more) {
-            fetch_half<1>(ra, arena + nx.a_off, ka);
-            fetch_half<1>(rb, arena + nx.b_off, kb);
-        }
-        mfma_half<T>(As, Bs, acc, lane, wm, wn);
+    // the contraction loop specialised on the fetch orders (uniform branch)
+    const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
+    if (ta) {
+        if (tb)
+            gemm_pairs<T, true, false>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+        else
+            gemm_pairs<T, true, true>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+    } else {
+        if (tb)
+            gemm_pairs<T, false, false>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+        else
+            gemm_pairs<T, false, true>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
     }
     if (tk.nchunk > 1) {
         // partial sums in accumulator order, reduced by the last arrival
@@ -217,15 +239,11 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
         // GF_POST_RIGHT: C = ([C +] alpha S) P, P the B operand (k along its rows)
         const bool left = tk.flags & GF_POST;
         const bool acc_c = !left && (tk.flags & GF_ACCUM);
-        TileRegs<T> rp;
-        const OpMap kp(!left, threadIdx.x);
-        fetch_half<0>(rp, arena + tk.post_off, kp);
-        fetch_half<1>(rp, arena + tk.post_off, kp);
         typename Mfma<T>::acc_t res[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) res[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-        post_half<0, T>(As, Bs, C, rp, acc, res, left, acc_c, alpha, lane, wm, wn);
-        post_half<1, T>(As, Bs, C, rp, acc, res, left, acc_c, alpha, lane, wm, wn);
+        post_half<0, T>(As, Bs, C, arena + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
+        post_half<1, T>(As, Bs, C, arena + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = res[i][j];
     }
