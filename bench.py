@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--precision", type=int, default=64, choices=[64, 32, 16])
     ap.add_argument("--smoother-form", choices=["auto", "factors", "inverse"], default="auto",
                     help="local solves of the smoother as W^T (W x) or as S x with S = W^T W "
-                         "(auto: the inverse form at float64)")
+                         "(auto: the inverse form, except with bfloat16 storage)")
     ap.add_argument("--assembled", action="store_true",
                     help="products with A from the assembled blocks (default: matrix-free from the voxel grid)")
     ap.add_argument("--autotune-reps", type=int, default=3,

@@ -135,10 +135,11 @@ typedef struct hplmm_mortar {
     int32_t kind;
 } hplmm_mortar;
 
-/* Smoother precision: 64 = float64; 32 = float32 contact factorisation and
- * float32 smoother operators; 16 = float32 contact factorisation and
- * bfloat16 smoother operators.  The coarse space (basis, coarse operator,
- * coarse solve) and the Krylov solver are float64 in every mode.
+/* Smoother precision: 64 = float64; 32 = float32 smoother operators; 16 =
+ * bfloat16 smoother operators.  In the factor form (below) the contact grids
+ * are then factored in float32; in the inverse form every factorisation is
+ * float64 and only the stored S is rounded.  The coarse space (basis, coarse
+ * operator, coarse solve) and the Krylov solver are float64 in every mode.
  * coarse_leaf_dofs: the nested dissection of the coarse operator stops at
  * subsets of at most this many dofs (0 = the default, 192); larger leaves
  * give fewer front levels (fewer launches per coarse solve) and larger dense
@@ -153,10 +154,15 @@ typedef struct hplmm_mortar {
  *                           S, each off-diagonal tile serving S_ij x_j and
  *                           S_ij^T x_i, then a short sum of the transposed
  *                           products per tile row.  Half the smoother's HBM
- *                           reads.  float64 smoother only (HPLMM_E_ARG
- *                           otherwise);
- *   HPLMM_SMOOTHER_AUTO (0) the inverse form at smoother_precision 64, the
- *                           factor form otherwise. */
+ *                           reads.  At smoother_precision 32 / 16 every block
+ *                           (the contact grids too) is factored in float64,
+ *                           and S is stored rounded to float32 / bfloat16.
+ *                           Rounding S (unlike rounding W, whose Gram product
+ *                           W^T W stays positive definite) perturbs it by about
+ *                           u |S|, so S can turn indefinite once kappa(A_g)
+ *                           exceeds about 1/u: 2^8 for bfloat16;
+ *   HPLMM_SMOOTHER_AUTO (0) the inverse form at smoother_precision 64 and 32,
+ *                           the factor form at 16. */
 #define HPLMM_SMOOTHER_AUTO     0
 #define HPLMM_SMOOTHER_FACTORS  1
 #define HPLMM_SMOOTHER_INVERSE  2

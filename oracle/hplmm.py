@@ -58,7 +58,7 @@ class HPLMM:
     """
 
     def __init__(self, problem, A=None, b=None, mesh=None, n=None, beta=None, w_zeta=None,
-                 use_rhs=True, smoother_precision="f64", tile=64, mortar_kind="gaussian"):
+                 use_rhs=True, smoother_precision="f64", tile=64, mortar_kind="gaussian", smoother_form="factors"):
         if A is None:
             A, b_asm, mesh = fem.assemble(problem)
             if b is None:
@@ -76,6 +76,7 @@ class HPLMM:
         mortar_mod.build_mortars(P, mesh, self.n, self.beta, kind=mortar_kind, A=self.A)
         self.part = P
         self.smoother_precision = smoother_precision
+        self.smoother_form = smoother_form
         self.tile = tile
         self._build_W_Q()
         self._build_P(use_rhs)
@@ -190,7 +191,7 @@ class HPLMM:
             self.contact_chol.append(sla.cho_factor(Az, lower=True))
         self.lowp = None
         if self.smoother_precision != "f64":
-            self.lowp = prec.LowPrecisionSmoother(self, self.smoother_precision, self.tile)
+            self.lowp = prec.LowPrecisionSmoother(self, self.smoother_precision, self.tile, self.smoother_form)
 
     # ---- applications -----------------------------------------------------
     def apply_MG(self, r):

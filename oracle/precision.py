@@ -12,6 +12,12 @@ blocks) or FP32 (contact blocks), as the variant prescribes:
   z = W_i^T (W_i r) evaluated in FP64 on the rounded W_i;
 * contact blocks: A_zeta is rounded to FP32, factored and inverted in FP32,
   and the FP32 inverse factor is rounded to the storage precision.
+
+That is the factor form (form="factors").  In the inverse form
+(form="inverse") every block, grain and contact grid alike, is factored and
+inverted in FP64, the symmetric inverse S = W^T W is formed in FP64 and
+rounded once to the storage precision, and the smoother is z = S r evaluated
+in FP64 on the rounded S.
 """
 from __future__ import annotations
 
@@ -43,9 +49,15 @@ def round_to(x, precision):
 
 
 class LowPrecisionSmoother:
-    def __init__(self, H, precision, tile=64):
+    def __init__(self, H, precision, tile=64, form="factors"):
         self.H = H
         self.precision = precision
+        self.form = form
+        if form == "inverse":
+            self._build_inverse()
+            return
+        if form != "factors":
+            raise ValueError(form)
         self.grain_W = []
         for ch in H.grain_chol:
             if ch is None:
@@ -61,8 +73,22 @@ class LowPrecisionSmoother:
             W32 = sla.solve_triangular(L32, np.eye(L32.shape[0], dtype=np.float32), lower=True)
             self.contact_W.append(round_to(W32.astype(np.float64), precision))
 
+    def _build_inverse(self):
+        def rounded_inverse(A):
+            L = np.linalg.cholesky(A)
+            W = sla.solve_triangular(L, np.eye(L.shape[0]), lower=True)
+            return round_to(W.T @ W, self.precision)
+        self.grain_S = [None if ch is None else rounded_inverse(self.H.A[d][:, d].toarray())
+                        for d, ch in zip(self.H.grain_dofs, self.H.grain_chol)]
+        self.contact_S = [rounded_inverse(self.H.A[d][:, d].toarray()) for d in self.H.contact_dofs]
+
     def apply_grains(self, r):
         z = np.zeros_like(r)
+        if self.form == "inverse":
+            for dofs, Si in zip(self.H.grain_dofs, self.grain_S):
+                if Si is not None:
+                    z[dofs] = Si @ r[dofs]
+            return z
         for dofs, Wi in zip(self.H.grain_dofs, self.grain_W):
             if Wi is None:
                 continue
@@ -71,6 +97,10 @@ class LowPrecisionSmoother:
 
     def apply_contacts(self, r):
         z = np.zeros_like(r)
+        if self.form == "inverse":
+            for dofs, Sz in zip(self.H.contact_dofs, self.contact_S):
+                z[dofs] += Sz @ r[dofs]
+            return z
         for dofs, Wz in zip(self.H.contact_dofs, self.contact_W):
             z[dofs] += Wz.T @ (Wz @ r[dofs])
         return z

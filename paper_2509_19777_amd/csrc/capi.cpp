@@ -85,14 +85,26 @@ struct SgSetup {
 };
 static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s);
 
-// Contact grids (Eq. 26): blocks, factor and inverse, on stream s.
+// S (FP64) of a dense set rounded into the reduced-precision arena.
+static void store_low_inverse(Handle &h, const DenseSet &ds, hipStream_t s) {
+    if (h.smoother_precision == 32)
+        launch_convert_f64_f32(h.ar64 + ds.s_base, h.ar32 + ds.low_s_base, ds.region, s);
+    else if (h.smoother_precision == 16)
+        launch_convert_f64_bf16(h.ar64 + ds.s_base, h.arbf + ds.low_s_base, ds.region, s);
+}
+
+// Contact grids (Eq. 26): blocks, factor and inverse, on stream s; in FP64
+// except in the reduced-precision factor form.
 static void contact_setup(Handle &h, hipStream_t s) {
-    if (h.smoother_precision == 64) {
+    if (h.smoother_precision == 64 || h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        // FP64 programs beside those on the main stream: never on its scratch
+        if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
         zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
         run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
         run_program<double>(h, h.tl64, h.ar64, h.cset.inverse_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+        store_low_inverse(h, h.cset, s);
     } else {
         zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
@@ -154,10 +166,12 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         // the grain inverse S = W^T W follows the contact grids on the side
         // stream, beside the basis and the coarse operator on s
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+            if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
             hip_check(hipEventRecord(ev[4], s), "event");
             hip_check(hipStreamWaitEvent(h.side, ev[4], 0), "wait");
             run_program<double>(h, h.tl64, h.ar64, h.gset.inverse_prog, h.d_flag, h.side, h.d_part_side,
                                 h.d_cnt_side);
+            store_low_inverse(h, h.gset, h.side);
         }
         hip_check(hipEventRecord(h.side_ev[2], h.side), "event");
     }
@@ -174,7 +188,9 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         return;
     }
     launch_gather_scalar(h.d_corr_koff, h.n_corr, h.ar64, h.corr_d, s);
-    if (h.smoother_precision == 32) {
+    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        // the smoother reads S, rounded on the side stream
+    } else if (h.smoother_precision == 32) {
         launch_convert_f64_f32(h.ar64 + h.gset.w_base, h.ar32 + h.gset.low_w_base, h.gset.region, s);
         launch_convert_f64_f32(h.ar64 + h.gset.wt_base, h.ar32 + h.gset.low_wt_base, h.gset.region, s);
     } else if (h.smoother_precision == 16) {
@@ -444,9 +460,14 @@ static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
 
 static void launch_set(Handle &h, const Range &r, bool smoother_low, const double *x, double *y, hipStream_t s) {
     const GemvTask *t = h.d_vtasks + r.start;
-    if (r.sym)
-        launch_sym_gemv(h.ar64, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
-    else if (!smoother_low || h.smoother_precision == 64)
+    if (r.sym) {
+        if (h.smoother_precision == 64)
+            launch_sym_gemv<double>(h.ar64, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
+        else if (h.smoother_precision == 32)
+            launch_sym_gemv<float>(h.ar32, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
+        else
+            launch_sym_gemv<uint16_t>(h.arbf, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
+    } else if (!smoother_low || h.smoother_precision == 64)
         launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
     else if (h.smoother_precision == 32)
         launch_gemv<float>(h.ar32, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);

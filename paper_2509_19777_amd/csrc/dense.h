@@ -132,11 +132,13 @@ template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
                  const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
                  int32_t waves = 4, double *part = nullptr, int32_t *cnt = nullptr);
-// Symmetric-operator GEMV (FP64): one work-group of `waves` (4 or 16)
-// wavefronts per tile row; y receives the rows' own parts, part the
-// transposed products of the tiles below the diagonal.  x and y must not
-// alias.  launch_sym_reduce then adds the transposed products into y.
-void launch_sym_gemv(const double *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
+// Symmetric-operator GEMV (S stored as T = double, float or bfloat16 bits;
+// FP64 arithmetic): one work-group of `waves` (4 or 16) wavefronts per tile
+// row; y receives the rows' own parts, part the transposed products of the
+// tiles below the diagonal.  x and y must not alias.  launch_sym_reduce then
+// adds the transposed products into y.
+template <class T>
+void launch_sym_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
                      int64_t ntasks, double *part, int32_t waves, hipStream_t s);
 void launch_sym_reduce(const SymReduce *tasks, int64_t ntasks, const double *part, double *y, hipStream_t s);
 

@@ -189,7 +189,11 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     __shared__ T S[2 * KH * LD];
     T *As = S, *Bs = S + KH * LD;
     __shared__ int32_t last;
-    const GemmTask tk = tasks[blockIdx.x];
+    // work-groups are dealt to the 8 XCDs in turn; give each XCD a contiguous
+    // slice of the list, so neighbouring tasks (which share operand tiles)
+    // meet in the same L2
+    const uint32_t nb = gridDim.x, b = blockIdx.x, xcd = b & 7, q = nb >> 3, r = nb & 7;
+    const GemmTask tk = tasks[xcd * q + (xcd < r ? xcd : r) + (b >> 3)];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     typename Mfma<T>::acc_t acc[2][2];
@@ -470,67 +474,84 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
 }
 
 // ---- symmetric-operator GEMV ----------------------------------------------
-// Lane l of a wave reads rows 2 (l & 31) and 2 (l & 31) + 1 of the tile
-// columns c = (l >> 5) + 2 u, sixteen bytes per load, so each load
-// instruction covers two whole columns.  The row part S_ij x_j accumulates in
-// two registers over all tiles of the task.  The transposed part needs, per
-// column, the sum over the 32 lanes of a half-wave; it is formed per
-// 16-column chunk (8 columns per lane): a reduce-scatter over lane bits 4, 3
-// and 2 (8 -> 4 -> 2 -> 1 values per lane) and a butterfly over bits 1 and 0
-// leave lane l with the column u = 4 b4 + 2 b3 + b2 of its half.
-template <int NW>
-__global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const double *__restrict__ arena,
+// Storage T (double, float or bfloat16); products and sums in FP64.  Lane l
+// of a wave reads R = 16 / sizeof(T) consecutive rows of a tile column with
+// one 16-byte load: the LPC = 64 / R lanes l % LPC cover the column, and the
+// R groups l / LPC take R neighbouring columns, so each load instruction
+// covers R whole columns.  The row part S_ij x_j accumulates in R registers
+// over all tiles of the task.  The transposed part needs, per column, the sum
+// over the LPC lanes of a group; it is formed per chunk of 8 columns per
+// lane: a reduce-scatter over the top three bits of l % LPC (8 -> 4 -> 2 -> 1
+// values per lane) and a butterfly over the remaining low bits leave lane l
+// with column u = 4 b2 + 2 b1 + b0 of the chunk (b2 b1 b0 those three bits).
+template <class T, int NW>
+__global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__ arena,
                                                            const double *__restrict__ x, double *__restrict__ y,
                                                            const GemvTask *__restrict__ tasks,
                                                            const SymPair *__restrict__ pairs,
                                                            double *__restrict__ part) {
-    __shared__ double red[NW * 2 * TS];
+    constexpr int R = Vec16<T>::R;                      // rows per lane: 2, 4, 8
+    constexpr int LPC = TS / R;                         // lanes per column: 32, 16, 8
+    constexpr int NCH = TS / (8 * R);                   // chunks of 8 columns per lane: 4, 2, 1
+    constexpr int H2 = LPC / 2, H1 = LPC / 4, H0 = LPC / 8;   // the reduce-scatter's lane bits
+    __shared__ double red[NW * R * TS];
     const GemvTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int phase = lane >> 5, row0 = 2 * (lane & 31);
-    const bool b4 = lane & 16, b3 = lane & 8, b2 = lane & 4;
-    const int uq = 4 * (int)b4 + 2 * (int)b3 + (int)b2;
-    const double xi0 = x[tk.y_off + row0], xi1 = x[tk.y_off + row0 + 1];
-    double acc0 = 0.0, acc1 = 0.0;
+    const int phase = lane / LPC, lc = lane % LPC, row0 = lc * R;
+    const bool b2 = lc & H2, b1 = lc & H1, b0 = lc & H0;
+    const int uq = 4 * (int)b2 + 2 * (int)b1 + (int)b0;
+    double xi[R], acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        xi[r] = x[tk.y_off + row0 + r];
+        acc[r] = 0.0;
+    }
     for (int p = wave; p < tk.pair_count; p += NW) {
         const SymPair pr = pairs[tk.pair_start + p];
-        const double *tile = arena + pr.t_off;
+        const T *tile = arena + pr.t_off;
         const double *xs = x + pr.x_off;
         const bool below = pr.p_off >= 0;
 #pragma unroll 1
-        for (int ch = 0; ch < 4; ++ch) {
+        for (int ch = 0; ch < NCH; ++ch) {
             double cs[8];
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
-                const int c = 16 * ch + 2 * u + phase;
-                const double2 v = *reinterpret_cast<const double2 *>(tile + c * TS + row0);
+                const int c = R * (8 * ch + u) + phase;
+                double v[R];
+                Vec16<T>::load(tile + c * TS + row0, v);
                 const double xc = xs[c];
-                acc0 += v.x * xc;
-                acc1 += v.y * xc;
-                cs[u] = v.x * xi0 + v.y * xi1;
+                double t = 0.0;
+#pragma unroll
+                for (int r = 0; r < R; ++r) {
+                    acc[r] += v[r] * xc;
+                    t += v[r] * xi[r];
+                }
+                cs[u] = t;
+                // narrow storage widens to 2R registers per load: four loads in flight
+                if (R > 2 && u == 3) __builtin_amdgcn_sched_barrier(0);
             }
             if (below) {
                 double t4[4], t3[2];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
-                    t4[k] = (b4 ? cs[k + 4] : cs[k]) + __shfl_xor(b4 ? cs[k] : cs[k + 4], 16);
+                    t4[k] = (b2 ? cs[k + 4] : cs[k]) + __shfl_xor(b2 ? cs[k] : cs[k + 4], H2);
 #pragma unroll
                 for (int k = 0; k < 2; ++k)
-                    t3[k] = (b3 ? t4[k + 2] : t4[k]) + __shfl_xor(b3 ? t4[k] : t4[k + 2], 8);
-                double t = (b2 ? t3[1] : t3[0]) + __shfl_xor(b2 ? t3[0] : t3[1], 4);
-                t += __shfl_xor(t, 2);
-                t += __shfl_xor(t, 1);
-                if ((lane & 3) == 0) part[pr.p_off + 16 * ch + 2 * uq + phase] = t;
+                    t3[k] = (b1 ? t4[k + 2] : t4[k]) + __shfl_xor(b1 ? t4[k] : t4[k + 2], H1);
+                double t = (b0 ? t3[1] : t3[0]) + __shfl_xor(b0 ? t3[0] : t3[1], H0);
+#pragma unroll
+                for (int m = H0 / 2; m >= 1; m /= 2) t += __shfl_xor(t, m);
+                if ((lc & (H0 - 1)) == 0) part[pr.p_off + R * (8 * ch + uq) + phase] = t;
             }
         }
     }
-    red[(wave * 2 + phase) * TS + row0] = acc0;
-    red[(wave * 2 + phase) * TS + row0 + 1] = acc1;
+#pragma unroll
+    for (int r = 0; r < R; ++r) red[(wave * R + phase) * TS + row0 + r] = acc[r];
     __syncthreads();
     if (threadIdx.x >= TS) return;   // wave 0 finishes the row
     const int t = threadIdx.x;
     double s = 0.0;
-    for (int q = 0; q < NW * 2; ++q) s += red[q * TS + t];
+    for (int q = 0; q < NW * R; ++q) s += red[q * TS + t];
     y[tk.y_off + t] = s;
 }
 
@@ -578,16 +599,27 @@ void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tas
                            base, part, cnt);
 }
 
-void launch_sym_gemv(const double *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
+template <class T>
+void launch_sym_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const SymPair *pairs,
                      int64_t ntasks, double *part, int32_t waves, hipStream_t s) {
     if (ntasks <= 0) return;
-    if (waves == 16)
-        hipLaunchKernelGGL(sym_gemv_kernel<16>, dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y, tasks, pairs,
-                           part);
-    else
-        hipLaunchKernelGGL(sym_gemv_kernel<4>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
-                           part);
+    // narrow storage needs more registers per lane than 16 waves leave: 4 waves
+    if constexpr (sizeof(T) == 8) {
+        if (waves == 16) {
+            hipLaunchKernelGGL((sym_gemv_kernel<T, 16>), dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y,
+                               tasks, pairs, part);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((sym_gemv_kernel<T, 4>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
+                       part);
 }
+template void launch_sym_gemv<double>(const double *, const double *, double *, const GemvTask *, const SymPair *,
+                                      int64_t, double *, int32_t, hipStream_t);
+template void launch_sym_gemv<float>(const float *, const double *, double *, const GemvTask *, const SymPair *,
+                                     int64_t, double *, int32_t, hipStream_t);
+template void launch_sym_gemv<uint16_t>(const uint16_t *, const double *, double *, const GemvTask *,
+                                        const SymPair *, int64_t, double *, int32_t, hipStream_t);
 void launch_sym_reduce(const SymReduce *tasks, int64_t ntasks, const double *part, double *y, hipStream_t s) {
     if (ntasks <= 0) return;
     hipLaunchKernelGGL(sym_reduce_kernel, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, tasks, ntasks, part,

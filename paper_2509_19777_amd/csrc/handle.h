@@ -102,6 +102,7 @@ struct DenseSet {
     int64_t vec_len = 0;               // local vector length (sum nt*64)
     std::vector<int64_t> voff;         // local vector offset per matrix
     int64_t low_w_base = 0, low_wt_base = 0;   // offsets in the reduced-precision arena
+    int64_t low_s_base = 0;            // S as the smoother reads it (= s_base at FP64)
     std::vector<int64_t> nt_own;       // tiles factored per matrix (partial factorisation); empty = nt
 };
 

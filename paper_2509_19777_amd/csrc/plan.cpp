@@ -266,7 +266,7 @@ void build_inverse_program(DenseSet &ds, TaskLists &tl) {
 // S_IJ^T x_I, kept in a slot of the partial buffer.  The slots of row J (from
 // rows I = J+1 .. nt-1) lie contiguously, and one sum task per row adds them.
 void build_sym_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<SymPair> &sp, std::vector<SymReduce> &rt,
-                    int64_t &part_len) {
+                    int64_t &part_len, int64_t s_abs) {
     const int64_t nm = (int64_t)ds.n.size();
     std::vector<int64_t> pbase((size_t)nm);
     for (int64_t m = 0; m < nm; ++m) {
@@ -285,7 +285,7 @@ void build_sym_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<SymPair
     for (auto [m, I] : order) {
         vt.push_back({ds.voff[m] + I * TS, (int32_t)sp.size(), (int32_t)(I + 1), -1});
         for (int64_t J = 0; J <= I; ++J)
-            sp.push_back({ds.s_base + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS, J < I ? slot(m, I, J) : -1});
+            sp.push_back({s_abs + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS, J < I ? slot(m, I, J) : -1});
     }
     ds.gemv_S.count = (int64_t)vt.size() - ds.gemv_S.start;
     ds.gemv_S.sym = true;
@@ -928,11 +928,12 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.smoother_precision = opt.smoother_precision;
     if (opt.smoother_form < HPLMM_SMOOTHER_AUTO || opt.smoother_form > HPLMM_SMOOTHER_INVERSE)
         fail(HPLMM_E_ARG, "smoother_form must be 0 (auto), 1 (factors) or 2 (inverse)");
-    if (opt.smoother_form == HPLMM_SMOOTHER_INVERSE && h.smoother_precision != 64)
-        fail(HPLMM_E_ARG, "the inverse smoother form needs smoother_precision 64");
-    h.smoother_form = opt.smoother_form == HPLMM_SMOOTHER_AUTO
-                          ? (h.smoother_precision == 64 ? HPLMM_SMOOTHER_INVERSE : HPLMM_SMOOTHER_FACTORS)
-                          : opt.smoother_form;
+    // auto: the inverse form, except with bfloat16 storage, where rounding S
+    // itself (rather than W, whose Gram product W^T W stays definite) can
+    // leave it indefinite once kappa(A_g) exceeds about 2^8
+    h.smoother_form = opt.smoother_form != HPLMM_SMOOTHER_AUTO ? opt.smoother_form
+                      : h.smoother_precision == 16         ? HPLMM_SMOOTHER_FACTORS
+                                                           : HPLMM_SMOOTHER_INVERSE;
     if (opt.coarse_leaf_dofs < 0) fail(HPLMM_E_ARG, "coarse_leaf_dofs must be >= 0");
     h.coarse_leaf_dofs = opt.coarse_leaf_dofs > 0 ? opt.coarse_leaf_dofs : 192;
     h.n_nodes = n;
@@ -1153,7 +1154,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.gcol_len = co;
     }
     const bool lowp = h.smoother_precision != 64;
-    if (!lowp) {
+    const bool inverse = h.smoother_form == HPLMM_SMOOTHER_INVERSE;
+    // contact grids factored in FP32: the reduced-precision factor form only
+    const bool c32 = lowp && !inverse;
+    if (!c32) {
         h.cset.a_base = take64(h.cset.region);
         h.cset.w_base = take64(h.cset.region);
         h.cset.wt_base = take64(h.cset.region);
@@ -1166,8 +1170,19 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.wt_base = off32;
         off32 += h.cset.region;
     }
-    // reduced-precision smoother copies
-    if (h.smoother_precision == 32) {
+    // reduced-precision smoother copies: S of both sets (inverse form) or W
+    // and Wt (factor form)
+    if (inverse && h.smoother_precision == 32) {
+        h.gset.low_s_base = off32;
+        off32 += h.gset.region;
+        h.cset.low_s_base = off32;
+        off32 += h.cset.region;
+    } else if (inverse && h.smoother_precision == 16) {
+        h.gset.low_s_base = offbf;
+        offbf += h.gset.region;
+        h.cset.low_s_base = offbf;
+        offbf += h.cset.region;
+    } else if (h.smoother_precision == 32) {
         h.gset.low_w_base = off32;
         off32 += h.gset.region;
         h.gset.low_wt_base = off32;
@@ -1184,9 +1199,13 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.low_wt_base = offbf;
         offbf += h.cset.region;
     }
-    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+    if (inverse) {
         h.gset.s_base = take64(h.gset.region);
         h.cset.s_base = take64(h.cset.region);
+        if (!lowp) {
+            h.gset.low_s_base = h.gset.s_base;
+            h.cset.low_s_base = h.cset.s_base;
+        }
     }
     h.ar64_n = off64;
     h.ar32_n = off32;
@@ -1194,7 +1213,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.grain_region_zero_n = h.gset.region;
     // ---- task lists ---------------------------------------------------------------
     build_factor_program(h.gset, h.tl64, 0);
-    if (!lowp)
+    if (!c32)
         build_factor_program(h.cset, h.tl64, 1);
     else
         build_factor_program(h.cset, h.tl32, 1);
@@ -1211,8 +1230,8 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     // apply-time GEMV lists
     {
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
-            build_sym_gemv(h.gset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len);
-            build_sym_gemv(h.cset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len);
+            build_sym_gemv(h.gset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len, h.gset.low_s_base);
+            build_sym_gemv(h.cset, h.vtasks, h.spairs, h.rtasks, h.sym_part_len, h.cset.low_s_base);
         } else {
             const int64_t gw = lowp ? h.gset.low_w_base : h.gset.w_base;
             const int64_t gwt = lowp ? h.gset.low_wt_base : h.gset.wt_base;
@@ -1242,14 +1261,14 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.gemv_X.count = (int64_t)h.vtasks.size() - h.gemv_X.start;
     }
     split_program(h.gset.factor_prog, h.tl64);
-    split_program(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
+    split_program(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     split_program(h.basis_prog, h.tl64);
     split_program(h.gset.inverse_prog, h.tl64);
     split_program(h.cset.inverse_prog, h.tl64);
     fill_flops(h.gset.inverse_prog, h.tl64);
     fill_flops(h.cset.inverse_prog, h.tl64);
     fill_flops(h.gset.factor_prog, h.tl64);
-    fill_flops(h.cset.factor_prog, lowp ? h.tl32 : h.tl64);
+    fill_flops(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
     {
         const double ge = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
@@ -1259,7 +1278,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
         for (DenseSet *ds : {&h.gset, &h.cset}) {
             // the symmetric product reads its own x segment once more per row
-            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, 8.0) + (double)ds->gemv_S.count * TS * 8.0;
+            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, ge) + (double)ds->gemv_S.count * TS * 8.0;
             ds->red_S.bytes = sym_reduce_bytes(h.rtasks, ds->red_S);
         }
         h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
@@ -1275,7 +1294,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                         8.0 * (6.0 * h.N + 3.0 * (double)h.gset.vec_len + 2.0 * (double)h.cset.vec_len);
     }
     pad_ones(h.gset, h.pad_ones_g, h.gset.a_base);
-    pad_ones(h.cset, h.pad_ones_c, lowp ? h.c_stage_base : h.cset.a_base);
+    pad_ones(h.cset, h.pad_ones_c, c32 ? h.c_stage_base : h.cset.a_base);
     // ---- index maps ------------------------------------------------------------------
     const int64_t s_pad = h.n_mortar;   // corrections follow the mortar dofs
     h.cvec_len = s_pad + h.n_corr;
@@ -1514,7 +1533,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                     what);
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const SymPair &pr = h.spairs[(size_t)(t.pair_start + q)];
-                    chk(in(pr.t_off, TE, h.ar64_n) && in(pr.x_off, TS, ds.vec_len), what);
+                    chk(in(pr.t_off, TE, low_n) && in(pr.x_off, TS, ds.vec_len), what);
                     // the diagonal tile, last in its row, carries no transposed product
                     chk(q + 1 == t.pair_count ? pr.p_off == -1 : in(pr.p_off, TS, h.sym_part_len), what);
                 }
@@ -1659,7 +1678,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.d_pad_g = h.upload(h.pad_ones_g, s);
     // contacts
     std::vector<int64_t> caoff(h.cset.n.size());
-    for (size_t m = 0; m < h.cset.n.size(); ++m) caoff[m] = (lowp ? h.c_stage_base : h.cset.a_base) + h.cset.rel[m];
+    for (size_t m = 0; m < h.cset.n.size(); ++m) caoff[m] = (c32 ? h.c_stage_base : h.cset.a_base) + h.cset.rel[m];
     h.cg.mat_aoff = h.upload(caoff, s);
     h.cg.item_node = h.upload(item_node, s);
     h.cg.item_mat = h.upload(item_mat, s);
@@ -1711,9 +1730,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     h.tl64.d_part = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
     h.tl32.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tl32.part_len));
-    if (h.smoother_precision == 64) {
-        // the FP64 contact-grid program runs on the side stream next to the
-        // grain and coarse programs, which use tl64's scratch
+    if (h.smoother_precision == 64 || h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
+        // the FP64 contact-grid programs (and the grain inverse) run on the
+        // side stream next to the grain and coarse programs, which use tl64's
+        // scratch: the side stream needs split-task scratch of its own
         h.d_part_side = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
         h.d_cnt_side = h.dalloc<int32_t>(std::max<int32_t>(1, h.tl64.cnt_len));
         if (hipMemsetAsync(h.d_cnt_side, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.tl64.cnt_len), s) !=

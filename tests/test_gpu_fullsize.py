@@ -97,6 +97,18 @@ def test_solve_full_bf16_smoother(big):
     assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
 
 
+def test_solve_full_fp32_inverse_smoother(big):
+    # S formed in FP64 and stored in FP32 (the automatic choice at precision 32)
+    from paper_2509_19777_amd import hplmm as hp
+    p, A, b, mesh, part, S = big
+    S32 = hp.Solver(S.system, part, n_mortar=4, smoother_precision=32)
+    assert S32.smoother_form() == "inverse"
+    S32.setup()
+    x, info = S32.solve(rtol=1e-8, restart=50, maxit=300)
+    assert info["status"] == "OK"
+    assert np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b) < 1e-8
+
+
 def test_autotuned_solve_full(big):
     # the shapes the autotuner picks at full size solve to the same bar, and
     # M^-1 agrees with the default shapes to rounding

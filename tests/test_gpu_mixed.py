@@ -1,13 +1,18 @@
-"""Reduced-precision smoother on the GPU against the oracle's emulation.
+"""Reduced-precision smoother on the GPU against the oracle's emulation, in
+both smoother forms.
 
-Grain smoother operators are the FP64 inverse Cholesky factors rounded to the
-storage precision, so the GPU and the oracle store identical values up to
-rare rounding-boundary cases; contact-grid factors are computed in FP32 on
-both sides (matrix cores vs LAPACK), which differ by about kappa(A_zeta) u32.
-Bounds: M_g (grains only) 1e-12 relative; operators involving the FP32
-contact factorisation 3e-5 (FP32 storage) and 3e-3 (BF16 storage), measured
-on the 16^3 pore case whose local condition numbers are about 1e3.  FGMRES
-itself stays FP64 and must reach the 1e-8 true residual.
+Factor form: grain smoother operators are the FP64 inverse Cholesky factors
+rounded to the storage precision, so the GPU and the oracle store identical
+values up to rare rounding-boundary cases; contact-grid factors are computed
+in FP32 on both sides (matrix cores vs LAPACK), which differ by about
+kappa(A_zeta) u32.  Bounds: M_g (grains only) 1e-12 relative; operators
+involving the FP32 contact factorisation 3e-5 (FP32 storage) and 3e-3 (BF16
+storage), measured on the 16^3 pore case whose local condition numbers are
+about 1e3.
+Inverse form: every block's S = W^T W is formed in FP64 and rounded once, on
+both sides, so every operator meets 1e-12 against the emulation (again up to
+rare rounding-boundary cases).
+FGMRES itself stays FP64 and must reach the 1e-8 true residual.
 """
 import numpy as np
 import pytest
@@ -17,20 +22,22 @@ from paper_2509_19777_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-@pytest.fixture(scope="module", params=[32, 16])
+@pytest.fixture(scope="module", params=[(32, "factors"), (16, "factors"), (32, "inverse"), (16, "inverse")])
 def mixed(request):
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from oracle import fem, hplmm as oh
     from paper_2509_19777_amd import hplmm as hp
-    prec = request.param
+    prec, form = request.param
     p = synth.config_pores(16, 4, seed=1)
     A, b, mesh = fem.assemble(p)
-    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=2, smoother_precision="f32" if prec == 32 else "bf16")
+    H = oh.HPLMM(p, A=A, b=b, mesh=mesh, n=2, smoother_precision="f32" if prec == 32 else "bf16",
+                 smoother_form=form)
     sysm, part = hp.build_problem(p)
-    S = hp.Solver(sysm, part, n_mortar=2, smoother_precision=prec)
+    S = hp.Solver(sysm, part, n_mortar=2, smoother_precision=prec, smoother_form=form)
     S.setup()
+    assert S.smoother_form() == form
     return prec, p, A, b, H, S
 
 
@@ -50,7 +57,7 @@ def test_grain_smoother_matches_emulation(mixed):
 def test_full_apply_matches_emulation(mixed):
     import torch
     prec, p, A, b, H, S = mixed
-    tol = 3e-5 if prec == 32 else 3e-3
+    tol = 1e-12 if S.smoother_form() == "inverse" else (3e-5 if prec == 32 else 3e-3)
     for which, op in ((3, H.apply_Mzeta), (2, H.apply_MCG), (0, H.apply)):
         r = synth.random_vector(A.shape[0], 12)
         z = S.apply(torch.from_numpy(r).cuda(), which).cpu().numpy()

@@ -101,10 +101,11 @@ def test_profiler_sees_one_pass_and_the_sums(pair):
     assert ib < fb
 
 
-def test_inverse_form_needs_float64():
+def test_auto_form_by_precision():
+    # bfloat16 keeps the factor form: rounding S itself can leave it indefinite
     _torch()
     from paper_2509_19777_amd import hplmm as hp
     p = synth.config_pores(12, 4, seed=3)
     sysm, part = hp.build_problem(p)
-    with pytest.raises(hp.HplmmError):
-        hp.Solver(sysm, part, n_mortar=2, smoother_precision=32, smoother_form="inverse")
+    for prec, form in ((64, "inverse"), (32, "inverse"), (16, "factors")):
+        assert hp.Solver(sysm, part, n_mortar=2, smoother_precision=prec).smoother_form() == form
