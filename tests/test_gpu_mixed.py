@@ -70,3 +70,24 @@ def test_fgmres_reaches_fp64_tolerance(mixed):
     assert info["status"] == "OK"
     xg = x.cpu().numpy()
     assert np.linalg.norm(b - A @ xg) / np.linalg.norm(b) < 1e-8
+
+
+def test_every_launch_shape_matches_emulation(mixed):
+    # the smoother launches at 16 waves per work-group (narrow storage runs
+    # its symmetric kernel at 4) and the autotuner's own choices keep the bars
+    import torch
+    prec, p, A, b, H, S = mixed
+    r = synth.random_vector(A.shape[0], 13)
+    z0 = S.apply(torch.from_numpy(r).cuda(), 0).cpu().numpy()
+    levels = S.sizes()["coarse_levels"]
+    n_sets = 4 if S.smoother_form() == "inverse" else 6
+    S.set_tuning([{"kind": 2, "index": i, "variant": 0, "waves": 16} for i in range(n_sets)] +
+                 [{"kind": k, "index": l, "variant": 0, "waves": 16} for k in (0, 1) for l in range(levels)])
+    z16 = S.apply(torch.from_numpy(r).cuda(), 0).cpu().numpy()
+    S.autotune(reps=2)
+    za = S.apply(torch.from_numpy(r).cuda(), 0).cpu().numpy()
+    S.set_tuning([])
+    tol = 1e-12 if S.smoother_form() == "inverse" else (3e-5 if prec == 32 else 3e-3)
+    for z in (z16, za):
+        assert _rel(z, H.apply(r)) <= tol
+        assert _rel(z, z0) <= 1e-13
