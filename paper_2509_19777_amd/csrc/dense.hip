@@ -483,7 +483,10 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
 // over the LPC lanes of a group; it is formed per chunk of 8 columns per
 // lane: a reduce-scatter over the top three bits of l % LPC (8 -> 4 -> 2 -> 1
 // values per lane) and a butterfly over the remaining low bits leave lane l
-// with column u = 4 b2 + 2 b1 + b0 of the chunk (b2 b1 b0 those three bits).
+// with column u = 4 b2 + 2 b1 + b0 of the chunk (b2 b1 b0 those three bits),
+// replicated over those low bits.  The chunk count equals the number of such
+// replicas, so the lane whose low bits equal the chunk keeps its value, and
+// one store per tile with every lane active writes the tile's 64 slot values.
 template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__ arena,
                                                            const double *__restrict__ x, double *__restrict__ y,
@@ -511,6 +514,7 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
         const T *tile = arena + pr.t_off;
         const double *xs = x + pr.x_off;
         const bool below = pr.p_off >= 0;
+        double mine = 0.0;   // this lane's slot value (the chunk given by its low bits)
 #pragma unroll 1
         for (int ch = 0; ch < NCH; ++ch) {
             double cs[8];
@@ -541,9 +545,11 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
                 double t = (b0 ? t3[1] : t3[0]) + __shfl_xor(b0 ? t3[0] : t3[1], H0);
 #pragma unroll
                 for (int m = H0 / 2; m >= 1; m /= 2) t += __shfl_xor(t, m);
-                if ((lc & (H0 - 1)) == 0) part[pr.p_off + R * (8 * ch + uq) + phase] = t;
+                if ((lc & (H0 - 1)) == ch) mine = t;
             }
         }
+        // one store per tile with every lane active
+        if (below) part[pr.p_off + R * (8 * (lc & (H0 - 1)) + uq) + phase] = mine;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) red[(wave * R + phase) * TS + row0 + r] = acc[r];
