@@ -162,9 +162,17 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         return;
     }
     run_program<double>(h, h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
+    if (stage < 2) {
+        hip_check(hipStreamSynchronize(s), "stage");
+        return;
+    }
+    if (sg)
+        surrogate_basis(h, *sg, s);
+    else
+        run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
     if (fork) {
         // the grain inverse S = W^T W follows the contact grids on the side
-        // stream, beside the basis and the coarse operator on s
+        // stream, beside the coarse operator on s
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
             if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
             hip_check(hipEventRecord(ev[4], s), "event");
@@ -175,14 +183,6 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         }
         hip_check(hipEventRecord(h.side_ev[2], h.side), "event");
     }
-    if (stage < 2) {
-        hip_check(hipStreamSynchronize(s), "stage");
-        return;
-    }
-    if (sg)
-        surrogate_basis(h, *sg, s);
-    else
-        run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
     if (stage < 3) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -298,7 +298,7 @@ static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
     sg_build_sample_tables(h, s);
     int64_t rlen = 0;
     for (int64_t m = 0; m < nG; ++m) rlen += h.gset.nt[m] * h.gm_ntc[(size_t)m] * TE;
-    const int64_t r_base = h.gm_roff[0], y_base = h.gm_ytoff[0], xt_base = h.gm_xtoff[0];
+    const int64_t r_base = h.gm_roff[0], xt_base = h.gm_xtoff[0];
     double *A = h.ar64;
     hip_check(hipMemcpyAsync(A + xt_base, A + r_base, sizeof(double) * (size_t)rlen, hipMemcpyDeviceToDevice, s),
               "save R0");
