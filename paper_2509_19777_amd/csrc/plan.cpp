@@ -167,6 +167,9 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
             if (own(m) > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0});
         d.count = (int64_t)tl.diag.size() - d.start;
         prog.push_back(d);
+        // the panel, and in the same launch row k of W = L^-1:
+        // W_kj = -W_kk sum_{q=j}^{k-1} L_kq W_qj, j < k, which reads rows of L
+        // and W finished in earlier steps and the W_kk just formed
         Launch p{LK_GEMM, (int64_t)tl.gemm.size(), 0};
         for (int64_t m = 0; m < nm; ++m) {
             if (own(m) <= k) continue;
@@ -174,6 +177,11 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
                 tl.gemm.push_back({A(m, i, k), Wt(m, k, k), (int32_t)tl.pairs.size(), (int32_t)k,
                                    GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST_RIGHT, 0});
                 for (int64_t q = 0; q < k; ++q) tl.pairs.push_back({A(m, i, q), A(m, k, q)});
+            }
+            for (int64_t j = 0; j < k; ++j) {
+                tl.gemm.push_back({W(m, k, j), W(m, k, k), (int32_t)tl.pairs.size(), (int32_t)(k - j),
+                                   GF_POST | GF_NEGATE, 0});
+                for (int64_t q = j; q < k; ++q) tl.pairs.push_back({A(m, k, q), W(m, q, j)});
             }
         }
         p.count = (int64_t)tl.gemm.size() - p.start;
@@ -195,18 +203,6 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         }
         u.count = (int64_t)tl.gemm.size() - u.start;
         if (u.count) prog.push_back(u);
-    }
-    // W_ij = -W_ii sum_{k=j}^{i-1} L_ik W_kj, computed for i - j = 1, 2, ...
-    for (int64_t d = 1; d < maxk; ++d) {
-        Launch t{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-        for (int64_t m = 0; m < nm; ++m)
-            for (int64_t j = 0; j + d < own(m); ++j) {
-                const int64_t i = j + d;
-                tl.gemm.push_back({W(m, i, j), W(m, i, i), (int32_t)tl.pairs.size(), (int32_t)d, GF_POST | GF_NEGATE, 0});
-                for (int64_t k = j; k < i; ++k) tl.pairs.push_back({A(m, i, k), W(m, k, j)});
-            }
-        t.count = (int64_t)tl.gemm.size() - t.start;
-        if (t.count) prog.push_back(t);
     }
     Launch c{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
     for (int64_t m = 0; m < nm; ++m)
