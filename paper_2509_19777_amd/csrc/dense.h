@@ -53,13 +53,16 @@ struct GemmPair {
 };
 
 // Diagonal-tile factorisation: A(a_off) = L L^T in place (upper part zeroed),
-// W(w_off) = L^-1, Wt(wt_off) = L^-T.  `id` is reported on a bad pivot.
+// W(w_off) = L^-1, Wt(wt_off) = L^-T.  `id` is reported on a bad pivot.  With
+// p_off >= 0 the tile P at p_off is first subtracted as A -= P P^T (the last
+// term of a left-looking diagonal update).
 struct DiagTask {
     int64_t a_off;
     int64_t w_off;
     int64_t wt_off;
     int32_t id;
     int32_t pad;
+    int64_t p_off = -1;
 };
 
 // Tiled matrix-vector product: y[y_off .. +64) = [base[base_off .. +64) +] sum_p T_p x[x_off_p .. +64)

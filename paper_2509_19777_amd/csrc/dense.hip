@@ -344,6 +344,24 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
         Lr[k] = r >= c ? a[c * TS + r] : T(0);
         Vr[k] = r == c ? T(1) : T(0);
     }
+    if (tk.p_off >= 0) {
+        // A -= P P^T: P staged column by column in LDS; a wave's 16 columns
+        // c = q + 4k read the same LDS words on every lane (broadcast)
+        const T *pp = A + tk.p_off;
+        for (int e = threadIdx.x; e < TE; e += 256) S[(e >> 6) * LD + (e & (TS - 1))] = pp[e];
+        __syncthreads();
+        T acc[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc[k] = T(0);
+        for (int p = 0; p < TS; ++p) {
+            const T prp = S[p * LD + r];
+#pragma unroll
+            for (int k = 0; k < 16; ++k) acc[k] += prp * S[p * LD + q + 4 * k];
+        }
+#pragma unroll
+        for (int k = 0; k < 16; ++k)
+            if (r >= q + 4 * k) Lr[k] -= acc[k];
+    }
     bool bad = false;
     DiagStep<T, 0>::run(Lr, Vr, colL, colV, r, q, bad);
     // L and W^T = V are stored with coalesced writes; W goes through LDS

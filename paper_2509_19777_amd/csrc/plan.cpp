@@ -147,29 +147,21 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
     auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto id = [&](int64_t m) { return (int32_t)(set_id * (1 << 26) + (ids ? (*ids)[m] : m)); };
-    // Left-looking tile Cholesky: step k first subtracts the finished columns
-    // p < k from the diagonal tile, factors it, then forms the panel
-    // L_ik = (A_ik - sum_p L_ip L_kp^T) L_kk^-T in one task per tile.
+    // Left-looking tile Cholesky, two launches per step k: the diagonal tile
+    // A_kk - sum_{p<k} L_kp L_kp^T is factored (the diagonal kernel subtracts
+    // the last term, p = k - 1, itself), then the panel
+    // L_ik = (A_ik - sum_p L_ip L_kp^T) L_kk^-T is formed in one task per tile.
     for (int64_t k = 0; k < maxk; ++k) {
-        if (k > 0) {
-            Launch u{LK_GEMM, (int64_t)tl.gemm.size(), 0};
-            for (int64_t m = 0; m < nm; ++m) {
-                if (own(m) <= k) continue;
-                tl.gemm.push_back({A(m, k, k), -1, (int32_t)tl.pairs.size(), (int32_t)k,
-                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
-                for (int64_t p = 0; p < k; ++p) tl.pairs.push_back({A(m, k, p), A(m, k, p)});
-            }
-            u.count = (int64_t)tl.gemm.size() - u.start;
-            if (u.count) prog.push_back(u);
-        }
         Launch d{LK_DIAG, (int64_t)tl.diag.size(), 0};
         for (int64_t m = 0; m < nm; ++m)
-            if (own(m) > k) tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0});
+            if (own(m) > k)
+                tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0, k > 0 ? A(m, k, k - 1) : -1});
         d.count = (int64_t)tl.diag.size() - d.start;
         prog.push_back(d);
         // the panel, and in the same launch row k of W = L^-1:
         // W_kj = -W_kk sum_{q=j}^{k-1} L_kq W_qj, j < k, which reads rows of L
-        // and W finished in earlier steps and the W_kk just formed
+        // and W finished in earlier steps and the W_kk just formed, and the
+        // terms p < k of the next diagonal tile's update
         Launch p{LK_GEMM, (int64_t)tl.gemm.size(), 0};
         for (int64_t m = 0; m < nm; ++m) {
             if (own(m) <= k) continue;
@@ -182,6 +174,11 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
                 tl.gemm.push_back({W(m, k, j), W(m, k, k), (int32_t)tl.pairs.size(), (int32_t)(k - j),
                                    GF_POST | GF_NEGATE, 0});
                 for (int64_t q = j; q < k; ++q) tl.pairs.push_back({A(m, k, q), W(m, q, j)});
+            }
+            if (k > 0 && k + 1 < own(m)) {
+                tl.gemm.push_back({A(m, k + 1, k + 1), -1, (int32_t)tl.pairs.size(), (int32_t)k,
+                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
+                for (int64_t q = 0; q < k; ++q) tl.pairs.push_back({A(m, k + 1, q), A(m, k + 1, q)});
             }
         }
         p.count = (int64_t)tl.gemm.size() - p.start;
@@ -1493,7 +1490,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                     chk(t.nchunk == 1 && t.chunk == 0, "gemm task");
             }
             for (const auto &pr : tl.pairs) chk(in(pr.a_off, TE, an) && in(pr.b_off, TE, an), "gemm operand tile");
-            for (const auto &d : tl.diag) chk(in(d.a_off, TE, an) && in(d.w_off, TE, an) && in(d.wt_off, TE, an), "diag tile");
+            for (const auto &d : tl.diag)
+                chk(in(d.a_off, TE, an) && in(d.w_off, TE, an) && in(d.wt_off, TE, an) && (d.p_off < 0 || in(d.p_off, TE, an)),
+                    "diag tile");
             for (const auto &c : tl.copy) chk(in(c.src_off, TE, an) && in(c.dst_off, TE, an), "transpose tile");
         }
         const int64_t low_n = h.smoother_precision == 32 ? h.ar32_n : (h.smoother_precision == 16 ? h.arbf_n : h.ar64_n);
