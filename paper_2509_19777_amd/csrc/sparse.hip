@@ -469,7 +469,7 @@ void launch_convert_f64_bf16(const double *src, uint16_t *dst, int64_t n, hipStr
 // base + t + 256 r.  Partial sums are reduced in a fixed order (per thread,
 // wave butterfly, waves 0..3, then blocks in the reduction kernel), so the
 // results are bitwise reproducible.
-constexpr int KR_ROWS = 4;
+constexpr int KR_ROWS = 2;
 constexpr int KR_MAXK = 128;
 
 int32_t multidot_blocks(int64_t n) {
