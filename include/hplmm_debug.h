@@ -26,10 +26,12 @@ extern "C" {
 hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A_dev, const void *B_dev, int32_t npairs,
                                    const void *P_dev, void *C_dev, int32_t flags, void *stream);
 
-/* One diagonal-tile factorisation: A_dev (64x64 column-major, SPD; lower part
- * read) is overwritten by its Cholesky factor L (zeros above), W_dev gets
- * L^-1 and Wt_dev gets L^-T.  Returns HPLMM_E_NOT_SPD on a bad pivot. */
-hplmm_status hplmm_debug_diag(int32_t precision, void *A_dev, void *W_dev, void *Wt_dev, void *stream);
+/* One diagonal-tile factorisation: A_dev (64x64 column-major; lower part
+ * read) is overwritten by the Cholesky factor L of A - P P^T (zeros above),
+ * W_dev gets L^-1 and Wt_dev gets L^-T.  P_dev is one 64x64 column-major tile
+ * or NULL (then P = 0).  Returns HPLMM_E_NOT_SPD on a bad pivot. */
+hplmm_status hplmm_debug_diag(int32_t precision, void *A_dev, const void *P_dev, void *W_dev, void *Wt_dev,
+                              void *stream);
 
 /* Run the numeric set-up of a planned handle up to a stage and stop:
  *   stage 0: zero and gather grain blocks, coupling blocks and loads

@@ -1307,16 +1307,17 @@ extern "C" hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A, 
     });
 }
 
-extern "C" hplmm_status hplmm_debug_diag(int32_t precision, void *A, void *W, void *Wt, void *stream) {
+extern "C" hplmm_status hplmm_debug_diag(int32_t precision, void *A, const void *P, void *W, void *Wt, void *stream) {
     return guarded([&]() -> hplmm_status {
         if (!A || !W || !Wt || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
         hipStream_t s = as_stream(stream);
         const size_t es = precision == 64 ? 8 : 4;
         void *ar = nullptr;
-        hip_check(hipMalloc(&ar, es * 3 * TE), "hipMalloc");
+        hip_check(hipMalloc(&ar, es * 4 * TE), "hipMalloc");
         char *base = (char *)ar;
         hip_check(hipMemcpyAsync(base, A, es * TE, hipMemcpyDeviceToDevice, s), "copy");
-        DiagTask t{0, TE, 2 * TE, 7, 0};
+        if (P) hip_check(hipMemcpyAsync(base + es * 3 * TE, P, es * TE, hipMemcpyDeviceToDevice, s), "copy");
+        DiagTask t{0, TE, 2 * TE, 7, 0, P ? 3 * TE : -1};
         DiagTask *dt = nullptr;
         int32_t *flag = nullptr;
         hip_check(hipMalloc(&dt, sizeof(t)), "hipMalloc");

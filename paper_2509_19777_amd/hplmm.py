@@ -79,7 +79,7 @@ EXPORTS = {
     "hplmm_autotune": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_set_tuning": (i32, [C.c_void_p, C.c_void_p, i64]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
-    "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_read_arena": (i32, [C.c_void_p, i32, i64, i64, C.c_void_p]),
     "hplmm_debug_grain_layout": (i32, [C.c_void_p, P(i64), i64]),
@@ -449,11 +449,13 @@ def debug_tile_gemm(A, B, C_, flags, P_=None, npairs=None):
     _check(lib().hplmm_debug_tile_gemm(prec, _vp(A), _vp(B), n, _vp(P_), _vp(C_), int(flags), _stream()))
 
 
-def debug_diag(A):
+def debug_diag(A, P=None):
     prec = 64 if A.dtype == torch.float64 else 32
+    if P is not None and (P.dtype != A.dtype or P.numel() != A.numel() or not P.is_contiguous()):
+        raise ValueError("P must be one contiguous tile of A's type")
     W = torch.empty_like(A)
     Wt = torch.empty_like(A)
-    _check(lib().hplmm_debug_diag(prec, _vp(A), _vp(W), _vp(Wt), _stream()))
+    _check(lib().hplmm_debug_diag(prec, _vp(A), _vp(P), _vp(W), _vp(Wt), _stream()))
     return A, W, Wt
 
 

@@ -79,6 +79,27 @@ def test_diag_factor_and_inverse(prec):
     assert np.array_equal(_untile(Wt), _untile(W).T)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+def test_diag_subtracts_panel_term(prec):
+    # the last term of a left-looking diagonal update: factor of A - P P^T
+    torch = _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    dt = torch.float64 if prec == 64 else torch.float32
+    rng = np.random.default_rng(5)
+    M = rng.standard_normal((TS, TS))
+    S = M @ M.T + TS * np.eye(TS)
+    P = rng.standard_normal((TS, TS))
+    At = _tiles((S + P @ P.T)[None], dt)[0].contiguous()
+    Pt = _tiles(P[None], dt)[0].contiguous()
+    L, W, Wt = hp.debug_diag(At, Pt)
+    Lr = np.linalg.cholesky(S)
+    tol = 1e-12 if prec == 64 else 1e-4
+    assert np.abs(_untile(L) - Lr).max() <= tol * np.abs(Lr).max()
+    Wr = np.linalg.inv(Lr)
+    assert np.abs(_untile(W) - Wr).max() <= tol * 10 * np.abs(Wr).max()
+    assert np.array_equal(_untile(Wt), _untile(W).T)
+
+
 def test_diag_reports_indefinite():
     torch = _torch()
     from paper_2509_19777_amd import hplmm as hp
