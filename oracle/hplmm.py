@@ -258,3 +258,41 @@ class HPLMM:
             s = np.linalg.svd(L, compute_uv=False)
             k = max(k, (s[0] / s[-1]) ** 2)
         return k
+
+
+class LocalSmoothers:
+    """The two additive-Schwarz sums of Eq. (26) and their composition
+    Eq. (25), without the coarse space: grain interiors (R4) and contact grids
+    (R5) classified and factored exactly as in HPLMM, so that the smoother of
+    a problem too large for the dense coarse factor can still be checked
+    block by block.  FP64 only."""
+
+    def __init__(self, problem, A, mesh, w_zeta=None):
+        self.A = A.tocsr()
+        w = problem.w_zeta if w_zeta is None else w_zeta
+        P = part_mod.classify(problem, mesh)
+        part_mod.contact_grids(P, mesh, w)
+        self.part = P
+        self.grain_dofs = [_dofs(nodes) for nodes in P.grain_nodes]
+        self.contact_dofs = [_dofs(nodes) for nodes in P.contact_nodes]
+        self.grain_chol = [sla.cho_factor(self.A[d][:, d].toarray(), lower=True) if d.size else None
+                           for d in self.grain_dofs]
+        self.contact_chol = [sla.cho_factor(self.A[d][:, d].toarray(), lower=True) for d in self.contact_dofs]
+
+    def apply_Mg(self, r):
+        z = np.zeros_like(r)
+        for dofs, ch in zip(self.grain_dofs, self.grain_chol):
+            if ch is not None:
+                z[dofs] = sla.cho_solve(ch, r[dofs])
+        return z
+
+    def apply_Mzeta(self, r):
+        z = np.zeros_like(r)
+        for dofs, ch in zip(self.contact_dofs, self.contact_chol):
+            z[dofs] += sla.cho_solve(ch, r[dofs])
+        return z
+
+    def apply_MCG(self, r):
+        z2 = self.apply_Mzeta(r)
+        return z2 + self.apply_Mg(r - self.A @ z2)
+

@@ -202,3 +202,27 @@ def test_coarse_literal_triple_product(tiny):
     Ph = W @ H.Q.toarray() @ H.Pr.toarray()
     Ac = Ph.T @ A.toarray() @ Ph
     assert np.allclose(Ac, H.Acoarse, rtol=0, atol=1e-13 * abs(Ac).max())
+
+
+def test_local_smoothers_without_coarse_space(tiny, small):
+    """LocalSmoothers (the smoother alone, for full-size checks) against the
+    literal Eq. (26) sums with explicit 0/1 restrictions on the tiny case, and
+    against the full preconditioner's smoother on the small one."""
+    p, A, b, mesh, H = tiny
+    L = hplmm.LocalSmoothers(p, A, mesh)
+    Ad = A.toarray()
+    N = Ad.shape[0]
+    r = np.random.default_rng(5).standard_normal(N)
+    for blocks, op in ((L.grain_dofs, L.apply_Mg), (L.contact_dofs, L.apply_Mzeta)):
+        M = np.zeros((N, N))
+        for d in blocks:
+            if d.size:
+                R = np.zeros((d.size, N))
+                R[np.arange(d.size), d] = 1.0
+                M += R.T @ np.linalg.inv(R @ Ad @ R.T) @ R
+        assert np.allclose(op(r), M @ r, rtol=0, atol=1e-10 * np.abs(M @ r).max())
+    p, A, b, mesh, H = small
+    L = hplmm.LocalSmoothers(p, A, mesh)
+    r = np.random.default_rng(6).standard_normal(A.shape[0])
+    for a, c in ((L.apply_Mg, H.apply_Mg), (L.apply_Mzeta, H.apply_Mzeta), (L.apply_MCG, H.apply_MCG)):
+        assert np.array_equal(a(r), c(r))
