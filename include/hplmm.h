@@ -218,6 +218,27 @@ hplmm_status hplmm_setup(hplmm_handle *h, void *stream);
 hplmm_status hplmm_apply(hplmm_handle *h, int32_t which, const double *r_dev,
                          double *z_dev, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * z = Op r as hplmm_apply (same which, same kernels, same results bit for
+ * bit), but the application's scratch -- the partial sums and arrival
+ * counters of the coarse sweeps' split rows -- is taken from a static 8 MiB
+ * device buffer of the library instead of the handle's, and the call
+ * allocates nothing: no device memory, no events (the built-in profiler does
+ * not see its launches).  The counters are cleared by a kernel at the start
+ * of every call.  Each device holds one such buffer until the process ends,
+ * shared by every call on that device: calls that overlap on one device (two
+ * streams, two threads, two handles) race and must be ordered by the caller.
+ * The other per-handle buffers (local vectors, the symmetric smoother's
+ * per-tile sums) are the handle's, allocated by hplmm_plan, as for
+ * hplmm_apply.  Errors: E_ARG for NULL or aliased vectors, which outside
+ * 0..4, a handle planned on another device than the current one, or a plan
+ * whose split rows need more than the buffer (the message gives the bytes);
+ * E_STATE before set-up.  Query 12 gives the split-row scratch a plan needs:
+ * int64[2] = {partial sums (doubles), counters (int32)}. */
+hplmm_status hplmm_apply_noalloc(hplmm_handle *h, int32_t which, const double *r_dev, double *z_dev,
+                                 void *stream);
+
 /* y = A x (device vectors, must not alias).  Asynchronous. */
 hplmm_status hplmm_spmv(hplmm_handle *h, const double *x_dev, double *y_dev, void *stream);
 
@@ -274,6 +295,8 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *            contact W^T, X^T, X in the factor form and grain S, contact S,
  *            X^T, X in the inverse form
  *  11 smoother form in use: int32[1] (HPLMM_SMOOTHER_FACTORS or _INVERSE)
+ *  12 split-row scratch of the coarse sweeps: int64[2] = {partial sums
+ *            (doubles), arrival counters (int32)}
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);

@@ -19,7 +19,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(LIBDIR, "libhplmm.so")
 ARCH = "gfx950"
 
-DEVICE_SOURCES = ["dense.hip", "sparse.hip", "surrogate.hip", "post.hip"]
+DEVICE_SOURCES = ["dense.hip", "sparse.hip", "surrogate.hip", "post.hip", "noalloc.hip"]
 HOST_SOURCES = ["host_problem.cpp", "plan.cpp", "capi.cpp", "sg_capi.cpp", "post_capi.cpp"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]

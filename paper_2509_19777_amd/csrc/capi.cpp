@@ -483,10 +483,14 @@ static void gemv_set(Handle &h, const Range &r, bool smoother_low, const double 
 }
 
 // Front sweeps: few long rows per launch, split over many work-groups.
+// Split rows use the handle's partial sums and counters, or the caller's
+// (split_part / split_cnt, set by the allocation-free entry point).
 static void gemv_front(Handle &h, const Range &r, hipStream_t s) {
     if (r.count == 0) return;
+    double *part = h.split_part ? h.split_part : h.d_gemv_part;
+    int32_t *cnt = h.split_cnt ? h.split_cnt : h.d_gemv_cnt;
     launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, r.waves,
-                        h.d_gemv_part, h.d_gemv_cnt);
+                        part, cnt);
 }
 
 // u = S^-1 f for the mortar block of the coarse operator with the
@@ -552,7 +556,7 @@ static void coarse_apply(Handle &h, const double *r, double *z, hipStream_t s) {
     launch_prolong_nodes(h.cm, h.n_nodes, h.d_g_dof_slot, h.gy, h.su, z, s);
 }
 
-static void apply_op(Handle &h, int32_t which, const double *r, double *z, hipStream_t s) {
+void apply_op(Handle &h, int32_t which, const double *r, double *z, hipStream_t s) {
     const int64_t N = h.N;
     ProfScope ps(h, PC_APPLY, which == 0 ? h.apply_bytes : 0.0, s);
     switch (which) {
@@ -773,6 +777,7 @@ extern "C" hplmm_status hplmm_plan(const hplmm_system *sys, const hplmm_partitio
         try {
             hh->h.device = dev;
             build_plan(hh->h, *sys, *part, *mortar, o, as_stream(stream), false);
+            (void)static_scratch_address(dev);   // the allocation-free entry point's buffer on this device
         } catch (...) {
             delete hh;
             throw;
@@ -1238,6 +1243,11 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 break;
             }
             case 11: put(&h.smoother_form, sizeof(int32_t)); break;
+            case 12: {
+                const int64_t v[2] = {h.gemv_part_len, (int64_t)h.gemv_cnt_len};
+                put(v, sizeof(v));
+                break;
+            }
             default: fail(HPLMM_E_ARG, "unknown query");
         }
         if (needed) *needed = (int64_t)buf.size();

@@ -249,6 +249,10 @@ struct Handle {
     int32_t gemv_cnt_len = 0;           // split-row arrival counters
     double *d_gemv_part = nullptr;
     int32_t *d_gemv_cnt = nullptr;
+    // when set, the coarse sweeps' split rows use these instead of
+    // d_gemv_part / d_gemv_cnt (the allocation-free application)
+    double *split_part = nullptr;
+    int32_t *split_cnt = nullptr;
     GemvPair *d_vpairs = nullptr;
     std::vector<GemvTask> vtasks;
     std::vector<GemvPair> vpairs;
@@ -348,6 +352,11 @@ void split_program(std::vector<Launch> &prog, TaskLists &tl);
 void fill_flops(std::vector<Launch> &prog, const TaskLists &tl);
 // sg_capi.cpp
 void sg_build_sample_tables(Handle &h, hipStream_t s);
+// capi.cpp: the preconditioner application behind hplmm_apply
+void apply_op(Handle &h, int32_t which, const double *r, double *z, hipStream_t s);
+// noalloc.hip: device address of the library's static split-row scratch on
+// device dev, which must be current (resolved once per device)
+void *static_scratch_address(int dev);
 
 }  // namespace hplmm
 

@@ -67,6 +67,7 @@ EXPORTS = {
     "hplmm_plan_check": (i32, [P(HplmmSystem), P(HplmmPartition), P(HplmmMortar), P(HplmmOptions), P(i64)]),
     "hplmm_setup": (i32, [C.c_void_p, C.c_void_p]),
     "hplmm_apply": (i32, [C.c_void_p, i32, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_apply_noalloc": (i32, [C.c_void_p, i32, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_spmv": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "hplmm_solve": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, f64, i32, i32, i32, P(HplmmSolveInfo),
                           C.c_void_p]),
@@ -375,6 +376,19 @@ class Solver:
         z = torch.empty_like(r) if out is None else out
         _check(lib().hplmm_apply(self.h, int(which), _dptr(r), _dptr(z), _stream()))
         return z
+
+    def apply_noalloc(self, r, which=0, out=None):
+        """hplmm_apply_noalloc: the same application with the library's static
+        split-row scratch; allocates nothing in the library (out must be given
+        for an allocation-free call from Python)."""
+        z = torch.empty_like(r) if out is None else out
+        _check(lib().hplmm_apply_noalloc(self.h, int(which), _dptr(r), _dptr(z), _stream()))
+        return z
+
+    def split_scratch(self):
+        """(partial sums in doubles, arrival counters) the coarse sweeps' split rows need."""
+        v = self.query(12, np.int64)
+        return int(v[0]), int(v[1])
 
     def spmv(self, x, out=None):
         y = torch.empty_like(x) if out is None else out
