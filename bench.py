@@ -61,6 +61,9 @@ def parse():
     ap.add_argument("--autotune-reps", type=int, default=3,
                     help="launch-shape autotuning after the warm-up steps, untimed (0: default shapes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="no GPU: time the oracle on the whole workload and print one JSON line")
+    ap.add_argument("--cpu-threads", type=int, default=0, help="--cpu-full: BLAS threads (0: as configured)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (counter calibration)")
     return ap.parse_args()
@@ -68,6 +71,9 @@ def parse():
 
 def main():
     a = parse()
+    if a.cpu_full:
+        cpu_full(a)
+        return
     if a.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -125,11 +131,18 @@ def main():
     names = dict(KERNEL_NAMES)
     if S.smoother_form() == "inverse":
         names["gemv_smoother"] = SYM_SMOOTHER_NAME
-    kclasses = [k for k in names if prof_all[k]["launches"] > 0]
-    dom = max(kclasses, key=lambda k: prof_all[k]["ms"])
-    second = max((k for k in kclasses if k != dom), key=lambda k: prof_all[k]["ms"], default=None)
+    meth = S.method_work()
+    # the set-up's dense factorisation work runs in two kernels (the tile
+    # contractions and the diagonal-tile factorisations): one roofline class
+    cls_ms = {k: v for k, v in
+              [("setup_dense", prof_all["tile_gemm"]["ms"] + prof_all["diag"]["ms"])] +
+              [(k, prof_all[k]["ms"]) for k in ("gemv_smoother", "gemv_coarse", "gemv_basis", "spmv")]
+              if v > 0}
+    ranked = sorted(cls_ms, key=lambda k: -cls_ms[k])
+    dom = ranked[0]
+    second = ranked[1] if len(ranked) > 1 else None
     # timed region: the dominant class timed live with HIP events on its stream
-    S.profile([dom])
+    S.profile(CLASS_KERNELS.get(dom, [dom]))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     infos = []
@@ -151,24 +164,13 @@ def main():
     ms_unprof = (time.perf_counter() - t3) * 1e3 / a.steps
     print(f"# step {ms:.1f} ms, iters {infos[-1]['iters']}, rel_res {infos[-1]['rel_res']:.2e}, "
           f"setup {setup_ms}", file=sys.stderr, flush=True)
-    # roofline of the dominant kernel class over the timed region
-    d = prof[dom]
-    if dom == "tile_gemm":
-        ach = d["units"] / (d["ms"] * 1e-3) / 1e12
-        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(ach / FP64_MFMA_TFLOPS, 4)}
-    else:
-        ach = d["units"] / (d["ms"] * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(ach / HBM_PEAK_GBS, 4)}
-    roof.update({"kernel": names[dom], "launches": d["launches"], "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 3),
-                 "units_per_launch": d["units"] / d["launches"],
-                 "traffic": traffic_for(dom + "_inverse" if dom == "gemv_smoother" and S.smoother_form() == "inverse"
-                                        else dom)})
+    roof = class_roofline(dom, prof, meth, a.steps, S, names)
+    apply_gbs = (meth["apply_bytes"]["total"] * prof_all["apply"]["launches"] / (prof_all["apply"]["ms"] * 1e-3) / 1e9
+                 if prof_all["apply"]["ms"] else None)
     spmv_gbs = prof_all["spmv"]["units"] / (prof_all["spmv"]["ms"] * 1e-3) / 1e9 if prof_all["spmv"]["ms"] else None
-    apply_gbs = prof_all["apply"]["units"] / (prof_all["apply"]["ms"] * 1e-3) / 1e9 if prof_all["apply"]["ms"] else None
+
     def _rate(k, v):
-        # tile_gemm units are flops, every other class counts algorithmic bytes
+        # tile_gemm units are issued flops, every other class counts algorithmic bytes
         if not v["ms"]:
             return None
         r = v["units"] / (v["ms"] * 1e-3)
@@ -193,37 +195,68 @@ def main():
         "ms_per_step_without_profiler_events": round(ms_unprof, 3),
         "spmv_gbs": None if spmv_gbs is None else round(spmv_gbs, 1),
         "apply_gbs": None if apply_gbs is None else round(apply_gbs, 1),
-        "apply_algorithmic_bytes": S.algorithmic_bytes()["apply"],
+        "method_work": {"setup_flops": meth["setup_flops"], "issued_setup_flops": meth["issued_setup_flops"],
+                        "apply_bytes": meth["apply_bytes"]},
         "spmv_algorithmic_bytes": S.algorithmic_bytes()["spmv"],
         "kernel_breakdown": breakdown,   # one untimed step with events around every class
         "autotune": tune,
         "roofline": roof,
-        "roofline_secondary": secondary_roofline(second, prof_all, names, S),
+        "roofline_secondary": None if second is None else class_roofline(second, prof_all, meth, 1, S, names),
         "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"], sizes["grain_mats"]),
     }
     print(json.dumps(out), flush=True)
 
 
-def secondary_roofline(k, prof_all, names, S):
-    """The same figures for the class with the second-largest kernel time,
-    from the untimed step with events around every class."""
-    if k is None:
-        return None
-    d = prof_all[k]
+# kernel classes of the built-in profiler behind each roofline class
+CLASS_KERNELS = {"setup_dense": ["tile_gemm", "diag"]}
+
+
+def class_roofline(k, prof, meth, steps, S, names):
+    """Roofline of one kernel class over the profiled region: achieved = the
+    method's own work (flops of the set-up, or bytes of the applications, from
+    unpadded sizes with every operator read once) / the summed duration of
+    the class's launches; the work its launches issue (64x64 tile padding,
+    explicit inverses, diagonal tiles) is reported beside it."""
+    if k == "setup_dense":
+        t, d = prof["tile_gemm"], prof["diag"]
+        launches = t["launches"] + d["launches"]
+        ms = t["ms"] + d["ms"]
+        method = meth["setup_flops"]["total"] * steps
+        ach = method / (ms * 1e-3) / 1e12
+        iss = t["units"] / (t["ms"] * 1e-3) / 1e12 if t["ms"] else None
+        r = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+             "frac": round(ach / FP64_MFMA_TFLOPS, 4),
+             "kernel": "tile_gemm_kernel<double> + diag_kernel<double> (set-up tile Cholesky, inverses, basis, "
+                       "Galerkin blocks, coarse fronts)",
+             "launches": launches, "avg_launch_us": round(ms * 1e3 / launches, 3),
+             "units_per_launch": method / launches,
+             "units": "method flops: sum N^3/3 + 2 N^2 (k+1) + 2 N k^2 over grains, n^3/3 over contact grids, "
+                      "d^3/3 + d^2 u + d u^2 over coarse fronts",
+             "issued": {"tile_gemm_tflops": None if iss is None else round(iss, 3),
+                        "tile_gemm_frac": None if iss is None else round(iss / FP64_MFMA_TFLOPS, 4),
+                        "issued_over_method": round(meth["issued_setup_flops"]["total"] / meth["setup_flops"]["total"], 3)},
+             "traffic": traffic_for("setup_dense")}
+        return r
+    d = prof[k]
     if not d["launches"] or not d["ms"]:
         return None
-    key = k + "_inverse" if k == "gemv_smoother" and S.smoother_form() == "inverse" else k
-    if k == "tile_gemm":
-        ach = d["units"] / (d["ms"] * 1e-3) / 1e12
-        r = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-             "frac": round(ach / FP64_MFMA_TFLOPS, 4)}
+    per_apply = {"gemv_smoother": (meth["apply_bytes"]["smoother"], 2 if S.smoother_form() == "inverse" else 4),
+                 "gemv_basis": (meth["apply_bytes"]["basis"], 2),
+                 "gemv_coarse": (meth["apply_bytes"]["coarse"], 1)}
+    if k in per_apply:
+        mb, lpa = per_apply[k]
+        method = mb * d["launches"] / lpa
     else:
-        ach = d["units"] / (d["ms"] * 1e-3) / 1e9
-        r = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-             "frac": round(ach / HBM_PEAK_GBS, 4)}
-    r.update({"kernel": names[k], "launches": d["launches"], "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 3),
-              "units_per_launch": d["units"] / d["launches"], "traffic": traffic_for(key)})
-    return r
+        method = d["units"]
+    ach = method / (d["ms"] * 1e-3) / 1e9
+    key = k + "_inverse" if k == "gemv_smoother" and S.smoother_form() == "inverse" else k
+    return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "kernel": names[k], "launches": d["launches"],
+            "avg_launch_us": round(d["ms"] * 1e3 / d["launches"], 3), "units_per_launch": method / d["launches"],
+            "units": "method bytes: each operator's stored triangle or block read once, vectors in and out",
+            "issued": {"bytes_per_launch": d["units"] / d["launches"],
+                       "issued_over_method": round(d["units"] / method, 3)},
+            "traffic": traffic_for(key)}
 
 
 def traffic_for(dom):
@@ -265,42 +298,135 @@ def workload_name(a):
     return f"grf{a.n}^3 solid 0.6, lognormal E, {a.box}^3-voxel boxes, n={a.mortar}, FGMRES(50) to 1e-8"
 
 
-def cpu_baseline(a, gpu_iters, gpu_dofs, full_grains):
-    """The oracle, untuned, on a bounded sample of the same workload: the lower
-    32^3 corner of the same 64^3 fields with the same 8^3 boxes, solved to
-    1e-8 (assembly excluded, as on the GPU; about 10-20 s of CPU work).  Its set-up time is scaled by the
-    subdomain-count ratio and its solve time by (dof ratio) x (GPU iteration
-    count / oracle iteration count)."""
+ORACLE_FILES = ["oracle/fem.py", "oracle/partition.py", "oracle/mortar.py", "oracle/hplmm.py", "oracle/gmres.py"]
+CPU_FULL_RECORD = os.path.join(ROOT, "profiles", "cpu_oracle_grf64_n4.json")
+
+
+def oracle_timed(problem, mortar, label="", progress=False):
+    """The oracle, untuned, on one problem: set-up (the literal W, Q, P, P^
+    and dense coarse Cholesky of Eqs. 18-24, grain and contact-grid
+    factorisations of Eq. 26) and FGMRES(50) to a 1e-8 true residual, timed by
+    phase with the host clock; assembly is excluded, as on the GPU.  A
+    subclass only wraps the oracle's set-up stages with timers."""
+    from oracle import fem, gmres, hplmm as oh
+    A, b, mesh = fem.assemble(problem)
+    ph = {}
+
+    def stamp(name, f):
+        t0 = time.perf_counter()
+        f()
+        ph[name] = time.perf_counter() - t0
+        if progress:
+            print(f"# oracle {label}: {name} {ph[name]:.1f} s", file=sys.stderr, flush=True)
+
+    class Timed(oh.HPLMM):
+        def _build_P(self, use_rhs):
+            stamp("grains_basis_s", lambda: oh.HPLMM._build_P(self, use_rhs))
+
+        def _coarse_operator(self):
+            stamp("coarse_operator_s", lambda: oh.HPLMM._coarse_operator(self))
+
+        def _coarse_factor(self):
+            stamp("coarse_factor_s", lambda: oh.HPLMM._coarse_factor(self))
+
+        def _build_smoothers(self):
+            stamp("contacts_s", lambda: oh.HPLMM._build_smoothers(self))
+
+    t0 = time.perf_counter()
+    H = Timed(problem, A=A, b=b, mesh=mesh, n=mortar)
+    t1 = time.perf_counter()
+    n_app = [0]
+
+    def M(r):
+        n_app[0] += 1
+        if progress and n_app[0] % 10 == 0:
+            print(f"# oracle {label}: {n_app[0]} applications, {time.perf_counter() - t1:.1f} s", file=sys.stderr,
+                  flush=True)
+        return H.apply(r)
+
+    r = gmres.gmres(A, b, M, tol=1e-8, restart=50, maxit=300, flexible=True)
+    t2 = time.perf_counter()
+    return {"setup_s": round(t1 - t0, 3), "phases_s": {k: round(v, 3) for k, v in ph.items()},
+            "solve_s": round(t2 - t1, 3), "iters": int(r.iters), "rel_res_true": float(r.rel_res),
+            "dofs": int(A.shape[0]), "coarse_dofs": int(H.Acoarse.shape[0]),
+            "subdomains": int(sum(1 for g in H.part.grain_nodes if len(g)))}
+
+
+def _blas_threads():
     try:
         import threadpoolctl
-        threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
+        return max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
     except Exception:
-        threads = None
-    from oracle import fem, gmres, hplmm as oh
+        return None
+
+
+def cpu_full(a):
+    """--cpu-full: the oracle on the whole workload (no GPU), with the BLAS
+    threads limited to --cpu-threads (0: as configured); prints one JSON line."""
+    import contextlib
+    try:
+        import threadpoolctl
+        lim = threadpoolctl.threadpool_limits(a.cpu_threads) if a.cpu_threads > 0 else contextlib.nullcontext()
+    except Exception:
+        lim = contextlib.nullcontext()
+    with lim:
+        threads = _blas_threads()
+        rec = oracle_timed(make_problem(a, a.n), a.mortar, label=f"{a.n}^3, {threads} threads", progress=True)
+    rec.update({"workload": workload_name(a), "blas_threads": threads, "host_cpus": len(os.sched_getaffinity(0)),
+                "oracle_sha256": _source_hash(ORACLE_FILES),
+                "setup_plus_solve_ms": round((rec["setup_s"] + rec["solve_s"]) * 1e3, 1)})
+    print(json.dumps(rec), flush=True)
+
+
+def cpu_baseline(a, gpu_iters, gpu_dofs, full_grains):
+    """The oracle beside the GPU.  Live: the untuned oracle on a bounded sample
+    of the workload, the lower 32^3 corner of the same fields with the same
+    8^3 boxes (about 10 s of host work), timed by phase.  Measured: the same
+    oracle on the whole workload on this host type, all cores and one BLAS
+    thread (the paper's serial protocol), from the committed record of
+    `bench.py --cpu-full`; it gives `value` when it was taken on the current
+    oracle sources, otherwise `value` falls back to the sample scaled by the
+    subdomain count (set-up) and by dofs x iterations (solve) -- a lower
+    bound, since the oracle's dense coarse factor grows with the cube of the
+    coarse size."""
     from paper_2509_19777_amd import synth
     if a.workload == "uneven":
-        # a smaller realisation of the same generator (cropping would re-partition)
         sub = make_problem(a, CPU_SAMPLE_N)
         what = f"a {CPU_SAMPLE_N}^3 realisation of the same generator"
     else:
         sub = synth.crop(synth.config_grf(a.n, a.box, seed=2, n_mortar=a.mortar), CPU_SAMPLE_N, box=a.box)
         what = f"the {CPU_SAMPLE_N}^3 corner crop of the same fields"
-    A, b, mesh = fem.assemble(sub)
-    t0 = time.perf_counter()
-    H = oh.HPLMM(sub, A=A, b=b, mesh=mesh, n=a.mortar)
-    t1 = time.perf_counter()
-    r = gmres.gmres(A, b, H.apply, tol=1e-8, restart=50, maxit=300, flexible=True)
-    t2 = time.perf_counter()
-    n_sub = sum(1 for g in H.part.grain_nodes if len(g))
-    setup_ms = (t1 - t0) * 1e3 * full_grains / n_sub
-    solve_ms = (t2 - t1) * 1e3 * (gpu_dofs / A.shape[0]) * (gpu_iters / max(r.iters, 1))
-    return {"value": round(setup_ms + solve_ms, 1), "unit": "ms", "cores": threads, "kind": "oracle",
-            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on {what} "
-                       f"({A.shape[0]} dofs, {n_sub} subdomains, {r.iters} iterations, set-up "
-                       f"{(t1 - t0):.2f} s, solve {(t2 - t1):.2f} s); set-up scaled x{full_grains / n_sub:.1f} "
-                       f"(subdomains), solve scaled x{gpu_dofs / A.shape[0]:.1f} (dofs) "
-                       f"x{gpu_iters / max(r.iters, 1):.2f} (iterations)"),
-            "setup_ms": round(setup_ms, 1), "solve_ms": round(solve_ms, 1)}
+    live = oracle_timed(sub, a.mortar)
+    live.update({"what": what, "blas_threads": _blas_threads()})
+    full = None
+    if os.path.exists(CPU_FULL_RECORD) and a.workload == "grf" and a.n == 64 and a.box == 8 and a.mortar == 4:
+        try:
+            full = json.load(open(CPU_FULL_RECORD))
+            if full.get("oracle_sha256") != _source_hash(ORACLE_FILES):
+                full = None
+        except Exception:
+            full = None
+    if full:
+        allc, one = full["all_cores"], full["one_thread"]
+        return {"value": allc["setup_plus_solve_ms"], "unit": "ms", "cores": allc["blas_threads"],
+                "kind": "oracle-measured",
+                "sample": (f"the whole workload ({allc['dofs']} dofs, {allc['coarse_dofs']} coarse dofs, "
+                           f"{allc['iters']} iterations) measured with bench.py --cpu-full on the box host: "
+                           f"set-up {allc['setup_s']:.1f} s + solve {allc['solve_s']:.1f} s with "
+                           f"{allc['blas_threads']} BLAS threads; {one['setup_s']:.1f} s + {one['solve_s']:.1f} s "
+                           f"with one thread"),
+                "one_thread": {"value": one["setup_plus_solve_ms"], "unit": "ms", "cores": 1},
+                "record": os.path.relpath(CPU_FULL_RECORD, ROOT),
+                "live_sample": live}
+    n_sub = live["subdomains"]
+    setup_ms = live["setup_s"] * 1e3 * full_grains / n_sub
+    solve_ms = live["solve_s"] * 1e3 * (gpu_dofs / live["dofs"]) * (gpu_iters / max(live["iters"], 1))
+    return {"value": round(setup_ms + solve_ms, 1), "unit": "ms", "cores": live["blas_threads"], "kind": "oracle",
+            "sample": (f"oracle set-up + FGMRES(50) to 1e-8 on {what} ({live['dofs']} dofs, {n_sub} subdomains, "
+                       f"{live['iters']} iterations, set-up {live['setup_s']:.2f} s, solve {live['solve_s']:.2f} s); "
+                       f"scaled x{full_grains / n_sub:.1f} (set-up), x{gpu_dofs / live['dofs']:.1f} dofs "
+                       f"x{gpu_iters / max(live['iters'], 1):.2f} iterations (solve): a lower bound"),
+            "live_sample": live}
 
 
 if __name__ == "__main__":

@@ -297,6 +297,18 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *  11 smoother form in use: int32[1] (HPLMM_SMOOTHER_FACTORS or _INVERSE)
  *  12 split-row scratch of the coarse sweeps: int64[2] = {partial sums
  *            (doubles), arrival counters (int32)}
+ *  13 the method's own work, from unpadded sizes: double[13] =
+ *            {set-up flops: grains (N^3/3 Cholesky + 2 N^2 c triangular
+ *            solves with the c = k (+1) basis and correction columns + 2 N k^2
+ *            Galerkin block), contact grids (n^3/3), coarse fronts (d^3/3 +
+ *            d^2 u + d u^2 for d own, u boundary dofs), total;
+ *            flops the set-up's 64x64 tile tasks issue (padding, explicit
+ *            inverses W = L^-1 and S = W^T W included): grains, contact grids,
+ *            coarse, total;
+ *            bytes of one M^-1 application with every operator's stored
+ *            triangle or block read once: smoother operators (as applied in
+ *            the chosen form and precision), restriction + prolongation,
+ *            coarse sweeps, the two residual products, whole application}
  * host_out receives at most cap_bytes bytes; *needed_bytes gets the size. */
 hplmm_status hplmm_query(hplmm_handle *h, int32_t what, void *host_out, int64_t cap_bytes,
                          int64_t *needed_bytes);
@@ -345,7 +357,8 @@ hplmm_status hplmm_set_voxel_operator(hplmm_handle *h, int32_t nx, int32_t ny, i
  * Gram-Schmidt passes, normalisation: kernel launches only) into a graph the
  * first time it runs (capture happens on an internal stream) and launches
  * the graph on the caller's stream from then on.  Graphs are rebuilt when the Krylov
- * buffers are reallocated and are not used while the profiler is on.  The
+ * buffers are reallocated and are not used while the profiler times a
+ * solve-phase class (classes 2-7).  The
  * results are identical with graphs on and off.  on = 0 turns them off and
  * frees them. */
 hplmm_status hplmm_use_graphs(hplmm_handle *h, int32_t on);

@@ -50,6 +50,13 @@ hplmm_status hplmm_debug_read_arena(hplmm_handle *h, int32_t arena, int64_t off,
  * offset, R offset, Y offset, K offset) -- 11 values per matrix. */
 hplmm_status hplmm_debug_grain_layout(hplmm_handle *h, int64_t *out, int64_t cap);
 
+/* Layout of the contact-grid blocks for tests: int64 per contact matrix m
+ * (dofs n, tiles nt, arena holding its factor (0 = float64, 1 = float32), A/L
+ * offset, W offset, Wt offset) -- 6 values per matrix, in contact-grid order.
+ * Tiles are 64 x 64, column-major inside a tile, packed lower tiles (I, J),
+ * I >= J, at I (I + 1) / 2 + J. */
+hplmm_status hplmm_debug_contact_layout(hplmm_handle *h, int64_t *out, int64_t cap);
+
 /* Host only: the per-interface mortar blocks that hplmm_plan would build (the
  * layout of query 2), concatenated in interface order, without touching the
  * device.  out receives at most cap doubles; *needed gets the total. */

@@ -177,8 +177,14 @@ class HPLMM:
 
     # ---- Eq. (18): coarse operator ---------------------------------------
     def _build_coarse(self):
+        self._coarse_operator()
+        self._coarse_factor()
+
+    def _coarse_operator(self):
         Ph = self.Phat
         self.Acoarse = (Ph.T @ self.A @ Ph).toarray()
+
+    def _coarse_factor(self):
         self.coarse_chol = sla.cho_factor(self.Acoarse, lower=True)
 
     # ---- Eq. (26): local blocks of the smoothers -------------------------

@@ -645,8 +645,9 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
     const int64_t N = h.N;
     // graphs of the Arnoldi steps, captured on an internal stream (the caller's
     // may be the null stream, which cannot be captured) and launched on the
-    // caller's; only with the profiler off (its events are recorded per launch)
-    const bool graphs = h.use_graphs && h.prof.mask == 0;
+    // caller's; only while the profiler times no solve-phase class (its events
+    // are recorded per launch; the set-up classes 0 and 1 are not in the graphs)
+    const bool graphs = h.use_graphs && (h.prof.mask & ~((1 << PC_TILE_GEMM) | (1 << PC_DIAG))) == 0;
     if (graphs) {
         if (!h.gstream) {
             hip_check(hipStreamCreateWithFlags(&h.gstream, hipStreamNonBlocking), "stream");
@@ -1243,6 +1244,14 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 break;
             }
             case 11: put(&h.smoother_form, sizeof(int32_t)); break;
+            case 13: {
+                double v[13];
+                std::memcpy(v, h.method_setup_flops, sizeof(h.method_setup_flops));
+                std::memcpy(v + 4, h.issued_setup_flops, sizeof(h.issued_setup_flops));
+                std::memcpy(v + 8, h.method_apply_bytes, sizeof(h.method_apply_bytes));
+                put(v, sizeof(v));
+                break;
+            }
             case 12: {
                 const int64_t v[2] = {h.gemv_part_len, (int64_t)h.gemv_cnt_len};
                 put(v, sizeof(v));
@@ -1396,6 +1405,27 @@ extern "C" hplmm_status hplmm_debug_grain_layout(hplmm_handle *hh, int64_t *out,
             o[8] = h.gm_roff[(size_t)m];
             o[9] = h.gm_ytoff[(size_t)m];
             o[10] = h.gm_koff[(size_t)m];
+        }
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_debug_contact_layout(hplmm_handle *hh, int64_t *out, int64_t cap) {
+    return guarded([&]() -> hplmm_status {
+        if (!hh || !out) fail(HPLMM_E_ARG, "bad arguments");
+        Handle &h = hh->h;
+        const int64_t nm = (int64_t)h.cset.n.size();
+        if (cap < 6 * nm) fail(HPLMM_E_ARG, "buffer too small");
+        // the float32 factor form factors the contact grids in the float32 arena
+        const bool f32 = h.smoother_precision != 64 && h.smoother_form == HPLMM_SMOOTHER_FACTORS;
+        for (int64_t m = 0; m < nm; ++m) {
+            int64_t *o = out + 6 * m;
+            o[0] = h.cset.n[(size_t)m];
+            o[1] = h.cset.nt[(size_t)m];
+            o[2] = f32 ? 1 : 0;
+            o[3] = h.cset.a_base + h.cset.rel[(size_t)m];
+            o[4] = h.cset.w_base + h.cset.rel[(size_t)m];
+            o[5] = h.cset.wt_base + h.cset.rel[(size_t)m];
         }
         return HPLMM_OK;
     });

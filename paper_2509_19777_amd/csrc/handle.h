@@ -302,6 +302,21 @@ struct Handle {
     double *ydev = nullptr;
     int32_t kr_blocks = 0;
 
+    // the method's own work (unpadded sizes, each operator once), the figures
+    // rooflines are stated against: set-up flops {grains: Cholesky N^3/3, two
+    // triangular solves with the k+1 basis and correction columns 2 N^2 (k+1),
+    // Galerkin block 2 N k^2; contact grids n^3/3; coarse fronts d^3/3 + d^2 u
+    // + d u^2; total}, and the flops the set-up's tile tasks issue (64x64 tiles
+    // with padding, the explicit inverses and S = W^T W included) {grains,
+    // contact grids, coarse, total}
+    double method_setup_flops[4] = {0, 0, 0, 0};
+    double issued_setup_flops[4] = {0, 0, 0, 0};
+    // bytes one application of M^-1 needs, each operator's stored triangle or
+    // block read once: {smoother operators (grain + contact, as applied in the
+    // chosen form and precision), restriction + prolongation, coarse sweeps,
+    // fine products (two), whole application}
+    double method_apply_bytes[5] = {0, 0, 0, 0, 0};
+
     // timings
     double t_setup_ms[4] = {0, 0, 0, 0};
     Profiler prof;

@@ -845,6 +845,59 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
 }
 }  // namespace
 
+// The method's own set-up flops and application bytes from the unpadded
+// sizes (grain interiors N with k mortar and c = k + 1 or k columns, contact
+// grids n, coarse fronts with d own and u boundary dofs), and the flops the
+// set-up's tile tasks issue, for comparison.
+static void method_work(Handle &h) {
+    const double se = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
+    const bool inv = h.smoother_form == HPLMM_SMOOTHER_INVERSE;
+    double fg = 0.0, fc = 0.0, ff = 0.0, bs = 0.0, bb = 0.0;
+    for (size_t m = 0; m < h.gset.n.size(); ++m) {
+        const double N = (double)h.gset.n[m], k = (double)h.gm_k[m], c = (double)h.gm_ncol[m];
+        fg += N * N * N / 3.0 + 2.0 * N * N * c + 2.0 * N * k * k;
+        // smoother: S (one triangle) or W and W^T (two passes over one triangle);
+        // x read and y written
+        bs += (inv ? 1.0 : 2.0) * se * N * (N + 1) / 2 + 16.0 * N;
+        // restriction and prolongation: the N x c block twice, vectors in and out
+        bb += 2.0 * (8.0 * N * c + 8.0 * (N + c));
+    }
+    for (size_t m = 0; m < h.cset.n.size(); ++m) {
+        const double n = (double)h.cset.n[m];
+        fc += n * n * n / 3.0;
+        bs += (inv ? 1.0 : 2.0) * se * n * (n + 1) / 2 + 16.0 * n;
+    }
+    double bf = 0.0;
+    for (int32_t t = 0; t < h.mf.n_fronts; ++t) {
+        const double d = (double)h.mf.d[(size_t)t], u = (double)h.mf.u[(size_t)t];
+        ff += d * d * d / 3.0 + d * d * u + d * u * u;
+        bf += 2.0 * (8.0 * (d * (d + 1) / 2 + d * u) + 8.0 * (2.0 * d + 2.0 * u));
+    }
+    h.method_setup_flops[0] = fg;
+    h.method_setup_flops[1] = fc;
+    h.method_setup_flops[2] = ff;
+    h.method_setup_flops[3] = fg + fc + ff;
+    auto sum = [](const std::vector<Launch> &prog) {
+        double f = 0.0;
+        for (const Launch &L : prog) f += L.flops;
+        return f;
+    };
+    h.issued_setup_flops[0] = sum(h.gset.factor_prog) + sum(h.gset.inverse_prog) + sum(h.basis_prog);
+    h.issued_setup_flops[1] = sum(h.cset.factor_prog) + sum(h.cset.inverse_prog);
+    h.issued_setup_flops[2] = h.mf.flops;
+    h.issued_setup_flops[3] = h.issued_setup_flops[0] + h.issued_setup_flops[1] + h.issued_setup_flops[2];
+    const double n = (double)h.N;
+    // two residual products r - A z, each reading r and z and writing the result
+    const double sp = 2.0 * (h.spmv_bytes + 24.0 * (double)h.n_nodes);
+    h.method_apply_bytes[0] = bs;
+    h.method_apply_bytes[1] = bb;
+    h.method_apply_bytes[2] = bf;
+    h.method_apply_bytes[3] = sp;
+    // plus the vector traffic between the steps: gathers into the local
+    // vectors, the combines of Eqs. 16 and 25 (read and write of N-vectors)
+    h.method_apply_bytes[4] = bs + bb + bf + sp + 8.0 * 6.0 * n;
+}
+
 // Basis tasks (Eqs. 23-24) of the grain matrices ms, appended to tl and prog:
 // BP_Y: Y = W R; BP_X: X = W^T Y written over R; BP_K: K = Y^T Y;
 // BP_XT: per-tile transposes of X into the XT region.
@@ -1431,6 +1484,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         // the front factors (W11 and G, then W11^T and G^T) and their vectors
         h.apply_bytes += 2.0 * h.mf.factor_bytes + 8.0 * 8.0 * (double)h.mf.vec_len;
     }
+    method_work(h);
     // ---- SELL-64 fine matrix ---------------------------------------------------------
     std::vector<int64_t> slice_step;
     std::vector<int32_t> scol;

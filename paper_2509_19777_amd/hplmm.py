@@ -84,6 +84,7 @@ EXPORTS = {
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_read_arena": (i32, [C.c_void_p, i32, i64, i64, C.c_void_p]),
     "hplmm_debug_grain_layout": (i32, [C.c_void_p, P(i64), i64]),
+    "hplmm_debug_contact_layout": (i32, [C.c_void_p, P(i64), i64]),
     "hplmm_last_error": (C.c_char_p, []),
     "hplmm_sg_create": (i32, [P(i32), i32, P(C.c_void_p)]),
     "hplmm_sg_param_count": (i32, [C.c_void_p, P(i64)]),
@@ -442,6 +443,16 @@ class Solver:
         v = self.query(8, np.float64)
         return {"apply": float(v[0]), "spmv": float(v[1])}
 
+    def method_work(self):
+        """The method's own work (query 13): set-up flops from unpadded sizes,
+        the flops the set-up's tile tasks issue, and the bytes one M^-1
+        application needs with every operator read once."""
+        v = self.query(13, np.float64)
+        k4 = ["grains", "contacts", "coarse", "total"]
+        return {"setup_flops": dict(zip(k4, map(float, v[0:4]))),
+                "issued_setup_flops": dict(zip(k4, map(float, v[4:8]))),
+                "apply_bytes": dict(zip(["smoother", "basis", "coarse", "spmv", "total"], map(float, v[8:13])))}
+
     def setup_times_ms(self):
         v = self.query(5, np.float64)
         return {"grains": v[0], "contacts": v[1], "coarse": v[2], "total": v[3]}
@@ -489,6 +500,26 @@ def debug_grain_layout(solver):
     out = np.zeros(11 * nm, dtype=np.int64)
     _check(lib().hplmm_debug_grain_layout(solver.h, _ptr(out, i64), out.size))
     return out.reshape(nm, 11)
+
+
+def debug_contact_layout(solver):
+    nm = solver.sizes()["n_contacts"]
+    out = np.zeros(6 * nm, dtype=np.int64)
+    _check(lib().hplmm_debug_contact_layout(solver.h, _ptr(out, i64), out.size))
+    return out.reshape(nm, 6)
+
+
+def debug_read_lower(solver, arena, off, n, nt):
+    """The packed lower tiles of an n x n block at arena offset off (tiles
+    column-major inside, (I, J) at I (I + 1) / 2 + J) as a dense lower
+    triangular float64 array."""
+    v = debug_read_arena(solver, arena, off, nt * (nt + 1) // 2 * 4096).astype(np.float64)
+    M = np.zeros((nt * 64, nt * 64))
+    for I in range(nt):
+        for J in range(I + 1):
+            t = v[(I * (I + 1) // 2 + J) * 4096:(I * (I + 1) // 2 + J + 1) * 4096].reshape(64, 64).T
+            M[I * 64:(I + 1) * 64, J * 64:(J + 1) * 64] = t
+    return np.tril(M[:n, :n])
 
 
 class VoxelGrid:
