@@ -353,6 +353,7 @@ def oracle_timed(problem, mortar, label="", progress=False):
 
 
 def _blas_threads():
+    """Threads of the BLAS / OpenMP pools loaded in this process (the largest)."""
     try:
         import threadpoolctl
         return max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] or [1])
@@ -364,6 +365,11 @@ def cpu_full(a):
     """--cpu-full: the oracle on the whole workload (no GPU), with the BLAS
     threads limited to --cpu-threads (0: as configured); prints one JSON line."""
     import contextlib
+    # load every BLAS the oracle uses before limiting their threads (a limit
+    # reaches only the libraries loaded when it is set)
+    import scipy.linalg  # noqa: F401
+    import scipy.sparse.linalg  # noqa: F401
+    from oracle import fem, gmres, hplmm  # noqa: F401
     try:
         import threadpoolctl
         lim = threadpoolctl.threadpool_limits(a.cpu_threads) if a.cpu_threads > 0 else contextlib.nullcontext()

@@ -136,10 +136,8 @@ typedef struct hplmm_mortar {
 } hplmm_mortar;
 
 /* Smoother precision: 64 = float64; 32 = float32 smoother operators; 16 =
- * bfloat16 smoother operators.  In the factor form (below) the contact grids
- * are then factored in float32; in the inverse form every factorisation is
- * float64 and only the stored S is rounded.  The coarse space (basis, coarse
- * operator, coarse solve) and the Krylov solver are float64 in every mode.
+ * bfloat16 smoother operators.  The coarse space (basis, coarse operator,
+ * coarse solve) and the Krylov solver are float64 in every mode.
  * coarse_leaf_dofs: the nested dissection of the coarse operator stops at
  * subsets of at most this many dofs (0 = the default, 192); larger leaves
  * give fewer front levels (fewer launches per coarse solve) and larger dense
@@ -147,22 +145,27 @@ typedef struct hplmm_mortar {
  * smoother_form: how the smoother applies the local inverses A_g^-1 and
  * A_zeta^-1 of Eqs. 25-26 (the same operator either way, up to rounding):
  *   HPLMM_SMOOTHER_FACTORS  y = W^T (W x) with W = L^-1: two passes, each over
- *                           the lower tiles of the block;
+ *                           the lower tiles of the block.  At smoother_precision
+ *                           32 / 16 the grain W is the float64 one rounded to
+ *                           float32 / bfloat16, and the contact grids are
+ *                           factored and inverted in float32 on the matrix cores
+ *                           (float32 accumulation), their W rounded to the
+ *                           storage precision;
  *   HPLMM_SMOOTHER_INVERSE  y = S x with S = W^T W formed in the set-up (one
  *                           more batched tile product and one more arena
  *                           region per set): one pass over the lower tiles of
  *                           S, each off-diagonal tile serving S_ij x_j and
  *                           S_ij^T x_i, then a short sum of the transposed
  *                           products per tile row.  Half the smoother's HBM
- *                           reads.  At smoother_precision 32 / 16 every block
- *                           (the contact grids too) is factored in float64,
- *                           and S is stored rounded to float32 / bfloat16.
- *                           Rounding S (unlike rounding W, whose Gram product
- *                           W^T W stays positive definite) perturbs it by about
- *                           u |S|, so S can turn indefinite once kappa(A_g)
- *                           exceeds about 1/u: 2^8 for bfloat16;
- *   HPLMM_SMOOTHER_AUTO (0) the inverse form at smoother_precision 64 and 32,
- *                           the factor form at 16. */
+ *                           reads.  At smoother_precision 32 / 16 every block is
+ *                           factored and inverted in float64, W is rounded to
+ *                           float32 / bfloat16 (Wp), and S = Wp^T Wp is formed
+ *                           from the rounded values on the matrix cores
+ *                           (float32 / bfloat16 operands, float32
+ *                           accumulation) and kept in float32: the Gram matrix
+ *                           of Wp, positive definite however coarse the
+ *                           rounding;
+ *   HPLMM_SMOOTHER_AUTO (0) the inverse form. */
 #define HPLMM_SMOOTHER_AUTO     0
 #define HPLMM_SMOOTHER_FACTORS  1
 #define HPLMM_SMOOTHER_INVERSE  2

@@ -22,7 +22,9 @@ extern "C" {
  * into C, bit3 alpha = -1, bit4 left-multiply by P (C = alpha P S), bit5
  * right-multiply by P (C = ([C +] alpha S) P); bits 4 and 5 exclude each other
  * and need P.  npairs may be 0 only with bit5.  precision 64 or 32 selects
- * float64 or float32 tiles (all buffers of that type). */
+ * float64 or float32 tiles (all buffers of that type); precision 16 takes
+ * bfloat16 A and B (their 16 bits), a float32 C and bits 0-3 only (the
+ * bfloat16 matrix-core instruction with float32 accumulation). */
 hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A_dev, const void *B_dev, int32_t npairs,
                                    const void *P_dev, void *C_dev, int32_t flags, void *stream);
 

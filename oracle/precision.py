@@ -15,9 +15,13 @@ blocks) or FP32 (contact blocks), as the variant prescribes:
 
 That is the factor form (form="factors").  In the inverse form
 (form="inverse") every block, grain and contact grid alike, is factored and
-inverted in FP64, the symmetric inverse S = W^T W is formed in FP64 and
-rounded once to the storage precision, and the smoother is z = S r evaluated
-in FP64 on the rounded S.
+inverted in FP64, W is rounded to the storage precision (Wp), and the
+smoother's operator is the Gram matrix S = Wp^T Wp, formed exactly (the
+products of rounded values are exact in FP64, the sums carry FP64 rounding
+only) and rounded once to FP32, the precision it is kept in; the smoother is
+z = S r evaluated in FP64.  S is positive definite whatever the rounding of W
+(the Gram matrix of a nonsingular matrix), unlike W^T W rounded entrywise.
+With storage "f64" nothing is rounded: S = W^T W.
 """
 from __future__ import annotations
 
@@ -74,13 +78,20 @@ class LowPrecisionSmoother:
             self.contact_W.append(round_to(W32.astype(np.float64), precision))
 
     def _build_inverse(self):
-        def rounded_inverse(A):
+        def gram_of_rounded(A):
             L = np.linalg.cholesky(A)
             W = sla.solve_triangular(L, np.eye(L.shape[0]), lower=True)
-            return round_to(W.T @ W, self.precision)
-        self.grain_S = [None if ch is None else rounded_inverse(self.H.A[d][:, d].toarray())
-                        for d, ch in zip(self.H.grain_dofs, self.H.grain_chol)]
-        self.contact_S = [rounded_inverse(self.H.A[d][:, d].toarray()) for d in self.H.contact_dofs]
+            if self.precision == "f64":
+                return W, W.T @ W
+            Wp = round_to(W, self.precision)
+            return Wp, round_f32(Wp.T @ Wp)
+        g = [None if ch is None else gram_of_rounded(self.H.A[d][:, d].toarray())
+             for d, ch in zip(self.H.grain_dofs, self.H.grain_chol)]
+        c = [gram_of_rounded(self.H.A[d][:, d].toarray()) for d in self.H.contact_dofs]
+        self.grain_Wp = [None if x is None else x[0] for x in g]
+        self.grain_S = [None if x is None else x[1] for x in g]
+        self.contact_Wp = [x[0] for x in c]
+        self.contact_S = [x[1] for x in c]
 
     def apply_grains(self, r):
         z = np.zeros_like(r)

@@ -85,12 +85,34 @@ struct SgSetup {
 };
 static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s);
 
-// S (FP64) of a dense set rounded into the reduced-precision arena.
-static void store_low_inverse(Handle &h, const DenseSet &ds, hipStream_t s) {
-    if (h.smoother_precision == 32)
-        launch_convert_f64_f32(h.ar64 + ds.s_base, h.ar32 + ds.low_s_base, ds.region, s);
-    else if (h.smoother_precision == 16)
-        launch_convert_f64_bf16(h.ar64 + ds.s_base, h.arbf + ds.low_s_base, ds.region, s);
+// Tile contractions with bfloat16 operands and FP32 results.
+static void run_bf16_program(Handle &h, const TaskLists &tl, const std::vector<Launch> &prog, hipStream_t s) {
+    for (const Launch &L : prog) {
+        if (L.kind != LK_GEMM) fail(HPLMM_E_STATE, "internal: bfloat16 programs hold contractions only");
+        ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
+        launch_tile_gemm_bf16(h.arbf, h.ar32, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (float *)tl.d_part,
+                              tl.d_cnt);
+    }
+}
+
+// The smoother's symmetric inverse S of a dense set (inverse form), on
+// stream s after its factor program.  FP64: S = W^T W from the FP64 W and
+// its transposed tiles.  Reduced precision: W is rounded to the storage
+// precision first and S = Wp^T Wp is formed from the rounded values on the
+// matrix cores with FP32 accumulation (FP32 operands at 32, bfloat16 operands
+// at 16) and kept in FP32 -- the Gram matrix of Wp, positive definite however
+// coarse the rounding.
+static void form_inverse(Handle &h, const DenseSet &ds, hipStream_t s) {
+    if (h.smoother_precision == 64) {
+        if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
+        run_program<double>(h, h.tl64, h.ar64, ds.inverse_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+    } else if (h.smoother_precision == 32) {
+        launch_convert_f64_f32(h.ar64 + ds.w_base, h.ar32 + ds.low_w_base, ds.region, s);
+        run_program<float>(h, h.tl32, h.ar32, ds.inverse_prog, h.d_flag, s);
+    } else {
+        launch_convert_f64_bf16(h.ar64 + ds.w_base, h.arbf + ds.low_w_base, ds.region, s);
+        run_bf16_program(h, h.tlbf, ds.inverse_prog, s);
+    }
 }
 
 // Contact grids (Eq. 26): blocks, factor and inverse, on stream s; in FP64
@@ -103,8 +125,7 @@ static void contact_setup(Handle &h, hipStream_t s) {
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
         run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
-        run_program<double>(h, h.tl64, h.ar64, h.cset.inverse_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
-        store_low_inverse(h, h.cset, s);
+        if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) form_inverse(h, h.cset, s);
     } else {
         zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
@@ -174,12 +195,9 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         // the grain inverse S = W^T W follows the contact grids on the side
         // stream, beside the coarse operator on s
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
-            if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
             hip_check(hipEventRecord(ev[4], s), "event");
             hip_check(hipStreamWaitEvent(h.side, ev[4], 0), "wait");
-            run_program<double>(h, h.tl64, h.ar64, h.gset.inverse_prog, h.d_flag, h.side, h.d_part_side,
-                                h.d_cnt_side);
-            store_low_inverse(h, h.gset, h.side);
+            form_inverse(h, h.gset, h.side);
         }
         hip_check(hipEventRecord(h.side_ev[2], h.side), "event");
     }
@@ -461,12 +479,11 @@ static void surrogate_basis(Handle &h, const SgSetup &sg, hipStream_t s) {
 static void launch_set(Handle &h, const Range &r, bool smoother_low, const double *x, double *y, hipStream_t s) {
     const GemvTask *t = h.d_vtasks + r.start;
     if (r.sym) {
+        // S is kept in FP64 at full precision and in FP32 otherwise
         if (h.smoother_precision == 64)
             launch_sym_gemv<double>(h.ar64, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
-        else if (h.smoother_precision == 32)
-            launch_sym_gemv<float>(h.ar32, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
         else
-            launch_sym_gemv<uint16_t>(h.arbf, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
+            launch_sym_gemv<float>(h.ar32, x, y, t, h.d_spairs, r.count, h.d_sym_part, r.waves, s);
     } else if (!smoother_low || h.smoother_precision == 64)
         launch_gemv<double>(h.ar64, x, y, t, h.d_vpairs, r.count, s, nullptr, r.waves);
     else if (h.smoother_precision == 32)
@@ -1286,6 +1303,37 @@ extern "C" void hplmm_destroy(hplmm_handle *hh) {
 extern "C" hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A, const void *B, int32_t npairs,
                                               const void *Pm, void *Cm, int32_t flags, void *stream) {
     return guarded([&]() -> hplmm_status {
+        if (precision == 16) {
+            // bfloat16 operands, FP32 C: contraction flags only
+            if (!A || !B || !Cm || npairs < 1) fail(HPLMM_E_ARG, "bad arguments");
+            if (flags & ~(GF_TRANS_A | GF_TRANS_B | GF_ACCUM | GF_NEGATE)) fail(HPLMM_E_ARG, "flag not available");
+            hipStream_t s = as_stream(stream);
+            uint16_t *in = nullptr;
+            float *out = nullptr;
+            GemmTask *dt = nullptr;
+            GemmPair *dp = nullptr;
+            hip_check(hipMalloc(&in, sizeof(uint16_t) * TE * 2 * (size_t)npairs), "hipMalloc");
+            hip_check(hipMalloc(&out, sizeof(float) * TE), "hipMalloc");
+            hip_check(hipMemcpyAsync(in, A, sizeof(uint16_t) * TE * npairs, hipMemcpyDeviceToDevice, s), "copy");
+            hip_check(hipMemcpyAsync(in + (size_t)TE * npairs, B, sizeof(uint16_t) * TE * npairs,
+                                     hipMemcpyDeviceToDevice, s), "copy");
+            hip_check(hipMemcpyAsync(out, Cm, sizeof(float) * TE, hipMemcpyDeviceToDevice, s), "copy");
+            std::vector<GemmPair> pr;
+            for (int32_t p = 0; p < npairs; ++p) pr.push_back({(int64_t)p * TE, (int64_t)(npairs + p) * TE});
+            GemmTask t{0, -1, 0, npairs, flags, 0};
+            hip_check(hipMalloc(&dt, sizeof(t)), "hipMalloc");
+            hip_check(hipMalloc(&dp, sizeof(GemmPair) * pr.size()), "hipMalloc");
+            hip_check(hipMemcpyAsync(dt, &t, sizeof(t), hipMemcpyHostToDevice, s), "copy");
+            hip_check(hipMemcpyAsync(dp, pr.data(), sizeof(GemmPair) * pr.size(), hipMemcpyHostToDevice, s), "copy");
+            launch_tile_gemm_bf16(in, out, dt, dp, 1, s);
+            hip_check(hipMemcpyAsync(Cm, out, sizeof(float) * TE, hipMemcpyDeviceToDevice, s), "copy");
+            hip_check(hipStreamSynchronize(s), "sync");
+            (void)hipFree(in);
+            (void)hipFree(out);
+            (void)hipFree(dt);
+            (void)hipFree(dp);
+            return HPLMM_OK;
+        }
         if (!A || !B || !Cm || npairs < 0 || (precision != 64 && precision != 32)) fail(HPLMM_E_ARG, "bad arguments");
         if (flags & ~(GF_TRANS_A | GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST | GF_POST_RIGHT))
             fail(HPLMM_E_ARG, "unknown flag");

@@ -119,6 +119,10 @@ struct SymReduce {
 template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
                       hipStream_t s, T *part = nullptr, int32_t *cnt = nullptr);
+// bfloat16 operands (their 16 bits) from `in`, FP32 accumulation and output
+// to `out`; tasks without a second product (GF_POST / GF_POST_RIGHT ignored).
+void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,
+                           int64_t ntasks, hipStream_t s, float *part = nullptr, int32_t *cnt = nullptr);
 template <class T>
 void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int64_t ntasks,
                  int32_t *flag, hipStream_t s);

@@ -9,6 +9,8 @@
 // a 32x32 quadrant.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "dense.h"
 
 namespace hplmm {
@@ -34,6 +36,17 @@ struct Mfma<float> {
     static __device__ __forceinline__ acc_t mac(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
     }
+    static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
+};
+
+// bfloat16 operands (stored as their 16 bits) with FP32 accumulation:
+// v_mfma_f32_16x16x32_bf16 takes 8 contraction indices per lane, so one
+// instruction covers a whole 32-deep staged half; the output layout is that
+// of the FP32 instruction.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+template <>
+struct Mfma<uint16_t> {
+    typedef v4f acc_t;
     static __device__ __forceinline__ int row(int lq, int r) { return 4 * lq + r; }
 };
 
@@ -104,6 +117,27 @@ __device__ __forceinline__ void mfma_half(const T *As, const T *Bs, typename Mfm
         acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
         acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
     }
+}
+
+template <>
+__device__ __forceinline__ void mfma_half<uint16_t>(const uint16_t *As, const uint16_t *Bs, v4f acc[2][2], int lane,
+                                                    int wm, int wn) {
+    // lane l supplies row (A) or column (B) l & 15 at contraction indices
+    // 8 (l >> 4) .. 8 (l >> 4) + 7 of the half
+    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    v8bf a0, a1, b0, b1;
+#pragma unroll
+    for (int t = 0; t < 8; ++t) {
+        const int k = (k0 + t) * LD;
+        a0[t] = __builtin_bit_cast(__bf16, As[k + wm + lr]);
+        a1[t] = __builtin_bit_cast(__bf16, As[k + wm + 16 + lr]);
+        b0[t] = __builtin_bit_cast(__bf16, Bs[k + wn + lr]);
+        b1[t] = __builtin_bit_cast(__bf16, Bs[k + wn + 16 + lr]);
+    }
+    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
+    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
+    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
+    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
 }
 
 // Second product of a GF_POST / GF_POST_RIGHT task, half H: the accumulated
@@ -178,16 +212,19 @@ __device__ __forceinline__ void gemm_pairs(const T *__restrict__ arena, const Ge
 }
 
 // Tile contraction task: the pairs in 32-deep halves, then the optional
-// second product and the output.
-template <class T>
-__global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
+// second product and the output.  Operands are read from `in` (element type
+// Ti) and the output tile is written to `out` (type T, the accumulation type):
+// Ti = T for FP64 and FP32 work on one arena; Ti = bfloat16 with T = FP32
+// reads bfloat16 operands and writes FP32 results (no second product).
+template <class Ti, class T>
+__global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ in, T *__restrict__ out,
                                                         const GemmTask *__restrict__ tasks,
                                                         const GemmPair *__restrict__ pairs, T *part,
                                                         int32_t *cnt) {
     // the two operand halves; together they hold one padded 64x64 tile for
     // the output staging
     __shared__ T S[2 * KH * LD];
-    T *As = S, *Bs = S + KH * LD;
+    Ti *As = reinterpret_cast<Ti *>(S), *Bs = As + KH * LD;
     __shared__ int32_t last;
     // work-groups are dealt to the 8 XCDs in turn; give each XCD a contiguous
     // slice of the list, so neighbouring tasks (which share operand tiles)
@@ -196,21 +233,21 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     const GemmTask tk = tasks[xcd * q + (xcd < r ? xcd : r) + (b >> 3)];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-    typename Mfma<T>::acc_t acc[2][2];
+    typename Mfma<Ti>::acc_t acc[2][2];
     for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<Ti>::acc_t{0, 0, 0, 0};
     // the contraction loop specialised on the fetch orders (uniform branch)
     const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
     if (ta) {
         if (tb)
-            gemm_pairs<T, true, false>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+            gemm_pairs<Ti, true, false>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
         else
-            gemm_pairs<T, true, true>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+            gemm_pairs<Ti, true, true>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
     } else {
         if (tb)
-            gemm_pairs<T, false, false>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+            gemm_pairs<Ti, false, false>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
         else
-            gemm_pairs<T, false, true>(arena, pairs, tk, As, Bs, acc, lane, wm, wn);
+            gemm_pairs<Ti, false, true>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
     }
     if (tk.nchunk > 1) {
         // partial sums in accumulator order, reduced by the last arrival
@@ -236,9 +273,10 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     }
     const int lr = lane & 15, lq = lane >> 4;
     const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
-    T *C = arena + tk.c_off;
-    const bool post = tk.flags & (GF_POST | GF_POST_RIGHT);
-    if (post) {
+    T *C = out + tk.c_off;
+    bool post = false;
+    if constexpr (std::is_same<Ti, T>::value) post = tk.flags & (GF_POST | GF_POST_RIGHT);
+    if constexpr (std::is_same<Ti, T>::value) if (post) {
         // GF_POST: C = alpha P S, P the A operand (k along its columns);
         // GF_POST_RIGHT: C = ([C +] alpha S) P, P the B operand (k along its rows)
         const bool left = tk.flags & GF_POST;
@@ -246,8 +284,8 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
         typename Mfma<T>::acc_t res[2][2];
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) res[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-        post_half<0, T>(As, Bs, C, arena + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
-        post_half<1, T>(As, Bs, C, arena + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
+        post_half<0, T>(As, Bs, C, in + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
+        post_half<1, T>(As, Bs, C, in + tk.post_off, acc, res, left, acc_c, alpha, lane, wm, wn);
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = res[i][j];
     }
@@ -256,7 +294,7 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(T *__restrict__ arena,
     for (int i = 0; i < 2; ++i)
         for (int j = 0; j < 2; ++j)
             for (int r = 0; r < 4; ++r) {
-                const int m = wm + 16 * i + Mfma<T>::row(lq, r), n = wn + 16 * j + lr;
+                const int m = wm + 16 * i + Mfma<Ti>::row(lq, r), n = wn + 16 * j + lr;
                 S[n * LD + m] = acc[i][j][r];
             }
     __syncthreads();
@@ -599,7 +637,14 @@ template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s,
                       T *part, int32_t *cnt) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL(tile_gemm_kernel<T>, dim3(grid_of(ntasks)), dim3(256), 0, s, arena, tasks, pairs, part, cnt);
+    hipLaunchKernelGGL((tile_gemm_kernel<T, T>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, arena, tasks, pairs,
+                       part, cnt);
+}
+void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,
+                           int64_t ntasks, hipStream_t s, float *part, int32_t *cnt) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL((tile_gemm_kernel<uint16_t, float>), dim3(grid_of(ntasks)), dim3(256), 0, s, in, out, tasks,
+                       pairs, part, cnt);
 }
 template <class T>
 void launch_diag(T *a, T *w, T *wt, const DiagTask *tasks, int64_t ntasks, int32_t *flag, hipStream_t s) {

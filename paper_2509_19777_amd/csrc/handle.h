@@ -212,6 +212,7 @@ struct Handle {
     uint16_t *arbf = nullptr;
     int64_t arbf_n = 0;
     TaskLists tl64, tl32;
+    TaskLists tlbf;   // bfloat16 operands, FP32 results (S of the reduced-precision inverse form)
     // learned-basis surrogate inputs (host copies kept by the plan)
     std::vector<int32_t> sg_xyz;                 // [3 n_nodes] lattice coordinates
     std::vector<float> sg_logtr, sg_fill;        // per node: log trace of A_vv, stored blocks / 27

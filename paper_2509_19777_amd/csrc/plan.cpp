@@ -239,16 +239,23 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
 // S = W^T W for every matrix of a dense set (the inverse smoother form), lower
 // tiles S_ij = sum_{k >= i} W_ki^T W_kj, i >= j, one task per tile with the
 // stored transposes Wt_ki = W_ki^T as left operands.
-void build_inverse_program(DenseSet &ds, TaskLists &tl) {
-    auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
+// S_ij = sum_{k >= i} W_ki^T W_kj over the lower tiles.  FP64: the
+// transposed tiles Wt_ki as left operands.  Reduced precision (low): the
+// rounded W at low_w_base as both operands (the left one read transposed),
+// S written to low_s_base of the FP32 arena.
+void build_inverse_program(DenseSet &ds, TaskLists &tl, bool low) {
+    const int64_t wb = low ? ds.low_w_base : ds.w_base, sb = low ? ds.low_s_base : ds.s_base;
+    auto W = [&](int64_t m, int64_t I, int64_t J) { return wb + ds.rel[m] + tri_index(I, J) * TE; };
     auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
-    auto S = [&](int64_t m, int64_t I, int64_t J) { return ds.s_base + ds.rel[m] + tri_index(I, J) * TE; };
+    auto S = [&](int64_t m, int64_t I, int64_t J) { return sb + ds.rel[m] + tri_index(I, J) * TE; };
     Launch L{LK_GEMM, (int64_t)tl.gemm.size(), 0};
     for (int64_t m = 0; m < (int64_t)ds.n.size(); ++m)
         for (int64_t i = 0; i < ds.nt[m]; ++i)
             for (int64_t j = 0; j <= i; ++j) {
-                tl.gemm.push_back({S(m, i, j), -1, (int32_t)tl.pairs.size(), (int32_t)(ds.nt[m] - i), 0, 0});
-                for (int64_t k = i; k < ds.nt[m]; ++k) tl.pairs.push_back({Wt(m, k, i), W(m, k, j)});
+                tl.gemm.push_back({S(m, i, j), -1, (int32_t)tl.pairs.size(), (int32_t)(ds.nt[m] - i),
+                                   low ? (int32_t)GF_TRANS_A : 0, 0});
+                for (int64_t k = i; k < ds.nt[m]; ++k)
+                    tl.pairs.push_back({low ? W(m, k, i) : Wt(m, k, i), W(m, k, j)});
             }
     L.count = (int64_t)tl.gemm.size() - L.start;
     if (L.count) ds.inverse_prog.push_back(L);
@@ -850,8 +857,10 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
 // grids n, coarse fronts with d own and u boundary dofs), and the flops the
 // set-up's tile tasks issue, for comparison.
 static void method_work(Handle &h) {
-    const double se = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
     const bool inv = h.smoother_form == HPLMM_SMOOTHER_INVERSE;
+    // stored element: FP64, FP32 or bfloat16 W in the factor form; S in FP64
+    // or (reduced precision) FP32 in the inverse form
+    const double se = h.smoother_precision == 64 ? 8.0 : (inv || h.smoother_precision == 32 ? 4.0 : 2.0);
     double fg = 0.0, fc = 0.0, ff = 0.0, bs = 0.0, bb = 0.0;
     for (size_t m = 0; m < h.gset.n.size(); ++m) {
         const double N = (double)h.gset.n[m], k = (double)h.gm_k[m], c = (double)h.gm_ncol[m];
@@ -977,9 +986,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     // auto: the inverse form, except with bfloat16 storage, where rounding S
     // itself (rather than W, whose Gram product W^T W stays definite) can
     // leave it indefinite once kappa(A_g) exceeds about 2^8
-    h.smoother_form = opt.smoother_form != HPLMM_SMOOTHER_AUTO ? opt.smoother_form
-                      : h.smoother_precision == 16         ? HPLMM_SMOOTHER_FACTORS
-                                                           : HPLMM_SMOOTHER_INVERSE;
+    h.smoother_form = opt.smoother_form != HPLMM_SMOOTHER_AUTO ? opt.smoother_form : HPLMM_SMOOTHER_INVERSE;
     if (opt.coarse_leaf_dofs < 0) fail(HPLMM_E_ARG, "coarse_leaf_dofs must be >= 0");
     h.coarse_leaf_dofs = opt.coarse_leaf_dofs > 0 ? opt.coarse_leaf_dofs : 192;
     h.n_nodes = n;
@@ -1216,18 +1223,21 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.wt_base = off32;
         off32 += h.cset.region;
     }
-    // reduced-precision smoother copies: S of both sets (inverse form) or W
-    // and Wt (factor form)
-    if (inverse && h.smoother_precision == 32) {
-        h.gset.low_s_base = off32;
-        off32 += h.gset.region;
-        h.cset.low_s_base = off32;
-        off32 += h.cset.region;
-    } else if (inverse && h.smoother_precision == 16) {
-        h.gset.low_s_base = offbf;
-        offbf += h.gset.region;
-        h.cset.low_s_base = offbf;
-        offbf += h.cset.region;
+    // reduced-precision smoother copies.  Inverse form: W of both sets rounded
+    // to the storage precision (FP32 arena at 32, bfloat16 arena at 16) and
+    // S = Wp^T Wp formed from it, kept in FP32.  Factor form: W and Wt.
+    if (inverse && lowp) {
+        for (DenseSet *ds : {&h.gset, &h.cset}) {
+            if (h.smoother_precision == 32) {
+                ds->low_w_base = off32;
+                off32 += ds->region;
+            } else {
+                ds->low_w_base = offbf;
+                offbf += ds->region;
+            }
+            ds->low_s_base = off32;
+            off32 += ds->region;
+        }
     } else if (h.smoother_precision == 32) {
         h.gset.low_w_base = off32;
         off32 += h.gset.region;
@@ -1245,13 +1255,11 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         h.cset.low_wt_base = offbf;
         offbf += h.cset.region;
     }
-    if (inverse) {
+    if (inverse && !lowp) {
         h.gset.s_base = take64(h.gset.region);
         h.cset.s_base = take64(h.cset.region);
-        if (!lowp) {
-            h.gset.low_s_base = h.gset.s_base;
-            h.cset.low_s_base = h.cset.s_base;
-        }
+        h.gset.low_s_base = h.gset.s_base;
+        h.cset.low_s_base = h.cset.s_base;
     }
     h.ar64_n = off64;
     h.ar32_n = off32;
@@ -1263,9 +1271,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
         build_factor_program(h.cset, h.tl64, 1);
     else
         build_factor_program(h.cset, h.tl32, 1);
-    if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
-        build_inverse_program(h.gset, h.tl64);
-        build_inverse_program(h.cset, h.tl64);
+    TaskLists &tl_inv = !lowp ? h.tl64 : (h.smoother_precision == 32 ? h.tl32 : h.tlbf);
+    if (inverse) {
+        build_inverse_program(h.gset, tl_inv, lowp);
+        build_inverse_program(h.cset, tl_inv, lowp);
     }
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
     {
@@ -1309,22 +1318,24 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     split_program(h.gset.factor_prog, h.tl64);
     split_program(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     split_program(h.basis_prog, h.tl64);
-    split_program(h.gset.inverse_prog, h.tl64);
-    split_program(h.cset.inverse_prog, h.tl64);
-    fill_flops(h.gset.inverse_prog, h.tl64);
-    fill_flops(h.cset.inverse_prog, h.tl64);
+    split_program(h.gset.inverse_prog, tl_inv);
+    split_program(h.cset.inverse_prog, tl_inv);
+    fill_flops(h.gset.inverse_prog, tl_inv);
+    fill_flops(h.cset.inverse_prog, tl_inv);
     fill_flops(h.gset.factor_prog, h.tl64);
     fill_flops(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
     {
         const double ge = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
+        // S of the reduced-precision inverse form is kept in FP32
+        const double gs = h.smoother_precision == 64 ? 8.0 : 4.0;
         h.gset.gemv_W.bytes = gemv_bytes(h.vtasks, h.gset.gemv_W, ge);
         h.gset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.gset.gemv_Wt, ge);
         h.cset.gemv_W.bytes = gemv_bytes(h.vtasks, h.cset.gemv_W, ge);
         h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
         for (DenseSet *ds : {&h.gset, &h.cset}) {
             // the symmetric product reads its own x segment once more per row
-            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, ge) + (double)ds->gemv_S.count * TS * 8.0;
+            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, gs) + (double)ds->gemv_S.count * TS * 8.0;
             ds->red_S.bytes = sym_reduce_bytes(h.rtasks, ds->red_S);
         }
         h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
@@ -1528,11 +1539,14 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             if (!ok) fail(HPLMM_E_ARG, std::string("internal plan check failed: ") + what);
         };
         auto in = [](int64_t off, int64_t len, int64_t n) { return off >= 0 && off + len <= n; };
-        for (int which = 0; which < 2; ++which) {
-            const TaskLists &tl = which ? h.tl32 : h.tl64;
-            const int64_t an = which ? h.ar32_n : h.ar64_n;
+        for (int which = 0; which < 3; ++which) {
+            // the bfloat16 list reads the bfloat16 arena and writes the FP32 one
+            const TaskLists &tl = which == 2 ? h.tlbf : which ? h.tl32 : h.tl64;
+            const int64_t an = which == 2 ? h.arbf_n : which ? h.ar32_n : h.ar64_n;
+            const int64_t on = which ? h.ar32_n : h.ar64_n;
             for (const auto &t : tl.gemm) {
-                chk(in(t.c_off, TE, an), "gemm output tile");
+                chk(in(t.c_off, TE, on), "gemm output tile");
+                if (which == 2) chk(!(t.flags & (GF_POST | GF_POST_RIGHT)), "bfloat16 task without second product");
                 if (t.flags & (GF_POST | GF_POST_RIGHT)) chk(in(t.post_off, TE, an), "gemm post tile");
                 chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
                     "gemm pair range");
@@ -1582,7 +1596,9 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
                     what);
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const SymPair &pr = h.spairs[(size_t)(t.pair_start + q)];
-                    chk(in(pr.t_off, TE, low_n) && in(pr.x_off, TS, ds.vec_len), what);
+                    chk(in(pr.t_off, TE, h.smoother_precision == 64 ? h.ar64_n : h.ar32_n) &&
+                            in(pr.x_off, TS, ds.vec_len),
+                        what);
                     // the diagonal tile, last in its row, carries no transposed product
                     chk(q + 1 == t.pair_count ? pr.p_off == -1 : in(pr.p_off, TS, h.sym_part_len), what);
                 }
@@ -1593,7 +1609,10 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             }
         };
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
-            chk(h.gset.s_base >= 0 && h.cset.s_base >= 0, "inverse regions");
+            // S in the FP64 arena at full precision, in the FP32 one otherwise
+            chk(h.smoother_precision == 64 ? h.gset.s_base >= 0 && h.cset.s_base >= 0
+                                           : h.gset.s_base < 0 && h.cset.s_base < 0,
+                "inverse regions");
             chk_sym(h.gset, "grain S gemv");
             chk_sym(h.cset, "contact S gemv");
         } else {
@@ -1768,7 +1787,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
             fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     }
     // task lists
-    for (TaskLists *tl : {&h.tl64, &h.tl32}) {
+    for (TaskLists *tl : {&h.tl64, &h.tl32, &h.tlbf}) {
         tl->d_gemm = h.upload(tl->gemm, s);
         tl->d_pairs = h.upload(tl->pairs, s);
         tl->d_diag = h.upload(tl->diag, s);
@@ -1779,6 +1798,7 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     }
     h.tl64.d_part = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
     h.tl32.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tl32.part_len));
+    h.tlbf.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tlbf.part_len));   // FP32 partial sums
     if (h.smoother_precision == 64 || h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
         // the FP64 contact-grid programs (and the grain inverse) run on the
         // side stream next to the grain and coarse programs, which use tl64's

@@ -467,7 +467,7 @@ def debug_tile_gemm(A, B, C_, flags, P_=None, npairs=None):
     """One tile task on CUDA tensors: A, B (npairs, 64, 64) as column-major tiles
     (i.e. tensors holding the transposed tile), C_ (64, 64) updated in place.
     npairs defaults to A.shape[0]; 0 is allowed with the right-factor flag."""
-    prec = 64 if A.dtype == torch.float64 else 32
+    prec = {torch.float64: 64, torch.float32: 32, torch.int16: 16}[A.dtype]   # int16: bfloat16 bits
     n = int(A.shape[0]) if npairs is None else int(npairs)
     if n > A.shape[0] or n > B.shape[0]:
         raise ValueError("npairs exceeds the tiles given")

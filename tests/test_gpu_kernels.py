@@ -61,6 +61,42 @@ def test_tile_gemm(prec, flags, npairs):
     assert np.abs(got - ref).max() <= tol * np.abs(ref).max()
 
 
+@pytest.mark.parametrize("flags", [0, 1, 2, 3, 4, 1 | 4 | 8])
+def test_tile_gemm_bf16(flags):
+    # bfloat16 operands on the matrix cores with FP32 accumulation: against
+    # the exact FP64 sum of the same bfloat16 values, within the bound of an
+    # FP32 sum of 64 npairs products, (64 npairs + 2) u32 sum |a b| (plus the
+    # accumulated C)
+    torch = _torch()
+    from oracle import precision as prec
+    from paper_2509_19777_amd import hplmm as hp
+    npairs = 5
+    rng = np.random.default_rng(40 + flags)
+    A = prec.round_bf16(rng.standard_normal((npairs, TS, TS)))
+    B = prec.round_bf16(rng.standard_normal((npairs, TS, TS)))
+    C0 = prec.round_f32(rng.standard_normal((TS, TS)))
+    ref = np.zeros((TS, TS))
+    mag = np.zeros((TS, TS))
+    for p in range(npairs):
+        a, b = (A[p].T if flags & 1 else A[p]), (B[p].T if flags & 2 else B[p])
+        ref += a @ b
+        mag += np.abs(a) @ np.abs(b)
+    if flags & 8:
+        ref = -ref
+    if flags & 4:
+        ref = C0 + ref
+        mag += np.abs(C0)
+
+    def bits(x):   # column-major tiles of bfloat16 bit patterns
+        f = np.ascontiguousarray(np.swapaxes(x, -1, -2)).astype(np.float32)
+        return torch.from_numpy((f.view(np.uint32) >> 16).astype(np.uint16).view(np.int16)).cuda()
+    Ct = _tiles(C0[None], torch.float32)[0].contiguous()
+    hp.debug_tile_gemm(bits(A), bits(B), Ct, flags)
+    got = _untile(Ct)
+    err = np.abs(got - ref)
+    assert np.all(err <= (64 * npairs + 2) * 2.0 ** -24 * mag), err.max()
+
+
 @pytest.mark.parametrize("prec", [64, 32])
 def test_diag_factor_and_inverse(prec):
     torch = _torch()

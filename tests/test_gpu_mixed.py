@@ -1,18 +1,47 @@
 """Reduced-precision smoother on the GPU against the oracle's emulation, in
-both smoother forms.
+both smoother forms, with bars derived from the arithmetic.
 
-Factor form: grain smoother operators are the FP64 inverse Cholesky factors
-rounded to the storage precision, so the GPU and the oracle store identical
-values up to rare rounding-boundary cases; contact-grid factors are computed
-in FP32 on both sides (matrix cores vs LAPACK), which differ by about
-kappa(A_zeta) u32.  Bounds: M_g (grains only) 1e-12 relative; operators
-involving the FP32 contact factorisation 3e-5 (FP32 storage) and 3e-3 (BF16
-storage), measured on the 16^3 pore case whose local condition numbers are
-about 1e3.
-Inverse form: every block's S = W^T W is formed in FP64 and rounded once, on
-both sides, so every operator meets 1e-12 against the emulation (again up to
-rare rounding-boundary cases).
-FGMRES itself stays FP64 and must reach the 1e-8 true residual.
+Inverse form (the default).  Every block is factored and inverted in FP64
+(W = L^-1, the same values on both sides to ~1e-13), W is rounded to the
+storage precision (Wp: FP32 or bfloat16, identical on both sides except for
+values within ~1e-13 of a rounding boundary), and S = Wp^T Wp is formed on
+the matrix cores (FP32 or bfloat16 operands) with FP32 accumulation and kept
+in FP32; the emulation forms the same Gram sum exactly and rounds it once to
+FP32.  A sum of n products accumulated in FP32 is within gamma_n u32 of the
+exact sum relative to the sum of the products' magnitudes, and the final
+rounding adds u32: |S_gpu - S_emu| <= (n + 2) u32 |Wp|^T |Wp| entrywise, so
+for one application |z_gpu - z_emu| <= (n + 2) u32 |sum_c E_c |Wp_c|^T |Wp_c|
+|R_c r||, computed here from the emulation's Wp (the oracle's values): a
+worst-case bar of ~6e-5 of |z| here.  The observed differences (~1e-7) are
+also held to the 1e-5 the reduced-precision smoother is required to meet.
+
+Factor form.  Grain operators are the FP64 W rounded once: identical stored
+values, bar 1e-12.  The contact grids are factored in FP32 on the matrix
+cores (the emulation uses LAPACK in FP32); the two factors differ by rounding
+amplified by the block's condition number:
+* pin of the GPU's factor alone: the backward error of every contact block,
+  |A - L L^T|_F <= 2 (n + 1) u32 trace(A) (the normwise form of the classical
+  componentwise bound gamma_{n+1} |L| |L^T|, with |L|_F^2 = trace(A) and a
+  factor 2 for the FP32 rounding of A itself and for the explicit inverses of
+  the diagonal tiles the panel uses), and the inverse factor's residual
+  |W L - I|_F <= 2 (n + 1) u32 | |W| |L| |_F;
+* apply bar, FP32 storage: two factorisations with backward errors e1, e2
+  give inverse operators that differ by about kappa (e1 + e2) relative, and
+  the triangular inversions add errors of the same order: 2 kappa_max
+  (e_gpu + e_emu) with the measured largest backward errors;
+* apply bar, bfloat16 storage: each side rounds its FP32 W entrywise with
+  relative error at most u16 = 2^-9, adding (4 u16 + 2 u16^2) |sum_c E_c
+  |W_c|^T |W_c| |R_c r|| to the FP32 bar.  That is ~1e-2 of |z|: two correct
+  FP32 factors round to different bfloat16 values wherever they straddle a
+  rounding boundary, so the 1e-5 bar is not reachable for this form against
+  an independent FP32 factorisation (the inverse form meets it).
+
+Compositions (Eqs. 16, 25): M_CG^-1 r = z2 + M_g^-1 (r - A z2), z2 = M_zeta^-1 r,
+so a difference d in z2 reaches z as (I - M_g^-1 A) d, at most |I - M_g^-1 A|_2
+|d| (estimated by power iteration, 10 % margin), plus the grain operator's own
+bar on r - A z2; M^-1 applies M_CG^-1 to r - A M_G^-1 r (the coarse part is
+FP64 on both sides).  FGMRES itself stays FP64 and must reach the 1e-8 true
+residual.
 """
 import numpy as np
 import pytest
@@ -20,6 +49,9 @@ import pytest
 from paper_2509_19777_amd import synth
 
 pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+U16 = 2.0 ** -9
 
 
 @pytest.fixture(scope="module", params=[(32, "factors"), (16, "factors"), (32, "inverse"), (16, "inverse")])
@@ -41,27 +73,124 @@ def mixed(request):
     return prec, p, A, b, H, S
 
 
+@pytest.fixture(scope="module")
+def contact_errors(mixed):
+    """Backward errors of the GPU's and the emulation's FP32 contact factors
+    (factor form), and the largest contact-block condition number."""
+    from paper_2509_19777_amd import hplmm as hp
+    prec, p, A, b, H, S = mixed
+    if S.smoother_form() != "factors":
+        return None
+    lay = hp.debug_contact_layout(S)
+    assert lay.shape[0] == len(H.contact_dofs)
+    rows = []
+    for m, d in enumerate(H.contact_dofs):
+        n, nt, arena, a_off, w_off, _ = (int(x) for x in lay[m])
+        assert n == d.size and arena == 1
+        Az = A[d][:, d].toarray()
+        L = hp.debug_read_lower(S, 1, a_off, n, nt)
+        W = hp.debug_read_lower(S, 1, w_off, n, nt)
+        L32 = np.linalg.cholesky(Az.astype(np.float32)).astype(np.float64)
+        rows.append((n, np.trace(Az), np.linalg.norm(Az - L @ L.T), np.linalg.norm(W @ L - np.eye(n)),
+                     np.linalg.norm(np.abs(W) @ np.abs(L)), np.linalg.norm(Az - L @ L.T) / np.linalg.norm(Az),
+                     np.linalg.norm(Az - L32 @ L32.T) / np.linalg.norm(Az), np.linalg.cond(Az)))
+    return np.array(rows)
+
+
 def _rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
 
 
-def test_grain_smoother_matches_emulation(mixed):
+def _abs_products(dofs, Ws, r):
+    """|sum_c E_c |W_c|^T |W_c| |R_c r||."""
+    g = np.zeros_like(r)
+    for d, W in zip(dofs, Ws):
+        if W is not None and d.size:
+            aW = np.abs(W)
+            g[d] += aW.T @ (aW @ np.abs(r[d]))
+    return np.linalg.norm(g)
+
+
+class Bounds:
+    """Absolute bounds on |z_gpu - z_emu| for the grain and contact-grid
+    operators of one configuration (see the module notes)."""
+
+    def __init__(self, prec, H, A, contact_errors):
+        self.prec, self.H, self.A, self.ce = prec, H, A, contact_errors
+        self.inverse = H.lowp.form == "inverse"
+
+    def grains(self, r):
+        H = self.H
+        if not self.inverse:
+            return 1e-12 * np.linalg.norm(H.apply_Mg(r))
+        n = max(d.size for d in H.grain_dofs)
+        return (n + 2) * U32 * _abs_products(H.grain_dofs, H.lowp.grain_Wp, r)
+
+    def contacts(self, r):
+        H = self.H
+        if self.inverse:
+            n = max(d.size for d in H.contact_dofs)
+            return (n + 2) * U32 * _abs_products(H.contact_dofs, H.lowp.contact_Wp, r)
+        kappa = self.ce[:, 7].max()
+        bar = 2.0 * kappa * (self.ce[:, 5].max() + self.ce[:, 6].max()) * np.linalg.norm(H.apply_Mzeta(r))
+        if self.prec == 16:
+            bar += (4 * U16 + 2 * U16 ** 2) * _abs_products(H.contact_dofs, [W * (1 + U16) for W in H.lowp.contact_W],
+                                                             r)
+        return bar
+
+
+def _composition_gain(H, A, steps=30):
+    """|I - M_g A|_2 by power iteration on (I - M_g A)^T (I - M_g A) =
+    (I - A M_g)(I - M_g A) (A and M_g symmetric)."""
+    v = np.random.default_rng(5).standard_normal(A.shape[0])
+    lam = 0.0
+    for _ in range(steps):
+        v /= np.linalg.norm(v)
+        w = v - H.apply_Mg(A @ v)
+        v = w - A @ H.apply_Mg(w)
+        lam = np.linalg.norm(v)
+    return np.sqrt(lam)
+
+
+def test_contact_factor_backward_error(mixed, contact_errors):
+    prec, p, A, b, H, S = mixed
+    if contact_errors is None:
+        pytest.skip("the inverse form factors every block in FP64")
+    n, tr, res, wres, wl = (contact_errors[:, i] for i in range(5))
+    chol = res / (2 * (n + 1) * U32 * tr)
+    inv = wres / (2 * (n + 1) * U32 * wl)
+    print(f"contact FP32 factors: backward error / bound max {chol.max():.3f}, "
+          f"inverse residual / bound max {inv.max():.3f}, largest |A - L L^T|_F / |A|_F "
+          f"{contact_errors[:, 5].max():.2e} (LAPACK FP32 {contact_errors[:, 6].max():.2e})")
+    assert chol.max() <= 1.0
+    assert inv.max() <= 1.0
+
+
+@pytest.mark.parametrize("which", [4, 3, 2, 0])
+def test_apply_matches_emulation(mixed, contact_errors, which):
     import torch
     prec, p, A, b, H, S = mixed
-    for seed in (10, 11):
+    B = Bounds(prec, H, A, contact_errors)
+    gain = 1.1 * _composition_gain(H, A)
+    ops = {4: H.apply_Mg, 3: H.apply_Mzeta, 2: H.apply_MCG, 0: H.apply}
+    for seed in (12, 13):
         r = synth.random_vector(A.shape[0], seed)
-        z = S.apply(torch.from_numpy(r).cuda(), 4).cpu().numpy()
-        assert _rel(z, H.apply_Mg(r)) <= 1e-12
-
-
-def test_full_apply_matches_emulation(mixed):
-    import torch
-    prec, p, A, b, H, S = mixed
-    tol = 1e-12 if S.smoother_form() == "inverse" else (3e-5 if prec == 32 else 3e-3)
-    for which, op in ((3, H.apply_Mzeta), (2, H.apply_MCG), (0, H.apply)):
-        r = synth.random_vector(A.shape[0], 12)
         z = S.apply(torch.from_numpy(r).cuda(), which).cpu().numpy()
-        assert _rel(z, op(r)) <= tol, (which, _rel(z, op(r)))
+        zo = ops[which](r)
+        if which == 4:
+            bound = B.grains(r)
+        elif which == 3:
+            bound = B.contacts(r)
+        else:
+            rin = r if which == 2 else r - A @ H.apply_MG(r)
+            bound = gain * B.contacts(rin) + B.grains(rin - A @ H.apply_Mzeta(rin))
+        bar = max(bound / np.linalg.norm(zo), 1e-12)
+        print(f"which {which} ({prec}, {S.smoother_form()}): {_rel(z, zo):.2e} against the derived bar {bar:.2e}")
+        assert _rel(z, zo) <= bar, (which, _rel(z, zo), bar)
+        if S.smoother_form() == "inverse":
+            # the reduced-precision target, met with room to spare in this form
+            # (the worst-case bar above takes gamma_n = n u32 for every sum)
+            assert _rel(z, zo) <= 1e-5
 
 
 def test_fgmres_reaches_fp64_tolerance(mixed):
@@ -74,7 +203,8 @@ def test_fgmres_reaches_fp64_tolerance(mixed):
 
 def test_every_launch_shape_matches_emulation(mixed):
     # the smoother launches at 16 waves per work-group (narrow storage runs
-    # its symmetric kernel at 4) and the autotuner's own choices keep the bars
+    # its symmetric kernel at 4) and the autotuner's own choices give the same
+    # operator up to FP64 rounding of the products
     import torch
     prec, p, A, b, H, S = mixed
     r = synth.random_vector(A.shape[0], 13)
@@ -87,7 +217,5 @@ def test_every_launch_shape_matches_emulation(mixed):
     S.autotune(reps=2)
     za = S.apply(torch.from_numpy(r).cuda(), 0).cpu().numpy()
     S.set_tuning([])
-    tol = 1e-12 if S.smoother_form() == "inverse" else (3e-5 if prec == 32 else 3e-3)
     for z in (z16, za):
-        assert _rel(z, H.apply(r)) <= tol
         assert _rel(z, z0) <= 1e-13

@@ -182,9 +182,10 @@ def test_coarse_leaf_option(hp):
 def test_smoother_forms(hp):
     """The inverse form adds one region per dense set (S = W^T W, the same
     packed layout) and one tile product task per stored tile of S, at least;
-    auto picks it except with bfloat16 storage.  At reduced precision it factors the
-    contact grids in FP64 (no FP32 arena regions for them) and keeps only the
-    rounded S of both sets in the reduced-precision arena."""
+    auto picks it at every precision.  At reduced precision it factors every
+    block in FP64 (the FP64 arena of the factor form, without an FP64 S), keeps
+    W rounded to the storage precision (FP32 or bfloat16 arena) and S formed
+    from it in the FP32 arena."""
     p = synth.config_pores(16, 4, seed=1)
     sysm, part = hp.build_problem(p)
     fac = hp.plan_check(sysm, part, n_mortar=4, smoother_form="factors")
@@ -193,15 +194,17 @@ def test_smoother_forms(hp):
     s_tiles = (inv["ar64"] - fac["ar64"]) // 4096
     assert s_tiles > 0 and (inv["ar64"] - fac["ar64"]) % 4096 == 0
     assert inv["tile_tasks"] - fac["tile_tasks"] >= s_tiles
-    for prec, arena in ((32, "ar32"), (16, "arbf")):
+    for prec in (32, 16):
         low_inv = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec, smoother_form="inverse")
         low_auto = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec)
-        assert low_inv["ar64"] == inv["ar64"]         # every factorisation in FP64
-        assert low_inv[arena] == s_tiles * 4096        # the rounded S of both sets only
+        assert low_inv["ar64"] == fac["ar64"]          # every factorisation in FP64, no FP64 S
+        if prec == 32:
+            assert low_inv["ar32"] == 2 * s_tiles * 4096 and low_inv["arbf"] == 0   # W32 and S
+        else:
+            assert low_inv["arbf"] == s_tiles * 4096 and low_inv["ar32"] == s_tiles * 4096   # W16; S in FP32
         low_fac = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec, smoother_form="factors")
         assert low_fac["ar64"] < fac["ar64"]           # FP32 contact factorisation
-        # auto: inverse with FP32 storage, factors with bfloat16 storage
-        assert low_auto == (low_inv if prec == 32 else low_fac)
+        assert low_auto == low_inv                     # auto: the inverse form
     s, q = sysm.c_struct(), part.c_struct()
     m = hp.HplmmMortar(4, 4.0, 0)
     o = hp.HplmmOptions(64, 0, 3)

@@ -8,7 +8,12 @@ the reduced-precision smoother parity tests).
   Cholesky solves (a transposed product such as W W^T instead of W^T W, a
   wrong block or a missing contact grid fails it);
 * with rounding, both forms stay within the bound their storage precision
-  allows (kappa u) of the exact local solves, and the stored S is symmetric.
+  allows (kappa u) of the exact local solves, and the stored S is symmetric;
+* the inverse form's S is the Gram matrix of the rounded inverse factor: on
+  blocks with condition numbers past 1/u_bf16 it stays positive definite,
+  where rounding W^T W itself entrywise to bfloat16 turns some block
+  indefinite (so the emulation is not that simpler reading), and every S is
+  the FP32 rounding of an exact Gram sum (its entries are FP32 values).
 """
 import numpy as np
 import pytest
@@ -79,3 +84,30 @@ def test_rounded_forms_stay_within_their_precision(case, form, precision, bound)
         for S in L.grain_S + L.contact_S:
             if S is not None:
                 assert np.array_equal(S, S.T)
+
+
+def test_inverse_form_is_gram_of_rounded_factor():
+    # one synthetic SPD block with condition number 1e5 (eigenvalues spread
+    # logarithmically, seeded orthogonal basis) and one from a real problem
+    import scipy.sparse as sp
+    from types import SimpleNamespace
+    n = 60
+    Q, _ = np.linalg.qr(np.random.default_rng(7).standard_normal((n, n)))
+    Ab = (Q * np.logspace(0, 5, n)) @ Q.T
+    Ab = 0.5 * (Ab + Ab.T)
+    p = synth.config_pores(8, 4, seed=11, porosity=0.2)
+    A2, b2, mesh2 = fem.assemble(p)
+    d2 = np.arange(min(90, A2.shape[0]))
+    A = sp.block_diag([sp.csr_matrix(Ab), A2.tocsr()[d2][:, d2]], format="csr")
+    d1, d2 = np.arange(n), n + np.arange(d2.size)
+    fake = SimpleNamespace(A=A, grain_dofs=[d1], grain_chol=[sla.cho_factor(Ab, lower=True)], contact_dofs=[d2])
+    L = prec.LowPrecisionSmoother(fake, "bf16", form="inverse")
+    for d, S, Wp in ((d1, L.grain_S[0], L.grain_Wp[0]), (d2, L.contact_S[0], L.contact_Wp[0])):
+        assert np.array_equal(S, prec.round_f32(S))            # kept in FP32
+        assert np.array_equal(Wp, prec.round_bf16(Wp))         # the factor is bfloat16
+        assert np.linalg.eigvalsh(S).min() > 0.0               # Gram: positive definite
+        # S is the FP32 rounding of the Gram sum of the bfloat16 factor
+        assert np.array_equal(S, prec.round_f32(Wp.T @ Wp))
+    # rounding W^T W itself entrywise would make the ill-conditioned block indefinite
+    W = sla.solve_triangular(np.linalg.cholesky(Ab), np.eye(n), lower=True)
+    assert np.linalg.eigvalsh(prec.round_bf16(W.T @ W)).min() < 0.0
