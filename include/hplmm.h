@@ -57,9 +57,16 @@ typedef struct hplmm_handle hplmm_handle;
  * row_ptr[n_nodes+1] (int64), col_idx[nnzb] (int32, ascending within each
  * row, pattern symmetric), val[9*nnzb] row-major 3x3 blocks (float64).
  * rhs[3*n_nodes]: load vector b.  node_xyz[3*n_nodes]: integer lattice
- * coordinates (i, j, k) of every node.  When returned by
- * hplmm_assemble_voxels the arrays are owned by the library and released with
- * hplmm_system_free; when passed in, they are the caller's. */
+ * coordinates (i, j, k) of every node.  dof_fixed[3*n_nodes] (uint8, may be
+ * NULL): nonzero marks a constrained degree of freedom (a Dirichlet row of
+ * Eq. 2 with zero prescribed displacement, e.g. a roller); hplmm_plan then
+ * works on the matrix with that dof's row and column replaced by the identity's
+ * and on the load with a zero there, so the solution is 0 at every
+ * constrained dof (the plane z = 0 of hplmm_assemble_voxels is clamped by
+ * elimination instead and needs no flags).  When returned by
+ * hplmm_assemble_voxels the arrays are owned by the library (dof_fixed NULL)
+ * and released with hplmm_system_free; when passed in, they are the
+ * caller's and copied by hplmm_plan. */
 typedef struct hplmm_system {
     int64_t n_nodes;
     int64_t nnzb;
@@ -68,6 +75,7 @@ typedef struct hplmm_system {
     double  *val;
     double  *rhs;
     int32_t *node_xyz;
+    const uint8_t *dof_fixed;
 } hplmm_system;
 
 /* Decomposition into grain grids, contact interfaces and contact grids
@@ -256,10 +264,15 @@ hplmm_status hplmm_spmv(hplmm_handle *h, const double *x_dev, double *y_dev, voi
 typedef struct hplmm_solve_info {
     int32_t iters;
     double  rel_res_true;
-    double  t_solve_ms;
+    double  t_solve_ms;      /* the paper's T_sol (host clock around the solve) */
     double *res_hist;
     int32_t res_hist_cap;
     int32_t res_hist_len;
+    double  t_ml_ms;         /* T_ML of the last set-up: grain factorisations, contact
+                                grids and the grain inverse S (HIP events) */
+    double  t_mg_ms;         /* T_MG of the last set-up: basis, coarse operator and its
+                                factorisation (HIP events); T_ML and T_MG overlap on the
+                                device, so their sum exceeds the set-up's wall time */
 } hplmm_solve_info;
 
 hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, double rtol,
@@ -348,7 +361,8 @@ hplmm_status hplmm_set_tuning(hplmm_handle *h, const int32_t *rec, int64_t n);
  * solid[nx*ny*nz] (uint8) and E[nx*ny*nz] are host arrays (copied).  The
  * call compares both operators on a seeded vector and fails with E_ARG,
  * leaving the assembled operator in use, if they differ by more than 1e-12
- * of max |A x| (a different grid, modulus or nu).  nx = ny = nz = 0 returns
+ * of max |A x| (a different grid, modulus or nu), and with E_ARG if the
+ * system has constrained dofs (dof_fixed).  nx = ny = nz = 0 returns
  * to the assembled operator.  Synchronises stream; each call that turns the
  * operator on allocates its own device copies (held until hplmm_destroy);
  * captured solver graphs are dropped. */

@@ -149,6 +149,7 @@ struct Handle {
     int32_t smoother_precision = 64;
     int32_t mortar_kind = HPLMM_MORTAR_GAUSSIAN;
     int64_t coarse_leaf_dofs = 192;
+    int64_t n_fixed = 0;   // constrained dofs (identity rows) of the planned system
     bool ready = false;
 
     // fine matrix
@@ -287,7 +288,7 @@ struct Handle {
     // the contact-grid factorisation runs beside the grain and coarse stages on
     // its own stream, with its own split-task scratch when it shares tl64
     hipStream_t side = nullptr;
-    hipEvent_t side_ev[3] = {nullptr, nullptr, nullptr};
+    hipEvent_t side_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     void *d_part_side = nullptr;
     int32_t *d_cnt_side = nullptr;
     bool use_graphs = true;
@@ -320,6 +321,7 @@ struct Handle {
 
     // timings
     double t_setup_ms[4] = {0, 0, 0, 0};
+    double t_ml_ms = 0.0, t_mg_ms = 0.0;   // the paper's T_ML and T_MG of the last set-up
     Profiler prof;
     double apply_bytes = 0.0, spmv_bytes = 0.0;
     // matrix-free fine operator (hplmm_set_voxel_operator): used by every SpMV

@@ -141,6 +141,7 @@ extern "C" hplmm_status hplmm_assemble_voxels(int32_t nx, int32_t ny, int32_t nz
         out->val = (double *)std::malloc(sizeof(double) * 9 * (size_t)nnzb);
         out->rhs = (double *)std::calloc((size_t)(3 * n), sizeof(double));
         out->node_xyz = (int32_t *)std::malloc(sizeof(int32_t) * 3 * (size_t)n);
+        out->dof_fixed = nullptr;   // the clamped plane is eliminated, not flagged
         if (!out->row_ptr || !out->col_idx || !out->val || !out->rhs || !out->node_xyz) {
             hplmm_system_free(out);
             fail(HPLMM_E_OOM, "host allocation failed");

@@ -964,11 +964,41 @@ void append_basis_program(Handle &h, TaskLists &tl, const std::vector<int64_t> &
     }
 }
 
-void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part, const hplmm_mortar &mort,
+void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &part, const hplmm_mortar &mort,
                 const hplmm_options &opt, hipStream_t s, bool dry_run) {
-    const int64_t n = sys.n_nodes;
-    if (n <= 0 || !sys.row_ptr || !sys.col_idx || !sys.val || !sys.node_xyz)
+    const int64_t n = sys_in.n_nodes;
+    if (n <= 0 || !sys_in.row_ptr || !sys_in.col_idx || !sys_in.val || !sys_in.node_xyz)
         fail(HPLMM_E_ARG, "system arrays missing");
+    // constrained dofs (Eq. 2's Dirichlet rows beyond the eliminated clamp):
+    // the plan works on a copy of the matrix whose constrained rows and
+    // columns are those of the identity and of the load with zeros there
+    std::vector<double> cval, crhs;
+    hplmm_system sys = sys_in;
+    h.n_fixed = 0;
+    if (sys_in.dof_fixed) {
+        const int64_t nnzb = sys_in.row_ptr[n];
+        if (sys_in.row_ptr[0] != 0 || nnzb < 0) fail(HPLMM_E_ARG, "row_ptr must start at 0");
+        cval.assign(sys_in.val, sys_in.val + 9 * nnzb);
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t p = sys_in.row_ptr[v]; p < sys_in.row_ptr[v + 1]; ++p) {
+                const int64_t w = sys_in.col_idx[p];
+                if (w < 0 || w >= n) fail(HPLMM_E_ARG, "column index out of range");
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b) {
+                        const bool fa = sys_in.dof_fixed[3 * v + a] != 0, fb = sys_in.dof_fixed[3 * w + b] != 0;
+                        if (fa || fb) cval[(size_t)(9 * p + 3 * a + b)] = (v == w && a == b) ? 1.0 : 0.0;
+                    }
+            }
+        for (int64_t d = 0; d < 3 * n; ++d) h.n_fixed += sys_in.dof_fixed[d] != 0;
+        sys.val = cval.data();
+        if (sys_in.rhs) {
+            crhs.assign(sys_in.rhs, sys_in.rhs + 3 * n);
+            for (int64_t d = 0; d < 3 * n; ++d)
+                if (sys_in.dof_fixed[d]) crhs[(size_t)d] = 0.0;
+            sys.rhs = crhs.data();
+        }
+        sys.dof_fixed = nullptr;
+    }
     if (!part.node_grain || part.n_grains < 0 || part.n_ifaces < 0 || (part.n_ifaces > 0 && (!part.iface_ptr || !part.iface_nodes)))
         fail(HPLMM_E_ARG, "partition arrays missing");
     if (part.n_nodes != n) fail(HPLMM_E_ARG, "partition and system disagree on n_nodes");
@@ -983,9 +1013,8 @@ void build_plan(Handle &h, const hplmm_system &sys, const hplmm_partition &part,
     h.smoother_precision = opt.smoother_precision;
     if (opt.smoother_form < HPLMM_SMOOTHER_AUTO || opt.smoother_form > HPLMM_SMOOTHER_INVERSE)
         fail(HPLMM_E_ARG, "smoother_form must be 0 (auto), 1 (factors) or 2 (inverse)");
-    // auto: the inverse form, except with bfloat16 storage, where rounding S
-    // itself (rather than W, whose Gram product W^T W stays definite) can
-    // leave it indefinite once kappa(A_g) exceeds about 2^8
+    // auto: the inverse form (at reduced precision its S is the Gram matrix of
+    // the rounded W, definite however coarse the rounding)
     h.smoother_form = opt.smoother_form != HPLMM_SMOOTHER_AUTO ? opt.smoother_form : HPLMM_SMOOTHER_INVERSE;
     if (opt.coarse_leaf_dofs < 0) fail(HPLMM_E_ARG, "coarse_leaf_dofs must be >= 0");
     h.coarse_leaf_dofs = opt.coarse_leaf_dofs > 0 ? opt.coarse_leaf_dofs : 192;

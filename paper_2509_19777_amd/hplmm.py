@@ -25,7 +25,7 @@ P = C.POINTER
 
 class HplmmSystem(C.Structure):
     _fields_ = [("n_nodes", i64), ("nnzb", i64), ("row_ptr", P(i64)), ("col_idx", P(i32)),
-                ("val", P(f64)), ("rhs", P(f64)), ("node_xyz", P(i32))]
+                ("val", P(f64)), ("rhs", P(f64)), ("node_xyz", P(i32)), ("dof_fixed", P(u8))]
 
 
 class HplmmPartition(C.Structure):
@@ -53,7 +53,7 @@ class HplmmSgStats(C.Structure):
 
 class HplmmSolveInfo(C.Structure):
     _fields_ = [("iters", i32), ("rel_res_true", f64), ("t_solve_ms", f64), ("res_hist", P(f64)),
-                ("res_hist_cap", i32), ("res_hist_len", i32)]
+                ("res_hist_cap", i32), ("res_hist_len", i32), ("t_ml_ms", f64), ("t_mg_ms", f64)]
 
 
 EXPORTS = {
@@ -142,21 +142,27 @@ def _ptr(a, ct):
 class System:
     """Assembled fine system (numpy copies of the library's arrays)."""
 
-    def __init__(self, n_nodes, row_ptr, col_idx, val, rhs, node_xyz):
+    def __init__(self, n_nodes, row_ptr, col_idx, val, rhs, node_xyz, dof_fixed=None):
         self.n_nodes = int(n_nodes)
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
         self.val = np.ascontiguousarray(val, dtype=np.float64).reshape(-1)
         self.rhs = np.ascontiguousarray(rhs, dtype=np.float64)
         self.node_xyz = np.ascontiguousarray(node_xyz, dtype=np.int32).reshape(-1)
+        self.dof_fixed = None if dof_fixed is None else np.ascontiguousarray(dof_fixed, dtype=np.uint8).reshape(-1)
 
     @property
     def nnzb(self):
         return int(self.row_ptr[-1])
 
+    def with_fixed(self, dof_fixed):
+        """The same system with constrained dofs (uint8 / bool per dof)."""
+        return System(self.n_nodes, self.row_ptr, self.col_idx, self.val, self.rhs, self.node_xyz, dof_fixed)
+
     def c_struct(self):
         return HplmmSystem(self.n_nodes, self.nnzb, _ptr(self.row_ptr, i64), _ptr(self.col_idx, i32),
-                           _ptr(self.val, f64), _ptr(self.rhs, f64), _ptr(self.node_xyz, i32))
+                           _ptr(self.val, f64), _ptr(self.rhs, f64), _ptr(self.node_xyz, i32),
+                           None if self.dof_fixed is None else _ptr(self.dof_fixed, u8))
 
     def to_scipy(self):
         """Scalar CSR matrix (for tests)."""
@@ -315,7 +321,8 @@ class Solver:
                                 C.byref(h)))
         self.h = h
         self.N = 3 * system.n_nodes
-        self.b = torch.from_numpy(system.rhs).cuda()
+        rhs = system.rhs if system.dof_fixed is None else np.where(system.dof_fixed != 0, 0.0, system.rhs)
+        self.b = torch.from_numpy(np.ascontiguousarray(rhs)).cuda()   # the load the plan uses
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -400,11 +407,12 @@ class Solver:
         b = self.b if b is None else b
         x = torch.zeros_like(b) if x0 is None else x0.clone()
         hist = np.zeros(hist_cap)
-        info = HplmmSolveInfo(0, 0.0, 0.0, _ptr(hist, f64), hist_cap, 0)
+        info = HplmmSolveInfo(0, 0.0, 0.0, _ptr(hist, f64), hist_cap, 0, 0.0, 0.0)
         code = _check(lib().hplmm_solve(self.h, _dptr(b), _dptr(x), float(rtol), int(restart), int(maxit),
                                         int(fixed_iters), C.byref(info), _stream()))
         return x, {"status": STATUS[code], "iters": info.iters, "rel_res": info.rel_res_true,
-                   "t_solve_ms": info.t_solve_ms, "history": hist[:info.res_hist_len].copy()}
+                   "t_solve_ms": info.t_solve_ms, "t_ml_ms": info.t_ml_ms, "t_mg_ms": info.t_mg_ms,
+                   "history": hist[:info.res_hist_len].copy()}
 
     def query(self, what, dtype):
         need = i64(0)

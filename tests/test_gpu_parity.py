@@ -103,6 +103,7 @@ def test_solve_parity(case16):
     x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
     assert info["status"] == "OK"
     assert abs(info["iters"] - ro.iters) <= 1
+    assert info["t_ml_ms"] > 0 and info["t_mg_ms"] > 0     # the set-up's T_ML / T_MG split
     xg = x.cpu().numpy()
     assert np.linalg.norm(b - A @ xg) / np.linalg.norm(b) < 1e-8
     # at the oracle's iteration count the iterates agree to 1e-8

@@ -210,3 +210,18 @@ def test_smoother_forms(hp):
     o = hp.HplmmOptions(64, 0, 3)
     with pytest.raises(hp.HplmmError):
         hp._check(hp.lib().hplmm_plan_check(hp.C.byref(s), hp.C.byref(q), hp.C.byref(m), hp.C.byref(o), None))
+
+
+def test_plan_accepts_constrained_dofs(hp):
+    # constrained dofs change values, not structure: the same plan sizes;
+    # flags on every dof still plan (the identity system)
+    p = synth.config_pores(12, 4, seed=3)
+    sysm, part = hp.build_problem(p)
+    base = hp.plan_check(sysm, part, n_mortar=2)
+    fixed = np.zeros(3 * sysm.n_nodes, dtype=np.uint8)
+    fixed[0::3] = sysm.node_xyz[0::3] == 0
+    assert fixed.sum() > 0
+    assert hp.plan_check(sysm.with_fixed(fixed), part, n_mortar=2) == base
+    every = hp.plan_check(sysm.with_fixed(np.ones_like(fixed)), part, n_mortar=2)
+    # every dof constrained: the load vanishes, so no correction columns (R3)
+    assert every["n_corr"] == 0 and every["n_coarse"] == base["n_coarse"] - base["n_corr"]

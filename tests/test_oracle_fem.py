@@ -113,3 +113,47 @@ def test_clamped_system_symmetric_spd_and_load():
     assert np.all(b[0::3] == 0) and np.all(b[1::3] == 0)
     L = np.linalg.cholesky(A.toarray())
     assert np.all(np.isfinite(L))
+
+
+def test_constrained_dofs_identity_rows():
+    """oracle.constraints on the uniaxial bar: roller supports on x = 0, y = 0
+    and z = 0 as identity rows reproduce the closed form exactly, and on a
+    porous block the constrained system's solution is zero at the fixed dofs
+    and equals the reduced system's elsewhere."""
+    from oracle import constraints
+    nx, ny, nz = 3, 2, 4
+    E, nu, p = 2.0, 0.3, 0.5
+    solid = np.ones((nz, ny, nx), dtype=np.uint8)
+    A, xyz, _ = fem.assemble_unconstrained(solid, np.full(solid.shape, E), nu)
+    nn = xyz.shape[0]
+    b = np.zeros(3 * nn)
+    for i in range(nx):
+        for j in range(ny):
+            for cx in (0, 1):
+                for cy in (0, 1):
+                    v = np.flatnonzero((xyz[:, 0] == i + cx) & (xyz[:, 1] == j + cy) & (xyz[:, 2] == nz))[0]
+                    b[3 * v + 2] -= 0.25 * p
+    fixed = np.zeros(3 * nn, dtype=bool)
+    fixed[0::3] = xyz[:, 0] == 0
+    fixed[1::3] = xyz[:, 1] == 0
+    fixed[2::3] = xyz[:, 2] == 0
+    Ac, bc = constraints.constrain(A, b, fixed)
+    assert abs(Ac - Ac.T).max() <= 1e-15 * abs(A).max()
+    u = spla.spsolve(Ac.tocsc(), bc)
+    x, y, z = (xyz[:, d].astype(float) for d in range(3))
+    assert np.allclose(u[2::3], -p * z / E, atol=1e-13)
+    assert np.allclose(u[0::3], nu * p * x / E, atol=1e-13)
+    assert np.allclose(u[1::3], nu * p * y / E, atol=1e-13)
+    # porous block with the clamp eliminated and rollers on x = 0, y = 0
+    pr = synth.config_pores(8, 4, seed=11, porosity=0.2)
+    A2, b2, mesh = fem.assemble(pr)
+    xyz2 = mesh.xyz
+    f2 = np.zeros(A2.shape[0], dtype=bool)
+    f2[0::3] = xyz2[:, 0] == 0
+    f2[1::3] = xyz2[:, 1] == 0
+    A2c, b2c = constraints.constrain(A2, b2, f2)
+    u2 = spla.spsolve(A2c.tocsc(), b2c)
+    assert np.all(u2[f2] == 0.0)
+    free = ~f2
+    ur = spla.spsolve(A2[free][:, free].tocsc(), b2[free])
+    assert np.abs(u2[free] - ur).max() <= 1e-12 * np.abs(ur).max()
