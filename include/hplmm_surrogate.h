@@ -47,6 +47,14 @@ hplmm_status hplmm_sg_get_params(const hplmm_sg_net *net, float *host, int64_t c
  * Asynchronous on stream. */
 hplmm_status hplmm_sg_forward(hplmm_sg_net *net, const float *x_dev, int32_t n, float *y_dev, void *stream);
 
+/* Inference precision of hplmm_sg_forward and of the predictions of
+ * hplmm_setup_surrogate: 32 (default) = float32 operands; 16 = every layer's
+ * staged inputs and weights rounded to bfloat16 (to nearest even) on the
+ * matrix cores (v_mfma_f32_16x16x32_bf16), float32 accumulation, bias, ReLU
+ * and activations.  Training (hplmm_sg_gradient) stays float32.  E_ARG on
+ * another value. */
+hplmm_status hplmm_sg_set_inference_precision(hplmm_sg_net *net, int32_t precision);
+
 /* Forward pass, loss and gradients of the loss w.r.t. every parameter for
  * the batch (x_dev as above, y_dev the targets [n][729][c4]).  Loss = mean
  * over samples of |m (net(x) - y)|^2 / (|m y|^2 + 1e-30), m = interior

@@ -88,6 +88,19 @@ def forward(params, x):
     return acts
 
 
+def forward_bf16(params, x):
+    """The inference the GPU runs with bfloat16 operands: every layer's input
+    activations and weights rounded to bfloat16 (to nearest even, via
+    float32), the convolution summed exactly (FP64 here), the float32 bias
+    added, ReLU on hidden layers.  Returns the last layer's output."""
+    from .precision import round_bf16, round_f32
+    a = x
+    for l, (w, b) in enumerate(params):
+        z = conv3d(round_bf16(a), round_bf16(w), round_f32(b))
+        a = np.maximum(z, 0.0) if l < len(params) - 1 else z
+    return a
+
+
 def loss(pred, y, mask):
     """Mean over samples of |m (pred - y)|^2 / (|m y|^2 + 1e-30)."""
     m = mask[..., None]

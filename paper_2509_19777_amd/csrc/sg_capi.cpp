@@ -38,6 +38,7 @@ struct hplmm_sg_net {
     int64_t w_off[4] = {0, 0, 0, 0}, b_off[4] = {0, 0, 0, 0};
     float *params = nullptr, *grads = nullptr, *adam_m = nullptr, *adam_v = nullptr;
     int32_t t = 0;
+    int32_t infer_precision = 32;   // forward passes of inference: 32 or 16 (bfloat16 operands)
     float *act[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};   // act[0] unused (caller's x)
     float *gbuf[2] = {nullptr, nullptr};
     float *part = nullptr;
@@ -50,12 +51,17 @@ struct hplmm_sg_net {
     }
 };
 
-static void forward_all(hplmm_sg_net &nt, const float *x, int32_t n, float *y, hipStream_t s) {
+// bf16: bfloat16 operands (inference only; training keeps FP32 throughout)
+static void forward_all(hplmm_sg_net &nt, const float *x, int32_t n, float *y, hipStream_t s, bool bf16 = false) {
     const float *in = x;
     for (int l = 0; l < 4; ++l) {
         float *out = (l == 3 && y) ? y : nt.act[l + 1];
-        sg::launch_conv_fwd(in, nt.ch[l], nt.params + nt.w_off[l], nt.params + nt.b_off[l], out, nt.ch[l + 1], n,
-                            l < 3 ? 1 : 0, s);
+        if (bf16)
+            sg::launch_conv_fwd_bf16(in, nt.ch[l], nt.params + nt.w_off[l], nt.params + nt.b_off[l], out,
+                                     nt.ch[l + 1], n, l < 3 ? 1 : 0, s);
+        else
+            sg::launch_conv_fwd(in, nt.ch[l], nt.params + nt.w_off[l], nt.params + nt.b_off[l], out, nt.ch[l + 1],
+                                n, l < 3 ? 1 : 0, s);
         in = out;
     }
 }
@@ -134,8 +140,17 @@ extern "C" hplmm_status hplmm_sg_forward(hplmm_sg_net *net, const float *x, int3
     return guarded([&]() -> hplmm_status {
         if (!net || !x || !y) fail(HPLMM_E_ARG, "NULL argument");
         if (n < 1 || n > net->max_batch) fail(HPLMM_E_ARG, "n must be in [1, max_batch]");
-        forward_all(*net, x, n, y, to_stream(stream));
+        forward_all(*net, x, n, y, to_stream(stream), net->infer_precision == 16);
         sg_check(hipGetLastError(), "kernel launch");
+        return HPLMM_OK;
+    });
+}
+
+extern "C" hplmm_status hplmm_sg_set_inference_precision(hplmm_sg_net *net, int32_t precision) {
+    return guarded([&]() -> hplmm_status {
+        if (!net) fail(HPLMM_E_ARG, "NULL argument");
+        if (precision != 32 && precision != 16) fail(HPLMM_E_ARG, "precision must be 32 or 16");
+        net->infer_precision = precision;
         return HPLMM_OK;
     });
 }
@@ -290,7 +305,7 @@ void sg_build_sample_tables(Handle &h, hipStream_t s) {
 }
 
 void sg_net_forward(hplmm_sg_net *net, const float *x, int32_t n, float *y, hipStream_t s) {
-    forward_all(*net, x, n, y, s);
+    forward_all(*net, x, n, y, s, net->infer_precision == 16);
 }
 int32_t sg_net_max_batch(const hplmm_sg_net *net) { return net->max_batch; }
 bool sg_net_is_basis_net(const hplmm_sg_net *net) { return net->ch[0] == 4 && net->ch[4] == 9; }

@@ -20,6 +20,10 @@ constexpr int NOFF = 27;
 // (zero outside the lattice), then ReLU when relu != 0.  cin <= 32, cout <= 32.
 void launch_conv_fwd(const float *in, int cin, const float *w, const float *bias, float *out, int cout, int n,
                      int relu, hipStream_t s);
+// The same with the staged inputs and weights rounded to bfloat16 (to
+// nearest even), FP32 accumulation and FP32 output (inference).
+void launch_conv_fwd_bf16(const float *in, int cin, const float *w, const float *bias, float *out, int cout, int n,
+                          int relu, hipStream_t s);
 // gin[s][p][ci] = [act[s][p][ci] > 0] sum_{d, co} w[d][ci][co] g[s][p - o(d)][co]
 // (act may be null: no mask).  g has cout channels, gin cin.
 void launch_conv_bwd_data(const float *g, int cout, const float *w, float *gin, int cin, const float *act, int n,

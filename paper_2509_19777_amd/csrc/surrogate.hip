@@ -93,6 +93,85 @@ __global__ void __launch_bounds__(256) conv_kernel(const float *__restrict__ in,
         }
 }
 
+// Forward convolution with bfloat16 operands (inference): the staged input
+// rows and weight slices are rounded to bfloat16 (to nearest even) and one
+// v_mfma_f32_16x16x32_bf16 per 16 output channels contracts all 32 (padded)
+// input channels of an offset, with FP32 accumulation; bias, ReLU and the
+// stored activations stay FP32.  Lane l supplies position (or output channel)
+// l & 15 at channels 8 (l >> 4) .. + 7, one 16-byte LDS read each.
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+constexpr int KB = 32, KBL = KB + 8;   // channels per offset, padded LDS row (bf16 elements)
+
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+template <int NOUT>
+__global__ void __launch_bounds__(256) conv_fwd_bf16_kernel(const float *__restrict__ in, int cin,
+                                                            const float *__restrict__ w,
+                                                            const float *__restrict__ bias, float *__restrict__ out,
+                                                            int cout, int relu) {
+    __shared__ __align__(16) uint16_t Xs[64][KBL];
+    __shared__ __align__(16) uint16_t Ws[NOUT][KBL];   // w^T: [co][ci]
+    const int s = blockIdx.y;
+    const int p0 = blockIdx.x * 64;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lr = lane & 15, k0 = 8 * (lane >> 4);
+    v4f acc[NOUT / 16];
+#pragma unroll
+    for (int nb = 0; nb < NOUT / 16; ++nb) acc[nb] = v4f{0.f, 0.f, 0.f, 0.f};
+    const float *ins = in + (int64_t)s * P * cin;
+    for (int d = 0; d < NOFF; ++d) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * KB; e += 256) {
+            const int pl = e / KB, k = e % KB;
+            const int p = p0 + pl;
+            float v = 0.f;
+            if (p < P && k < cin) {
+                const int q = neighbour(p, d);
+                if (q >= 0) v = ins[q * cin + k];
+            }
+            Xs[pl][k] = to_bf16(v);
+        }
+        for (int e = threadIdx.x; e < KB * NOUT; e += 256) {
+            const int k = e / NOUT, n = e % NOUT;
+            Ws[n][k] = to_bf16((k < cin && n < cout) ? w[((int64_t)d * cin + k) * cout + n] : 0.f);
+        }
+        __syncthreads();
+        const v8bf a = *reinterpret_cast<const v8bf *>(&Xs[16 * wave + lr][k0]);
+#pragma unroll
+        for (int nb = 0; nb < NOUT / 16; ++nb) {
+            const v8bf b = *reinterpret_cast<const v8bf *>(&Ws[16 * nb + lr][k0]);
+            acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[nb], 0, 0, 0);
+        }
+    }
+    float *outs = out + (int64_t)s * P * cout;
+#pragma unroll
+    for (int nb = 0; nb < NOUT / 16; ++nb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int p = p0 + 16 * wave + 4 * (lane >> 4) + r;
+            const int n = 16 * nb + lr;
+            if (p >= P || n >= cout) continue;
+            float v = acc[nb][r];
+            if (bias) v += bias[n];
+            if (relu) v = v > 0.f ? v : 0.f;
+            outs[p * cout + n] = v;
+        }
+}
+
+void launch_conv_fwd_bf16(const float *in, int cin, const float *w, const float *bias, float *out, int cout, int n,
+                          int relu, hipStream_t s) {
+    if (n <= 0) return;
+    const dim3 grid((P + 63) / 64, n);
+    if (cout <= 16)
+        hipLaunchKernelGGL(conv_fwd_bf16_kernel<16>, grid, dim3(256), 0, s, in, cin, w, bias, out, cout, relu);
+    else
+        hipLaunchKernelGGL(conv_fwd_bf16_kernel<32>, grid, dim3(256), 0, s, in, cin, w, bias, out, cout, relu);
+}
+
 template <bool BWD>
 static void conv_dispatch(const float *in, int cin, const float *w, int wc0, int wc1, const float *bias,
                           const float *mask, float *out, int cout, int n, int relu, hipStream_t s) {

@@ -91,6 +91,7 @@ EXPORTS = {
     "hplmm_sg_set_params": (i32, [C.c_void_p, P(C.c_float), i64]),
     "hplmm_sg_get_params": (i32, [C.c_void_p, P(C.c_float), i64]),
     "hplmm_sg_forward": (i32, [C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p]),
+    "hplmm_sg_set_inference_precision": (i32, [C.c_void_p, i32]),
     "hplmm_sg_gradient": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, i32, P(f64), C.c_void_p]),
     "hplmm_sg_get_grads": (i32, [C.c_void_p, P(C.c_float), i64, C.c_void_p]),
     "hplmm_sg_adam": (i32, [C.c_void_p, C.c_float, C.c_void_p]),
@@ -603,6 +604,11 @@ class SurrogateNet:
         y = torch.empty((n, 9, 9, 9, self.channels[-1]), dtype=torch.float32, device=x.device) if out is None else out
         _check(lib().hplmm_sg_forward(self.h, _vp(x), int(n), _vp(y), _stream()))
         return y
+
+    def set_inference_precision(self, precision):
+        """32 (float32) or 16 (bfloat16 operands, float32 accumulation) for
+        forward() and the set-up's predictions; training stays float32."""
+        _check(lib().hplmm_sg_set_inference_precision(self.h, int(precision)))
 
     def gradient(self, x, y):
         loss = f64(0.0)

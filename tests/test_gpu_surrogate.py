@@ -47,6 +47,34 @@ def test_forward_matches_oracle(channels, n):
     assert _rel(out, ref) <= 2e-5
 
 
+@pytest.mark.parametrize("channels,n", [((4, 8, 8, 8, 9), 3), ((4, 32, 32, 32, 9), 2), ((4, 5, 17, 3, 9), 1)])
+def test_bf16_inference_matches_emulation(channels, n):
+    # bfloat16 operands on the matrix cores against the oracle's emulation
+    # (each layer's inputs and weights rounded to bfloat16, exact sums): the
+    # first layer differs only by FP32 summation (<= 864 u32 of the
+    # magnitudes), later layers also where the two sides' activations straddle
+    # a bfloat16 rounding boundary (a fraction ~1e-3 of the entries, one
+    # ulp = 2^-8 each): ~1e-3 expected, bar 1e-2
+    torch = _torch()
+    from paper_2509_19777_amd import hplmm as hp
+    params, x, y = _case(channels, n, 2)
+    net = hp.SurrogateNet(channels, max_batch=4)
+    net.set_params(hp.flatten_params(params))
+    xt = torch.from_numpy(x.astype(np.float32)).cuda()
+    out32 = net.forward(xt).cpu().numpy().astype(np.float64)
+    net.set_inference_precision(16)
+    out16 = net.forward(xt).cpu().numpy().astype(np.float64)
+    p32 = [(w.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for w, b in params]
+    ref = osg.forward_bf16(p32, x.astype(np.float32).astype(np.float64))
+    print(f"bf16 inference {channels}: {_rel(out16, ref):.2e} from the emulation, {_rel(out16, out32):.2e} from FP32")
+    assert _rel(out16, ref) <= 1e-2
+    assert _rel(out16, out32) > 1e-5          # the operands really are rounded
+    net.set_inference_precision(32)
+    assert np.array_equal(net.forward(xt).cpu().numpy().astype(np.float64), out32)
+    with pytest.raises(hp.HplmmError):
+        net.set_inference_precision(8)
+
+
 @pytest.mark.parametrize("channels,n", [((4, 8, 8, 8, 9), 3), ((4, 32, 32, 32, 9), 2)])
 def test_gradients_match_oracle(channels, n):
     torch = _torch()

@@ -54,3 +54,29 @@ def test_fallback_keeps_the_method_and_acceptance_costs_iterations(fresh):
     assert strict["accepted"] == 0 or strict["max_residual_accepted"] <= 1e-3
     assert loose["accepted"] > 0
     assert loose["iters"] > exact["iters"]
+
+
+def test_bf16_inference_keeps_the_method(fresh):
+    # the same network with bfloat16 operands: its shape vectors stay as
+    # accurate (the error is the network's, not bfloat16's), the 1e-3 fallback
+    # still keeps the exact method's iterations, and the inference time is
+    # printed beside the FP32 one
+    from paper_2509_19777_amd import hplmm as hp, surrogate as sgm
+    p, net = fresh
+    sysm, part = hp.build_problem(p)
+    S = hp.Solver(sysm, part, n_mortar=4)
+    S.setup()
+    x, y, meta = hp.surrogate_samples(S)
+    e32 = sgm.per_sample_error(net, x, y, 128)
+    rows32 = sgm.compare(net, p, [1e-3], reps=2)
+    net.set_inference_precision(16)
+    try:
+        e16 = sgm.per_sample_error(net, x, y, 128)
+        rows16 = sgm.compare(net, p, [1e-3], reps=2)
+    finally:
+        net.set_inference_precision(32)
+    print(json.dumps({"median_rel_err_fp32": float(np.median(e32)), "median_rel_err_bf16": float(np.median(e16)),
+                      "t_infer_ms_fp32": rows32[1]["t_infer_ms"], "t_infer_ms_bf16": rows16[1]["t_infer_ms"],
+                      "setup_ms_exact": rows16[0]["setup_ms"], "setup_ms_surrogate_bf16": rows16[1]["setup_ms"]}))
+    assert abs(np.median(e16) - np.median(e32)) <= 0.05 * np.median(e32)
+    assert rows16[1]["status"] == "OK" and rows16[1]["iters"] == rows16[0]["iters"]

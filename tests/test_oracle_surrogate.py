@@ -159,3 +159,21 @@ def test_predicted_blocks_cover_every_mortar_column(small_oracle):
     cols, B = blocks[g]
     ecols, EB = H.B_blocks[g]
     assert np.array_equal(np.sort(cols), np.sort(ecols)) and B.shape == EB.shape
+
+
+def test_bf16_forward_emulation():
+    """forward_bf16 equals forward exactly when the inputs, weights and
+    biases are already bfloat16 values and the net has one layer (nothing
+    left to round), and stays within the bfloat16 rounding bound of forward
+    otherwise (a relative error of a few u16 = 2^-9 per layer)."""
+    from oracle import precision as prec
+    rng = np.random.default_rng(3)
+    params = sg.init_params(rng, (4, 5))
+    params = [(prec.round_bf16(w), prec.round_bf16(rng.standard_normal(b.shape))) for w, b in params]
+    x = prec.round_bf16(rng.standard_normal((2, 9, 9, 9, 4)))
+    assert np.array_equal(sg.forward_bf16(params, x), sg.forward(params, x)[-1])
+    params = sg.init_params(rng, (4, 8, 8, 8, 9))
+    x = rng.standard_normal((2, 9, 9, 9, 4))
+    ref = sg.forward(params, x)[-1]
+    rel = np.linalg.norm(sg.forward_bf16(params, x) - ref) / np.linalg.norm(ref)
+    assert 1e-5 < rel < 4 * 4 * 2.0 ** -9
