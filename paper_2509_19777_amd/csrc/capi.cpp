@@ -1102,7 +1102,23 @@ extern "C" hplmm_status hplmm_set_voxel_operator(hplmm_handle *hh, int32_t nx, i
         q1_element_stiffness(nu, K);
         const std::vector<uint8_t> vs(solid, solid + nvox);
         const std::vector<double> ve(E, E + nvox), vk(&K[0][0], &K[0][0] + 24 * 24);
-        VoxelGrid g{nx, ny, nz, h.upload(vs, s), h.upload(ve, s), nu, h.upload(lat, s), h.n_nodes};
+        // the padded copies the matrix-free operator reads (halo of void
+        // voxels and of lattice points without a node)
+        const int64_t PX = nx + 2, PY = ny + 2, PZ = nz + 2, QX = nx + 3, QY = ny + 3, QZ = nz + 3;
+        std::vector<double> ep((size_t)(PX * PY * PZ), 0.0);
+        for (int64_t ez = 0; ez < nz; ++ez)
+            for (int64_t ey = 0; ey < ny; ++ey)
+                for (int64_t ex = 0; ex < nx; ++ex) {
+                    const int64_t q = ex + nx * (ey + ny * ez);
+                    if (solid[q]) ep[(size_t)((ex + 1) + PX * ((ey + 1) + PY * (ez + 1)))] = E[q];
+                }
+        std::vector<int32_t> lp((size_t)(QX * QY * QZ), -1);
+        for (int64_t c = 0; c < NZ; ++c)
+            for (int64_t b = 0; b < NY; ++b)
+                for (int64_t a = 0; a < NX; ++a)
+                    lp[(size_t)((a + 1) + QX * ((b + 1) + QY * (c + 1)))] = lat[(size_t)(a + NX * (b + NY * c))];
+        VoxelGrid g{nx, ny, nz, h.upload(vs, s), h.upload(ve, s), nu, h.upload(lat, s), h.n_nodes,
+                    h.upload(ep, s), h.upload(lp, s)};
         const int32_t *xyz = h.upload(h.sg_xyz, s);
         const double *Kd = h.upload(vk, s);
         // the two operators on one seeded vector must agree to rounding

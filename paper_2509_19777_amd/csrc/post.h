@@ -14,6 +14,10 @@ struct VoxelGrid {
     double nu;
     const int32_t *lat2node;   // [(nz+1)(ny+1)(nx+1)] free node or -1
     int64_t n_nodes;
+    // the same with a one-cell halo, so that every neighbour lookup of the
+    // matrix-free operator is in range and needs no branch:
+    const double *Ep;          // [(nz+2)(ny+2)(nx+2)] E on solid voxels, 0 on void and halo
+    const int32_t *latp;       // [(nz+3)(ny+3)(nx+3)] free node or -1 (-1 on the halo)
 };
 
 // sigma_t[v] = max shear stress, uc[3v + c] = centroid displacement of voxel v

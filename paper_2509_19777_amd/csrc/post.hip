@@ -83,8 +83,8 @@ __global__ void __launch_bounds__(256) voxel_fields_kernel(VoxelGrid g, const do
 // read once (zero for void or outside voxels); then for each of the 27
 // neighbouring lattice nodes w the displacement x_w is read once and
 // multiplied by the sum over the voxels holding both nodes of E_e times the
-// 3x3 block of Khat that couples their corners.  Khat is staged in LDS; the
-// loops are unrolled so every corner index is a constant.
+// 3x3 block of Khat that couples their corners.  Khat is staged in LDS.  The
+// grids carry a halo, so no lookup needs a range test.
 __global__ void __launch_bounds__(256) spmv_voxel_kernel(VoxelGrid g, const int32_t *__restrict__ xyz,
                                                          const double *__restrict__ Khat,
                                                          const double *__restrict__ x,
@@ -95,38 +95,56 @@ __global__ void __launch_bounds__(256) spmv_voxel_kernel(VoxelGrid g, const int3
     const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (v >= g.n_nodes) return;
     const int32_t i = xyz[3 * v], j = xyz[3 * v + 1], k = xyz[3 * v + 2];
-    const int64_t NX = g.nx + 1, NY = g.ny + 1;
+    // padded grids: voxel (ex, ey, ez) at Ep[(ex + 1) + PX ((ey + 1) + PY (ez + 1))],
+    // lattice point (a, b, c) at latp[(a + 1) + QX ((b + 1) + QY (c + 1))]; every
+    // index below stays inside them, so all loads are issued without branches
+    const int64_t PX = g.nx + 2, PY = g.ny + 2, QX = g.nx + 3, QY = g.ny + 3;
     double Ee[8];   // voxel (i - cx, j - cy, k - cz) holds this node at its corner e = cx + 2 cy + 4 cz
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        const int32_t ex = i - (e & 1), ey = j - ((e >> 1) & 1), ez = k - ((e >> 2) & 1);
-        double val = 0.0;
-        if (ex >= 0 && ey >= 0 && ez >= 0 && ex < g.nx && ey < g.ny && ez < g.nz) {
-            const int64_t vox = ex + (int64_t)g.nx * (ey + (int64_t)g.ny * ez);
-            if (g.solid[vox]) val = g.E[vox];
+    for (int e = 0; e < 8; ++e)
+        Ee[e] = g.Ep[(i - (e & 1) + 1) + PX * ((j - ((e >> 1) & 1) + 1) + PY * (int64_t)(k - ((e >> 2) & 1) + 1))];
+    // the neighbours' displacements in groups of three offsets (one lattice
+    // row q = (dy + 1) + 3 (dz + 1)), the next row's node numbers and
+    // displacements loaded before the current row's products; the rows run as
+    // a loop (not unrolled), so the compiler cannot hoist every row's loads at
+    // once, and the in-element tests below are uniform branches
+    double cur[9], nxt[9];
+    auto load_row = [&](int q, double (&xg)[9]) {
+        const int32_t *lrow = g.latp + i + QX * ((j + q % 3) + QY * (int64_t)(k + q / 3));
+#pragma unroll
+        for (int t = 0; t < 3; ++t) {
+            const int32_t wv = lrow[t];
+            const bool ok = wv >= 0 && wv < g.n_nodes;
+            const int64_t w = ok ? wv : v;   // a valid address either way
+            xg[3 * t] = ok ? x[3 * w] : 0.0;
+            xg[3 * t + 1] = ok ? x[3 * w + 1] : 0.0;
+            xg[3 * t + 2] = ok ? x[3 * w + 2] : 0.0;
         }
-        Ee[e] = val;
-    }
+    };
     double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+    load_row(0, nxt);
+#pragma unroll 1
+    for (int q = 0; q < 9; ++q) {
 #pragma unroll
-    for (int o = 0; o < 27; ++o) {
-        const int ox = o % 3 - 1, oy = (o / 3) % 3 - 1, oz = o / 9 - 1;
-        const int32_t wi = i + ox, wj = j + oy, wk = k + oz;
-        if (wi < 0 || wj < 0 || wk < 0 || wi > g.nx || wj > g.ny || wk > g.nz) continue;
-        const int32_t w = g.lat2node[wi + NX * (wj + NY * (int64_t)wk)];
-        if (w < 0 || w >= g.n_nodes) continue;
-        const double x0 = x[3 * (int64_t)w], x1 = x[3 * (int64_t)w + 1], x2 = x[3 * (int64_t)w + 2];
+        for (int c = 0; c < 9; ++c) cur[c] = nxt[c];
+        if (q + 1 < 9) load_row(q + 1, nxt);
+        const int oy = q % 3 - 1, oz = q / 3 - 1;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int cx = e & 1, cy = (e >> 1) & 1, cz = (e >> 2) & 1;
-            const int bx = cx + ox, by = cy + oy, bz = cz + oz;
-            if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;
-            const int b = bx + 2 * by + 4 * bz;
-            const double *Kr = K + 3 * e * 24 + 3 * b;
-            const double E = Ee[e];
-            a0 += E * (Kr[0] * x0 + Kr[1] * x1 + Kr[2] * x2);
-            a1 += E * (Kr[24] * x0 + Kr[25] * x1 + Kr[26] * x2);
-            a2 += E * (Kr[48] * x0 + Kr[49] * x1 + Kr[50] * x2);
+        for (int t = 0; t < 3; ++t) {
+            const int ox = t - 1;
+            const double x0 = cur[3 * t], x1 = cur[3 * t + 1], x2 = cur[3 * t + 2];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const int cx = e & 1, cy = (e >> 1) & 1, cz = (e >> 2) & 1;
+                const int bx = cx + ox, by = cy + oy, bz = cz + oz;
+                if (bx < 0 || bx > 1 || by < 0 || by > 1 || bz < 0 || bz > 1) continue;   // uniform
+                const int b = bx + 2 * by + 4 * bz;
+                const double *Kr = K + 3 * e * 24 + 3 * b;
+                const double E = Ee[e];
+                a0 += E * (Kr[0] * x0 + Kr[1] * x1 + Kr[2] * x2);
+                a1 += E * (Kr[24] * x0 + Kr[25] * x1 + Kr[26] * x2);
+                a2 += E * (Kr[48] * x0 + Kr[49] * x1 + Kr[50] * x2);
+            }
         }
     }
     if (r) {
