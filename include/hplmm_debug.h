@@ -49,12 +49,14 @@ hplmm_status hplmm_debug_read_arena(hplmm_handle *h, int32_t arena, int64_t off,
 
 /* Layout of a planned handle for tests: int64 per grain matrix m (grain id,
  * dofs, tiles nt, columns ncol, column tiles ntc, A offset, W offset, Wt
- * offset, R offset, Y offset, K offset) -- 11 values per matrix. */
+ * offset, R offset, Y offset, K offset) -- 11 values per matrix.  The Wt
+ * offset is -1 in the inverse smoother form, which stores no transposes. */
 hplmm_status hplmm_debug_grain_layout(hplmm_handle *h, int64_t *out, int64_t cap);
 
 /* Layout of the contact-grid blocks for tests: int64 per contact matrix m
  * (dofs n, tiles nt, arena holding its factor (0 = float64, 1 = float32), A/L
- * offset, W offset, Wt offset) -- 6 values per matrix, in contact-grid order.
+ * offset, W offset, Wt offset or -1 as for the grains) -- 6 values per
+ * matrix, in contact-grid order.
  * Tiles are 64 x 64, column-major inside a tile, packed lower tiles (I, J),
  * I >= J, at I (I + 1) / 2 + J. */
 hplmm_status hplmm_debug_contact_layout(hplmm_handle *h, int64_t *out, int64_t cap);

@@ -104,6 +104,11 @@ struct DenseSet {
     int64_t low_w_base = 0, low_wt_base = 0;   // offsets in the reduced-precision arena
     int64_t low_s_base = 0;            // S as the smoother reads it (= s_base at FP64)
     std::vector<int64_t> nt_own;       // tiles factored per matrix (partial factorisation); empty = nt
+    std::vector<int64_t> wrel;         // W / Wt relative offsets, only tri(nt_own) tiles each; empty = rel
+    // Wt holds only the diagonal tiles W_kk^T (the inverse form, whose
+    // products read W transposed instead): tile k of matrix m at wdrel[m] + k TE
+    bool wt_diag = false;
+    std::vector<int64_t> wdrel;
 };
 
 // Multifrontal Cholesky of the coarse operator on a nested-dissection tree of
@@ -114,11 +119,11 @@ struct DenseSet {
 struct CoarseMF {
     int32_t n_fronts = 0, n_levels = 0;
     std::vector<int32_t> parent, level, side;
-    std::vector<int64_t> d, u, nt_d, nt_u, rel, ltrel, voff;
+    std::vector<int64_t> d, u, nt_d, nt_u, rel, wrel, ltrel, voff;   // wrel: W11 / W11^T, tri(nt_d) tiles each
     std::vector<std::vector<int32_t>> own, bnd;
     std::vector<int32_t> iface_front;
     std::vector<int64_t> iface_pos;           // position inside its owner front
-    int64_t region = 0, lt_region = 0, vec_len = 0;
+    int64_t region = 0, w_region = 0, lt_region = 0, vec_len = 0;
     int64_t a_base = 0, w_base = 0, wt_base = 0, lt_base = 0, ng_base = 0;
     std::vector<std::vector<Launch>> factor_prog;   // per level
     std::vector<Range> ext_tiles[2];                // per level: extend-add tiles (left / right children)

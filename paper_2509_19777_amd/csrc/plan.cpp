@@ -144,8 +144,17 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
     int64_t maxk = 0;
     for (int64_t m = 0; m < nm; ++m) maxk = std::max(maxk, own(m));
     auto A = [&](int64_t m, int64_t I, int64_t J) { return ds.a_base + ds.rel[m] + tri_index(I, J) * TE; };
-    auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + ds.rel[m] + tri_index(I, J) * TE; };
-    auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
+    // W = L^-1 exists for the factored rows only (I < own), so a partially
+    // factored matrix may keep W and Wt in smaller slots of their own
+    auto wrel = [&](int64_t m) { return ds.wrel.empty() ? ds.rel[m] : ds.wrel[m]; };
+    auto W = [&](int64_t m, int64_t I, int64_t J) { return ds.w_base + wrel(m) + tri_index(I, J) * TE; };
+    auto Wt = [&](int64_t m, int64_t I, int64_t J) {
+        if (ds.wt_diag) {
+            if (I != J) fail(HPLMM_E_ARG, "internal: off-diagonal Wt tile without storage");
+            return ds.wt_base + ds.wdrel[m] + I * TE;
+        }
+        return ds.wt_base + wrel(m) + tri_index(I, J) * TE;
+    };
     auto id = [&](int64_t m) { return (int32_t)(set_id * (1 << 26) + (ids ? (*ids)[m] : m)); };
     // Left-looking tile Cholesky, two launches per step k: the diagonal tile
     // A_kk - sum_{p<k} L_kp L_kp^T is factored (the diagonal kernel subtracts
@@ -201,6 +210,7 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         u.count = (int64_t)tl.gemm.size() - u.start;
         if (u.count) prog.push_back(u);
     }
+    if (ds.wt_diag) return;   // no stored transposes
     Launch c{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
     for (int64_t m = 0; m < nm; ++m)
         for (int64_t i = 0; i < own(m); ++i)
@@ -236,26 +246,22 @@ void build_smoother_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<Ge
     ds.gemv_Wt.count = (int64_t)vt.size() - ds.gemv_Wt.start;
 }
 
-// S = W^T W for every matrix of a dense set (the inverse smoother form), lower
-// tiles S_ij = sum_{k >= i} W_ki^T W_kj, i >= j, one task per tile with the
-// stored transposes Wt_ki = W_ki^T as left operands.
-// S_ij = sum_{k >= i} W_ki^T W_kj over the lower tiles.  FP64: the
-// transposed tiles Wt_ki as left operands.  Reduced precision (low): the
-// rounded W at low_w_base as both operands (the left one read transposed),
-// S written to low_s_base of the FP32 arena.
+// S = W^T W for every matrix of a dense set (the inverse smoother form): lower
+// tiles S_ij = sum_{k >= i} W_ki^T W_kj, i >= j, one task per tile, W as both
+// operands (the left one read transposed).  FP64: W and S in the FP64 arena.
+// Reduced precision (low): the rounded W at low_w_base, S written to
+// low_s_base of the FP32 arena.
 void build_inverse_program(DenseSet &ds, TaskLists &tl, bool low) {
     const int64_t wb = low ? ds.low_w_base : ds.w_base, sb = low ? ds.low_s_base : ds.s_base;
     auto W = [&](int64_t m, int64_t I, int64_t J) { return wb + ds.rel[m] + tri_index(I, J) * TE; };
-    auto Wt = [&](int64_t m, int64_t I, int64_t J) { return ds.wt_base + ds.rel[m] + tri_index(I, J) * TE; };
     auto S = [&](int64_t m, int64_t I, int64_t J) { return sb + ds.rel[m] + tri_index(I, J) * TE; };
     Launch L{LK_GEMM, (int64_t)tl.gemm.size(), 0};
     for (int64_t m = 0; m < (int64_t)ds.n.size(); ++m)
         for (int64_t i = 0; i < ds.nt[m]; ++i)
             for (int64_t j = 0; j <= i; ++j) {
                 tl.gemm.push_back({S(m, i, j), -1, (int32_t)tl.pairs.size(), (int32_t)(ds.nt[m] - i),
-                                   low ? (int32_t)GF_TRANS_A : 0, 0});
-                for (int64_t k = i; k < ds.nt[m]; ++k)
-                    tl.pairs.push_back({low ? W(m, k, i) : Wt(m, k, i), W(m, k, j)});
+                                   (int32_t)GF_TRANS_A, 0});
+                for (int64_t k = i; k < ds.nt[m]; ++k) tl.pairs.push_back({W(m, k, i), W(m, k, j)});
             }
     L.count = (int64_t)tl.gemm.size() - L.start;
     if (L.count) ds.inverse_prog.push_back(L);
@@ -608,11 +614,12 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
     mf.nt_d.resize(nf);
     mf.nt_u.resize(nf);
     mf.rel.resize(nf);
+    mf.wrel.resize(nf);
     mf.ltrel.resize(nf);
     mf.voff.resize(nf);
     mf.iface_pos.assign((size_t)nI, -1);
     std::vector<std::unordered_map<int32_t, int64_t>> pos((size_t)nf);
-    int64_t off = 0, lt = 0, vo = 0;
+    int64_t off = 0, wo = 0, lt = 0, vo = 0;
     for (int32_t t = 0; t < nf; ++t) {
         int64_t d = 0, u = 0;
         for (int32_t c : mf.own[(size_t)t]) {
@@ -632,20 +639,23 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         mf.nt_u[(size_t)t] = ntu;
         mf.rel[(size_t)t] = off;
         off += tri_tiles(ntd + ntu) * TE;
+        mf.wrel[(size_t)t] = wo;
+        wo += tri_tiles(ntd) * TE;
         mf.ltrel[(size_t)t] = lt;
         lt += ntd * ntu * TE;
         mf.voff[(size_t)t] = vo;
         vo += (ntd + ntu) * TS;
     }
     mf.region = off;
+    mf.w_region = wo;
     mf.lt_region = lt;
     mf.vec_len = vo;
     mf.a_base = off64;
     off64 += off;
     mf.w_base = off64;
-    off64 += off;
+    off64 += wo;
     mf.wt_base = off64;
-    off64 += off;
+    off64 += wo;
     mf.lt_base = off64;
     off64 += lt;
     mf.ng_base = off64;
@@ -668,8 +678,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         }
     }
     auto A = [&](int32_t t, int64_t I, int64_t J) { return mf.a_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
-    auto W = [&](int32_t t, int64_t I, int64_t J) { return mf.w_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
-    auto Wt = [&](int32_t t, int64_t I, int64_t J) { return mf.wt_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
+    auto W = [&](int32_t t, int64_t I, int64_t J) { return mf.w_base + mf.wrel[(size_t)t] + tri_index(I, J) * TE; };
+    auto Wt = [&](int32_t t, int64_t I, int64_t J) { return mf.wt_base + mf.wrel[(size_t)t] + tri_index(I, J) * TE; };
     // G = L21 W11 (boundary rows times the inverse of the own block) is stored
     // negated, NG(I, J) with I a boundary tile and J an own tile, and as
     // per-tile transposes NGT(I, J) = NG(I, J)^T.
@@ -697,6 +707,7 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
             lv.nt.push_back(mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t]);
             lv.nt_own.push_back(mf.nt_d[(size_t)t]);
             lv.rel.push_back(mf.rel[(size_t)t]);
+            lv.wrel.push_back(mf.wrel[(size_t)t]);
             ids.push_back(t);
         }
         lv.a_base = mf.a_base;
@@ -913,7 +924,6 @@ static void method_work(Handle &h) {
 void append_basis_program(Handle &h, TaskLists &tl, const std::vector<int64_t> &ms, std::vector<Launch> &prog,
                           int parts) {
     auto Wg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.w_base + h.gset.rel[m] + tri_index(I, J) * TE; };
-    auto Wtg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.wt_base + h.gset.rel[m] + tri_index(I, J) * TE; };
     auto Rt = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
     if (parts & BP_Y) {
         Launch L1{LK_GEMM, (int64_t)tl.gemm.size(), 0};
@@ -928,13 +938,14 @@ void append_basis_program(Handle &h, TaskLists &tl, const std::vector<int64_t> &
     }
     if (parts & BP_X) {
         Launch L2{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+        // X_IC = sum_{J >= I} W_JI^T Y_JC: W read transposed
         for (int64_t m : ms)
             for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C)
                 for (int64_t I = 0; I < h.gset.nt[m]; ++I) {
                     tl.gemm.push_back({Rt(h.gm_roff[(size_t)m], m, I, C), -1, (int32_t)tl.pairs.size(),
-                                       (int32_t)(h.gset.nt[m] - I), 0, 0});
+                                       (int32_t)(h.gset.nt[m] - I), GF_TRANS_A, 0});
                     for (int64_t J = I; J < h.gset.nt[m]; ++J)
-                        tl.pairs.push_back({Wtg(m, J, I), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
+                        tl.pairs.push_back({Wg(m, J, I), Rt(h.gm_ytoff[(size_t)m], m, J, C)});
                 }
         L2.count = (int64_t)tl.gemm.size() - L2.start;
         if (L2.count) prog.push_back(L2);
@@ -1206,9 +1217,24 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     layout_set(h.cset);
     int64_t off64 = 0, off32 = 0, offbf = 0;
     auto take64 = [&](int64_t k) { const int64_t o = off64; off64 += k; return o; };
+    const bool lowp = h.smoother_precision != 64;
+    const bool inverse = h.smoother_form == HPLMM_SMOOTHER_INVERSE;
+    // the inverse form reads W transposed in its products: of Wt it keeps only
+    // the diagonal tiles that the Cholesky panels multiply by
+    auto wt_elems = [&](DenseSet &ds) {
+        ds.wt_diag = inverse;
+        if (!inverse) return ds.region;
+        ds.wdrel.resize(ds.n.size());
+        int64_t o = 0;
+        for (size_t m = 0; m < ds.n.size(); ++m) {
+            ds.wdrel[m] = o;
+            o += ds.nt[m] * TE;
+        }
+        return o;
+    };
     h.gset.a_base = take64(h.gset.region);
     h.gset.w_base = take64(h.gset.region);
-    h.gset.wt_base = take64(h.gset.region);
+    h.gset.wt_base = take64(wt_elems(h.gset));
     h.gm_roff.resize(nG);
     h.gm_ytoff.resize(nG);
     h.gm_xtoff.resize(nG);
@@ -1235,14 +1261,12 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         }
         h.gcol_len = co;
     }
-    const bool lowp = h.smoother_precision != 64;
-    const bool inverse = h.smoother_form == HPLMM_SMOOTHER_INVERSE;
     // contact grids factored in FP32: the reduced-precision factor form only
     const bool c32 = lowp && !inverse;
     if (!c32) {
         h.cset.a_base = take64(h.cset.region);
         h.cset.w_base = take64(h.cset.region);
-        h.cset.wt_base = take64(h.cset.region);
+        h.cset.wt_base = take64(wt_elems(h.cset));
     } else {
         h.c_stage_base = take64(h.cset.region);
         h.cset.a_base = off32;
@@ -1679,6 +1703,9 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
             for (int32_t t = 0; t < mf.n_fronts; ++t) {
                 const int64_t nt = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
                 chk(in(mf.a_base + mf.rel[(size_t)t], tri_tiles(nt) * TE, h.ar64_n), "front tiles");
+                chk(in(mf.wrel[(size_t)t], tri_tiles(mf.nt_d[(size_t)t]) * TE, mf.w_region) &&
+                        mf.wt_base == mf.w_base + mf.w_region && in(mf.wt_base, mf.w_region, h.ar64_n),
+                    "front W11 tiles");
                 chk(in(mf.lt_base + mf.ltrel[(size_t)t], mf.nt_d[(size_t)t] * mf.nt_u[(size_t)t] * TE, h.ar64_n),
                     "front NG^T tiles");
                 chk(in(mf.ng_base + mf.ltrel[(size_t)t], mf.nt_d[(size_t)t] * mf.nt_u[(size_t)t] * TE, h.ar64_n),

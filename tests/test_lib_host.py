@@ -181,27 +181,32 @@ def test_coarse_leaf_option(hp):
 
 def test_smoother_forms(hp):
     """The inverse form adds one region per dense set (S = W^T W, the same
-    packed layout) and one tile product task per stored tile of S, at least;
-    auto picks it at every precision.  At reduced precision it factors every
-    block in FP64 (the FP64 arena of the factor form, without an FP64 S), keeps
-    W rounded to the storage precision (FP32 or bfloat16 arena) and S formed
+    packed layout, R tiles over both sets) and one tile product task per
+    stored tile of S, at least; its products read W transposed, so of Wt it
+    keeps only the diagonal tiles (D = sum of nt over grains and contact
+    grids) instead of a full region.  auto picks it at every precision.  At
+    reduced precision it factors every block in FP64 (no FP64 S), keeps W
+    rounded to the storage precision (FP32 or bfloat16 arena) and S formed
     from it in the FP32 arena."""
     p = synth.config_pores(16, 4, seed=1)
     sysm, part = hp.build_problem(p)
     fac = hp.plan_check(sysm, part, n_mortar=4, smoother_form="factors")
     inv = hp.plan_check(sysm, part, n_mortar=4, smoother_form="inverse")
     assert hp.plan_check(sysm, part, n_mortar=4) == inv
-    s_tiles = (inv["ar64"] - fac["ar64"]) // 4096
-    assert s_tiles > 0 and (inv["ar64"] - fac["ar64"]) % 4096 == 0
-    assert inv["tile_tasks"] - fac["tile_tasks"] >= s_tiles
+    ng = np.bincount(part.node_grain[part.node_grain >= 0], minlength=part.n_grains) * 3
+    nc = np.diff(part.contact_ptr) * 3
+    nt = np.concatenate([(ng[ng > 0] + 63) // 64, (nc + 63) // 64])
+    D, R = int(nt.sum()), int((nt * (nt + 1) // 2).sum())
+    assert inv["ar64"] - fac["ar64"] == D * 4096     # + S (R tiles), - Wt beyond its diagonal tiles (R - D)
+    assert inv["tile_tasks"] - fac["tile_tasks"] >= R
     for prec in (32, 16):
         low_inv = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec, smoother_form="inverse")
         low_auto = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec)
-        assert low_inv["ar64"] == fac["ar64"]          # every factorisation in FP64, no FP64 S
+        assert inv["ar64"] - low_inv["ar64"] == R * 4096          # every factorisation in FP64, no FP64 S
         if prec == 32:
-            assert low_inv["ar32"] == 2 * s_tiles * 4096 and low_inv["arbf"] == 0   # W32 and S
+            assert low_inv["ar32"] == 2 * R * 4096 and low_inv["arbf"] == 0   # W32 and S
         else:
-            assert low_inv["arbf"] == s_tiles * 4096 and low_inv["ar32"] == s_tiles * 4096   # W16; S in FP32
+            assert low_inv["arbf"] == R * 4096 and low_inv["ar32"] == R * 4096   # W16; S in FP32
         low_fac = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec, smoother_form="factors")
         assert low_fac["ar64"] < fac["ar64"]           # FP32 contact factorisation
         assert low_auto == low_inv                     # auto: the inverse form
