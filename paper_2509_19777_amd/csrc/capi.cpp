@@ -96,8 +96,8 @@ static void run_bf16_program(Handle &h, const TaskLists &tl, const std::vector<L
 }
 
 // The smoother's symmetric inverse S of a dense set (inverse form), on
-// stream s after its factor program.  FP64: S = W^T W from the FP64 W and
-// its transposed tiles.  Reduced precision: W is rounded to the storage
+// stream s after its factor program.  FP64: S = W^T W from the FP64 W (the
+// left operand read transposed).  Reduced precision: W is rounded to the storage
 // precision first and S = Wp^T Wp is formed from the rounded values on the
 // matrix cores with FP32 accumulation (FP32 operands at 32, bfloat16 operands
 // at 16) and kept in FP32 -- the Gram matrix of Wp, positive definite however
@@ -162,10 +162,6 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
             hip_check(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking), "stream");
             for (auto &e : h.side_ev) hip_check(hipEventCreate(&e), "event");
         }
-        hip_check(hipStreamWaitEvent(h.side, ev[0], 0), "fork");
-        hip_check(hipEventRecord(h.side_ev[0], h.side), "event");
-        contact_setup(h, h.side);
-        hip_check(hipEventRecord(h.side_ev[1], h.side), "event");
     }
     // ---- grains: blocks, factor, inverse, basis (Eqs. 23-24) ----
     zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
@@ -184,6 +180,15 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
     }
     run_program<double>(h, h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
     hip_check(hipEventRecord(ev[5], s), "event");
+    if (fork) {
+        // the contact grids start once the grain factorisation is done: its
+        // chain of small dependent launches runs best alone, while the grain
+        // basis and the coarse factorisation leave room beside them
+        hip_check(hipStreamWaitEvent(h.side, ev[5], 0), "fork");
+        hip_check(hipEventRecord(h.side_ev[0], h.side), "event");
+        contact_setup(h, h.side);
+        hip_check(hipEventRecord(h.side_ev[1], h.side), "event");
+    }
     if (stage < 2) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -1485,7 +1490,7 @@ extern "C" hplmm_status hplmm_debug_grain_layout(hplmm_handle *hh, int64_t *out,
             o[4] = h.gm_ntc[(size_t)m];
             o[5] = h.gset.a_base + h.gset.rel[(size_t)m];
             o[6] = h.gset.w_base + h.gset.rel[(size_t)m];
-            o[7] = h.gset.wt_base + h.gset.rel[(size_t)m];
+            o[7] = h.gset.wt_diag ? -1 : h.gset.wt_base + h.gset.rel[(size_t)m];
             o[8] = h.gm_roff[(size_t)m];
             o[9] = h.gm_ytoff[(size_t)m];
             o[10] = h.gm_koff[(size_t)m];
@@ -1509,7 +1514,7 @@ extern "C" hplmm_status hplmm_debug_contact_layout(hplmm_handle *hh, int64_t *ou
             o[2] = f32 ? 1 : 0;
             o[3] = h.cset.a_base + h.cset.rel[(size_t)m];
             o[4] = h.cset.w_base + h.cset.rel[(size_t)m];
-            o[5] = h.cset.wt_base + h.cset.rel[(size_t)m];
+            o[5] = h.cset.wt_diag ? -1 : h.cset.wt_base + h.cset.rel[(size_t)m];
         }
         return HPLMM_OK;
     });
