@@ -310,20 +310,39 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ i
     }
 }
 
+// 1/d for a positive normal d.  FP64: the hardware reciprocal refined by
+// two Newton-Raphson steps x <- x + x (1 - d x), within an ulp or so of the
+// rounded quotient and a third of the latency of an IEEE division, which
+// sits on the diagonal factorisation's serial path once per column.
+template <class T>
+__device__ __forceinline__ T pivot_recip(T d) {
+    return T(1) / d;
+}
+template <>
+__device__ __forceinline__ double pivot_recip<double>(double d) {
+    double x = __builtin_amdgcn_rcp(d);
+    double e = fma(-d, x, 1.0);
+    x = fma(x, e, x);
+    e = fma(-d, x, 1.0);
+    return fma(x, e, x);
+}
+
 // Cholesky factor L and inverse W = L^-1 of one 64x64 tile, held in
 // registers: lane r of wave q keeps row r of L and row r of V = W^T at the
 // columns c = q + 4k (k < 16).  Step j uses the unscaled pivot d_j = L_jj:
 // the owners of column j publish it (L and V) through LDS, then every thread
 // subtracts L_rj L_cj / d_j from its entries of L and V_rj L_cj / d_j from V
-// (forward elimination on the identity) for c > j, and the owners scale
-// column j by 1/sqrt(d_j).  Entries above the diagonal of L are never read
-// for the lower part and are masked on store.  One barrier per step
-// (double-buffered columns); the published column is stored permuted
-// (slot (c & 3) * 16 + c / 4) so a thread's 16 values are contiguous.  The
-// 64 steps are unrolled at compile time so every register index is static.
+// (forward elimination on the identity) for c > j.  Later steps read only
+// later columns, so the scaling of column j by 1/sqrt(d_j) waits until all
+// 64 steps are done (d_j is kept in LDS) and leaves the serial path.
+// Entries above the diagonal of L are never read for the lower part and are
+// masked on store.  One barrier per step (double-buffered columns); the
+// published column is stored permuted (slot (c & 3) * 16 + c / 4) so a
+// thread's 16 values are contiguous.  The 64 steps are unrolled at compile
+// time so every register index is static.
 template <class T, int J>
 struct DiagStep {
-    static __device__ __forceinline__ void run(T (&Lr)[16], T (&Vr)[16], T *colL, T *colV, int r, int q,
+    static __device__ __forceinline__ void run(T (&Lr)[16], T (&Vr)[16], T *colL, T *colV, T *piv, int r, int q,
                                                bool &bad) {
         constexpr int kj = J >> 2, qj = J & 3;
         T *cl = colL + (J & 1) * TS;
@@ -339,7 +358,8 @@ struct DiagStep {
             bad = true;
             d = T(1);
         }
-        const T inv_d = T(1) / d;
+        if (threadIdx.x == 0) piv[J] = d;
+        const T inv_d = pivot_recip<T>(d);
         const T lrj = cl[pr] * inv_d;
         const T vrj = cv[pr] * inv_d;
         const T *cq = cl + q * 16;
@@ -351,17 +371,12 @@ struct DiagStep {
                 Vr[k] -= vrj * lcj;
             }
         }
-        if (q == qj) {
-            const T sc = T(1) / sqrt(d);
-            Lr[kj] *= sc;
-            Vr[kj] *= sc;
-        }
-        DiagStep<T, J + 1>::run(Lr, Vr, colL, colV, r, q, bad);
+        DiagStep<T, J + 1>::run(Lr, Vr, colL, colV, piv, r, q, bad);
     }
 };
 template <class T>
 struct DiagStep<T, TS> {
-    static __device__ __forceinline__ void run(T (&)[16], T (&)[16], T *, T *, int, int, bool &) {}
+    static __device__ __forceinline__ void run(T (&)[16], T (&)[16], T *, T *, T *, int, int, bool &) {}
 };
 
 template <class T>
@@ -371,6 +386,7 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
                                                    int32_t *__restrict__ flag) {
     __shared__ T colL[2 * TS];
     __shared__ T colV[2 * TS];
+    __shared__ T piv[TS];
     __shared__ T S[TS * LD];
     const DiagTask tk = tasks[blockIdx.x];
     const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
@@ -383,25 +399,54 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
         Vr[k] = r == c ? T(1) : T(0);
     }
     if (tk.p_off >= 0) {
-        // A -= P P^T: P staged column by column in LDS; a wave's 16 columns
-        // c = q + 4k read the same LDS words on every lane (broadcast)
+        // A -= P P^T on the matrix cores: P staged in LDS as S[k][m] = P(m, k)
+        // (both operands read from it); the waves of the three lower 32x32
+        // quadrants accumulate theirs over k = 0..63, the upper one idles
         const T *pp = A + tk.p_off;
         for (int e = threadIdx.x; e < TE; e += 256) S[(e >> 6) * LD + (e & (TS - 1))] = pp[e];
         __syncthreads();
-        T acc[16];
-#pragma unroll
-        for (int k = 0; k < 16; ++k) acc[k] = T(0);
-        for (int p = 0; p < TS; ++p) {
-            const T prp = S[p * LD + r];
-#pragma unroll
-            for (int k = 0; k < 16; ++k) acc[k] += prp * S[p * LD + q + 4 * k];
+        const int lr = r & 15, lq = r >> 4;
+        const int wm = (q >> 1) * 32, wn = (q & 1) * 32;
+        typename Mfma<T>::acc_t acc[2][2];
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+        if (wm >= wn) {
+#pragma unroll 4
+            for (int kk = 0; kk < TS; kk += 4) {
+                const int k = kk + lq;
+                const T a0 = S[k * LD + wm + lr], a1 = S[k * LD + wm + 16 + lr];
+                const T b0 = S[k * LD + wn + lr], b1 = S[k * LD + wn + 16 + lr];
+                acc[0][0] = Mfma<T>::mac(a0, b0, acc[0][0]);
+                acc[0][1] = Mfma<T>::mac(a0, b1, acc[0][1]);
+                acc[1][0] = Mfma<T>::mac(a1, b0, acc[1][0]);
+                acc[1][1] = Mfma<T>::mac(a1, b1, acc[1][1]);
+            }
         }
+        __syncthreads();   // every wave has read P
+        if (wm >= wn)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    for (int rr = 0; rr < 4; ++rr)
+                        S[(wn + 16 * j + lr) * LD + wm + 16 * i + Mfma<T>::row(lq, rr)] = acc[i][j][rr];
+        __syncthreads();
 #pragma unroll
-        for (int k = 0; k < 16; ++k)
-            if (r >= q + 4 * k) Lr[k] -= acc[k];
+        for (int k = 0; k < 16; ++k) {
+            const int c = q + 4 * k;
+            if (r >= c) Lr[k] -= S[c * LD + r];
+        }
     }
     bool bad = false;
-    DiagStep<T, 0>::run(Lr, Vr, colL, colV, r, q, bad);
+    DiagStep<T, 0>::run(Lr, Vr, colL, colV, piv, r, q, bad);
+    // the deferred column scaling: column c of L and of V by 1/sqrt(d_c)
+    __syncthreads();
+    if (threadIdx.x < TS) colL[threadIdx.x] = T(1) / sqrt(piv[threadIdx.x]);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+        const T sc = colL[q + 4 * k];
+        Lr[k] *= sc;
+        Vr[k] *= sc;
+    }
     // L and W^T = V are stored with coalesced writes; W goes through LDS
     T *w = Wa + tk.w_off;
     T *wt = Wta + tk.wt_off;
