@@ -101,6 +101,10 @@ struct SymPair {
     int64_t t_off;
     int64_t x_off;
     int64_t p_off;   // -1 on the diagonal
+    // valid rows and columns of the tile (the last tile row and column of a
+    // matrix hold fewer): the padding beyond them is never read
+    int32_t rows;
+    int32_t cols;
 };
 
 // Row j of the symmetric product: y[y_off + r] += sum_k part[p_off + 64 k + r]

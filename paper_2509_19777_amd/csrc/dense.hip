@@ -532,6 +532,7 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
     constexpr int R = Vec16<T>::R;          // rows per lane
     constexpr int LPC = TS / R;             // lanes per column
     __shared__ double red[NW * R * TS];
+    __shared__ double dgs[TS];   // the diagonal tile's transposed part, added to this row
     const GemvTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int phase = lane / LPC, row0 = (lane % LPC) * R;
@@ -588,6 +589,12 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
 // replicated over those low bits.  The chunk count equals the number of such
 // replicas, so the lane whose low bits equal the chunk keeps its value, and
 // one store per tile with every lane active writes the tile's 64 slot values.
+// The last tile row and column of a matrix extend past its end: their padded
+// rows and columns (zero, or the identity on the diagonal, times a zero x)
+// are masked off instead of read.  Of the diagonal tile S_II only the lower
+// triangle is read: its rows r >= c give the row part, rows r > c the
+// transposed part, reduce-scattered like the others into LDS and added to
+// this row's result (the diagonal tile is the last pair of every row task).
 template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__ arena,
                                                            const double *__restrict__ x, double *__restrict__ y,
@@ -599,6 +606,7 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
     constexpr int NCH = TS / (8 * R);                   // chunks of 8 columns per lane: 4, 2, 1
     constexpr int H2 = LPC / 2, H1 = LPC / 4, H0 = LPC / 8;   // the reduce-scatter's lane bits
     __shared__ double red[NW * R * TS];
+    __shared__ double dgs[TS];   // the diagonal tile's transposed part, added to this row
     const GemvTask tk = tasks[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int phase = lane / LPC, lc = lane % LPC, row0 = lc * R;
@@ -615,6 +623,8 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
         const T *tile = arena + pr.t_off;
         const double *xs = x + pr.x_off;
         const bool below = pr.p_off >= 0;
+        const bool diag = !below;            // the diagonal tile: its lower triangle only
+        const bool rok = row0 < pr.rows;   // rows beyond the matrix's end: padding, not read
         double mine = 0.0;   // this lane's slot value (the chunk given by its low bits)
 #pragma unroll 1
         for (int ch = 0; ch < NCH; ++ch) {
@@ -623,19 +633,27 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
             for (int u = 0; u < 8; ++u) {
                 const int c = R * (8 * ch + u) + phase;
                 double v[R];
-                Vec16<T>::load(tile + c * TS + row0, v);
+                if (rok && c < pr.cols && (below || row0 + R > c)) {
+                    Vec16<T>::load(tile + c * TS + row0, v);
+                } else {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[r] = 0.0;
+                }
                 const double xc = xs[c];
                 double t = 0.0;
 #pragma unroll
                 for (int r = 0; r < R; ++r) {
-                    acc[r] += v[r] * xc;
-                    t += v[r] * xi[r];
+                    // diagonal tile: row part from rows r >= c, transposed part
+                    // from rows r > c (the upper triangle is their mirror)
+                    const double vr = diag && row0 + r < c ? 0.0 : v[r];
+                    acc[r] += vr * xc;
+                    t += diag && row0 + r == c ? 0.0 : vr * xi[r];
                 }
                 cs[u] = t;
                 // narrow storage widens to 2R registers per load: four loads in flight
                 if (R > 2 && u == 3) __builtin_amdgcn_sched_barrier(0);
             }
-            if (below) {
+            {
                 double t4[4], t3[2];
 #pragma unroll
                 for (int k = 0; k < 4; ++k)
@@ -649,8 +667,13 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
                 if ((lc & (H0 - 1)) == ch) mine = t;
             }
         }
-        // one store per tile with every lane active
-        if (below) part[pr.p_off + R * (8 * (lc & (H0 - 1)) + uq) + phase] = mine;
+        // one store per tile with every lane active: a slot of row J, or for
+        // the diagonal tile this row's own part
+        const int col = R * (8 * (lc & (H0 - 1)) + uq) + phase;
+        if (below)
+            part[pr.p_off + col] = mine;
+        else
+            dgs[col] = mine;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) red[(wave * R + phase) * TS + row0 + r] = acc[r];
@@ -659,7 +682,7 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
     const int t = threadIdx.x;
     double s = 0.0;
     for (int q = 0; q < NW * R; ++q) s += red[q * TS + t];
-    y[tk.y_off + t] = s;
+    y[tk.y_off + t] = s + dgs[t];
 }
 
 // One wavefront per row: lane r adds the row's transposed products in order.

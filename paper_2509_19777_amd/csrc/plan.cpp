@@ -288,10 +288,12 @@ void build_sym_gemv(DenseSet &ds, std::vector<GemvTask> &vt, std::vector<SymPair
         for (int64_t I = 0; I < ds.nt[m]; ++I) order.push_back({m, I});
     std::stable_sort(order.begin(), order.end(), [&](auto a, auto b) { return a.second > b.second; });
     ds.gemv_S.start = (int64_t)vt.size();
+    auto valid = [&](int64_t m, int64_t I) { return (int32_t)std::min<int64_t>(TS, ds.n[m] - I * TS); };
     for (auto [m, I] : order) {
         vt.push_back({ds.voff[m] + I * TS, (int32_t)sp.size(), (int32_t)(I + 1), -1});
         for (int64_t J = 0; J <= I; ++J)
-            sp.push_back({s_abs + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS, J < I ? slot(m, I, J) : -1});
+            sp.push_back({s_abs + ds.rel[m] + tri_index(I, J) * TE, ds.voff[m] + J * TS, J < I ? slot(m, I, J) : -1,
+                          valid(m, I), valid(m, J)});
     }
     ds.gemv_S.count = (int64_t)vt.size() - ds.gemv_S.start;
     ds.gemv_S.sym = true;
@@ -314,6 +316,24 @@ double gemv_bytes(const std::vector<GemvTask> &vt, Range r, double elem) {
     double b = 0.0;
     for (int64_t i = r.start; i < r.start + r.count; ++i)
         b += (double)vt[(size_t)i].pair_count * (TE * elem + TS * 8.0) + TS * 8.0;
+    return b;
+}
+
+// Bytes the symmetric GEMV launch reads and writes: the valid part of every
+// tile (the lower triangle of the diagonal one), its x segment and the row's
+// own x segment, the row of y and a slot per transposed product.
+double sym_gemv_bytes(const std::vector<GemvTask> &vt, const std::vector<SymPair> &sp, Range r, double elem) {
+    double b = 0.0;
+    for (int64_t i = r.start; i < r.start + r.count; ++i) {
+        const GemvTask &t = vt[(size_t)i];
+        for (int32_t q = 0; q < t.pair_count; ++q) {
+            const SymPair &pr = sp[(size_t)(t.pair_start + q)];
+            // off the diagonal the valid block; on it the lower triangle
+            const double e = pr.p_off >= 0 ? (double)pr.rows * pr.cols : 0.5 * pr.rows * (pr.rows + 1.0);
+            b += e * elem + TS * 8.0 + (pr.p_off >= 0 ? TS * 8.0 : 0.0);
+        }
+        b += 2.0 * TS * 8.0;
+    }
     return b;
 }
 
@@ -1387,8 +1407,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         h.cset.gemv_W.bytes = gemv_bytes(h.vtasks, h.cset.gemv_W, ge);
         h.cset.gemv_Wt.bytes = gemv_bytes(h.vtasks, h.cset.gemv_Wt, ge);
         for (DenseSet *ds : {&h.gset, &h.cset}) {
-            // the symmetric product reads its own x segment once more per row
-            ds->gemv_S.bytes = gemv_bytes(h.vtasks, ds->gemv_S, gs) + (double)ds->gemv_S.count * TS * 8.0;
+            ds->gemv_S.bytes = sym_gemv_bytes(h.vtasks, h.spairs, ds->gemv_S, gs);
             ds->red_S.bytes = sym_reduce_bytes(h.rtasks, ds->red_S);
         }
         h.gemv_XT.bytes = gemv_bytes(h.vtasks, h.gemv_XT, 8.0);
@@ -1650,7 +1669,8 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const SymPair &pr = h.spairs[(size_t)(t.pair_start + q)];
                     chk(in(pr.t_off, TE, h.smoother_precision == 64 ? h.ar64_n : h.ar32_n) &&
-                            in(pr.x_off, TS, ds.vec_len),
+                            in(pr.x_off, TS, ds.vec_len) && pr.rows >= 1 && pr.rows <= TS && pr.cols >= 1 &&
+                            pr.cols <= TS,
                         what);
                     // the diagonal tile, last in its row, carries no transposed product
                     chk(q + 1 == t.pair_count ? pr.p_off == -1 : in(pr.p_off, TS, h.sym_part_len), what);
