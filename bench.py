@@ -101,6 +101,9 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    hbm = measure_triad(torch, hp)
+    print(f"# streaming triad: {hbm}", file=sys.stderr, flush=True)
+
     def step():
         S.setup()
         x, info = S.solve(rtol=1e-8, restart=50, maxit=300)
@@ -202,11 +205,41 @@ def main():
         "spmv_algorithmic_bytes": S.algorithmic_bytes()["spmv"],
         "kernel_breakdown": breakdown,   # one untimed step with events around every class
         "autotune": tune,
+        "hbm_measured": hbm,
         "roofline": roof,
         "roofline_secondary": None if second is None else class_roofline(second, prof_all, meth, 1, S, names),
         "cpu_baseline": None if a.no_cpu_baseline else cpu_baseline(a, infos[-1]["iters"], 3 * sizes["n_nodes"], sizes["grain_mats"]),
     }
+    for rk in ("roofline", "roofline_secondary"):
+        r = out[rk]
+        if r and r.get("bound") == "hbm":
+            r["frac_of_triad"] = round(r["achieved"] / hbm["triad_gbs_best"], 4)
     print(json.dumps(out), flush=True)
+
+
+def measure_triad(torch, hp, mib=1024, reps=20):
+    """Streaming-triad bandwidth of this GPU (a = b + s c, three arrays of
+    `mib` MiB, the library's own kernel): the best and the median of `reps`
+    timed launches, beside the vendor's 8 TB/s."""
+    n = mib * (1 << 20) // 8
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.ones(n, dtype=torch.float64, device="cuda")
+    c = torch.full((n,), 0.5, dtype=torch.float64, device="cuda")
+    hp.stream_triad(a, b, c, 3.0)
+    torch.cuda.synchronize()
+    if not bool(torch.all(a == 2.5)):
+        raise RuntimeError("streaming triad returned wrong values")
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    for e0, e1 in ev:
+        e0.record()
+        hp.stream_triad(a, b, c, 3.0)
+        e1.record()
+    torch.cuda.synchronize()
+    gbs = sorted(3 * 8 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9 for e0, e1 in ev)
+    del a, b, c
+    return {"triad_gbs_best": round(gbs[-1], 1), "triad_gbs_median": round(gbs[len(gbs) // 2], 1),
+            "vendor_peak_gbs": HBM_PEAK_GBS, "arrays_mib": mib,
+            "kernel": "a = b + s c, two reads and one write per element (hplmm_stream_triad)"}
 
 
 # kernel classes of the built-in profiler behind each roofline class

@@ -35,6 +35,14 @@ hplmm_status hplmm_debug_tile_gemm(int32_t precision, const void *A_dev, const v
 hplmm_status hplmm_debug_diag(int32_t precision, void *A_dev, const void *P_dev, void *W_dev, void *Wt_dev,
                               void *stream);
 
+/* Bandwidth reference for measurements: a[i] = b[i] + scalar c[i], i < n,
+ * on caller device arrays (float64, 16-byte aligned, a distinct from b and
+ * c), launched on the stream without synchronising.  Moves 24 n bytes (two
+ * reads, one write): the streaming-triad figure that HBM rates are compared
+ * with beside the vendor peak. */
+hplmm_status hplmm_stream_triad(double *a, const double *b, const double *c, double scalar, int64_t n,
+                                void *stream);
+
 /* Run the numeric set-up of a planned handle up to a stage and stop:
  *   stage 0: zero and gather grain blocks, coupling blocks and loads
  *   stage 1: + grain factorisation (Cholesky and inverse)

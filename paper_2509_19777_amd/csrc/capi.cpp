@@ -1451,6 +1451,17 @@ extern "C" hplmm_status hplmm_debug_diag(int32_t precision, void *A, const void 
     });
 }
 
+extern "C" hplmm_status hplmm_stream_triad(double *a, const double *b, const double *c, double scalar, int64_t n,
+                                           void *stream) {
+    return guarded([&]() -> hplmm_status {
+        if (n < 0 || (n > 0 && (!a || !b || !c))) fail(HPLMM_E_ARG, "bad arguments");
+        if (((uintptr_t)a | (uintptr_t)b | (uintptr_t)c) & 15) fail(HPLMM_E_ARG, "arrays must be 16-byte aligned");
+        launch_triad(a, b, c, scalar, n, as_stream(stream));
+        hip_check(hipGetLastError(), "triad launch");
+        return HPLMM_OK;
+    });
+}
+
 extern "C" hplmm_status hplmm_debug_setup_stage(hplmm_handle *hh, int32_t stage, void *stream) {
     return guarded([&]() -> hplmm_status {
         if (!hh) fail(HPLMM_E_ARG, "NULL handle");

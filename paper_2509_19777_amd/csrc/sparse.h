@@ -164,6 +164,10 @@ void launch_convert_f64_f32(const double *src, float *dst, int64_t n, hipStream_
 void launch_convert_f32_bf16(const float *src, uint16_t *dst, int64_t n, hipStream_t s);
 void launch_convert_f64_bf16(const double *src, uint16_t *dst, int64_t n, hipStream_t s);
 
+// ---- bandwidth reference ----------------------------------------------------
+// a = b + sc c over n doubles (16-byte aligned arrays)
+void launch_triad(double *a, const double *b, const double *c, double sc, int64_t n, hipStream_t s);
+
 // ---- Krylov -----------------------------------------------------------------
 // One pass over a Krylov basis, per block of rows (multidot_blocks(n) blocks):
 //   x = w - sum_{j < k_sub} hsub[j] V_j  (V_j = V + j*ld; written to wout when

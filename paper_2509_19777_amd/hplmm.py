@@ -81,6 +81,7 @@ EXPORTS = {
     "hplmm_set_tuning": (i32, [C.c_void_p, C.c_void_p, i64]),
     "hplmm_debug_tile_gemm": (i32, [i32, C.c_void_p, C.c_void_p, i32, C.c_void_p, C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_diag": (i32, [i32, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "hplmm_stream_triad": (i32, [C.c_void_p, C.c_void_p, C.c_void_p, f64, i64, C.c_void_p]),
     "hplmm_debug_setup_stage": (i32, [C.c_void_p, i32, C.c_void_p]),
     "hplmm_debug_read_arena": (i32, [C.c_void_p, i32, i64, i64, C.c_void_p]),
     "hplmm_debug_grain_layout": (i32, [C.c_void_p, P(i64), i64]),
@@ -491,6 +492,17 @@ def debug_diag(A, P=None):
     Wt = torch.empty_like(A)
     _check(lib().hplmm_debug_diag(prec, _vp(A), _vp(P), _vp(W), _vp(Wt), _stream()))
     return A, W, Wt
+
+
+def stream_triad(a, b, c, scalar):
+    """a = b + scalar c on float64 device tensors (the bandwidth reference)."""
+    for t in (a, b, c):
+        if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+            raise ValueError("triad arrays must be contiguous float64 device tensors")
+    if not (a.numel() == b.numel() == c.numel()):
+        raise ValueError("triad arrays must have one length")
+    _check(lib().hplmm_stream_triad(_vp(a), _vp(b), _vp(c), float(scalar), a.numel(), _stream()))
+    return a
 
 
 def debug_setup_stage(solver, stage):

@@ -201,3 +201,22 @@ def test_stage_gather_and_factor(staged):
         Lr = np.linalg.cholesky(blocks[g])
         assert np.abs(np.tril(L) - Lr).max() <= 1e-12 * np.abs(Lr).max(), g
         assert np.abs(np.tril(W) @ Lr - np.eye(n)).max() <= 1e-11, g
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [1, 7, 4096 * 3 + 5, 1 << 22])
+def test_stream_triad(n):
+    # the bandwidth reference: a = b + s c, one multiply-add per element (the
+    # kernel may fuse it: within one rounding of the product of the two-step sum)
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2509_19777_amd import hplmm as hp
+    g = torch.Generator().manual_seed(n)
+    b = torch.randn(n, generator=g, dtype=torch.float64)
+    c = torch.randn(n, generator=g, dtype=torch.float64)
+    a = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+    hp.stream_triad(a, b.cuda(), c.cuda(), -1.5)
+    prod = (-1.5) * c.numpy()
+    ref = b.numpy() + prod
+    assert np.all(np.abs(a.cpu().numpy() - ref) <= 2.0 ** -52 * (np.abs(prod) + np.abs(ref)))
