@@ -644,6 +644,14 @@ static void ensure_krylov(Handle &h, int32_t restart) {
     h.hbuf = h.dalloc<double>(restart + 4);
     h.h2 = h.dalloc<double>(restart + 4);
     h.ydev = h.dalloc<double>(restart + 4);
+    if (h.hcol_host) {
+        (void)hipHostFree(h.hcol_host);
+        h.hcol_host = nullptr;
+    }
+    hip_check(hipHostMalloc((void **)&h.hcol_host, sizeof(double) * 2 * (size_t)(restart + 4), hipHostMallocDefault),
+              "hipHostMalloc");
+    for (hipEvent_t &e : h.hcol_ev)
+        if (!e) hip_check(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
 }
 
 static double device_dot(Handle &h, const double *a, const double *b, double *dst, hipStream_t s) {
@@ -674,6 +682,12 @@ static void arnoldi_step(Handle &h, int32_t j, hipStream_t s) {
     launch_kr_reduce(h.part, h.kr_blocks, 1, h.hbuf + j + 1, nullptr, s);
     launch_normalize(vn, h.hbuf + j + 1, vn, N, s);
 }
+
+// The residual estimate must be at least this many times the tolerance for
+// the next Arnoldi step to be queued before the current one is read: a single
+// step of this solver has not dropped it by more than about 2x here, so the
+// extra step at convergence practically never happens.
+constexpr double LOOKAHEAD_MARGIN = 50.0;
 
 static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, int32_t m, int32_t maxit,
                           int32_t fixed, hplmm_solve_info *info, hipStream_t s) {
@@ -718,15 +732,21 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
         std::fill(H.begin(), H.end(), 0.0);
         std::fill(g.begin(), g.end(), 0.0);
         g[0] = beta;
-        int32_t j = 0;
-        for (; j < m && it < limit; ++j) {
+        // Step j's kernels are followed on the stream by the copy of its
+        // Hessenberg column to a pinned slot and an event.  While the residual
+        // estimate is far above the tolerance, step j + 1 (which needs only
+        // device data: v_{j+1} is normalised on the device) is queued before
+        // the host waits for step j's column, so the host's Givens work and the
+        // launch latency hide behind step j + 1.  If step j then converges,
+        // the queued step was extra work whose results are never read.
+        auto queue_step = [&](int32_t jj) {
             if (graphs) {
-                hipGraphExec_t &ge = h.arnoldi_graphs[(size_t)j];
+                hipGraphExec_t &ge = h.arnoldi_graphs[(size_t)jj];
                 if (!ge) {
                     hipGraph_t g = nullptr;
                     hip_check(hipStreamBeginCapture(h.gstream, hipStreamCaptureModeThreadLocal), "begin capture");
                     try {
-                        arnoldi_step(h, j, h.gstream);
+                        arnoldi_step(h, jj, h.gstream);
                     } catch (...) {
                         // leave the stream out of capture mode before reporting
                         if (hipStreamEndCapture(h.gstream, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
@@ -739,10 +759,23 @@ static hplmm_status gmres(Handle &h, const double *b, double *x, double rtol, in
                 }
                 hip_check(hipGraphLaunch(ge, s), "graph launch");
             } else {
-                arnoldi_step(h, j, s);
+                arnoldi_step(h, jj, s);
             }
-            hip_check(hipMemcpyAsync(hv.data(), h.hbuf, sizeof(double) * (size_t)(j + 2), hipMemcpyDeviceToHost, s), "copy h");
-            hip_check(hipStreamSynchronize(s), "step");
+            double *slot = h.hcol_host + (size_t)(jj & 1) * (size_t)(m + 4);
+            hip_check(hipMemcpyAsync(slot, h.hbuf, sizeof(double) * (size_t)(jj + 2), hipMemcpyDeviceToHost, s),
+                      "copy h");
+            hip_check(hipEventRecord(h.hcol_ev[jj & 1], s), "event");
+        };
+        int32_t j = 0;
+        bool queued = false;   // step j already queued
+        for (; j < m && it < limit; ++j) {
+            if (!queued) queue_step(j);
+            // look ahead while a one-step drop to the tolerance is out of reach
+            queued = j + 1 < m && it + 1 < limit && (fixed > 0 || std::fabs(g[j]) / bnorm > LOOKAHEAD_MARGIN * rtol);
+            if (queued) queue_step(j + 1);
+            hip_check(hipEventSynchronize(h.hcol_ev[j & 1]), "step");
+            const double *slot = h.hcol_host + (size_t)(j & 1) * (size_t)(m + 4);
+            for (int32_t i = 0; i <= j + 1; ++i) hv[(size_t)i] = slot[i];
             hv[(size_t)j + 1] = std::sqrt(hv[(size_t)j + 1]);
             for (int32_t i = 0; i <= j + 1; ++i)
                 if (!std::isfinite(hv[(size_t)i])) fail(HPLMM_E_NONFINITE, "non-finite Arnoldi coefficient");

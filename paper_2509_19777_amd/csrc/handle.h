@@ -308,6 +308,11 @@ struct Handle {
     }
     double *ydev = nullptr;
     int32_t kr_blocks = 0;
+    // pinned host copies of the last two steps' Hessenberg columns and the
+    // events that mark them ready: step j + 1 is queued before the host
+    // reads step j's column (one-step lookahead)
+    double *hcol_host = nullptr;
+    hipEvent_t hcol_ev[2] = {nullptr, nullptr};
 
     // the method's own work (unpadded sizes, each operator once), the figures
     // rooflines are stated against: set-up flops {grains: Cholesky N^3/3, two
@@ -355,6 +360,9 @@ struct Handle {
     }
     ~Handle() {
         drop_graphs();
+        for (hipEvent_t e : hcol_ev)
+            if (e) (void)hipEventDestroy(e);
+        if (hcol_host) (void)hipHostFree(hcol_host);
         if (gstream) (void)hipStreamDestroy(gstream);
         for (hipEvent_t e : side_ev)
             if (e) (void)hipEventDestroy(e);
