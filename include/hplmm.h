@@ -232,12 +232,12 @@ hplmm_status hplmm_apply(hplmm_handle *h, int32_t which, const double *r_dev,
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
  * z = Op r as hplmm_apply (same which, same kernels, same results bit for
- * bit), but the application's scratch -- the partial sums and arrival
- * counters of the coarse sweeps' split rows -- is taken from a static 8 MiB
- * device buffer of the library instead of the handle's, and the call
- * allocates nothing: no device memory, no events (the built-in profiler does
- * not see its launches).  The counters are cleared by a kernel at the start
- * of every call.  Each device holds one such buffer until the process ends,
+ * bit), but the application's scratch -- the partial sums of the coarse
+ * sweeps' split rows -- is taken from a static 8 MiB device buffer of the
+ * library instead of the handle's, and the call allocates nothing: no device
+ * memory, no events (the built-in profiler does not see its launches).  Every
+ * partial sum is written before it is read within the call, so the buffer
+ * needs no clearing.  Each device holds one such buffer until the process ends,
  * shared by every call on that device: calls that overlap on one device (two
  * streams, two threads, two handles) race and must be ordered by the caller.
  * The other per-handle buffers (local vectors, the symmetric smoother's
@@ -246,7 +246,7 @@ hplmm_status hplmm_apply(hplmm_handle *h, int32_t which, const double *r_dev,
  * 0..4, a handle planned on another device than the current one, or a plan
  * whose split rows need more than the buffer (the message gives the bytes);
  * E_STATE before set-up.  Query 12 gives the split-row scratch a plan needs:
- * int64[2] = {partial sums (doubles), counters (int32)}. */
+ * int64[1] = {partial sums (doubles)}. */
 hplmm_status hplmm_apply_noalloc(hplmm_handle *h, int32_t which, const double *r_dev, double *z_dev,
                                  void *stream);
 
@@ -311,8 +311,8 @@ hplmm_status hplmm_solve(hplmm_handle *h, const double *b_dev, double *x_dev, do
  *            contact W^T, X^T, X in the factor form and grain S, contact S,
  *            X^T, X in the inverse form
  *  11 smoother form in use: int32[1] (HPLMM_SMOOTHER_FACTORS or _INVERSE)
- *  12 split-row scratch of the coarse sweeps: int64[2] = {partial sums
- *            (doubles), arrival counters (int32)}
+ *  12 split-row scratch of the coarse sweeps: int64[1] = {partial sums
+ *            (doubles)}
  *  13 the method's own work, from unpadded sizes: double[13] =
  *            {set-up flops: grains (N^3/3 Cholesky + 2 N^2 c triangular
  *            solves with the c = k (+1) basis and correction columns + 2 N k^2

@@ -519,14 +519,14 @@ static void gemv_set(Handle &h, const Range &r, bool smoother_low, const double 
 }
 
 // Front sweeps: few long rows per launch, split over many work-groups.
-// Split rows use the handle's partial sums and counters, or the caller's
-// (split_part / split_cnt, set by the allocation-free entry point).
+// Split rows use the handle's partial-sum buffer, or the static one
+// (split_part, set by the allocation-free entry point), and a reduction
+// launch finishes them.
 static void gemv_front(Handle &h, const Range &r, hipStream_t s) {
     if (r.count == 0) return;
     double *part = h.split_part ? h.split_part : h.d_gemv_part;
-    int32_t *cnt = h.split_cnt ? h.split_cnt : h.d_gemv_cnt;
-    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, r.waves,
-                        part, cnt);
+    launch_gemv<double>(h.ar64, h.mf.V, h.mf.V, h.d_vtasks + r.start, h.d_vpairs, r.count, s, h.mf.V, r.waves, part);
+    if (r.split) launch_gemv_split_reduce(h.d_vtasks + r.start, r.count, part, h.mf.V, h.mf.V, s);
 }
 
 // u = S^-1 f for the mortar block of the coarse operator with the
@@ -1344,7 +1344,7 @@ extern "C" hplmm_status hplmm_query(hplmm_handle *hh, int32_t what, void *out, i
                 break;
             }
             case 12: {
-                const int64_t v[2] = {h.gemv_part_len, (int64_t)h.gemv_cnt_len};
+                const int64_t v[1] = {h.gemv_part_len};
                 put(v, sizeof(v));
                 break;
             }

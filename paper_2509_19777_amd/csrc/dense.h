@@ -69,15 +69,14 @@ struct DiagTask {
 // (no base term when base_off < 0).  A long row may be split into nchunk
 // tasks (one work-group each) that share y_off and base_off and cover
 // consecutive parts of its pair list: each writes its partial sum to
-// part[part_off + 64 chunk ..] and bumps counter grp; the work-group that
-// arrives last adds the partials in chunk order and writes y.
+// part[part_off + 64 chunk ..], and a reduction launch after the product
+// adds the partials in chunk order, then the base, and writes y.
 struct GemvTask {
     int64_t y_off;
     int32_t pair_start;
     int32_t pair_count;
     int64_t base_off;
     int64_t part_off = 0;
-    int32_t grp = -1;
     int16_t chunk = 0;
     int16_t nchunk = 1;
 };
@@ -135,14 +134,17 @@ void launch_tile_transpose(T *arena_src, T *arena_dst, const CopyTask *tasks, in
                            hipStream_t s);
 // One work-group per task with `waves` (4 or 16) wavefronts splitting the
 // pairs; base (needed only if some task has base_off >= 0) may alias y when
-// every task reads its base at its own output rows.
-// Split rows need the partial buffer `part` and the counters `cnt` (zero
-// before the launch; the last work-group of a group resets its counter, so
-// launches on one stream can reuse them).
+// every task reads its base at its own output rows.  Split rows need the
+// partial buffer `part` and, after the launch and on the same stream,
+// launch_gemv_split_reduce over the same tasks to finish them.
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks,
                  const GemvPair *pairs, int64_t ntasks, hipStream_t s, const double *base = nullptr,
-                 int32_t waves = 4, double *part = nullptr, int32_t *cnt = nullptr);
+                 int32_t waves = 4, double *part = nullptr);
+// The split rows of a launch_gemv launch over the same tasks: y = [base +]
+// the sum of the row's partials in chunk order; rows not split are left alone.
+void launch_gemv_split_reduce(const GemvTask *tasks, int64_t ntasks, const double *part, const double *base,
+                              double *y, hipStream_t s);
 // Symmetric-operator GEMV (S stored as T = double, float or bfloat16 bits;
 // FP64 arithmetic): one work-group of `waves` (4 or 16) wavefronts per tile
 // row; y receives the rows' own parts, part the transposed products of the

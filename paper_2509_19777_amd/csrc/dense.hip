@@ -534,7 +534,7 @@ template <class T, int NW>
 __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ arena, const double *__restrict__ x,
                                                        double *y, const GemvTask *__restrict__ tasks,
                                                        const GemvPair *__restrict__ pairs, const double *base,
-                                                       double *part, int32_t *cnt) {
+                                                       double *part) {
     constexpr int R = Vec16<T>::R;          // rows per lane
     constexpr int LPC = TS / R;             // lanes per column
     __shared__ double red[NW * R * TS];
@@ -565,16 +565,11 @@ __global__ void __launch_bounds__(64 * NW) gemv_kernel(const T *__restrict__ are
     double s = 0.0;
     for (int q = 0; q < NW * R; ++q) s += red[q * TS + t];
     if (tk.nchunk > 1) {
+        // a chunk of a split row: its partial sum, added up by the reduction
+        // launch that follows (a kernel boundary instead of agent-scope fences,
+        // whose L2 write-back and invalidation cost more than the launch)
         part[tk.part_off + (int64_t)tk.chunk * TS + t] = s;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        int32_t old = 0;
-        if (t == 0) old = atomicAdd(&cnt[tk.grp], 1);
-        old = __shfl(old, 0, 64);
-        if (old != tk.nchunk - 1) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-        s = 0.0;
-        for (int c = 0; c < tk.nchunk; ++c) s += part[tk.part_off + (int64_t)c * TS + t];
-        if (t == 0) atomicExch(&cnt[tk.grp], 0);
+        return;
     }
     if (tk.base_off >= 0) s += base[tk.base_off + t];
     y[tk.y_off + t] = s;
@@ -720,6 +715,23 @@ __global__ void __launch_bounds__(64 * NW) sym_gemv_kernel(const T *__restrict__
     y[tk.y_off + t] = s + dgs[t];
 }
 
+// The split rows of a GEMV launch: one wavefront per task of the launch; the
+// first chunk's wavefront adds the row's partial sums in chunk order, then the
+// base, and stores the row.
+__global__ void __launch_bounds__(256) gemv_split_reduce_kernel(const GemvTask *__restrict__ tasks, int64_t ntasks,
+                                                                const double *__restrict__ part,
+                                                                const double *base, double *y) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= ntasks) return;
+    const GemvTask tk = tasks[i];
+    if (tk.nchunk <= 1 || tk.chunk != 0) return;
+    const int t = threadIdx.x & 63;
+    double s = 0.0;
+    for (int c = 0; c < tk.nchunk; ++c) s += part[tk.part_off + (int64_t)c * TS + t];
+    if (tk.base_off >= 0) s += base[tk.base_off + t];
+    y[tk.y_off + t] = s;
+}
+
 // One wavefront per row: lane r adds the row's transposed products in order.
 __global__ void __launch_bounds__(256) sym_reduce_kernel(const SymReduce *__restrict__ tasks, int64_t ntasks,
                                                          const double *__restrict__ part, double *__restrict__ y) {
@@ -761,14 +773,20 @@ void launch_tile_transpose(T *src, T *dst, const CopyTask *tasks, int64_t ntasks
 }
 template <class T>
 void launch_gemv(const T *arena, const double *x, double *y, const GemvTask *tasks, const GemvPair *pairs,
-                 int64_t ntasks, hipStream_t s, const double *base, int32_t waves, double *part, int32_t *cnt) {
+                 int64_t ntasks, hipStream_t s, const double *base, int32_t waves, double *part) {
     if (ntasks <= 0) return;
     if (waves == 16)
         hipLaunchKernelGGL((gemv_kernel<T, 16>), dim3(grid_of(ntasks)), dim3(1024), 0, s, arena, x, y, tasks, pairs,
-                           base, part, cnt);
+                           base, part);
     else
         hipLaunchKernelGGL((gemv_kernel<T, 4>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, x, y, tasks, pairs,
-                           base, part, cnt);
+                           base, part);
+}
+void launch_gemv_split_reduce(const GemvTask *tasks, int64_t ntasks, const double *part, const double *base,
+                              double *y, hipStream_t s) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL(gemv_split_reduce_kernel, dim3((unsigned)((ntasks + 3) / 4)), dim3(256), 0, s, tasks, ntasks,
+                       part, base, y);
 }
 
 template <class T>
@@ -805,11 +823,10 @@ template void launch_diag<float>(float *, float *, float *, const DiagTask *, in
 template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);
 template void launch_tile_transpose<float>(float *, float *, const CopyTask *, int64_t, hipStream_t);
 template void launch_gemv<double>(const double *, const double *, double *, const GemvTask *, const GemvPair *,
-                                  int64_t, hipStream_t, const double *, int32_t, double *, int32_t *);
+                                  int64_t, hipStream_t, const double *, int32_t, double *);
 template void launch_gemv<float>(const float *, const double *, double *, const GemvTask *, const GemvPair *,
-                                 int64_t, hipStream_t, const double *, int32_t, double *, int32_t *);
+                                 int64_t, hipStream_t, const double *, int32_t, double *);
 template void launch_gemv<uint16_t>(const uint16_t *, const double *, double *, const GemvTask *,
-                                    const GemvPair *, int64_t, hipStream_t, const double *, int32_t, double *,
-                                    int32_t *);
+                                    const GemvPair *, int64_t, hipStream_t, const double *, int32_t, double *);
 
 }  // namespace hplmm

@@ -68,6 +68,7 @@ struct Range {
     double bytes = 0.0;   // algorithmic bytes read and written by the launch
     int32_t waves = 4;    // GEMV launches: wavefronts per work-group (4 or 16)
     bool sym = false;     // GEMV launches: symmetric-operator tasks (SymPair lists)
+    bool split = false;   // GEMV launches: some rows split (a reduction launch follows)
 };
 
 // Launch shapes of one GEMV launch that the autotuner chooses from: the same
@@ -253,13 +254,10 @@ struct Handle {
     sg::SampleArgs sg_args{};
     GemvTask *d_vtasks = nullptr;
     int64_t gemv_part_len = 0;          // split-row partial sums (doubles)
-    int32_t gemv_cnt_len = 0;           // split-row arrival counters
     double *d_gemv_part = nullptr;
-    int32_t *d_gemv_cnt = nullptr;
-    // when set, the coarse sweeps' split rows use these instead of
-    // d_gemv_part / d_gemv_cnt (the allocation-free application)
+    // when set, the coarse sweeps' split rows use this instead of
+    // d_gemv_part (the allocation-free application)
     double *split_part = nullptr;
-    int32_t *split_cnt = nullptr;
     GemvPair *d_vpairs = nullptr;
     std::vector<GemvTask> vtasks;
     std::vector<GemvPair> vpairs;

@@ -1,9 +1,9 @@
 // Allocation-free application of the preconditioner.
 //
 // hplmm_apply_noalloc runs the same kernels as hplmm_apply, but the one
-// scratch buffer of the application -- the partial sums and arrival counters
-// of the coarse sweeps' split rows -- lives in a fixed-size static device
-// array instead of memory that hplmm_plan allocated.  Nothing in the call
+// scratch buffer of the application -- the partial sums of the coarse
+// sweeps' split rows -- lives in a fixed-size static device array instead of
+// memory that hplmm_plan allocated.  Nothing in the call
 // allocates (no hipMalloc, no events, no library routine that allocates), so
 // it can run under HIP graph capture or in loops that must not allocate.
 //
@@ -29,11 +29,6 @@ static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 std::mutex g_scratch_mu;
 void *g_scratch_ptr[kMaxDevices] = {};
-
-__global__ void zero_i32_kernel(int32_t *p, int64_t n) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = 0;
-}
 
 }  // namespace
 
@@ -65,21 +60,15 @@ extern "C" hplmm_status hplmm_apply_noalloc(hplmm_handle *hh, int32_t which, con
         int cur = -1;
         if (hipGetDevice(&cur) != hipSuccess) fail(HPLMM_E_HIP, "hipGetDevice failed");
         if (cur != h.device) fail(HPLMM_E_ARG, "the handle's device is not the current device");
-        // layout: [split-row partial sums (double)][256-byte aligned arrival counters (int32)]
-        const size_t part_bytes = ((sizeof(double) * (size_t)h.gemv_part_len + 255) / 256) * 256;
-        const size_t need = part_bytes + sizeof(int32_t) * (size_t)h.gemv_cnt_len;
+        // the split-row partial sums (doubles); every one is written by its
+        // chunk before the reduction launch reads it, so nothing needs clearing
+        const size_t need = sizeof(double) * (size_t)h.gemv_part_len;
         if (need > kScratchBytes)
             fail(HPLMM_E_ARG, "the coarse sweeps need " + std::to_string(need) +
                                   " bytes of split-row scratch; the static buffer holds " +
                                   std::to_string(kScratchBytes));
         char *base = (char *)static_scratch_address(cur);
         hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-        // counters start at zero (a fill kernel, not a memset node, so that a
-        // captured graph clears them on every replay)
-        if (h.gemv_cnt_len > 0) {
-            const int64_t n = h.gemv_cnt_len;
-            zero_i32_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>((int32_t *)(base + part_bytes), n);
-        }
         // route the split rows to the static buffer and keep the profiler
         // (which creates events) off for the duration of the call
         struct Restore {
@@ -87,12 +76,10 @@ extern "C" hplmm_status hplmm_apply_noalloc(hplmm_handle *hh, int32_t which, con
             int32_t mask;
             ~Restore() {
                 h.split_part = nullptr;
-                h.split_cnt = nullptr;
                 h.prof.mask = mask;
             }
         } restore{h, h.prof.mask};
         h.split_part = (double *)base;
-        h.split_cnt = (int32_t *)(base + part_bytes);
         h.prof.mask = 0;
         apply_op(h, which, r, z, s);
         const hipError_t e = hipGetLastError();

@@ -343,14 +343,14 @@ double sym_gemv_bytes(const std::vector<GemvTask> &vt, const std::vector<SymPair
 // least 4 pairs) are cut into chunks whose partial sums the last work-group of
 // the row reduces in chunk order.  target 0 returns r unchanged.  part_len and
 // cnt_len grow to what the launch needs.
-Range split_rows(std::vector<GemvTask> &vt, Range r, int64_t target, int64_t &part_len, int32_t &cnt_len) {
+Range split_rows(std::vector<GemvTask> &vt, Range r, int64_t target, int64_t &part_len) {
     if (target <= 0) return r;
     int64_t total = 0;
     for (int64_t i = r.start; i < r.start + r.count; ++i) total += vt[(size_t)i].pair_count;
     const int64_t chunk = std::max<int64_t>(4, (total + target - 1) / target);
     const int64_t start = (int64_t)vt.size();
     int64_t part = 0;
-    int32_t grp = 0;
+    bool any = false;
     for (int64_t i = r.start; i < r.start + r.count; ++i) {
         const GemvTask t = vt[(size_t)i];
         const int64_t nc = (t.pair_count + chunk - 1) / chunk;
@@ -365,35 +365,32 @@ Range split_rows(std::vector<GemvTask> &vt, Range r, int64_t target, int64_t &pa
             u.pair_start = (int32_t)(t.pair_start + c * per);
             u.pair_count = (int32_t)std::min<int64_t>(per, t.pair_count - c * per);
             u.part_off = part;
-            u.grp = grp;
             u.chunk = (int16_t)c;
             u.nchunk = (int16_t)nc;
             vt.push_back(u);
         }
         part += nc * TS;
-        ++grp;
+        any = true;
     }
     Range out = r;
     out.start = start;
     out.count = (int64_t)vt.size() - start;
+    out.split = any;
     part_len = std::max(part_len, part);
-    cnt_len = std::max(cnt_len, grp);
     return out;
 }
 
 // The shapes of one coarse-sweep launch: by default a launch with fewer than
-// 128 rows is split over about 256 work-groups and a larger one is left alone
-// (the release/acquire fences of split work-groups cost more than they save
-// there); the autotuner may also pick the unsplit rows or 256 to 2048
-// work-groups.
-GemvShapes sweep_shapes(std::vector<GemvTask> &vt, Range base, int64_t &part_len, int32_t &cnt_len) {
+// 128 rows is split over about 256 work-groups and a larger one is left alone;
+// the autotuner may also pick the unsplit rows or 256 to 2048 work-groups.
+GemvShapes sweep_shapes(std::vector<GemvTask> &vt, Range base, int64_t &part_len) {
     GemvShapes g;
     const int32_t def = base.count < 128 ? 256 : 0;
     const double bytes = gemv_bytes(vt, base, 8.0);   // the same rows whatever the shape
     for (int32_t t : {def, 0, 256, 512, 1024, 2048}) {
         if (!g.target.empty() && t == def) continue;
         g.target.push_back(t);
-        g.var.push_back(split_rows(vt, base, t, part_len, cnt_len));
+        g.var.push_back(split_rows(vt, base, t, part_len));
         g.var.back().bytes = bytes;
     }
     return g;
@@ -834,8 +831,8 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
             }
         }
         mf.bwd[(size_t)l].count = (int64_t)vt.size() - mf.bwd[(size_t)l].start;
-        mf.fwd_shapes[(size_t)l] = sweep_shapes(vt, mf.fwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
-        mf.bwd_shapes[(size_t)l] = sweep_shapes(vt, mf.bwd[(size_t)l], h.gemv_part_len, h.gemv_cnt_len);
+        mf.fwd_shapes[(size_t)l] = sweep_shapes(vt, mf.fwd[(size_t)l], h.gemv_part_len);
+        mf.bwd_shapes[(size_t)l] = sweep_shapes(vt, mf.bwd[(size_t)l], h.gemv_part_len);
         mf.fwd[(size_t)l] = mf.fwd_shapes[(size_t)l].var[0];
         mf.bwd[(size_t)l] = mf.bwd_shapes[(size_t)l].var[0];
     }
@@ -1638,22 +1635,38 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         const int64_t low_n = h.smoother_precision == 32 ? h.ar32_n : (h.smoother_precision == 16 ? h.arbf_n : h.ar64_n);
         const int64_t c_n = h.smoother_precision == 64 ? h.ar64_n : (h.smoother_precision == 32 ? h.ar32_n : h.arbf_n);
         auto chk_gemv = [&](Range r, int64_t an, int64_t xl, int64_t yl, const char *what) {
+            bool any_split = false;
             for (int64_t i = r.start; i < r.start + r.count; ++i) {
                 const GemvTask &t = h.vtasks[(size_t)i];
                 chk(in(t.y_off, TS, yl), what);
                 chk(t.base_off < 0 || in(t.base_off, TS, yl), what);
-                if (t.nchunk > 1)
-                    chk(t.grp >= 0 && t.grp < h.gemv_cnt_len && t.chunk >= 0 && t.chunk < t.nchunk &&
-                            t.part_off >= 0 && t.part_off + (int64_t)t.nchunk * TS <= h.gemv_part_len,
+                if (t.nchunk > 1) {
+                    any_split = true;
+                    chk(t.chunk >= 0 && t.chunk < t.nchunk && t.part_off >= 0 &&
+                            t.part_off + (int64_t)t.nchunk * TS <= h.gemv_part_len,
                         what);
-                else
+                    // the reduction launch reads a row's partials from its first
+                    // chunk: the row's chunks follow it, in order, in this launch
+                    if (t.chunk == 0) {
+                        chk(i + t.nchunk <= r.start + r.count, what);
+                        for (int64_t c = 1; c < t.nchunk && i + c < r.start + r.count; ++c) {
+                            const GemvTask &u = h.vtasks[(size_t)(i + c)];
+                            chk(u.chunk == c && u.nchunk == t.nchunk && u.y_off == t.y_off &&
+                                    u.base_off == t.base_off && u.part_off == t.part_off,
+                                what);
+                        }
+                    }
+                } else {
                     chk(t.nchunk == 1 && t.chunk == 0, what);
+                }
                 chk(t.pair_start >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)h.vpairs.size(), what);
                 for (int32_t q = 0; q < t.pair_count; ++q) {
                     const GemvPair &pr = h.vpairs[(size_t)(t.pair_start + q)];
                     chk(in(pr.t_off, TE, an) && in(pr.x_off, TS, xl), what);
                 }
             }
+            // the reduction launch follows exactly the launches with split rows
+            chk(any_split == r.split, what);
         };
         chk_gemv(h.gset.gemv_W, low_n, h.gset.vec_len, h.gset.vec_len, "grain W gemv");
         chk_gemv(h.gset.gemv_Wt, low_n, h.gset.vec_len, h.gset.vec_len, "grain Wt gemv");
@@ -1755,6 +1768,11 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
             for (int32_t l = 0; l < mf.n_levels; ++l) {
                 chk_gemv(mf.fwd[(size_t)l], h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front forward sweep");
                 chk_gemv(mf.bwd[(size_t)l], h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front backward sweep");
+                // every launch shape the autotuner may pick
+                for (const Range &v : mf.fwd_shapes[(size_t)l].var)
+                    chk_gemv(v, h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front forward sweep shape");
+                for (const Range &v : mf.bwd_shapes[(size_t)l].var)
+                    chk_gemv(v, h.ar64_n, 3 * mf.vec_len, 3 * mf.vec_len, "front backward sweep shape");
             }
             for (const auto &pr : pairs) {
                 chk(in(pr.f_off, 1, h.ar64_n), "coarse pair front");
@@ -1891,9 +1909,6 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     h.d_rtasks = h.upload(h.rtasks, s);
     h.d_sym_part = h.dalloc<double>(std::max<int64_t>(1, h.sym_part_len));
     h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
-    h.d_gemv_cnt = h.dalloc<int32_t>(std::max<int32_t>(1, h.gemv_cnt_len));
-    if (hipMemsetAsync(h.d_gemv_cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.gemv_cnt_len), s) != hipSuccess)
-        fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     // arenas and vectors
     h.ar64 = h.dalloc<double>(h.ar64_n);
     if (h.ar32_n) h.ar32 = h.dalloc<float>(h.ar32_n);

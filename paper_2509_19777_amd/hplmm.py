@@ -396,9 +396,9 @@ class Solver:
         return z
 
     def split_scratch(self):
-        """(partial sums in doubles, arrival counters) the coarse sweeps' split rows need."""
+        """Partial sums (doubles) the coarse sweeps' split rows need."""
         v = self.query(12, np.int64)
-        return int(v[0]), int(v[1])
+        return int(v[0])
 
     def spmv(self, x, out=None):
         y = torch.empty_like(x) if out is None else out
