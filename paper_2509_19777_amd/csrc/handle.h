@@ -110,6 +110,10 @@ struct DenseSet {
     // products read W transposed instead): tile k of matrix m at wdrel[m] + k TE
     bool wt_diag = false;
     std::vector<int64_t> wdrel;
+    // tile envelope: first[m][I] is the first tile column of row I of matrix
+    // m that holds a nonzero; the Cholesky factor has none left of it.  Empty:
+    // every matrix dense
+    std::vector<std::vector<int32_t>> first;
 };
 
 // Multifrontal Cholesky of the coarse operator on a nested-dissection tree of

@@ -136,6 +136,30 @@ std::vector<double> algebraic_block(const hplmm_system &sys, const int32_t *node
     return M;
 }
 
+// Tile envelope of a diagonal block of the fine matrix whose nodes are
+// `nodes` (local node l = nodes[l], dofs 3l .. 3l+2): first[I] is the first
+// tile column with a nonzero in tile row I (the padding rows past the block
+// hold only their diagonal).  `loc` is a scratch map of every node to -1.
+std::vector<int32_t> tile_envelope(const hplmm_system &sys, const int32_t *nodes, int64_t cnt,
+                                   std::vector<int32_t> &loc) {
+    for (int64_t l = 0; l < cnt; ++l) loc[(size_t)nodes[l]] = (int32_t)l;
+    const int64_t nt = ceil_tiles(3 * cnt);
+    std::vector<int32_t> first((size_t)nt);
+    for (int64_t I = 0; I < nt; ++I) first[(size_t)I] = (int32_t)I;
+    for (int64_t l = 0; l < cnt; ++l) {
+        const int32_t v = nodes[l];
+        int64_t lo = l;
+        for (int64_t p = sys.row_ptr[v]; p < sys.row_ptr[v + 1]; ++p) {
+            const int32_t u = loc[(size_t)sys.col_idx[p]];
+            if (u >= 0) lo = std::min<int64_t>(lo, u);
+        }
+        const int32_t c = (int32_t)(3 * lo / TS);
+        for (int64_t r = 3 * l; r < 3 * l + 3; ++r) first[(size_t)(r / TS)] = std::min(first[(size_t)(r / TS)], c);
+    }
+    for (int64_t l = 0; l < cnt; ++l) loc[(size_t)nodes[l]] = -1;
+    return first;
+}
+
 void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vector<Launch> *out = nullptr,
                           const std::vector<int64_t> *ids = nullptr) {
     std::vector<Launch> &prog = out ? *out : ds.factor_prog;
@@ -156,15 +180,24 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         return ds.wt_base + wrel(m) + tri_index(I, J) * TE;
     };
     auto id = [&](int64_t m) { return (int32_t)(set_id * (1 << 26) + (ids ? (*ids)[m] : m)); };
+    // first tile column of L's row I that can be nonzero (the envelope)
+    auto first = [&](int64_t m, int64_t I) -> int64_t { return ds.first.empty() ? 0 : ds.first[m][I]; };
+    auto push_pairs = [&](int64_t lo, int64_t hi, auto pair) {
+        for (int64_t q = lo; q < hi; ++q) tl.pairs.push_back(pair(q));
+        return (int32_t)std::max<int64_t>(0, hi - lo);
+    };
     // Left-looking tile Cholesky, two launches per step k: the diagonal tile
     // A_kk - sum_{p<k} L_kp L_kp^T is factored (the diagonal kernel subtracts
     // the last term, p = k - 1, itself), then the panel
     // L_ik = (A_ik - sum_p L_ip L_kp^T) L_kk^-T is formed in one task per tile.
+    // Tiles left of a row's envelope are zero in A and stay zero in L: no
+    // task writes them and no pair reads them.
     for (int64_t k = 0; k < maxk; ++k) {
         Launch d{LK_DIAG, (int64_t)tl.diag.size(), 0};
         for (int64_t m = 0; m < nm; ++m)
             if (own(m) > k)
-                tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0, k > 0 ? A(m, k, k - 1) : -1});
+                tl.diag.push_back({A(m, k, k), W(m, k, k), Wt(m, k, k), id(m), 0,
+                                   k > 0 && first(m, k) < k ? A(m, k, k - 1) : -1});
         d.count = (int64_t)tl.diag.size() - d.start;
         prog.push_back(d);
         // the panel, and in the same launch row k of W = L^-1:
@@ -175,19 +208,27 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         for (int64_t m = 0; m < nm; ++m) {
             if (own(m) <= k) continue;
             for (int64_t i = k + 1; i < ds.nt[m]; ++i) {
-                tl.gemm.push_back({A(m, i, k), Wt(m, k, k), (int32_t)tl.pairs.size(), (int32_t)k,
-                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST_RIGHT, 0});
-                for (int64_t q = 0; q < k; ++q) tl.pairs.push_back({A(m, i, q), A(m, k, q)});
+                if (first(m, i) > k) continue;
+                const int32_t ps = (int32_t)tl.pairs.size();
+                const int32_t pc = push_pairs(std::max(first(m, i), first(m, k)), k, [&](int64_t q) {
+                    return GemmPair{A(m, i, q), A(m, k, q)};
+                });
+                tl.gemm.push_back({A(m, i, k), Wt(m, k, k), ps, pc, GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST_RIGHT, 0});
             }
             for (int64_t j = 0; j < k; ++j) {
-                tl.gemm.push_back({W(m, k, j), W(m, k, k), (int32_t)tl.pairs.size(), (int32_t)(k - j),
-                                   GF_POST | GF_NEGATE, 0});
-                for (int64_t q = j; q < k; ++q) tl.pairs.push_back({A(m, k, q), W(m, q, j)});
+                // an empty sum (row k uncoupled to earlier rows) writes a zero tile
+                const int32_t ps = (int32_t)tl.pairs.size();
+                const int32_t pc = push_pairs(std::max(j, first(m, k)), k, [&](int64_t q) {
+                    return GemmPair{A(m, k, q), W(m, q, j)};
+                });
+                tl.gemm.push_back({W(m, k, j), W(m, k, k), ps, pc, GF_POST | GF_NEGATE, 0});
             }
-            if (k > 0 && k + 1 < own(m)) {
-                tl.gemm.push_back({A(m, k + 1, k + 1), -1, (int32_t)tl.pairs.size(), (int32_t)k,
-                                   GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
-                for (int64_t q = 0; q < k; ++q) tl.pairs.push_back({A(m, k + 1, q), A(m, k + 1, q)});
+            if (k + 1 < own(m) && first(m, k + 1) < k) {
+                const int32_t ps = (int32_t)tl.pairs.size();
+                const int32_t pc = push_pairs(first(m, k + 1), k, [&](int64_t q) {
+                    return GemmPair{A(m, k + 1, q), A(m, k + 1, q)};
+                });
+                tl.gemm.push_back({A(m, k + 1, k + 1), -1, ps, pc, GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
             }
         }
         p.count = (int64_t)tl.gemm.size() - p.start;
@@ -1228,6 +1269,19 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
             cn_cnt[(size_t)v + 1]++;
         }
         h.cset.n.push_back(3 * (part.contact_ptr[c + 1] - part.contact_ptr[c]));
+    }
+    // ---- tile envelopes of the grain and contact-grid blocks ---------------------
+    {
+        std::vector<int32_t> loc((size_t)n, -1);
+        h.gset.first.resize((size_t)nG);
+        for (int64_t m = 0; m < nG; ++m) {
+            const auto &nodes = gnodes[(size_t)h.gm_grain[(size_t)m]];
+            h.gset.first[(size_t)m] = tile_envelope(sys, nodes.data(), (int64_t)nodes.size(), loc);
+        }
+        h.cset.first.resize((size_t)part.n_contacts);
+        for (int32_t c = 0; c < part.n_contacts; ++c)
+            h.cset.first[(size_t)c] = tile_envelope(sys, part.contact_nodes + part.contact_ptr[c],
+                                                    part.contact_ptr[c + 1] - part.contact_ptr[c], loc);
     }
     // ---- layout ------------------------------------------------------------------
     layout_set(h.gset);
