@@ -180,15 +180,23 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
     }
     run_program<double>(h, h.tl64, h.ar64, h.gset.factor_prog, h.d_flag, s);
     hip_check(hipEventRecord(ev[5], s), "event");
-    if (fork) {
-        // the contact grids start once the grain factorisation is done: its
-        // chain of small dependent launches runs best alone, while the grain
-        // basis and the coarse factorisation leave room beside them
+    // W = L^-1 of the grains, when not formed in the factorisation's steps,
+    // is needed only by the grain inverse (side stream, below), except by the
+    // learned basis's exact fallback and in a staged set-up
+    const bool w_side = fork && !sg && h.smoother_form == HPLMM_SMOOTHER_INVERSE;
+    if (!w_side) run_program<double>(h, h.tl64, h.ar64, h.gset.w_prog, h.d_flag, s);
+    // the contact grids start once the grain factorisation is done: its
+    // chain of small dependent launches runs best alone, while the grain
+    // basis and the coarse factorisation leave room beside them.  With the
+    // exact basis they are queued after it, so that queueing their many
+    // launches never leaves the main stream idle.
+    auto fork_contacts = [&] {
         hip_check(hipStreamWaitEvent(h.side, ev[5], 0), "fork");
         hip_check(hipEventRecord(h.side_ev[0], h.side), "event");
         contact_setup(h, h.side);
         hip_check(hipEventRecord(h.side_ev[1], h.side), "event");
-    }
+    };
+    if (fork && sg) fork_contacts();
     if (stage < 2) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
@@ -197,13 +205,22 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         surrogate_basis(h, *sg, s);
     else
         run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
+    if (fork && !sg) fork_contacts();
     if (fork) {
-        // the grain inverse S = W^T W follows the contact grids on the side
-        // stream, beside the coarse operator on s
+        // the grain inverse S = W^T W (after the rows of W, when those are
+        // not formed in the factorisation's steps) follows the contact grids
+        // on the side stream, beside the coarse operator on s
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
-            hip_check(hipEventRecord(ev[4], s), "event");
-            hip_check(hipStreamWaitEvent(h.side, ev[4], 0), "wait");
+            if (!w_side) {
+                // W came from the main stream
+                hip_check(hipEventRecord(ev[4], s), "event");
+                hip_check(hipStreamWaitEvent(h.side, ev[4], 0), "wait");
+            }
             hip_check(hipEventRecord(h.side_ev[3], h.side), "event");
+            if (w_side) {
+                if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
+                run_program<double>(h, h.tl64, h.ar64, h.gset.w_prog, h.d_flag, h.side, h.d_part_side, h.d_cnt_side);
+            }
             form_inverse(h, h.gset, h.side);
         }
         hip_check(hipEventRecord(h.side_ev[2], h.side), "event");

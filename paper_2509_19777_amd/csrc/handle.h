@@ -97,6 +97,7 @@ struct DenseSet {
     int64_t a_base = 0, w_base = 0, wt_base = 0;   // absolute arena offsets
     int64_t s_base = -1;
     std::vector<Launch> factor_prog;   // potrf + trtri + transposes
+    std::vector<Launch> w_prog;        // the rows of W = L^-1 when not fused into factor_prog
     std::vector<Launch> inverse_prog;  // S = W^T W (lower tiles)
     Range gemv_W, gemv_Wt;             // apply-time task ranges (factor form)
     Range gemv_S, red_S;               // apply-time task ranges (inverse form)
@@ -186,7 +187,12 @@ struct Handle {
     int64_t *d_g_slot_dof = nullptr;   // grain vector slot -> dof
     int64_t *d_g_dof_slot = nullptr;   // dof -> grain vector slot
     int64_t *d_gcol_upos = nullptr;    // grain column slot -> coarse vector position
-    std::vector<Launch> basis_prog;    // Y = W R, X = Wt Y, K = Y^T Y, XT
+    // Y = W R, X = W^T Y, K = Y^T Y, XT; or, by substitution (basis_subst),
+    // the backward rows of X, K and XT, the forward rows of Y having run in
+    // the grain factorisation's steps
+    std::vector<Launch> basis_prog;
+    bool basis_subst = false;
+    int64_t negi_off = -1;             // a -I tile in the FP64 arena (substitution terms)
     Range gemv_XT, gemv_X;
     std::vector<int64_t> pad_ones_g;   // identity on padded diagonals
     int64_t *d_pad_g = nullptr;

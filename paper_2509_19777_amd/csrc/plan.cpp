@@ -2,6 +2,7 @@
 // W and reduction Q (Eqs. 20-21), the column layout of P (Eq. 23), contact
 // grids (Eq. 26), device data layout and all launch task lists.
 #include <algorithm>
+#include <functional>
 #include <array>
 #include <map>
 #include <cmath>
@@ -160,9 +161,16 @@ std::vector<int32_t> tile_envelope(const hplmm_system &sys, const int32_t *nodes
     return first;
 }
 
+// The factor program of a dense set.  With fuse_w the rows of W = L^-1 are
+// formed in the Cholesky steps' launches; otherwise they go to ds.w_prog, one
+// launch per row, to run after the factorisation (and beside other work).
+// step_extra(k) may append tasks to step k's panel launch (they run after
+// the diagonal tile k is factored).
 void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vector<Launch> *out = nullptr,
-                          const std::vector<int64_t> *ids = nullptr) {
+                          const std::vector<int64_t> *ids = nullptr, bool fuse_w = true,
+                          const std::function<void(int64_t)> &step_extra = {}) {
     std::vector<Launch> &prog = out ? *out : ds.factor_prog;
+    if (!fuse_w) ds.w_prog.clear();
     const int64_t nm = (int64_t)ds.n.size();
     auto own = [&](int64_t m) { return ds.nt_own.empty() ? ds.nt[m] : ds.nt_own[m]; };
     int64_t maxk = 0;
@@ -186,6 +194,18 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         for (int64_t q = lo; q < hi; ++q) tl.pairs.push_back(pair(q));
         return (int32_t)std::max<int64_t>(0, hi - lo);
     };
+    // row k of W = L^-1: W_kj = -W_kk sum_{q=j}^{k-1} L_kq W_qj, j < k, reading
+    // rows of L and W finished before; an empty sum (row k uncoupled to earlier
+    // rows) writes a zero tile
+    auto w_row = [&](int64_t m, int64_t k) {
+        for (int64_t j = 0; j < k; ++j) {
+            const int32_t ps = (int32_t)tl.pairs.size();
+            const int32_t pc = push_pairs(std::max(j, first(m, k)), k, [&](int64_t q) {
+                return GemmPair{A(m, k, q), W(m, q, j)};
+            });
+            tl.gemm.push_back({W(m, k, j), W(m, k, k), ps, pc, GF_POST | GF_NEGATE, 0});
+        }
+    };
     // Left-looking tile Cholesky, two launches per step k: the diagonal tile
     // A_kk - sum_{p<k} L_kp L_kp^T is factored (the diagonal kernel subtracts
     // the last term, p = k - 1, itself), then the panel
@@ -200,10 +220,8 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
                                    k > 0 && first(m, k) < k ? A(m, k, k - 1) : -1});
         d.count = (int64_t)tl.diag.size() - d.start;
         prog.push_back(d);
-        // the panel, and in the same launch row k of W = L^-1:
-        // W_kj = -W_kk sum_{q=j}^{k-1} L_kq W_qj, j < k, which reads rows of L
-        // and W finished in earlier steps and the W_kk just formed, and the
-        // terms p < k of the next diagonal tile's update
+        // the panel, in the same launch row k of W (fused) with the W_kk
+        // just formed, and the terms p < k of the next diagonal tile's update
         Launch p{LK_GEMM, (int64_t)tl.gemm.size(), 0};
         for (int64_t m = 0; m < nm; ++m) {
             if (own(m) <= k) continue;
@@ -215,14 +233,7 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
                 });
                 tl.gemm.push_back({A(m, i, k), Wt(m, k, k), ps, pc, GF_TRANS_B | GF_ACCUM | GF_NEGATE | GF_POST_RIGHT, 0});
             }
-            for (int64_t j = 0; j < k; ++j) {
-                // an empty sum (row k uncoupled to earlier rows) writes a zero tile
-                const int32_t ps = (int32_t)tl.pairs.size();
-                const int32_t pc = push_pairs(std::max(j, first(m, k)), k, [&](int64_t q) {
-                    return GemmPair{A(m, k, q), W(m, q, j)};
-                });
-                tl.gemm.push_back({W(m, k, j), W(m, k, k), ps, pc, GF_POST | GF_NEGATE, 0});
-            }
+            if (fuse_w) w_row(m, k);
             if (k + 1 < own(m) && first(m, k + 1) < k) {
                 const int32_t ps = (int32_t)tl.pairs.size();
                 const int32_t pc = push_pairs(first(m, k + 1), k, [&](int64_t q) {
@@ -231,9 +242,18 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
                 tl.gemm.push_back({A(m, k + 1, k + 1), -1, ps, pc, GF_TRANS_B | GF_ACCUM | GF_NEGATE, 0});
             }
         }
+        if (step_extra) step_extra(k);
         p.count = (int64_t)tl.gemm.size() - p.start;
         if (p.count) prog.push_back(p);
     }
+    if (!fuse_w)
+        for (int64_t k = 1; k < maxk; ++k) {
+            Launch w{LK_GEMM, (int64_t)tl.gemm.size(), 0};
+            for (int64_t m = 0; m < nm; ++m)
+                if (own(m) > k) w_row(m, k);
+            w.count = (int64_t)tl.gemm.size() - w.start;
+            if (w.count) ds.w_prog.push_back(w);
+        }
     // Partially factored matrices: Schur complement of the owned columns on
     // the remaining block, S_ij = A_ij - sum_{p < own} L_ip L_jp^T.
     {
@@ -257,7 +277,7 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         for (int64_t i = 0; i < own(m); ++i)
             for (int64_t j = 0; j < i; ++j) tl.copy.push_back({W(m, i, j), Wt(m, i, j)});
     c.count = (int64_t)tl.copy.size() - c.start;
-    if (c.count) prog.push_back(c);
+    if (c.count) (fuse_w ? prog : ds.w_prog).push_back(c);
 }
 
 // Apply-time GEMV task lists y = W x and y = W^T x of a dense set.
@@ -960,7 +980,8 @@ static void method_work(Handle &h) {
         for (const Launch &L : prog) f += L.flops;
         return f;
     };
-    h.issued_setup_flops[0] = sum(h.gset.factor_prog) + sum(h.gset.inverse_prog) + sum(h.basis_prog);
+    h.issued_setup_flops[0] =
+        sum(h.gset.factor_prog) + sum(h.gset.w_prog) + sum(h.gset.inverse_prog) + sum(h.basis_prog);
     h.issued_setup_flops[1] = sum(h.cset.factor_prog) + sum(h.cset.inverse_prog);
     h.issued_setup_flops[2] = h.mf.flops;
     h.issued_setup_flops[3] = h.issued_setup_flops[0] + h.issued_setup_flops[1] + h.issued_setup_flops[2];
@@ -1303,6 +1324,10 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         }
         return o;
     };
+    // the basis by substitution with the sparse factor (inverse form), which
+    // leaves W = L^-1 to the grain inverse alone
+    h.basis_subst = inverse;
+    h.negi_off = h.basis_subst ? take64(TE) : -1;
     h.gset.a_base = take64(h.gset.region);
     h.gset.w_base = take64(h.gset.region);
     h.gset.wt_base = take64(wt_elems(h.gset));
@@ -1390,7 +1415,30 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     h.arbf_n = offbf;
     h.grain_region_zero_n = h.gset.region;
     // ---- task lists ---------------------------------------------------------------
-    build_factor_program(h.gset, h.tl64, 0);
+    auto Lg = [&](int64_t m, int64_t I, int64_t J) { return h.gset.a_base + h.gset.rel[m] + tri_index(I, J) * TE; };
+    auto Rg = [&](int64_t base, int64_t m, int64_t I, int64_t C) { return base + (C * h.gset.nt[m] + I) * TE; };
+    auto fg = [&](int64_t m, int64_t I) -> int64_t { return h.gset.first.empty() ? 0 : h.gset.first[(size_t)m][(size_t)I]; };
+    // Forward rows of the basis, Y = L^-1 R by substitution (Eq. 23's solves):
+    // Y_k = W_kk (R_k - sum_q L_kq Y_q) over the factor's nonzero tiles of row
+    // k, in step k of the grain factorisation (after W_kk is formed), R_k
+    // entering as the product -I R_k
+    std::function<void(int64_t)> y_rows;
+    if (h.basis_subst)
+        y_rows = [&](int64_t k) {
+            for (int64_t m = 0; m < nG; ++m) {
+                if (h.gset.nt[m] <= k) continue;
+                for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C) {
+                    const int32_t ps = (int32_t)h.tl64.pairs.size();
+                    for (int64_t q = fg(m, k); q < k; ++q)
+                        h.tl64.pairs.push_back({Lg(m, k, q), Rg(h.gm_ytoff[(size_t)m], m, q, C)});
+                    h.tl64.pairs.push_back({h.negi_off, Rg(h.gm_roff[(size_t)m], m, k, C)});
+                    h.tl64.gemm.push_back({Rg(h.gm_ytoff[(size_t)m], m, k, C),
+                                           h.gset.w_base + h.gset.rel[m] + tri_index(k, k) * TE, ps,
+                                           (int32_t)(h.tl64.pairs.size() - ps), GF_POST | GF_NEGATE, 0});
+                }
+            }
+        };
+    build_factor_program(h.gset, h.tl64, 0, nullptr, nullptr, !h.basis_subst, y_rows);
     if (!c32)
         build_factor_program(h.cset, h.tl64, 1);
     else
@@ -1400,11 +1448,39 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         build_inverse_program(h.gset, tl_inv, lowp);
         build_inverse_program(h.cset, tl_inv, lowp);
     }
-    // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T
+    // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T; or by
+    // substitution: backward rows X_k = W_kk^T (Y_k - sum_q L_qk^T X_q) over
+    // the nonzero tiles L_qk, q > k (X over R, Y_k entering as -I Y_k), one
+    // launch per row counted from every matrix's last row, then K and XT
     {
         std::vector<int64_t> all((size_t)nG);
         std::iota(all.begin(), all.end(), 0);
-        append_basis_program(h, h.tl64, all, h.basis_prog, BP_ALL);
+        if (h.basis_subst) {
+            int64_t ntmax = 0;
+            for (int64_t m = 0; m < nG; ++m)
+                if (h.gm_ntc[(size_t)m] > 0) ntmax = std::max(ntmax, h.gset.nt[m]);
+            for (int64_t t = 0; t < ntmax; ++t) {
+                Launch L{LK_GEMM, (int64_t)h.tl64.gemm.size(), 0};
+                for (int64_t m = 0; m < nG; ++m) {
+                    const int64_t nt = h.gset.nt[m], k = nt - 1 - t;
+                    if (k < 0) continue;
+                    for (int64_t C = 0; C < h.gm_ntc[(size_t)m]; ++C) {
+                        const int32_t ps = (int32_t)h.tl64.pairs.size();
+                        for (int64_t q = k + 1; q < nt; ++q)
+                            if (fg(m, q) <= k) h.tl64.pairs.push_back({Lg(m, q, k), Rg(h.gm_roff[(size_t)m], m, q, C)});
+                        h.tl64.pairs.push_back({h.negi_off, Rg(h.gm_ytoff[(size_t)m], m, k, C)});
+                        h.tl64.gemm.push_back({Rg(h.gm_roff[(size_t)m], m, k, C), h.gset.wt_base + h.gset.wdrel[m] + k * TE,
+                                               ps, (int32_t)(h.tl64.pairs.size() - ps),
+                                               GF_POST | GF_NEGATE | GF_TRANS_A, 0});
+                    }
+                }
+                L.count = (int64_t)h.tl64.gemm.size() - L.start;
+                if (L.count) h.basis_prog.push_back(L);
+            }
+            append_basis_program(h, h.tl64, all, h.basis_prog, BP_K | BP_XT);
+        } else {
+            append_basis_program(h, h.tl64, all, h.basis_prog, BP_ALL);
+        }
     }
     // apply-time GEMV lists
     {
@@ -1440,6 +1516,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         h.gemv_X.count = (int64_t)h.vtasks.size() - h.gemv_X.start;
     }
     split_program(h.gset.factor_prog, h.tl64);
+    split_program(h.gset.w_prog, h.tl64);
     split_program(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     split_program(h.basis_prog, h.tl64);
     split_program(h.gset.inverse_prog, tl_inv);
@@ -1447,6 +1524,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     fill_flops(h.gset.inverse_prog, tl_inv);
     fill_flops(h.cset.inverse_prog, tl_inv);
     fill_flops(h.gset.factor_prog, h.tl64);
+    fill_flops(h.gset.w_prog, h.tl64);
     fill_flops(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
     {
@@ -1965,6 +2043,13 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
     // arenas and vectors
     h.ar64 = h.dalloc<double>(h.ar64_n);
+    std::vector<double> negi;
+    if (h.negi_off >= 0) {
+        negi.assign((size_t)TE, 0.0);
+        for (int i = 0; i < TS; ++i) negi[(size_t)(i * TS + i)] = -1.0;
+        if (hipMemcpyAsync(h.ar64 + h.negi_off, negi.data(), sizeof(double) * TE, hipMemcpyHostToDevice, s) != hipSuccess)
+            fail(HPLMM_E_HIP, "hipMemcpyAsync failed");
+    }
     if (h.ar32_n) h.ar32 = h.dalloc<float>(h.ar32_n);
     if (h.arbf_n) h.arbf = h.dalloc<uint16_t>(h.arbf_n);
     h.gx = h.dalloc<double>(h.gset.vec_len);

@@ -184,7 +184,8 @@ def test_smoother_forms(hp):
     packed layout, R tiles over both sets) and one tile product task per
     stored tile of S, at least; its products read W transposed, so of Wt it
     keeps only the diagonal tiles (D = sum of nt over grains and contact
-    grids) instead of a full region.  auto picks it at every precision.  At
+    grids) instead of a full region, plus one -I tile for the basis, formed
+    there by substitution with the factor.  auto picks it at every precision.  At
     reduced precision it factors every block in FP64 (no FP64 S), keeps W
     rounded to the storage precision (FP32 or bfloat16 arena) and S formed
     from it in the FP32 arena."""
@@ -197,7 +198,8 @@ def test_smoother_forms(hp):
     nc = np.diff(part.contact_ptr) * 3
     nt = np.concatenate([(ng[ng > 0] + 63) // 64, (nc + 63) // 64])
     D, R = int(nt.sum()), int((nt * (nt + 1) // 2).sum())
-    assert inv["ar64"] - fac["ar64"] == D * 4096     # + S (R tiles), - Wt beyond its diagonal tiles (R - D)
+    # + S (R tiles), - Wt beyond its diagonal tiles (R - D), + the -I tile
+    assert inv["ar64"] - fac["ar64"] == (D + 1) * 4096
     assert inv["tile_tasks"] - fac["tile_tasks"] >= R
     for prec in (32, 16):
         low_inv = hp.plan_check(sysm, part, n_mortar=4, smoother_precision=prec, smoother_form="inverse")
