@@ -46,9 +46,8 @@ struct ProfScope {
 // part / cnt: split-task scratch (default: the task lists' own)
 template <class T>
 static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vector<Launch> &prog, int32_t *flag,
-                        hipStream_t s, void *part = nullptr, int32_t *cnt = nullptr) {
+                        hipStream_t s, void *part = nullptr) {
     if (!part) part = tl.d_part;
-    if (!cnt) cnt = tl.d_cnt;
     for (const Launch &L : prog) {
         switch (L.kind) {
             case LK_DIAG: {
@@ -58,7 +57,7 @@ static void run_program(Handle &h, const TaskLists &tl, T *arena, const std::vec
             }
             case LK_GEMM: {
                 ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
-                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (T *)part, cnt);
+                launch_tile_gemm<T>(arena, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (T *)part, L.split);
                 break;
             }
             case LK_TRANSPOSE: launch_tile_transpose<T>(arena, arena, tl.d_copy + L.start, L.count, s); break;
@@ -91,7 +90,7 @@ static void run_bf16_program(Handle &h, const TaskLists &tl, const std::vector<L
         if (L.kind != LK_GEMM) fail(HPLMM_E_STATE, "internal: bfloat16 programs hold contractions only");
         ProfScope ps(h, PC_TILE_GEMM, L.flops, s);
         launch_tile_gemm_bf16(h.arbf, h.ar32, tl.d_gemm + L.start, tl.d_pairs, L.count, s, (float *)tl.d_part,
-                              tl.d_cnt);
+                              L.split);
     }
 }
 
@@ -104,8 +103,8 @@ static void run_bf16_program(Handle &h, const TaskLists &tl, const std::vector<L
 // coarse the rounding.
 static void form_inverse(Handle &h, const DenseSet &ds, hipStream_t s) {
     if (h.smoother_precision == 64) {
-        if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
-        run_program<double>(h, h.tl64, h.ar64, ds.inverse_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+        if (!h.d_part_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
+        run_program<double>(h, h.tl64, h.ar64, ds.inverse_prog, h.d_flag, s, h.d_part_side);
     } else if (h.smoother_precision == 32) {
         launch_convert_f64_f32(h.ar64 + ds.w_base, h.ar32 + ds.low_w_base, ds.region, s);
         run_program<float>(h, h.tl32, h.ar32, ds.inverse_prog, h.d_flag, s);
@@ -120,11 +119,11 @@ static void form_inverse(Handle &h, const DenseSet &ds, hipStream_t s) {
 static void contact_setup(Handle &h, hipStream_t s) {
     if (h.smoother_precision == 64 || h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
         // FP64 programs beside those on the main stream: never on its scratch
-        if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
+        if (!h.d_part_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
         zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
-        run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side, h.d_cnt_side);
+        run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side);
         if (h.smoother_form == HPLMM_SMOOTHER_INVERSE) form_inverse(h, h.cset, s);
     } else {
         zero(h.ar64 + h.c_stage_base, sizeof(double) * h.cset.region, s);
@@ -218,8 +217,8 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
             }
             hip_check(hipEventRecord(h.side_ev[3], h.side), "event");
             if (w_side) {
-                if (!h.d_part_side || !h.d_cnt_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
-                run_program<double>(h, h.tl64, h.ar64, h.gset.w_prog, h.d_flag, h.side, h.d_part_side, h.d_cnt_side);
+                if (!h.d_part_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
+                run_program<double>(h, h.tl64, h.ar64, h.gset.w_prog, h.d_flag, h.side, h.d_part_side);
             }
             form_inverse(h, h.gset, h.side);
         }

@@ -31,9 +31,10 @@ enum GemmFlags : int32_t {
 
 // One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p) [* P].
 // A long sum may be split into nchunk tasks over consecutive parts of its
-// pair list (same c_off, post_off and flags): each stores its partial sum in
-// part[part_off + 4096 chunk ..] and bumps counter grp; the work-group that
-// arrives last adds the partials in chunk order and applies the epilogue.
+// pair list (same c_off, post_off and flags, transposition aside): each
+// stores its partial sum in part[part_off + 4096 chunk ..], and a finishing
+// pass after the launch adds the partials in chunk order and applies the
+// epilogue.
 struct GemmTask {
     int64_t c_off;
     int64_t post_off;
@@ -42,7 +43,7 @@ struct GemmTask {
     int32_t flags;
     int32_t pad;
     int64_t part_off = 0;
-    int32_t grp = -1;
+    int32_t pad2 = 0;
     int16_t chunk = 0;
     int16_t nchunk = 1;
 };
@@ -117,15 +118,15 @@ struct SymReduce {
 
 // Launchers (stream-ordered, asynchronous).  `flag` points to a device int32
 // pair {status bits, first bad id}.
-// Split tasks need `part` (T) and the zeroed counters `cnt` (reset by the
-// last work-group of each group).
+// A list with split tasks (split = true) needs `part` (T); the finishing pass
+// runs as a second launch on the same stream.
 template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
-                      hipStream_t s, T *part = nullptr, int32_t *cnt = nullptr);
+                      hipStream_t s, T *part = nullptr, bool split = false);
 // bfloat16 operands (their 16 bits) from `in`, FP32 accumulation and output
 // to `out`; tasks without a second product (GF_POST / GF_POST_RIGHT ignored).
 void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,
-                           int64_t ntasks, hipStream_t s, float *part = nullptr, int32_t *cnt = nullptr);
+                           int64_t ntasks, hipStream_t s, float *part = nullptr, bool split = false);
 template <class T>
 void launch_diag(T *arena_a, T *arena_w, T *arena_wt, const DiagTask *tasks, int64_t ntasks,
                  int32_t *flag, hipStream_t s);

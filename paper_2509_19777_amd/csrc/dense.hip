@@ -220,17 +220,18 @@ template <class Ti, class T>
 __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ in, T *__restrict__ out,
                                                         const GemmTask *__restrict__ tasks,
                                                         const GemmPair *__restrict__ pairs, T *part,
-                                                        int32_t *cnt) {
+                                                        int finish) {
     // the two operand halves; together they hold one padded 64x64 tile for
     // the output staging
     __shared__ T S[2 * KH * LD];
     Ti *As = reinterpret_cast<Ti *>(S), *Bs = As + KH * LD;
-    __shared__ int32_t last;
     // work-groups are dealt to the 8 XCDs in turn; give each XCD a contiguous
     // slice of the list, so neighbouring tasks (which share operand tiles)
     // meet in the same L2
     const uint32_t nb = gridDim.x, b = blockIdx.x, xcd = b & 7, q = nb >> 3, r = nb & 7;
     const GemmTask tk = tasks[xcd * q + (xcd < r ? xcd : r) + (b >> 3)];
+    // the finishing pass: chunk 0 of each split task sums and finishes it
+    if (finish && (tk.nchunk <= 1 || tk.chunk != 0)) return;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
     typename Mfma<Ti>::acc_t acc[2][2];
@@ -238,7 +239,8 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ i
         for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<Ti>::acc_t{0, 0, 0, 0};
     // the contraction loop specialised on the fetch orders (uniform branch)
     const bool ta = tk.flags & GF_TRANS_A, tb = tk.flags & GF_TRANS_B;
-    if (ta) {
+    if (finish) {
+    } else if (ta) {
         if (tb)
             gemm_pairs<Ti, true, false>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
         else
@@ -250,17 +252,14 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ i
             gemm_pairs<Ti, false, true>(in, pairs, tk, As, Bs, acc, lane, wm, wn);
     }
     if (tk.nchunk > 1) {
-        // partial sums in accumulator order, reduced by the last arrival
-        T *pp = part + tk.part_off + (int64_t)tk.chunk * TE;
-        for (int i = 0; i < 2; ++i)
-            for (int j = 0; j < 2; ++j)
-                for (int r = 0; r < 4; ++r) pp[((i * 2 + j) * 4 + r) * 256 + threadIdx.x] = acc[i][j][r];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) last = atomicAdd(&cnt[tk.grp], 1) == tk.nchunk - 1;
-        __syncthreads();
-        if (!last) return;
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+        // partial sums in accumulator order, added by the finishing pass
+        if (!finish) {
+            T *pp = part + tk.part_off + (int64_t)tk.chunk * TE;
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j)
+                    for (int r = 0; r < 4; ++r) pp[((i * 2 + j) * 4 + r) * 256 + threadIdx.x] = acc[i][j][r];
+            return;
+        }
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
         for (int c = 0; c < tk.nchunk; ++c) {
@@ -269,7 +268,6 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ i
                 for (int j = 0; j < 2; ++j)
                     for (int r = 0; r < 4; ++r) acc[i][j][r] += pc[((i * 2 + j) * 4 + r) * 256 + threadIdx.x];
         }
-        if (threadIdx.x == 0) atomicExch(&cnt[tk.grp], 0);
     }
     const int lr = lane & 15, lq = lane >> 4;
     const T alpha = (tk.flags & GF_NEGATE) ? T(-1) : T(1);
@@ -750,16 +748,18 @@ static inline unsigned grid_of(int64_t n) { return (unsigned)n; }
 
 template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s,
-                      T *part, int32_t *cnt) {
+                      T *part, bool split) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL((tile_gemm_kernel<T, T>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, arena, tasks, pairs,
-                       part, cnt);
+    for (int finish = 0; finish <= (split ? 1 : 0); ++finish)
+        hipLaunchKernelGGL((tile_gemm_kernel<T, T>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, arena, tasks,
+                           pairs, part, finish);
 }
 void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,
-                           int64_t ntasks, hipStream_t s, float *part, int32_t *cnt) {
+                           int64_t ntasks, hipStream_t s, float *part, bool split) {
     if (ntasks <= 0) return;
-    hipLaunchKernelGGL((tile_gemm_kernel<uint16_t, float>), dim3(grid_of(ntasks)), dim3(256), 0, s, in, out, tasks,
-                       pairs, part, cnt);
+    for (int finish = 0; finish <= (split ? 1 : 0); ++finish)
+        hipLaunchKernelGGL((tile_gemm_kernel<uint16_t, float>), dim3(grid_of(ntasks)), dim3(256), 0, s, in, out,
+                           tasks, pairs, part, finish);
 }
 template <class T>
 void launch_diag(T *a, T *w, T *wt, const DiagTask *tasks, int64_t ntasks, int32_t *flag, hipStream_t s) {
@@ -815,9 +815,9 @@ void launch_sym_reduce(const SymReduce *tasks, int64_t ntasks, const double *par
 }
 
 template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, double *,
-                                       int32_t *);
+                                       bool);
 template void launch_tile_gemm<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, float *,
-                                      int32_t *);
+                                      bool);
 template void launch_diag<double>(double *, double *, double *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_diag<float>(float *, float *, float *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);

@@ -20,6 +20,7 @@ struct Launch {
     int64_t start;
     int64_t count;
     double flops = 0.0;   // algorithmic flops of the launch (2*64^3 per tile product)
+    bool split = false;   // GEMM launches: some tasks split (a finishing pass follows)
 };
 
 // Kernel classes timed by the built-in profiler.
@@ -58,9 +59,7 @@ struct TaskLists {
     DiagTask *d_diag = nullptr;
     CopyTask *d_copy = nullptr;
     int64_t part_len = 0;        // split-task partial tiles (elements of the list's type)
-    int32_t cnt_len = 0;         // split-task arrival counters
     void *d_part = nullptr;
-    int32_t *d_cnt = nullptr;
 };
 
 struct Range {
@@ -303,7 +302,6 @@ struct Handle {
     hipStream_t side = nullptr;
     hipEvent_t side_ev[4] = {nullptr, nullptr, nullptr, nullptr};
     void *d_part_side = nullptr;
-    int32_t *d_cnt_side = nullptr;
     bool use_graphs = true;
     hipStream_t gstream = nullptr;
     std::vector<hipGraphExec_t> arnoldi_graphs;

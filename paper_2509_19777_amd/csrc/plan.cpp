@@ -401,9 +401,9 @@ double sym_gemv_bytes(const std::vector<GemvTask> &vt, const std::vector<SymPair
 // Re-emit the rows of GEMV launch r at the end of vt so that the launch
 // spreads over about target work-groups (a work-group streams tiles at a small
 // fraction of the device bandwidth): rows longer than the chunk length (at
-// least 4 pairs) are cut into chunks whose partial sums the last work-group of
-// the row reduces in chunk order.  target 0 returns r unchanged.  part_len and
-// cnt_len grow to what the launch needs.
+// least 4 pairs) are cut into chunks whose partial sums a reduction launch
+// after the product adds in chunk order.  target 0 returns r unchanged.
+// part_len grows to what the launch needs.
 Range split_rows(std::vector<GemvTask> &vt, Range r, int64_t target, int64_t &part_len) {
     if (target <= 0) return r;
     int64_t total = 0;
@@ -462,8 +462,8 @@ GemvShapes sweep_shapes(std::vector<GemvTask> &vt, Range base, int64_t &part_len
 // Split the long sums of a GEMM launch that has too few tasks to fill the
 // device: a work-group loads its tile pairs at a small fraction of the device
 // bandwidth, so a chain of k products is cut into about sqrt(k/2)-pair
-// chunks that run on different compute units (the last one to finish adds the
-// partials in order, a cost that grows with the number of chunks).
+// chunks that run on different compute units; a finishing pass after the
+// launch adds each task's partials in order and applies its epilogue.
 void split_program(std::vector<Launch> &prog, TaskLists &tl) {
     for (Launch &L : prog) {
         if (L.kind != LK_GEMM || L.count >= 256) continue;
@@ -472,7 +472,6 @@ void split_program(std::vector<Launch> &prog, TaskLists &tl) {
         const int64_t floor_per = std::max<int64_t>(2, (total + 511) / 512);   // at most ~512 work-groups
         const int64_t start = (int64_t)tl.gemm.size();
         int64_t part = 0;
-        int32_t grp = 0;
         bool any = false;
         for (int64_t i = L.start; i < L.start + L.count; ++i) {
             const GemmTask t = tl.gemm[(size_t)i];
@@ -490,13 +489,11 @@ void split_program(std::vector<Launch> &prog, TaskLists &tl) {
                 u.pair_start = (int32_t)(t.pair_start + c * each);
                 u.pair_count = (int32_t)std::min<int64_t>(each, k - c * each);
                 u.part_off = part;
-                u.grp = grp;
                 u.chunk = (int16_t)c;
                 u.nchunk = (int16_t)nc;
                 tl.gemm.push_back(u);
             }
             part += nc * TE;
-            ++grp;
         }
         if (!any) {
             tl.gemm.resize((size_t)start);
@@ -504,8 +501,8 @@ void split_program(std::vector<Launch> &prog, TaskLists &tl) {
         }
         L.start = start;
         L.count = (int64_t)tl.gemm.size() - start;
+        L.split = true;
         tl.part_len = std::max(tl.part_len, part);
-        tl.cnt_len = std::max(tl.cnt_len, grp);
     }
 }
 
@@ -1752,7 +1749,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
                 chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
                     "gemm pair range");
                 if (t.nchunk > 1)
-                    chk(t.grp >= 0 && t.grp < tl.cnt_len && t.chunk >= 0 && t.chunk < t.nchunk && t.part_off >= 0 &&
+                    chk(t.chunk >= 0 && t.chunk < t.nchunk && t.part_off >= 0 &&
                             t.part_off + (int64_t)t.nchunk * TE <= tl.part_len,
                         "gemm split task");
                 else
@@ -2018,9 +2015,6 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         tl->d_pairs = h.upload(tl->pairs, s);
         tl->d_diag = h.upload(tl->diag, s);
         tl->d_copy = h.upload(tl->copy, s);
-        tl->d_cnt = h.dalloc<int32_t>(std::max<int32_t>(1, tl->cnt_len));
-        if (hipMemsetAsync(tl->d_cnt, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, tl->cnt_len), s) != hipSuccess)
-            fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     }
     h.tl64.d_part = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
     h.tl32.d_part = h.dalloc<float>(std::max<int64_t>(1, h.tl32.part_len));
@@ -2030,10 +2024,6 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         // side stream next to the grain and coarse programs, which use tl64's
         // scratch: the side stream needs split-task scratch of its own
         h.d_part_side = h.dalloc<double>(std::max<int64_t>(1, h.tl64.part_len));
-        h.d_cnt_side = h.dalloc<int32_t>(std::max<int32_t>(1, h.tl64.cnt_len));
-        if (hipMemsetAsync(h.d_cnt_side, 0, sizeof(int32_t) * (size_t)std::max<int32_t>(1, h.tl64.cnt_len), s) !=
-            hipSuccess)
-            fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     }
     h.d_vtasks = h.upload(h.vtasks, s);
     h.d_vpairs = h.upload(h.vpairs, s);
