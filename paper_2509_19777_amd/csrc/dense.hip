@@ -739,7 +739,16 @@ __global__ void __launch_bounds__(256) sym_reduce_kernel(const SymReduce *__rest
     const int r = threadIdx.x & 63;
     double s = y[tk.y_off + r];
     const double *pp = part + tk.p_off + r;
-    for (int32_t k = 0; k < tk.count; ++k) s += pp[(int64_t)k * TS];
+    // eight loads in flight, added in ascending k
+    int32_t k = 0;
+    for (; k + 8 <= tk.count; k += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = pp[(int64_t)(k + u) * TS];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; k < tk.count; ++k) s += pp[(int64_t)k * TS];
     y[tk.y_off + r] = s;
 }
 

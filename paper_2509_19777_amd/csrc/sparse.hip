@@ -184,33 +184,36 @@ __device__ __forceinline__ int64_t rect_elem(int64_t r, int64_t c, int64_t nt) {
     return ((c >> 6) * nt + (r >> 6)) * TE + (c & 63) * TS + (r & 63);
 }
 
-__global__ void gather_grain_kernel(FineCsr A, GrainGather g, const double *__restrict__ b,
-                                    double *__restrict__ arena) {
-    const int64_t v = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per node row: lane l takes values l, l + 64, ... of the row's
+// 3x3 blocks (coarse reads), writing those whose column node lies in the same
+// grain into the lower tiles of the grain's block; every element has one writer.
+__global__ void __launch_bounds__(256) gather_grain_kernel(FineCsr A, GrainGather g, const double *__restrict__ b,
+                                                           double *__restrict__ arena) {
+    const int64_t v = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (v >= A.n_nodes) return;
     const int32_t m = g.node_gmat[v];
     if (m < 0) return;
     const int64_t lv = g.node_local[v];
     double *T = arena + g.mat_aoff[m];
-    for (int64_t p = A.row_ptr[v]; p < A.row_ptr[v + 1]; ++p) {
-        const int32_t w = A.col[p];
+    const int64_t p0 = A.row_ptr[v], nv = 9 * (A.row_ptr[v + 1] - p0);
+    for (int64_t e = lane; e < nv; e += 64) {
+        const int32_t w = A.col[p0 + e / 9];
         if (g.node_gmat[w] != m) continue;
-        const int64_t lw = g.node_local[w];
-        for (int gi = 0; gi < 3; ++gi)
-            for (int di = 0; di < 3; ++di) {
-                const int64_t r = 3 * lv + gi, c = 3 * lw + di;
-                if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p + 3 * gi + di];
-            }
+        const int j = (int)(e % 9);
+        const int64_t r = 3 * lv + j / 3, c = 3 * (int64_t)g.node_local[w] + j % 3;
+        if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p0 + e];
     }
     const int32_t cc = g.mat_corrcol[m];
-    if (cc >= 0 && b) {
+    if (cc >= 0 && b && lane < 3) {
         double *R = arena + g.mat_roff[m];
-        for (int gi = 0; gi < 3; ++gi) R[rect_elem(3 * lv + gi, cc, g.mat_nt[m])] = b[3 * v + gi];
+        R[rect_elem(3 * lv + lane, cc, g.mat_nt[m])] = b[3 * v + lane];
     }
 }
 void launch_gather_grain_blocks(const FineCsr &A, const GrainGather &g, const double *b, double *arena,
                                 hipStream_t s) {
-    hipLaunchKernelGGL(gather_grain_kernel, dim3(blocks_for(A.n_nodes, 128)), dim3(128), 0, s, A, g, b, arena);
+    if (A.n_nodes <= 0) return;
+    hipLaunchKernelGGL(gather_grain_kernel, dim3((unsigned)((A.n_nodes + 3) / 4)), dim3(256), 0, s, A, g, b, arena);
 }
 
 template <class T>
@@ -271,14 +274,20 @@ void launch_gather_abar(const FineCsr &A, const AbarWork *work, int64_t nwork, c
                        arena);
 }
 
-__global__ void gather_contact_kernel(FineCsr A, ContactGather cg, int64_t nitems, double *__restrict__ arena) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// One wavefront per (node, contact grid) item, lanes over the row's values as
+// in the grain gather; a column node's position in the grid comes from its
+// (short) list of grid memberships.
+__global__ void __launch_bounds__(256) gather_contact_kernel(FineCsr A, ContactGather cg, int64_t nitems,
+                                                             double *__restrict__ arena) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (i >= nitems) return;
     const int32_t v = cg.item_node[i], m = cg.item_mat[i];
     const int64_t lv = cg.item_local[i];
     double *T = arena + cg.mat_aoff[m];
-    for (int64_t p = A.row_ptr[v]; p < A.row_ptr[v + 1]; ++p) {
-        const int32_t w = A.col[p];
+    const int64_t p0 = A.row_ptr[v], nv = 9 * (A.row_ptr[v + 1] - p0);
+    for (int64_t e = lane; e < nv; e += 64) {
+        const int32_t w = A.col[p0 + e / 9];
         int64_t lw = -1;
         for (int64_t q = cg.node_cptr[w]; q < cg.node_cptr[w + 1]; ++q)
             if (cg.node_cmat[q] == m) {
@@ -286,17 +295,16 @@ __global__ void gather_contact_kernel(FineCsr A, ContactGather cg, int64_t nitem
                 break;
             }
         if (lw < 0) continue;
-        for (int gi = 0; gi < 3; ++gi)
-            for (int di = 0; di < 3; ++di) {
-                const int64_t r = 3 * lv + gi, c = 3 * lw + di;
-                if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p + 3 * gi + di];
-            }
+        const int j = (int)(e % 9);
+        const int64_t r = 3 * lv + j / 3, c = 3 * lw + j % 3;
+        if ((r >> 6) >= (c >> 6)) T[tile_elem(r, c)] = A.val[9 * p0 + e];
     }
 }
 void launch_gather_contact_blocks(const FineCsr &A, const ContactGather &c, int64_t nitems, double *arena,
                                   hipStream_t s) {
     if (nitems <= 0) return;
-    hipLaunchKernelGGL(gather_contact_kernel, dim3(blocks_for(nitems, 128)), dim3(128), 0, s, A, c, nitems, arena);
+    hipLaunchKernelGGL(gather_contact_kernel, dim3((unsigned)((nitems + 3) / 4)), dim3(256), 0, s, A, c, nitems,
+                       arena);
 }
 
 // ---- coarse Galerkin assembly ----------------------------------------------------
