@@ -400,8 +400,16 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
         // A -= P P^T on the matrix cores: P staged in LDS as S[k][m] = P(m, k)
         // (both operands read from it); the waves of the three lower 32x32
         // quadrants accumulate theirs over k = 0..63, the upper one idles
+        // every load issued before the first store, so that they overlap
         const T *pp = A + tk.p_off;
-        for (int e = threadIdx.x; e < TE; e += 256) S[(e >> 6) * LD + (e & (TS - 1))] = pp[e];
+        T pv[TE / 256];
+#pragma unroll
+        for (int u = 0; u < TE / 256; ++u) pv[u] = pp[threadIdx.x + 256 * u];
+#pragma unroll
+        for (int u = 0; u < TE / 256; ++u) {
+            const int e = threadIdx.x + 256 * u;
+            S[(e >> 6) * LD + (e & (TS - 1))] = pv[u];
+        }
         __syncthreads();
         const int lr = r & 15, lq = r >> 4;
         const int wm = (q >> 1) * 32, wn = (q & 1) * 32;
@@ -409,7 +417,7 @@ __global__ void __launch_bounds__(256) diag_kernel(T *__restrict__ A, T *__restr
         for (int i = 0; i < 2; ++i)
             for (int j = 0; j < 2; ++j) acc[i][j] = typename Mfma<T>::acc_t{0, 0, 0, 0};
         if (wm >= wn) {
-#pragma unroll 4
+#pragma unroll
             for (int kk = 0; kk < TS; kk += 4) {
                 const int k = kk + lq;
                 const T a0 = S[k * LD + wm + lr], a1 = S[k * LD + wm + 16 + lr];
