@@ -481,14 +481,20 @@ __global__ void __launch_bounds__(256) tile_transpose_kernel(const T *__restrict
     const CopyTask tk = tasks[blockIdx.x];
     const int t = threadIdx.x;
     const T *s = src + tk.src_off;
-    for (int e = t; e < TE; e += 256) {
-        const int r = e & (TS - 1), c = e >> 6;
-        S[r * LD + c] = s[e];
+    // every load issued before the first store, so that they overlap
+    T v[TE / 256];
+#pragma unroll
+    for (int u = 0; u < TE / 256; ++u) v[u] = s[t + 256 * u];
+#pragma unroll
+    for (int u = 0; u < TE / 256; ++u) {
+        const int e = t + 256 * u, r = e & (TS - 1), c = e >> 6;
+        S[r * LD + c] = v[u];
     }
     __syncthreads();
     T *d = dst + tk.dst_off;
-    for (int e = t; e < TE; e += 256) {
-        const int r = e & (TS - 1), c = e >> 6;   // dst(r, c) = src(c, r)
+#pragma unroll
+    for (int u = 0; u < TE / 256; ++u) {
+        const int e = t + 256 * u, r = e & (TS - 1), c = e >> 6;   // dst(r, c) = src(c, r)
         d[e] = S[c * LD + r];
     }
 }
