@@ -200,10 +200,19 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         hip_check(hipStreamSynchronize(s), "stage");
         return;
     }
-    if (sg)
+    if (sg) {
         surrogate_basis(h, *sg, s);
-    else
+    } else {
         run_program<double>(h, h.tl64, h.ar64, h.basis_prog, h.d_flag, s);
+        // X (by substitution) is read only by the preconditioner's
+        // application: beside the coarse operator, ahead of the contact grids
+        if (fork) {
+            hip_check(hipStreamWaitEvent(h.side, ev[5], 0), "fork");
+            run_program<double>(h, h.tl64, h.ar64, h.basis_x_prog, h.d_flag, h.side, h.d_part_side);
+        } else {
+            run_program<double>(h, h.tl64, h.ar64, h.basis_x_prog, h.d_flag, s);
+        }
+    }
     if (fork && !sg) fork_contacts();
     if (fork) {
         // the grain inverse S = W^T W (after the rows of W, when those are

@@ -187,9 +187,9 @@ struct Handle {
     int64_t *d_g_dof_slot = nullptr;   // dof -> grain vector slot
     int64_t *d_gcol_upos = nullptr;    // grain column slot -> coarse vector position
     // Y = W R, X = W^T Y, K = Y^T Y, XT; or, by substitution (basis_subst),
-    // the backward rows of X, K and XT, the forward rows of Y having run in
-    // the grain factorisation's steps
-    std::vector<Launch> basis_prog;
+    // K = Y^T Y here and the backward rows of X and XT in basis_x_prog, the
+    // forward rows of Y having run in the grain factorisation's steps
+    std::vector<Launch> basis_prog, basis_x_prog;
     bool basis_subst = false;
     int64_t negi_off = -1;             // a -I tile in the FP64 arena (substitution terms)
     Range gemv_XT, gemv_X;

@@ -978,7 +978,8 @@ static void method_work(Handle &h) {
         return f;
     };
     h.issued_setup_flops[0] =
-        sum(h.gset.factor_prog) + sum(h.gset.w_prog) + sum(h.gset.inverse_prog) + sum(h.basis_prog);
+        sum(h.gset.factor_prog) + sum(h.gset.w_prog) + sum(h.gset.inverse_prog) + sum(h.basis_prog) +
+        sum(h.basis_x_prog);
     h.issued_setup_flops[1] = sum(h.cset.factor_prog) + sum(h.cset.inverse_prog);
     h.issued_setup_flops[2] = h.mf.flops;
     h.issued_setup_flops[3] = h.issued_setup_flops[0] + h.issued_setup_flops[1] + h.issued_setup_flops[2];
@@ -1448,7 +1449,9 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T; or by
     // substitution: backward rows X_k = W_kk^T (Y_k - sum_q L_qk^T X_q) over
     // the nonzero tiles L_qk, q > k (X over R, Y_k entering as -I Y_k), one
-    // launch per row counted from every matrix's last row, then K and XT
+    // launch per row counted from every matrix's last row, then XT, in a
+    // program of its own (only the preconditioner's application reads X), and
+    // K = Y^T Y, which the coarse operator needs
     {
         std::vector<int64_t> all((size_t)nG);
         std::iota(all.begin(), all.end(), 0);
@@ -1472,9 +1475,10 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
                     }
                 }
                 L.count = (int64_t)h.tl64.gemm.size() - L.start;
-                if (L.count) h.basis_prog.push_back(L);
+                if (L.count) h.basis_x_prog.push_back(L);
             }
-            append_basis_program(h, h.tl64, all, h.basis_prog, BP_K | BP_XT);
+            append_basis_program(h, h.tl64, all, h.basis_x_prog, BP_XT);
+            append_basis_program(h, h.tl64, all, h.basis_prog, BP_K);
         } else {
             append_basis_program(h, h.tl64, all, h.basis_prog, BP_ALL);
         }
@@ -1516,6 +1520,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     split_program(h.gset.w_prog, h.tl64);
     split_program(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     split_program(h.basis_prog, h.tl64);
+    split_program(h.basis_x_prog, h.tl64);
     split_program(h.gset.inverse_prog, tl_inv);
     split_program(h.cset.inverse_prog, tl_inv);
     fill_flops(h.gset.inverse_prog, tl_inv);
@@ -1524,6 +1529,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     fill_flops(h.gset.w_prog, h.tl64);
     fill_flops(h.cset.factor_prog, c32 ? h.tl32 : h.tl64);
     fill_flops(h.basis_prog, h.tl64);
+    fill_flops(h.basis_x_prog, h.tl64);
     {
         const double ge = h.smoother_precision == 64 ? 8.0 : (h.smoother_precision == 32 ? 4.0 : 2.0);
         // S of the reduced-precision inverse form is kept in FP32
