@@ -144,14 +144,14 @@ static void contact_setup(Handle &h, hipStream_t s) {
 // split-task scratch).
 static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup *sg = nullptr) {
     struct Events {
-        hipEvent_t e[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
         ~Events() {
             for (hipEvent_t x : e)
                 if (x) (void)hipEventDestroy(x);
         }
     } evs;
     hipEvent_t *ev = evs.e;
-    for (int i = 0; i < 6; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
+    for (int i = 0; i < 7; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
     const int32_t init_flag[2] = {0, 0x7fffffff};
     hip_check(hipMemcpyAsync(h.d_flag, init_flag, sizeof(init_flag), hipMemcpyHostToDevice, s), "flag init");
     hip_check(hipEventRecord(ev[0], s), "event");
@@ -161,6 +161,13 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
             hip_check(hipStreamCreateWithFlags(&h.side, hipStreamNonBlocking), "stream");
             for (auto &e : h.side_ev) hip_check(hipEventCreate(&e), "event");
         }
+    }
+    if (fork && h.n_mortar > 0) {
+        // the fronts' region is cleared on the side stream, idle until the
+        // grains are factored
+        hip_check(hipStreamWaitEvent(h.side, ev[0], 0), "fork");
+        zero(h.ar64 + h.mf.a_base, sizeof(double) * h.mf.region, h.side);
+        hip_check(hipEventRecord(ev[6], h.side), "event");
     }
     // ---- grains: blocks, factor, inverse, basis (Eqs. 23-24) ----
     zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
@@ -253,7 +260,10 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         // assemble every front, then factor level by level from the leaves,
         // adding each child's update matrix into its parent first
         CoarseMF &mf = h.mf;
-        zero(h.ar64 + mf.a_base, sizeof(double) * mf.region, s);
+        if (fork)
+            hip_check(hipStreamWaitEvent(s, ev[6], 0), "wait");
+        else
+            zero(h.ar64 + mf.a_base, sizeof(double) * mf.region, s);
         launch_coarse_assemble(h.d_pairs, h.n_pairs, h.d_edges, h.d_krefs, h.cm, h.csr.val, h.ar64, h.ar64,
                                h.pair_vals, s);
         launch_set_ones(mf.d_pad, (int64_t)mf.pad_ones.size(), h.ar64, s);

@@ -29,12 +29,13 @@ enum GemmFlags : int32_t {
     GF_POST_RIGHT = 32, // C = ([C +] alpha * sum) * P, P = tile at post_off
 };
 
-// One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p) [* P].
-// A long sum may be split into nchunk tasks over consecutive parts of its
-// pair list (same c_off, post_off and flags, transposition aside): each
-// stores its partial sum in part[part_off + 4096 chunk ..], and a finishing
-// pass after the launch adds the partials in chunk order and applies the
-// epilogue.
+// One output tile: C(c_off) (op)= alpha * [P *] sum_p op(A_p) op(B_p) [* P],
+// and, when t_off >= 0 (tasks that do not accumulate into C), its transpose
+// at t_off as well.  A long sum may be split into nchunk tasks over
+// consecutive parts of its pair list (same c_off, post_off, t_off and flags,
+// transposition aside): each stores its partial sum in
+// part[part_off + 4096 chunk ..], and a finishing pass after the launch adds
+// the partials in chunk order and applies the epilogue.
 struct GemmTask {
     int64_t c_off;
     int64_t post_off;
@@ -46,6 +47,7 @@ struct GemmTask {
     int32_t pad2 = 0;
     int16_t chunk = 0;
     int16_t nchunk = 1;
+    int64_t t_off = -1;
 };
 
 struct GemmPair {

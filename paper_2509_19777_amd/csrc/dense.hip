@@ -306,6 +306,17 @@ __global__ void __launch_bounds__(256) tile_gemm_kernel(const Ti *__restrict__ i
         const T v = a2 * S[n * LD + m];
         C[e] = accum ? C[e] + v : v;
     }
+    if (tk.t_off >= 0) {
+        // the transposed copy, coalesced in its own order (tasks that
+        // accumulate into C never ask for one)
+        T *Ct = out + tk.t_off;
+#pragma unroll 4
+        for (int q = 0; q < TE / 256; ++q) {
+            const int e = t + 256 * q;
+            const int m = e & (TS - 1), n = e >> 6;   // Ct(m, n) = C(n, m)
+            Ct[e] = a2 * S[m * LD + n];
+        }
+    }
 }
 
 // 1/d for a positive normal d.  FP64: the hardware reciprocal refined by

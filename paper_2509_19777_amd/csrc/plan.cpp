@@ -197,13 +197,16 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
     // row k of W = L^-1: W_kj = -W_kk sum_{q=j}^{k-1} L_kq W_qj, j < k, reading
     // rows of L and W finished before; an empty sum (row k uncoupled to earlier
     // rows) writes a zero tile
+    // (with stored transposes the task also writes Wt_jk = W_kj^T)
     auto w_row = [&](int64_t m, int64_t k) {
         for (int64_t j = 0; j < k; ++j) {
             const int32_t ps = (int32_t)tl.pairs.size();
             const int32_t pc = push_pairs(std::max(j, first(m, k)), k, [&](int64_t q) {
                 return GemmPair{A(m, k, q), W(m, q, j)};
             });
-            tl.gemm.push_back({W(m, k, j), W(m, k, k), ps, pc, GF_POST | GF_NEGATE, 0});
+            GemmTask g{W(m, k, j), W(m, k, k), ps, pc, GF_POST | GF_NEGATE, 0};
+            if (!ds.wt_diag) g.t_off = Wt(m, k, j);
+            tl.gemm.push_back(g);
         }
     };
     // Left-looking tile Cholesky, two launches per step k: the diagonal tile
@@ -271,13 +274,6 @@ void build_factor_program(DenseSet &ds, TaskLists &tl, int32_t set_id, std::vect
         u.count = (int64_t)tl.gemm.size() - u.start;
         if (u.count) prog.push_back(u);
     }
-    if (ds.wt_diag) return;   // no stored transposes
-    Launch c{LK_TRANSPOSE, (int64_t)tl.copy.size(), 0};
-    for (int64_t m = 0; m < nm; ++m)
-        for (int64_t i = 0; i < own(m); ++i)
-            for (int64_t j = 0; j < i; ++j) tl.copy.push_back({W(m, i, j), Wt(m, i, j)});
-    c.count = (int64_t)tl.copy.size() - c.start;
-    if (c.count) (fuse_w ? prog : ds.w_prog).push_back(c);
 }
 
 // Apply-time GEMV task lists y = W x and y = W^T x of a dense set.
@@ -789,24 +785,20 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         lv.w_base = mf.w_base;
         lv.wt_base = mf.wt_base;
         build_factor_program(lv, h.tl64, 2, &mf.factor_prog[(size_t)l], &ids);
-        // NG = -L21 W11, then its per-tile transposes
+        // NG = -L21 W11, each task also writing its transpose NGT
         Launch g{LK_GEMM, (int64_t)h.tl64.gemm.size(), 0};
         for (int32_t t : at[(size_t)l]) {
             const int64_t nd = mf.nt_d[(size_t)t];
             for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I)
                 for (int64_t J = 0; J < nd; ++J) {
-                    h.tl64.gemm.push_back({NG(t, I, J), -1, (int32_t)h.tl64.pairs.size(), (int32_t)(nd - J), GF_NEGATE, 0});
+                    GemmTask task{NG(t, I, J), -1, (int32_t)h.tl64.pairs.size(), (int32_t)(nd - J), GF_NEGATE, 0};
+                    task.t_off = NGT(t, I, J);
+                    h.tl64.gemm.push_back(task);
                     for (int64_t K = J; K < nd; ++K) h.tl64.pairs.push_back({A(t, nd + I, K), W(t, K, J)});
                 }
         }
         g.count = (int64_t)h.tl64.gemm.size() - g.start;
         if (g.count) mf.factor_prog[(size_t)l].push_back(g);
-        Launch c{LK_TRANSPOSE, (int64_t)h.tl64.copy.size(), 0};
-        for (int32_t t : at[(size_t)l])
-            for (int64_t I = 0; I < mf.nt_u[(size_t)t]; ++I)
-                for (int64_t J = 0; J < mf.nt_d[(size_t)t]; ++J) h.tl64.copy.push_back({NG(t, I, J), NGT(t, I, J)});
-        c.count = (int64_t)h.tl64.copy.size() - c.start;
-        if (c.count) mf.factor_prog[(size_t)l].push_back(c);
         // extend-add of the children (level l+1) into this level's fronts
         for (int s = 0; s < 2; ++s) {
             Range r{(int64_t)mf.ext.size(), 0};
@@ -1449,9 +1441,9 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     // basis: Y = W R, X = W^T Y (overwrites R), K = Y^T Y, XT = X^T; or by
     // substitution: backward rows X_k = W_kk^T (Y_k - sum_q L_qk^T X_q) over
     // the nonzero tiles L_qk, q > k (X over R, Y_k entering as -I Y_k), one
-    // launch per row counted from every matrix's last row, then XT, in a
-    // program of its own (only the preconditioner's application reads X), and
-    // K = Y^T Y, which the coarse operator needs
+    // launch per row counted from every matrix's last row, each task also
+    // writing X^T, in a program of its own (only the preconditioner's
+    // application reads X), and K = Y^T Y, which the coarse operator needs
     {
         std::vector<int64_t> all((size_t)nG);
         std::iota(all.begin(), all.end(), 0);
@@ -1469,15 +1461,15 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
                         for (int64_t q = k + 1; q < nt; ++q)
                             if (fg(m, q) <= k) h.tl64.pairs.push_back({Lg(m, q, k), Rg(h.gm_roff[(size_t)m], m, q, C)});
                         h.tl64.pairs.push_back({h.negi_off, Rg(h.gm_ytoff[(size_t)m], m, k, C)});
-                        h.tl64.gemm.push_back({Rg(h.gm_roff[(size_t)m], m, k, C), h.gset.wt_base + h.gset.wdrel[m] + k * TE,
-                                               ps, (int32_t)(h.tl64.pairs.size() - ps),
-                                               GF_POST | GF_NEGATE | GF_TRANS_A, 0});
+                        GemmTask task{Rg(h.gm_roff[(size_t)m], m, k, C), h.gset.wt_base + h.gset.wdrel[m] + k * TE,
+                                      ps, (int32_t)(h.tl64.pairs.size() - ps), GF_POST | GF_NEGATE | GF_TRANS_A, 0};
+                        task.t_off = h.gm_xtoff[(size_t)m] + (k * h.gm_ntc[(size_t)m] + C) * TE;   // X^T
+                        h.tl64.gemm.push_back(task);
                     }
                 }
                 L.count = (int64_t)h.tl64.gemm.size() - L.start;
                 if (L.count) h.basis_x_prog.push_back(L);
             }
-            append_basis_program(h, h.tl64, all, h.basis_x_prog, BP_XT);
             append_basis_program(h, h.tl64, all, h.basis_prog, BP_K);
         } else {
             append_basis_program(h, h.tl64, all, h.basis_prog, BP_ALL);
@@ -1750,6 +1742,11 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
             const int64_t on = which ? h.ar32_n : h.ar64_n;
             for (const auto &t : tl.gemm) {
                 chk(in(t.c_off, TE, on), "gemm output tile");
+                if (t.t_off >= 0)
+                    chk(in(t.t_off, TE, on) && (!(t.flags & GF_ACCUM) || (t.flags & (GF_POST | GF_POST_RIGHT))),
+                        "gemm transposed output tile");
+                else
+                    chk(t.t_off == -1, "gemm transposed output tile");
                 if (which == 2) chk(!(t.flags & (GF_POST | GF_POST_RIGHT)), "bfloat16 task without second product");
                 if (t.flags & (GF_POST | GF_POST_RIGHT)) chk(in(t.post_off, TE, an), "gemm post tile");
                 chk(t.pair_start >= 0 && t.pair_count >= 0 && (int64_t)t.pair_start + t.pair_count <= (int64_t)tl.pairs.size(),
