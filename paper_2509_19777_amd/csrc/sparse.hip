@@ -326,6 +326,11 @@ __device__ __forceinline__ void sym_put(double *F, int64_t r, int64_t c, double 
     }
 }
 
+// the staged path of the coarse assembly: up to 4 mortar nodes per interface
+// (its LDS then lets 18 work-groups share a CU); more take the plain path
+constexpr int CA_MAXNU = 4;
+constexpr int CA_PER = ((3 * CA_MAXNU) * (3 * CA_MAXNU) + 63) / 64;   // entries per thread
+
 __global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *__restrict__ pairs,
                                                              const CoarseEdge *__restrict__ edges,
                                                              const CoarseKRef *__restrict__ krefs, CoarseMaps cm,
@@ -337,6 +342,59 @@ __global__ void __launch_bounds__(64) coarse_assemble_kernel(const CoarsePair *_
     const int n1 = 3 * nu1, n2 = 3 * nu2;
     const double *H1 = cm.H + cm.iface_hoff[pr.c];
     const double *H2 = cm.H + cm.iface_hoff[pr.c2];
+    if (!cm.general && nu1 <= CA_MAXNU && nu2 <= CA_MAXNU) {
+        // Gaussian mortars: the pair's edges pass through LDS 64 at a time
+        // (their weight rows and 3x3 blocks), each thread keeping the sums of
+        // its entries in registers; every sum runs over the edges in order
+        __shared__ double sh1[64][CA_MAXNU], sh2[64][CA_MAXNU], sb[64][9];
+        const int ne = n1 * n2;
+        double acc[CA_PER];
+        int ia[CA_PER], ib[CA_PER], ig[CA_PER];
+#pragma unroll
+        for (int u = 0; u < CA_PER; ++u) {
+            const int e = threadIdx.x + 64 * u, i = e / n2, j = e - (e / n2) * n2;
+            acc[u] = 0.0;
+            ia[u] = i / 3;
+            ib[u] = j / 3;
+            ig[u] = 3 * (i % 3) + j % 3;
+        }
+        for (int32_t c0 = 0; c0 < pr.e_count; c0 += 64) {
+            const int cnt = pr.e_count - c0 < 64 ? pr.e_count - c0 : 64;
+            __syncthreads();   // the previous chunk is consumed
+            if ((int)threadIdx.x < cnt) {
+                const CoarseEdge ed = edges[pr.e_start + c0 + threadIdx.x];
+                for (int a = 0; a < nu1; ++a) sh1[threadIdx.x][a] = H1[(int64_t)ed.rv * nu1 + a];
+                for (int b2 = 0; b2 < nu2; ++b2) sh2[threadIdx.x][b2] = H2[(int64_t)ed.rw * nu2 + b2];
+                for (int j = 0; j < 9; ++j) sb[threadIdx.x][j] = bval[9 * ed.blk + j];
+            }
+            __syncthreads();
+            for (int k = 0; k < cnt; ++k)
+#pragma unroll
+                for (int u = 0; u < CA_PER; ++u)
+                    if ((int)threadIdx.x + 64 * u < ne) acc[u] += sh1[k][ia[u]] * sh2[k][ib[u]] * sb[k][ig[u]];
+        }
+#pragma unroll
+        for (int u = 0; u < CA_PER; ++u) {
+            const int e = threadIdx.x + 64 * u;
+            if (e >= ne) break;
+            const int i = e / n2, j = e - (e / n2) * n2;
+            double kk = 0.0;
+            for (int32_t k = 0; k < pr.k_count; ++k) {
+                const CoarseKRef kr = krefs[pr.k_start + k];
+                int64_t R = kr.lc + i, C = kr.lc2 + j;
+                if (R < C) {
+                    const int64_t t = R;
+                    R = C;
+                    C = t;
+                }
+                kk += karena[kr.koff + tile_elem(R, C)];
+            }
+            const double val = acc[u] - kk;
+            vals[pr.v_off + e] = val;
+            if (pr.c != pr.c2 || i >= j) sym_put(F + pr.f_off, pr.pos1 + i, pr.pos2 + j, val, true, false);
+        }
+        return;
+    }
     for (int e = threadIdx.x; e < n1 * n2; e += 64) {
         const int i = e / n2, j = e - (e / n2) * n2;
         const int a = i / 3, gi = i % 3, bb = j / 3, di = j % 3;
