@@ -988,6 +988,29 @@ static double time_us(hipStream_t s, int32_t reps, hipEvent_t e0, hipEvent_t e1,
     return 1e3 * best / reps;
 }
 
+// Median time (us) of fn run alone after the caches are overwritten by a
+// triad over `flush` (three arrays of flush_n doubles, larger than L2 and
+// the last-level cache together): a coarse-sweep launch reads its operators
+// once per application, so it is timed as the sweep meets them.
+template <class F>
+static double time_cold_us(hipStream_t s, int32_t reps, hipEvent_t e0, hipEvent_t e1, double *flush, int64_t flush_n,
+                           F fn) {
+    fn();
+    std::vector<float> t;
+    for (int32_t r = 0; r < reps; ++r) {
+        launch_triad(flush, flush + flush_n, flush + 2 * flush_n, 1.0, flush_n, s);
+        hip_check(hipEventRecord(e0, s), "event");
+        fn();
+        hip_check(hipEventRecord(e1, s), "event");
+        hip_check(hipEventSynchronize(e1), "sync");
+        float ms = 0.f;
+        hip_check(hipEventElapsedTime(&ms, e0, e1), "elapsed");
+        t.push_back(ms);
+    }
+    std::sort(t.begin(), t.end());
+    return 1e3 * t[t.size() / 2];
+}
+
 // Put the chosen shapes in place: coarse levels from their variant lists,
 // smoother / basis launches by their waves.
 static void apply_tuning(Handle &h, const std::vector<TuneRecord> &log) {
@@ -1033,8 +1056,23 @@ static void autotune(Handle &h, int32_t reps, hipStream_t s) {
     }
     std::vector<TuneRecord> log;
     try {
-        // the sweeps run on zeroed front vectors: their in-place updates stay zero
+        // the sweeps run on zeroed front vectors: their in-place updates stay
+        // zero.  Each shape is timed cold (see time_cold_us): repeated alone,
+        // a level's operators stay cached, which flatters long unsplit rows.
         if (mf.n_fronts) zero(mf.V, sizeof(double) * 3 * (size_t)mf.vec_len, s);
+        constexpr int64_t flush_n = (int64_t)1 << 24;   // 3 x 128 MiB
+        double *flush = nullptr;
+        if (mf.n_fronts) {
+            hip_check(hipMalloc(&flush, sizeof(double) * 3 * flush_n), "hipMalloc");
+            zero(flush, sizeof(double) * 3 * flush_n, s);
+        }
+        struct Free {
+            double *p;
+            ~Free() {
+                if (p) (void)hipFree(p);
+            }
+        } free_flush{flush};
+        const int32_t creps = std::max<int32_t>(3, reps / 2);
         for (int32_t kind = 0; kind < 2; ++kind)
             for (int32_t l = 0; l < mf.n_levels; ++l) {
                 const GemvShapes &g = (kind == 0 ? mf.fwd_shapes : mf.bwd_shapes)[(size_t)l];
@@ -1044,7 +1082,7 @@ static void autotune(Handle &h, int32_t reps, hipStream_t s) {
                     for (int32_t w : {4, 16}) {
                         Range r = g.var[(size_t)v];
                         r.waves = w;
-                        const double t = time_us(s, reps, e0, e1, [&] { gemv_front(h, r, s); });
+                        const double t = time_cold_us(s, creps, e0, e1, flush, flush_n, [&] { gemv_front(h, r, s); });
                         if (v == 0 && w == 4) best.t_default_us = best.t_best_us = t;
                         else if (t < best.t_best_us) {
                             best.variant = v;
