@@ -125,6 +125,11 @@ struct SymReduce {
 template <class T>
 void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
                       hipStream_t s, T *part = nullptr, bool split = false);
+// The finishing pass alone (after a launch_tile_gemm of the same list with
+// split = false).
+template <class T>
+void launch_tile_gemm_finish(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks,
+                             hipStream_t s, T *part);
 // bfloat16 operands (their 16 bits) from `in`, FP32 accumulation and output
 // to `out`; tasks without a second product (GF_POST / GF_POST_RIGHT ignored).
 void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,

@@ -788,6 +788,13 @@ void launch_tile_gemm(T *arena, const GemmTask *tasks, const GemmPair *pairs, in
         hipLaunchKernelGGL((tile_gemm_kernel<T, T>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, arena, tasks,
                            pairs, part, finish);
 }
+template <class T>
+void launch_tile_gemm_finish(T *arena, const GemmTask *tasks, const GemmPair *pairs, int64_t ntasks, hipStream_t s,
+                             T *part) {
+    if (ntasks <= 0) return;
+    hipLaunchKernelGGL((tile_gemm_kernel<T, T>), dim3(grid_of(ntasks)), dim3(256), 0, s, arena, arena, tasks, pairs,
+                       part, 1);
+}
 void launch_tile_gemm_bf16(const uint16_t *in, float *out, const GemmTask *tasks, const GemmPair *pairs,
                            int64_t ntasks, hipStream_t s, float *part, bool split) {
     if (ntasks <= 0) return;
@@ -852,6 +859,10 @@ template void launch_tile_gemm<double>(double *, const GemmTask *, const GemmPai
                                        bool);
 template void launch_tile_gemm<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t, float *,
                                       bool);
+template void launch_tile_gemm_finish<double>(double *, const GemmTask *, const GemmPair *, int64_t, hipStream_t,
+                                              double *);
+template void launch_tile_gemm_finish<float>(float *, const GemmTask *, const GemmPair *, int64_t, hipStream_t,
+                                             float *);
 template void launch_diag<double>(double *, double *, double *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_diag<float>(float *, float *, float *, const DiagTask *, int64_t, int32_t *, hipStream_t);
 template void launch_tile_transpose<double>(double *, double *, const CopyTask *, int64_t, hipStream_t);
