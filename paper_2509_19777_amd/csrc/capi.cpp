@@ -28,8 +28,11 @@ struct ProfScope {
         on = (p.mask >> c) & 1;
         if (!on) return;
         while (p.used + 2 > p.pool.size()) {
+            // timing only, read after a device synchronisation: no
+            // system-scope fence, whose L2 writeback and invalidation would
+            // otherwise land between the kernels being timed
             hipEvent_t e;
-            hip_check(hipEventCreate(&e), "hipEventCreate");
+            hip_check(hipEventCreateWithFlags(&e, hipEventDisableSystemFence), "hipEventCreate");
             p.pool.push_back(e);
         }
         ev = p.used;
@@ -127,7 +130,10 @@ static void contact_setup(Handle &h, hipStream_t s) {
     if (h.smoother_precision == 64 || h.smoother_form == HPLMM_SMOOTHER_INVERSE) {
         // FP64 programs beside those on the main stream: never on its scratch
         if (!h.d_part_side) fail(HPLMM_E_STATE, "side-stream split scratch missing");
-        zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
+        if (!h.zero_c.empty())
+            launch_zero_runs(h.d_zero_c, (int64_t)h.zero_c.size() / 2, h.ar64, s);
+        else
+            zero(h.ar64 + h.cset.a_base, sizeof(double) * h.cset.region, s);
         launch_gather_contact_blocks(h.csr, h.cg, h.n_citems, h.ar64, s);
         launch_set_ones(h.d_pad_c, (int64_t)h.pad_ones_c.size(), h.ar64, s);
         run_program<double>(h, h.tl64, h.ar64, h.cset.factor_prog, h.d_flag, s, h.d_part_side);
@@ -177,7 +183,10 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         hip_check(hipEventRecord(ev[6], h.side), "event");
     }
     // ---- grains: blocks, factor, inverse, basis (Eqs. 23-24) ----
-    zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
+    if (!h.zero_g.empty())
+        launch_zero_runs(h.d_zero_g, (int64_t)h.zero_g.size() / 2, h.ar64, s);
+    else
+        zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
     if (!h.gm_roff.empty()) {
         const int64_t r0 = h.gm_roff[0];
         int64_t rlen = 0;

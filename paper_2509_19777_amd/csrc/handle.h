@@ -195,6 +195,11 @@ struct Handle {
     Range gemv_XT, gemv_X;
     std::vector<int64_t> pad_ones_g;   // identity on padded diagonals
     int64_t *d_pad_g = nullptr;
+    // (offset, length) runs of the grain and contact-grid tiles inside the
+    // tile envelope, cleared before each gather (the tiles outside it are
+    // zeroed once and never written); empty: clear the whole region
+    std::vector<int64_t> zero_g, zero_c;
+    int64_t *d_zero_g = nullptr, *d_zero_c = nullptr;
 
     // contacts
     DenseSet cset;

@@ -1929,6 +1929,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     if (sys.rhs) std::memcpy(bvec.data(), sys.rhs, sizeof(double) * (size_t)h.N);
     h.d_b = h.upload(bvec, s);
     // coarse maps
+    h.cm.n_ifaces = h.n_ifaces;
     h.cm.n_mortar = h.n_mortar;
     h.cm.n_coarse = h.n_coarse;
     h.cm.fpos = h.upload(fpos, s);
@@ -1970,6 +1971,43 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     h.d_g_dof_slot = h.upload(g_dof_slot, s);
     h.d_gcol_upos = h.upload(gcol_upos, s);
     h.d_pad_g = h.upload(h.pad_ones_g, s);
+    // the tiles a gather and the factorisation can touch: row I of matrix m
+    // from its envelope's first column to the diagonal, contiguous in the
+    // packed lower-tile layout; runs of at most ZERO_RUN elements
+    auto envelope_runs = [](const DenseSet &ds, int64_t base, std::vector<int64_t> &runs) {
+        runs.clear();
+        if (ds.first.empty() || (base & 1)) return;
+        int64_t o0 = -1, o1 = -1;
+        auto flush = [&] {
+            for (int64_t o = o0; o < o1; o += ZERO_RUN) {
+                runs.push_back(o);
+                runs.push_back(std::min(ZERO_RUN, o1 - o));
+            }
+        };
+        for (size_t m = 0; m < ds.n.size(); ++m)
+            for (int64_t I = 0; I < ds.nt[m]; ++I) {
+                const int64_t J0 = ds.first[m][(size_t)I];
+                const int64_t a = base + ds.rel[m] + tri_index(I, J0) * TE, b = base + ds.rel[m] + tri_index(I, I + 1) * TE;
+                if (a == o1) {
+                    o1 = b;
+                } else {
+                    if (o0 >= 0) flush();
+                    o0 = a;
+                    o1 = b;
+                }
+            }
+        if (o0 >= 0) flush();
+        for (size_t i = 0; i < runs.size(); i += 2)
+            if (runs[i] < base || runs[i + 1] <= 0 || runs[i + 1] > ZERO_RUN || (runs[i] & 1) || (runs[i + 1] & 1) ||
+                runs[i] + runs[i + 1] > base + ds.region)
+                fail(HPLMM_E_ARG, "internal plan check failed: envelope zero run");
+    };
+    envelope_runs(h.gset, h.gset.a_base, h.zero_g);
+    h.d_zero_g = h.upload(h.zero_g, s);
+    if (!c32) {
+        envelope_runs(h.cset, h.cset.a_base, h.zero_c);
+        h.d_zero_c = h.upload(h.zero_c, s);
+    }
     // contacts
     std::vector<int64_t> caoff(h.cset.n.size());
     for (size_t m = 0; m < h.cset.n.size(); ++m) caoff[m] = (c32 ? h.c_stage_base : h.cset.a_base) + h.cset.rel[m];
@@ -2036,6 +2074,14 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     h.d_gemv_part = h.dalloc<double>(std::max<int64_t>(1, h.gemv_part_len));
     // arenas and vectors
     h.ar64 = h.dalloc<double>(h.ar64_n);
+    // the set-up clears only the envelope tiles of the grain and contact-grid
+    // blocks: the rest are zero from here on
+    if (!h.zero_g.empty() &&
+        hipMemsetAsync(h.ar64 + h.gset.a_base, 0, sizeof(double) * (size_t)h.gset.region, s) != hipSuccess)
+        fail(HPLMM_E_HIP, "hipMemsetAsync failed");
+    if (!h.zero_c.empty() &&
+        hipMemsetAsync(h.ar64 + h.cset.a_base, 0, sizeof(double) * (size_t)h.cset.region, s) != hipSuccess)
+        fail(HPLMM_E_HIP, "hipMemsetAsync failed");
     std::vector<double> negi;
     if (h.negi_off >= 0) {
         negi.assign((size_t)TE, 0.0);

@@ -37,6 +37,7 @@ void launch_combine(int64_t n, const double *base, const int64_t *gslot, const d
 //   f[fpos[q]] = [q < n_mortar] sum_{v in iface(q)} H[v, a(q)] r[3v + d(q)]
 //                + sum_{p in [tptr[q], tptr[q+1])} t[tslot[p]]
 struct CoarseMaps {
+    int64_t n_ifaces;            // interfaces
     int64_t n_mortar;            // mortar dofs
     int64_t n_coarse;            // mortar dofs + corrections
     const int64_t *fpos;         // [n_coarse] position in the coarse vector arena
@@ -86,6 +87,10 @@ void launch_gather_grain_blocks(const FineCsr &A, const GrainGather &g, const do
                                 hipStream_t s);
 // set arena[off[i]] = 1 (identity on padded diagonals)
 void launch_set_ones(const int64_t *off, int64_t n, double *arena, hipStream_t s);
+// arena[runs[2i] .. runs[2i] + runs[2i+1]) = 0 for i < nruns; offsets and
+// lengths are multiples of 2 elements, lengths at most ZERO_RUN
+constexpr int64_t ZERO_RUN = 8 * 4096;
+void launch_zero_runs(const int64_t *runs, int64_t nruns, double *arena, hipStream_t s);
 template <class T>
 void launch_set_ones_t(const int64_t *off, int64_t n, T *arena, hipStream_t s);
 

@@ -91,13 +91,11 @@ void launch_combine(int64_t n, const double *base, const int64_t *gslot, const d
 }
 
 // ---- restriction / prolongation ------------------------------------------------
-// One wavefront per coarse dof: the lanes share the interface's node sum and
-// the per-grain restriction terms, then a fixed butterfly adds them up.
-__global__ void __launch_bounds__(256) coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r,
-                                                         const double *__restrict__ t, double *__restrict__ f) {
-    const int lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (q >= m.n_coarse) return;
+// One coarse dof's sum, by one wavefront: the lanes share the interface's
+// node sum and the per-grain restriction terms, then a fixed butterfly adds
+// them up (every lane ends with the total).
+__device__ __forceinline__ double coarse_rhs_dof(const CoarseMaps &m, int64_t q, const double *__restrict__ r,
+                                                 const double *__restrict__ t, int lane) {
     double s = 0.0;
     if (q < m.n_mortar) {
         const int32_t c = m.q_iface[q];
@@ -120,11 +118,78 @@ __global__ void __launch_bounds__(256) coarse_rhs_kernel(CoarseMaps m, const dou
     for (int64_t p = m.tptr[q] + lane; p < m.tptr[q + 1]; p += 64) s += t[m.tslot[p]];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    return s;
+}
+
+// With Gaussian mortars one wavefront takes a whole interface: it reads the
+// node values and the rows of H once, accumulating all 3 nu sums together,
+// adds each up with the same butterfly, and lane j = 3 a + d finishes mortar
+// dof moff + j with its per-grain terms.  Interfaces of more than RHS_MAXNU
+// functions, the general blocks and the corrections go one dof per wavefront.
+constexpr int RHS_MAXNU = 4;
+__global__ void __launch_bounds__(256) coarse_rhs_kernel(CoarseMaps m, const double *__restrict__ r,
+                                                         const double *__restrict__ t, double *__restrict__ f) {
+    const int lane = threadIdx.x & 63;
+    const int64_t w = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t nw_if = m.general ? 0 : m.n_ifaces;
+    if (w < nw_if) {
+        const int32_t c = (int32_t)w;
+        const int32_t nu = m.iface_nu[c];
+        const int64_t mo = m.iface_moff[c];
+        if (nu > RHS_MAXNU) {
+            for (int j = 0; j < 3 * nu; ++j) {
+                const double s = coarse_rhs_dof(m, mo + j, r, t, lane);
+                if (lane == 0) f[m.fpos[mo + j]] = s;
+            }
+            return;
+        }
+        double acc[RHS_MAXNU][3];
+#pragma unroll
+        for (int a = 0; a < RHS_MAXNU; ++a) acc[a][0] = acc[a][1] = acc[a][2] = 0.0;
+        const double *H = m.H + m.iface_hoff[c];
+        const int64_t p0 = m.iface_ptr[c], p1 = m.iface_ptr[c + 1];
+        for (int64_t p = p0 + lane; p < p1; p += 64) {
+            const double *rv = r + 3 * (int64_t)m.iface_nodes[p];
+            const double r0 = rv[0], r1 = rv[1], r2 = rv[2];
+            const double *hp = H + (p - p0) * nu;
+#pragma unroll
+            for (int a = 0; a < RHS_MAXNU; ++a)
+                if (a < nu) {
+                    const double ha = hp[a];
+                    acc[a][0] += ha * r0;
+                    acc[a][1] += ha * r1;
+                    acc[a][2] += ha * r2;
+                }
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int a = 0; a < RHS_MAXNU; ++a)
+            if (a < nu) {   // nu is the same across the wavefront
+#pragma unroll
+                for (int d = 0; d < 3; ++d) {
+                    double v = acc[a][d];
+#pragma unroll
+                    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+                    if (lane == 3 * a + d) mine = v;
+                }
+            }
+        if (lane < 3 * nu) {
+            const int64_t q = mo + lane;
+            for (int64_t p = m.tptr[q]; p < m.tptr[q + 1]; ++p) mine += t[m.tslot[p]];
+            f[m.fpos[q]] = mine;
+        }
+        return;
+    }
+    const int64_t q = m.general ? w : m.n_mortar + (w - nw_if);
+    if (q >= m.n_coarse) return;
+    const double s = coarse_rhs_dof(m, q, r, t, lane);
     if (lane == 0) f[m.fpos[q]] = s;
 }
 void launch_coarse_rhs(const CoarseMaps &m, const double *r, const double *t, double *f, hipStream_t s) {
     if (m.n_coarse <= 0) return;
-    hipLaunchKernelGGL(coarse_rhs_kernel, dim3(blocks_for(m.n_coarse, 4)), dim3(256), 0, s, m, r, t, f);
+    const int64_t waves = m.general ? m.n_coarse : m.n_ifaces + (m.n_coarse - m.n_mortar);
+    if (waves <= 0) return;
+    hipLaunchKernelGGL(coarse_rhs_kernel, dim3(blocks_for(waves, 4)), dim3(256), 0, s, m, r, t, f);
 }
 
 __global__ void corr_solve_kernel(CoarseMaps m, const double *__restrict__ f, double *__restrict__ u) {
@@ -224,6 +289,16 @@ __global__ void set_ones_kernel(const int64_t *__restrict__ off, int64_t n, T *_
 void launch_set_ones(const int64_t *off, int64_t n, double *arena, hipStream_t s) {
     if (n <= 0) return;
     hipLaunchKernelGGL(set_ones_kernel<double>, dim3(blocks_for(n, 256)), dim3(256), 0, s, off, n, arena);
+}
+// one work-group per run, 16-byte stores
+__global__ void __launch_bounds__(256) zero_runs_kernel(const int64_t *__restrict__ runs, double *arena) {
+    const int64_t off = runs[2 * (int64_t)blockIdx.x], len = runs[2 * (int64_t)blockIdx.x + 1];
+    double2 *p = reinterpret_cast<double2 *>(arena + off);
+    for (int64_t i = threadIdx.x; i < len / 2; i += 256) p[i] = double2{0.0, 0.0};
+}
+void launch_zero_runs(const int64_t *runs, int64_t nruns, double *arena, hipStream_t s) {
+    if (nruns <= 0) return;
+    hipLaunchKernelGGL(zero_runs_kernel, dim3((unsigned)nruns), dim3(256), 0, s, runs, arena);
 }
 template <class T>
 void launch_set_ones_t(const int64_t *off, int64_t n, T *arena, hipStream_t s) {
