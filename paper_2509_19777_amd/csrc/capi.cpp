@@ -284,10 +284,8 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
                                h.pair_vals, s);
         launch_set_ones(mf.d_pad, (int64_t)mf.pad_ones.size(), h.ar64, s);
         for (int32_t l = mf.n_levels - 1; l >= 0; --l) {
-            for (int sd = 0; sd < 2; ++sd) {
-                const Range r = mf.ext_tiles[sd][(size_t)l];
-                launch_extend_add(mf.d_ext + r.start, r.count, mf.d_maps, h.ar64, s);
-            }
+            const Range r = mf.ext_lvl[(size_t)l];
+            launch_extend_add(mf.d_ext + r.start, r.count, mf.d_inv, h.ar64, s);
             run_program<double>(h, h.tl64, h.ar64, mf.factor_prog[(size_t)l], h.d_flag, s);
         }
     }

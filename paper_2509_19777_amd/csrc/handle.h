@@ -131,16 +131,18 @@ struct CoarseMF {
     int64_t region = 0, w_region = 0, lt_region = 0, vec_len = 0;
     int64_t a_base = 0, w_base = 0, wt_base = 0, lt_base = 0, ng_base = 0;
     std::vector<std::vector<Launch>> factor_prog;   // per level
-    std::vector<Range> ext_tiles[2];                // per level: extend-add tiles (left / right children)
+    std::vector<Range> ext_lvl;                     // per level: extend-add parent tiles
     std::vector<Range> vec_ext, bwd_copy;           // per level
     std::vector<Range> fwd, bwd;                    // per level: one GEMV launch each way (the chosen shape)
     std::vector<GemvShapes> fwd_shapes, bwd_shapes; // per level: the shapes the autotuner may pick
     std::vector<ExtendTile> ext;
     std::vector<int32_t> maps;
+    std::vector<int32_t> inv;                       // parent position -> child boundary row or -1, per child
+    std::vector<int64_t> inv_at;                    // per front: its inverse map in inv, -1 at the root
     std::vector<int64_t> va_dst, va_ptr, va_src, cp_dst, cp_src, init_map, out_dst, out_src;
     std::vector<int64_t> pad_ones;
     ExtendTile *d_ext = nullptr;
-    int32_t *d_maps = nullptr;
+    int32_t *d_inv = nullptr;
     int64_t *d_va_dst = nullptr, *d_va_ptr = nullptr, *d_va_src = nullptr, *d_cp_dst = nullptr, *d_cp_src = nullptr;
     int64_t *d_init_map = nullptr, *d_out_dst = nullptr, *d_out_src = nullptr, *d_pad = nullptr;
     double *V = nullptr, *WV = nullptr, *YV = nullptr, *XV = nullptr;   // WV, YV, XV are views of V

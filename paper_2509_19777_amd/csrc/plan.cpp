@@ -748,6 +748,22 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
             for (int32_t j = 0; j < dofs[(size_t)c]; ++j) mf.maps.push_back((int32_t)(it->second + j));
         }
     }
+    // and their inverses over the parent's positions
+    std::vector<int64_t> inv_off((size_t)nf, -1);
+    for (int32_t t = 0; t < nf; ++t) {
+        const int32_t par = mf.parent[(size_t)t];
+        if (par < 0) continue;
+        inv_off[(size_t)t] = (int64_t)mf.inv.size();
+        mf.inv.resize(mf.inv.size() + (size_t)((mf.nt_d[(size_t)par] + mf.nt_u[(size_t)par]) * TS), -1);
+        for (int64_t rr = 0; rr < mf.u[(size_t)t]; ++rr) {
+            const int64_t p = mf.maps[(size_t)(map_off[(size_t)t] + rr)];
+            if (p < 0 || p >= (mf.nt_d[(size_t)par] + mf.nt_u[(size_t)par]) * TS ||
+                mf.inv[(size_t)(inv_off[(size_t)t] + p)] != -1)
+                fail(HPLMM_E_ARG, "internal plan check failed: extend-add map");
+            mf.inv[(size_t)(inv_off[(size_t)t] + p)] = (int32_t)rr;
+        }
+    }
+    mf.inv_at = inv_off;
     auto A = [&](int32_t t, int64_t I, int64_t J) { return mf.a_base + mf.rel[(size_t)t] + tri_index(I, J) * TE; };
     auto W = [&](int32_t t, int64_t I, int64_t J) { return mf.w_base + mf.wrel[(size_t)t] + tri_index(I, J) * TE; };
     auto Wt = [&](int32_t t, int64_t I, int64_t J) { return mf.wt_base + mf.wrel[(size_t)t] + tri_index(I, J) * TE; };
@@ -761,7 +777,7 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         return mf.ng_base + mf.ltrel[(size_t)t] + (I * mf.nt_d[(size_t)t] + J) * TE;
     };
     mf.factor_prog.assign((size_t)nl, {});
-    for (int s = 0; s < 2; ++s) mf.ext_tiles[s].assign((size_t)nl, Range{});
+    mf.ext_lvl.assign((size_t)nl, Range{});
     mf.vec_ext.assign((size_t)nl, Range{});
     mf.bwd_copy.assign((size_t)nl, Range{});
     mf.fwd.assign((size_t)nl, Range{});
@@ -799,20 +815,37 @@ void build_coarse_mf(Handle &h, const hplmm_system &sys, const hplmm_partition &
         }
         g.count = (int64_t)h.tl64.gemm.size() - g.start;
         if (g.count) mf.factor_prog[(size_t)l].push_back(g);
-        // extend-add of the children (level l+1) into this level's fronts
-        for (int s = 0; s < 2; ++s) {
+        // extend-add of the children (level l+1) into this level's fronts:
+        // the parent tiles (PI, PJ) with rows of one child in both PI and PJ
+        {
             Range r{(int64_t)mf.ext.size(), 0};
             for (int32_t t : at[(size_t)l]) {
-                const int32_t ch = child[(size_t)t][s];
-                if (ch < 0) continue;
-                for (int64_t I = 0; I < mf.nt_u[(size_t)ch]; ++I)
-                    for (int64_t J = 0; J <= I; ++J)
-                        mf.ext.push_back({mf.a_base + mf.rel[(size_t)ch], mf.a_base + mf.rel[(size_t)t],
-                                          map_off[(size_t)ch], (int32_t)mf.nt_d[(size_t)ch], (int32_t)mf.u[(size_t)ch],
-                                          (int32_t)I, (int32_t)J, 0});
+                const int64_t ntp = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
+                std::vector<char> hit[2];
+                for (int s = 0; s < 2; ++s) {
+                    const int32_t ch = child[(size_t)t][s];
+                    if (ch < 0) continue;
+                    hit[s].assign((size_t)ntp, 0);
+                    for (int64_t rr = 0; rr < mf.u[(size_t)ch]; ++rr)
+                        hit[s][(size_t)(mf.maps[(size_t)(map_off[(size_t)ch] + rr)] / TS)] = 1;
+                }
+                for (int64_t I = 0; I < ntp; ++I)
+                    for (int64_t J = 0; J <= I; ++J) {
+                        ExtendTile e{A(t, I, J), {-1, -1}, {-1, -1}, {0, 0}, (int32_t)I, (int32_t)J, (int32_t)ntp, 0};
+                        bool any = false;
+                        for (int s = 0; s < 2; ++s) {
+                            const int32_t ch = child[(size_t)t][s];
+                            if (ch < 0 || !hit[s][(size_t)I] || !hit[s][(size_t)J]) continue;
+                            e.child_off[s] = mf.a_base + mf.rel[(size_t)ch];
+                            e.inv_off[s] = inv_off[(size_t)ch];
+                            e.nt_d[s] = (int32_t)mf.nt_d[(size_t)ch];
+                            any = true;
+                        }
+                        if (any) mf.ext.push_back(e);
+                    }
             }
             r.count = (int64_t)mf.ext.size() - r.start;
-            mf.ext_tiles[s][(size_t)l] = r;
+            mf.ext_lvl[(size_t)l] = r;
         }
         // forward vector extend-add: parent slot <- sum of child boundary slots
         {
@@ -1861,9 +1894,13 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
         {
             const CoarseMF &mf = h.mf;
             for (const auto &r : mf.ext) {
-                chk(in(r.child_off, 1, h.ar64_n) && in(r.parent_off, 1, h.ar64_n), "extend-add fronts");
-                chk(r.u > 0 && r.map_off >= 0 && r.map_off + r.u <= (int64_t)mf.maps.size(), "extend-add map");
-                chk(r.I >= r.J && r.J >= 0 && (int64_t)r.I * TS < r.u, "extend-add tile");
+                chk(in(r.parent_off, TE, h.ar64_n) && r.PI >= r.PJ && r.PJ >= 0 && r.PI < r.ntp, "extend-add tile");
+                for (int s = 0; s < 2; ++s)
+                    if (r.child_off[s] >= 0)
+                        chk(in(r.inv_off[s], (int64_t)r.ntp * TS, (int64_t)mf.inv.size()) && r.nt_d[s] >= 0,
+                            "extend-add child");
+                    else
+                        chk(r.child_off[s] == -1, "extend-add child");
             }
             for (int32_t t = 0; t < mf.n_fronts; ++t) {
                 const int64_t nt = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
@@ -1880,13 +1917,34 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
             std::unordered_map<int64_t, int64_t> front_nt;
             for (int32_t t = 0; t < mf.n_fronts; ++t)
                 front_nt[mf.a_base + mf.rel[(size_t)t]] = mf.nt_d[(size_t)t] + mf.nt_u[(size_t)t];
+            const std::vector<int64_t> &inv_at = mf.inv_at;
+            chk((int64_t)inv_at.size() == (int64_t)mf.n_fronts, "extend-add inverse maps");
+            std::unordered_map<int64_t, int32_t> front_of;
+            for (int32_t t = 0; t < mf.n_fronts; ++t) front_of[mf.a_base + mf.rel[(size_t)t]] = t;
             for (const auto &r : mf.ext) {
-                auto it = front_nt.find(r.parent_off), ic = front_nt.find(r.child_off);
-                chk(it != front_nt.end() && ic != front_nt.end(), "extend-add front offsets");
-                chk((int64_t)r.nt_d * TS + r.u <= ic->second * TS, "extend-add child rows");
-                if (r.J == 0)
-                    for (int64_t q = (int64_t)r.I * TS; q < std::min<int64_t>(r.u, (int64_t)(r.I + 1) * TS); ++q)
-                        chk(mf.maps[(size_t)(r.map_off + q)] < it->second * TS, "extend-add parent position");
+                auto it = front_nt.find(r.parent_off - tri_index(r.PI, r.PJ) * TE);
+                chk(it != front_nt.end() && it->second == r.ntp, "extend-add parent front");
+                for (int s = 0; s < 2; ++s) {
+                    if (r.child_off[s] < 0) continue;
+                    auto ic = front_of.find(r.child_off[s]);
+                    chk(ic != front_of.end(), "extend-add child front");
+                    const int32_t ch = ic->second;
+                    chk(r.nt_d[s] == mf.nt_d[(size_t)ch] && mf.parent[(size_t)ch] >= 0 &&
+                            mf.a_base + mf.rel[(size_t)mf.parent[(size_t)ch]] == it->first && r.inv_off[s] == inv_at[(size_t)ch],
+                        "extend-add child");
+                }
+            }
+            // every child row an inverse map names lies in the child's boundary block
+            for (int32_t t = 0; t < mf.n_fronts; ++t) {
+                const int32_t par = mf.parent[(size_t)t];
+                if (par < 0) continue;
+                chk(mf.u[(size_t)t] <= mf.nt_u[(size_t)t] * TS, "extend-add child rows");
+                const int64_t np = (mf.nt_d[(size_t)par] + mf.nt_u[(size_t)par]) * TS;
+                chk(in(inv_at[(size_t)t], np, (int64_t)mf.inv.size()), "extend-add inverse map");
+                for (int64_t p = 0; p < np; ++p) {
+                    const int32_t v = mf.inv[(size_t)(inv_at[(size_t)t] + p)];
+                    chk(v >= -1 && v < mf.u[(size_t)t], "extend-add child row");
+                }
             }
             for (auto v : mf.maps) chk(v >= 0, "extend-add position");
             for (auto v : mf.va_dst) chk(in(v, 1, mf.vec_len), "front vector extend-add");
@@ -2032,7 +2090,7 @@ void build_plan(Handle &h, const hplmm_system &sys_in, const hplmm_partition &pa
     {
         CoarseMF &mf = h.mf;
         mf.d_ext = h.upload(mf.ext, s);
-        mf.d_maps = h.upload(mf.maps, s);
+        mf.d_inv = h.upload(mf.inv, s);
         mf.d_va_dst = h.upload(mf.va_dst, s);
         mf.d_va_ptr = h.upload(mf.va_ptr, s);
         mf.d_va_src = h.upload(mf.va_src, s);

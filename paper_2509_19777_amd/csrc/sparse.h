@@ -142,19 +142,20 @@ void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const Coars
                             const CoarseKRef *krefs, const CoarseMaps &cm, const double *bsr_val,
                             const double *karena, double *farena, double *vals, hipStream_t s);
 
-// Multifrontal extend-add of update matrices: one work-group per 64x64 tile of
-// a child's boundary block; its lower-triangle elements (r, s), r >= s,
-// r, s < u, are added into the parent at positions (map[r], map[s]).
+// Multifrontal extend-add of update matrices, one work-group per 64x64 tile
+// (PI, PJ), PI >= PJ, of a parent front that a child's update matrix reaches.
+// Element (p, q) of the tile (both triangles of a diagonal tile) receives,
+// from child 0 and then child 1, the child's boundary-block element
+// (max(a, b), min(a, b)) with a = inv[p], b = inv[q], when both are >= 0.
 struct ExtendTile {
-    int64_t child_off;    // child front (packed lower tiles)
-    int64_t parent_off;   // parent front
-    int64_t map_off;      // child boundary row -> parent position (maps[map_off + r])
-    int32_t nt_d;         // tiles of the child's own block (its boundary block starts there)
-    int32_t u;            // boundary dofs of the child
-    int32_t I, J;         // tile of the child's boundary block, I >= J
-    int32_t pad;
+    int64_t parent_off;     // the parent tile (PI, PJ)
+    int64_t child_off[2];   // child fronts (packed lower tiles); -1: adds nothing to this tile
+    int64_t inv_off[2];     // parent position -> child boundary row or -1: inv[inv_off + p]
+    int32_t nt_d[2];        // tiles of the child's own block (its boundary block starts there)
+    int32_t PI, PJ;         // tile of the parent front
+    int32_t ntp, pad;       // tiles per side of the parent front
 };
-void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *maps, double *arena, hipStream_t s);
+void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *inv, double *arena, hipStream_t s);
 // dst[dst_idx[i]] += sum_{q in [ptr[i], ptr[i+1])} src[src_idx[q]], i < n
 void launch_gather_add(const int64_t *dst_idx, const int64_t *ptr, const int64_t *src_idx, int64_t n,
                        const double *src, double *dst, hipStream_t s);

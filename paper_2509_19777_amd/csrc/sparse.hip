@@ -520,28 +520,38 @@ void launch_coarse_assemble(const CoarsePair *pairs, int64_t npairs, const Coars
 }
 
 // ---- multifrontal extend-add ---------------------------------------------------------
-// One work-group per child tile: consecutive threads read consecutive rows
-// of a tile column (the stored order), and a column's parent positions are
-// mostly contiguous too.  Every child element is added exactly once.
+// One work-group per parent tile, both children in one launch: each parent
+// element is read and written once, and its two additions come in child
+// order.  Consecutive threads take consecutive rows of a tile column (the
+// stored order); their child rows are mostly consecutive too.
 __global__ void __launch_bounds__(256) extend_add_kernel(const ExtendTile *__restrict__ tiles,
-                                                         const int32_t *__restrict__ maps, double *arena) {
+                                                         const int32_t *__restrict__ inv, double *arena) {
     const ExtendTile w = tiles[blockIdx.x];
-    const double *C = arena + w.child_off + tri_index(w.nt_d + w.I, w.nt_d + w.J) * TE;
     double *P = arena + w.parent_off;
-    const int32_t *map = maps + w.map_off;
 #pragma unroll 4
     for (int q = 0; q < TE / 256; ++q) {
         const int e = threadIdx.x + 256 * q;
-        const int64_t r = (int64_t)w.I * TS + (e & (TS - 1)), c = (int64_t)w.J * TS + (e >> 6);
-        if (r >= w.u || c >= w.u || r < c) continue;
-        // (r, c) with r >= c of the child; same-tile mirror of the parent is
-        // written explicitly unless the positions coincide
-        sym_put(P, map[r], map[c], C[e], true, true);
+        const int64_t pr = (int64_t)w.PI * TS + (e & (TS - 1)), pc = (int64_t)w.PJ * TS + (e >> 6);
+        double v = 0.0;
+        bool hit = false;
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            if (w.child_off[s] < 0) continue;
+            const int32_t a = inv[w.inv_off[s] + pr], b = inv[w.inv_off[s] + pc];
+            if (a < 0 || b < 0) continue;
+            const int32_t hi = a > b ? a : b, lo = a > b ? b : a;
+            const double c = arena[w.child_off[s] + tri_index(w.nt_d[s] + (hi >> 6), w.nt_d[s] + (lo >> 6)) * TE +
+                                   (int64_t)(lo & (TS - 1)) * TS + (hi & (TS - 1))];
+            if (!hit) v = P[e];
+            hit = true;
+            v += c;
+        }
+        if (hit) P[e] = v;
     }
 }
-void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *maps, double *arena, hipStream_t s) {
+void launch_extend_add(const ExtendTile *tiles, int64_t ntiles, const int32_t *inv, double *arena, hipStream_t s) {
     if (ntiles <= 0) return;
-    hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, maps, arena);
+    hipLaunchKernelGGL(extend_add_kernel, dim3((unsigned)ntiles), dim3(256), 0, s, tiles, inv, arena);
 }
 
 __global__ void gather_add_kernel(const int64_t *__restrict__ dst_idx, const int64_t *__restrict__ ptr,
