@@ -157,14 +157,14 @@ static void contact_setup(Handle &h, hipStream_t s) {
 // split-task scratch).
 static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup *sg = nullptr) {
     struct Events {
-        hipEvent_t e[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+        hipEvent_t e[8] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
         ~Events() {
             for (hipEvent_t x : e)
                 if (x) (void)hipEventDestroy(x);
         }
     } evs;
     hipEvent_t *ev = evs.e;
-    for (int i = 0; i < 7; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
+    for (int i = 0; i < 8; ++i) hip_check(hipEventCreate(&ev[i]), "hipEventCreate");
     const int32_t init_flag[2] = {0, 0x7fffffff};
     hip_check(hipMemcpyAsync(h.d_flag, init_flag, sizeof(init_flag), hipMemcpyHostToDevice, s), "flag init");
     hip_check(hipEventRecord(ev[0], s), "event");
@@ -175,10 +175,25 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
             for (auto &e : h.side_ev) hip_check(hipEventCreate(&e), "event");
         }
     }
+    // the grains' coupling blocks R (the basis right-hand sides), cleared and
+    // gathered on the side stream beside the grain blocks on s
+    auto gather_r = [&](hipStream_t st) {
+        if (!h.gm_roff.empty()) {
+            const int64_t r0 = h.gm_roff[0];
+            int64_t rlen = 0;
+            for (size_t m = 0; m < h.gm_roff.size(); ++m) rlen += h.gset.nt[m] * h.gm_ntc[m] * TE;
+            zero(h.ar64 + r0, sizeof(double) * rlen, st);
+        }
+        launch_gather_abar(h.csr, h.d_abar, h.n_abar, h.cm, h.gg, h.ar64, st);
+    };
+    if (fork) {
+        hip_check(hipStreamWaitEvent(h.side, ev[0], 0), "fork");
+        gather_r(h.side);
+        hip_check(hipEventRecord(ev[7], h.side), "event");
+    }
     if (fork && h.n_mortar > 0) {
         // the fronts' region is cleared on the side stream, idle until the
         // grains are factored
-        hip_check(hipStreamWaitEvent(h.side, ev[0], 0), "fork");
         zero(h.ar64 + h.mf.a_base, sizeof(double) * h.mf.region, h.side);
         hip_check(hipEventRecord(ev[6], h.side), "event");
     }
@@ -187,15 +202,12 @@ static void numeric_setup(Handle &h, hipStream_t s, int stage = 3, const SgSetup
         launch_zero_runs(h.d_zero_g, (int64_t)h.zero_g.size() / 2, h.ar64, s);
     else
         zero(h.ar64 + h.gset.a_base, sizeof(double) * h.gset.region, s);
-    if (!h.gm_roff.empty()) {
-        const int64_t r0 = h.gm_roff[0];
-        int64_t rlen = 0;
-        for (size_t m = 0; m < h.gm_roff.size(); ++m) rlen += h.gset.nt[m] * h.gm_ntc[m] * TE;
-        zero(h.ar64 + r0, sizeof(double) * rlen, s);
-    }
     launch_gather_grain_blocks(h.csr, h.gg, h.d_b, h.ar64, s);
     launch_set_ones(h.d_pad_g, (int64_t)h.pad_ones_g.size(), h.ar64, s);
-    launch_gather_abar(h.csr, h.d_abar, h.n_abar, h.cm, h.gg, h.ar64, s);
+    if (fork)
+        hip_check(hipStreamWaitEvent(s, ev[7], 0), "join");
+    else
+        gather_r(s);
     if (stage < 1) {
         hip_check(hipStreamSynchronize(s), "stage");
         return;
