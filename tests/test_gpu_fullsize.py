@@ -92,6 +92,20 @@ def test_solve_full(big):
     assert np.array_equal(xg, x3.cpu().numpy())
 
 
+def test_second_setup_same_bits(big):
+    """A second set-up on the same handle starts from what the first left in
+    the arena: only the tiles inside each block's envelope are cleared, the
+    coupling blocks are gathered on the side stream and the fronts receive
+    their children's update matrices by parent tile.  Its preconditioner
+    gives the first one's bits."""
+    p, A, b, mesh, part, S = big
+    r = np.random.default_rng(7).standard_normal(A.shape[0])
+    z1 = S.apply(_cu(r), 0).cpu().numpy()
+    S.setup()
+    z2 = S.apply(_cu(r), 0).cpu().numpy()
+    assert np.array_equal(z1, z2)
+
+
 def test_solve_full_bf16_smoother(big):
     from paper_2509_19777_amd import hplmm as hp
     p, A, b, mesh, part, S = big
